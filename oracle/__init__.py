@@ -1,0 +1,196 @@
+"""CPU oracle for the learned integer compressor (arXiv 2412.10770).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package; the product path
+(``paper_2412_10770_amd``) never does, and the two share no code.
+
+Two layers:
+
+* plain definitions (Def. 1): ``decompress`` is the key list itself,
+  ``decompress_range(b, e)`` is ``K[b:e]``, ``access(i)`` is ``K[i]``, and
+  ``lower_bound(q)`` is the first index with ``K[i] >= q`` (the textbook
+  lower bound, ``numpy.searchsorted(K, q, 'left')``);
+* the encoding (Def. 2, Eq. 1, Sec. II-A): ``compress`` fits the greedy
+  anchored fixed-point eps-PLA per block and writes blob v1; ``decode``
+  is an independent blob decoder.  Both live in ``lcref.c`` (plain C,
+  ``unsigned __int128`` cone arithmetic, bit-by-bit packing).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lcref.c")
+_LIB = os.path.join(_HERE, "liblcref.so")
+
+REF_OK = 0
+REF_EINVAL = -1
+REF_ENOSPC = -2
+REF_EFORMAT = -3
+REF_EUNSORTED = -5
+
+HEADER_FIELDS = ("key_bytes", "log2_block", "frac_bits", "width", "eps", "max_nseg", "n",
+                 "nblocks", "nseg_total", "off_first", "off_dir", "off_res", "res_stride",
+                 "off_seg", "blob_bytes")
+
+
+def build(force: bool = True, src: str = _SRC, out: str = _LIB) -> str:
+    """Compile lcref.c with gcc (-O2, no intrinsics) into a shared library."""
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall",
+                               "-Wextra", "-o", tmp, src])
+        os.replace(tmp, out)
+    return out
+
+
+def _bind(path: str):
+    L = ctypes.CDLL(path)
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    L.lcref_width.argtypes = [ctypes.c_uint32]
+    L.lcref_width.restype = ctypes.c_int
+    L.lcref_fit_block.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                  ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p]
+    L.lcref_fit_block.restype = ctypes.c_uint32
+    L.lcref_compress.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_uint32, ctypes.c_uint32, u8p, ctypes.c_uint64,
+                                 ctypes.POINTER(ctypes.c_uint64)]
+    L.lcref_compress.restype = ctypes.c_int
+    L.lcref_decode.argtypes = [u8p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint64]
+    L.lcref_decode.restype = ctypes.c_int
+    L.lcref_header.argtypes = [u8p, ctypes.c_uint64, ctypes.c_void_p]
+    L.lcref_header.restype = ctypes.c_int
+    return L
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: oracle status {code}")
+        self.code = code
+
+
+def _keys_array(keys) -> np.ndarray:
+    a = np.ascontiguousarray(keys)
+    if a.dtype in (np.uint32, np.int32):
+        return a.view(np.uint32)
+    if a.dtype in (np.uint64, np.int64):
+        return a.view(np.uint64)
+    raise TypeError(f"keys must be 4- or 8-byte integers, got {a.dtype}")
+
+
+def _u8p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+
+class Ref:
+    """The encoder/decoder of one build of lcref.c (the default build, or a
+    variant compiled from a modified copy by the oracle's own tests)."""
+
+    def __init__(self, path: str):
+        self.L = _bind(path)
+
+    def width(self, eps: int) -> int:
+        """Residual width ceil(log2(2 eps + 1)) as the oracle computes it."""
+        return int(self.L.lcref_width(eps))
+
+    def fit_block(self, keys, eps: int, frac_bits: int = 20):
+        """Greedy anchored fit of one block; returns (start, anchor, A) arrays."""
+        k = np.ascontiguousarray(_keys_array(keys), dtype=np.uint64)
+        nb = len(k)
+        st = np.zeros(max(nb, 1), np.uint32)
+        an = np.zeros(max(nb, 1), np.uint64)
+        sl = np.zeros(max(nb, 1), np.uint64)
+        m = self.L.lcref_fit_block(k.ctypes.data, nb, eps, frac_bits, st.ctypes.data,
+                                   an.ctypes.data, sl.ctypes.data)
+        return st[:m].copy(), an[:m].copy(), sl[:m].copy()
+
+    def compress(self, keys, eps: int, log2_block: int = 10, frac_bits: int = 20) -> np.ndarray:
+        """Encode sorted keys into a blob v1 (uint8 array)."""
+        k = _keys_array(keys)
+        kb = k.dtype.itemsize
+        need = ctypes.c_uint64(0)
+        ptr = k.ctypes.data if len(k) else None
+        rc = self.L.lcref_compress(ptr, len(k), kb, log2_block, eps, frac_bits, None, 0,
+                                   ctypes.byref(need))
+        if rc not in (REF_OK, REF_ENOSPC):
+            raise OracleError(rc, "compress")
+        out = np.zeros(need.value, np.uint8)
+        rc = self.L.lcref_compress(ptr, len(k), kb, log2_block, eps, frac_bits, _u8p(out),
+                                   len(out), ctypes.byref(need))
+        if rc != REF_OK:
+            raise OracleError(rc, "compress")
+        return out
+
+    def header(self, blob) -> dict:
+        b = np.ascontiguousarray(blob, dtype=np.uint8)
+        f = np.zeros(15, np.uint64)
+        rc = self.L.lcref_header(_u8p(b), len(b), f.ctypes.data)
+        if rc != REF_OK:
+            raise OracleError(rc, "header")
+        return {k: int(v) for k, v in zip(HEADER_FIELDS, f)}
+
+    def decode(self, blob) -> np.ndarray:
+        """Decode a blob v1 into its key list."""
+        b = np.ascontiguousarray(blob, dtype=np.uint8)
+        h = self.header(b)
+        out = np.zeros(max(h["n"], 1), np.uint32 if h["key_bytes"] == 4 else np.uint64)
+        rc = self.L.lcref_decode(_u8p(b), len(b), out.ctypes.data, h["n"])
+        if rc != REF_OK:
+            raise OracleError(rc, "decode")
+        return out[:h["n"]]
+
+
+_default = None
+
+
+def default() -> Ref:
+    global _default
+    if _default is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        _default = Ref(_LIB)
+    return _default
+
+
+def width(eps: int) -> int:
+    return default().width(eps)
+
+
+def fit_block(keys, eps: int, frac_bits: int = 20):
+    return default().fit_block(keys, eps, frac_bits)
+
+
+def compress(keys, eps: int, log2_block: int = 10, frac_bits: int = 20) -> np.ndarray:
+    return default().compress(keys, eps, log2_block, frac_bits)
+
+
+def header(blob) -> dict:
+    return default().header(blob)
+
+
+def decode(blob) -> np.ndarray:
+    return default().decode(blob)
+
+
+# --- plain definitions (Def. 1): no compressed format involved -----------------
+
+def decompress(keys) -> np.ndarray:
+    return _keys_array(keys).copy()
+
+
+def decompress_range(keys, begin: int, end: int) -> np.ndarray:
+    return _keys_array(keys)[begin:end].copy()
+
+
+def access(keys, idx) -> np.ndarray:
+    return _keys_array(keys)[np.asarray(idx, dtype=np.int64)]
+
+
+def lower_bound(keys, q) -> np.ndarray:
+    k = _keys_array(keys)
+    return np.searchsorted(k, np.asarray(q, dtype=k.dtype), side="left").astype(np.uint64)

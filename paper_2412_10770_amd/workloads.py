@@ -1,0 +1,168 @@
+"""Seeded synthetic inputs: sorted integer key lists and query batches.
+
+This module only draws random numbers and sorts them; it holds none of the
+compressor's arithmetic, so both the HIP path and the CPU oracle's tests can
+use it.  Every generator takes a seed and a torch device; the keys are a
+function of (recipe, size, seed, device type) -- the CPU and GPU random
+streams differ, so a test always hands the *same* materialised keys to both
+sides.
+
+Key lists are returned as 1-D torch tensors holding the unsigned bit
+patterns: ``torch.int32`` for 4-byte keys and ``torch.int64`` for 8-byte
+keys (``as_numpy`` reinterprets them as uint32/uint64).
+
+Recipes (sizes are parameters; the full sizes are the defaults):
+
+* ``uniform_gaps``: K[0] = 0, gaps i.i.d. uniform integers in [1, 64],
+  1,000,000 uint32 keys.
+* ``lognormal_distinct``: floor(2^40 * x / M), x ~ lognormal(0, 2), M the
+  largest of the first n draws, clipped to 2^40 - 1; sorted and
+  de-duplicated, drawing further batches of n/2 until n distinct values
+  exist, then exactly n of them picked uniformly (100,000,000 uint64 keys).
+* ``heterogeneous_runs``: alternating runs (dense first) whose lengths are
+  floor(exp(U[ln lo, ln hi])) with lo, hi = 1e4, 1e6 by default; dense runs
+  draw gaps uniform in [1, 4], sparse runs Zipf(1.2) gaps capped at 2^20
+  (200,000,000 uint64 keys).
+* ``lognormal_gaps``: gaps max(1, ceil(lognormal(3, 1.5))), uint64.
+* queries: ``uniform_indices`` (i uniform in [0, n)) and ``uniform_keys``
+  (q uniform over [lo, hi]).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+SEED_BASE = 241210770
+
+
+def _gen(seed: int, device) -> torch.Generator:
+    g = torch.Generator(device=torch.device(device))
+    g.manual_seed(int(seed))
+    return g
+
+
+def as_numpy(keys: torch.Tensor) -> np.ndarray:
+    """Host copy of a key tensor as uint32 / uint64."""
+    a = keys.detach().cpu().contiguous().numpy()
+    return a.view(np.uint32 if a.dtype.itemsize == 4 else np.uint64)
+
+
+def from_numpy(a: np.ndarray, device="cpu") -> torch.Tensor:
+    """Key tensor (int32/int64 bit patterns) from a uint32/uint64 array."""
+    a = np.ascontiguousarray(a)
+    signed = a.view(np.int32 if a.dtype.itemsize == 4 else np.int64)
+    return torch.from_numpy(signed.copy()).to(device)
+
+
+def uniform_gaps(n: int = 1_000_000, seed: int = SEED_BASE + 1, device="cpu",
+                 lo: int = 1, hi: int = 64, key_bytes: int = 4) -> torch.Tensor:
+    g = _gen(seed, device)
+    if n == 0:
+        return torch.zeros(0, dtype=torch.int32 if key_bytes == 4 else torch.int64, device=device)
+    gaps = torch.randint(lo, hi + 1, (n,), generator=g, device=device, dtype=torch.int64)
+    gaps[0] = 0
+    keys = torch.cumsum(gaps, 0)
+    return keys.to(torch.int32) if key_bytes == 4 else keys
+
+
+def lognormal_distinct(n: int = 100_000_000, seed: int = SEED_BASE + 2, device="cpu",
+                       sigma: float = 2.0, bits: int = 40) -> torch.Tensor:
+    g = _gen(seed, device)
+    top = float(2 ** bits)
+    first = torch.empty(n, dtype=torch.float64, device=device).log_normal_(0.0, sigma, generator=g)
+    M = float(first.max())
+    batches = [first]
+    while True:
+        x = torch.cat(batches)
+        v = torch.floor(x * (top / M)).clamp_(max=top - 1).to(torch.int64)
+        del x
+        u = torch.unique(v, sorted=True)
+        del v
+        if u.numel() >= n:
+            break
+        del u
+        more = torch.empty(max(n // 2, 1), dtype=torch.float64, device=device)
+        more.log_normal_(0.0, sigma, generator=g)
+        batches.append(more)
+    del batches
+    if u.numel() > n:
+        pick = torch.randperm(u.numel(), generator=g, device=device)[:n]
+        pick, _ = torch.sort(pick)
+        u = u[pick]
+    return u.contiguous()
+
+
+def _zipf_gaps(count: int, g: torch.Generator, device, s: float = 1.2,
+               cap: int = 1 << 20) -> torch.Tensor:
+    """min(Zipf(s), cap) by inverse transform over k = 1 .. cap-1 (the rest -> cap)."""
+    from scipy.special import zeta
+    k = torch.arange(1, cap, dtype=torch.float64, device=device)
+    pmf = k.pow(-s) / float(zeta(s, 1))
+    cdf = torch.cumsum(pmf, 0)
+    u = torch.rand(count, dtype=torch.float64, device=device, generator=g)
+    idx = torch.searchsorted(cdf, u, right=True)  # number of k with cdf <= u
+    return (idx + 1).clamp_(max=cap).to(torch.int64)
+
+
+def heterogeneous_runs(n: int = 200_000_000, seed: int = SEED_BASE + 3, device="cpu",
+                       run_lo: float = 1e4, run_hi: float = 1e6) -> torch.Tensor:
+    g = _gen(seed, device)
+    gaps = torch.empty(n, dtype=torch.int64, device=device)
+    pos, dense = 0, True
+    while pos < n:
+        u = float(torch.rand(1, generator=g, dtype=torch.float64, device=device))
+        length = int(math.floor(math.exp(math.log(run_lo) + u * (math.log(run_hi) - math.log(run_lo)))))
+        length = max(1, min(length, n - pos))
+        if dense:
+            gaps[pos:pos + length] = torch.randint(1, 5, (length,), generator=g, device=device)
+        else:
+            gaps[pos:pos + length] = _zipf_gaps(length, g, device)
+        pos += length
+        dense = not dense
+    gaps[0] = 0
+    return torch.cumsum(gaps, 0)
+
+
+def lognormal_gaps(n: int, seed: int = SEED_BASE + 5, device="cpu", mu: float = 3.0,
+                   sigma: float = 1.5) -> torch.Tensor:
+    g = _gen(seed, device)
+    x = torch.empty(n, dtype=torch.float64, device=device).log_normal_(mu, sigma, generator=g)
+    gaps = torch.ceil(x).clamp_(min=1).to(torch.int64)
+    if n:
+        gaps[0] = 0
+    return torch.cumsum(gaps, 0)
+
+
+def uniform_indices(m: int, n: int, seed: int, device="cpu") -> torch.Tensor:
+    g = _gen(seed, device)
+    if n == 0:
+        return torch.zeros(m, dtype=torch.int64, device=device)
+    return torch.randint(0, n, (m,), generator=g, device=device, dtype=torch.int64)
+
+
+def uniform_keys(m: int, lo: int, hi: int, seed: int, device="cpu", key_bytes: int = 8) -> torch.Tensor:
+    """q uniform over the integers [lo, hi] (hi - lo < 2^63)."""
+    g = _gen(seed, device)
+    span = hi - lo + 1
+    if span <= 2 ** 62:
+        q = torch.randint(0, span, (m,), generator=g, device=device, dtype=torch.int64) + lo
+    else:
+        r = torch.rand(m, dtype=torch.float64, generator=g, device=device)
+        q = (r * float(span)).to(torch.int64) + lo
+    return q.to(torch.int32) if key_bytes == 4 else q
+
+
+def edge_lists():
+    """Small hand-made key lists for edge cases: (name, uint array)."""
+    out = []
+    out.append(("empty_u32", np.zeros(0, np.uint32)))
+    out.append(("single_u64", np.array([12345678901234], np.uint64)))
+    out.append(("all_equal", np.full(3000, 7, np.uint32)))
+    out.append(("max_u32", (np.uint64(2**32 - 1) - np.arange(2500, dtype=np.uint64)[::-1] * 3)
+                .astype(np.uint32)))
+    out.append(("max_u64", np.uint64(2**64 - 1) - np.arange(2500, dtype=np.uint64)[::-1] * np.uint64(5)))
+    huge = np.cumsum(np.full(2100, 1 << 45, dtype=np.uint64))  # gaps beyond the cap at F = 20
+    out.append(("cap_gaps", huge))
+    return out

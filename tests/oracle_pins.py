@@ -1,0 +1,313 @@
+"""Checks that pin the CPU oracle to facts fixed outside the oracle itself.
+
+Each ``check_*`` takes a ``Ref`` (a build of the oracle) and raises
+AssertionError when the build disagrees with:
+
+* Def. 1 (lossless): decode(compress(K)) == K;
+* Def. 2 (floor error bound): every key within eps of floor(f(i)), checked
+  with Python integers from the segment list, and every stored code <= 2 eps,
+  read back with a bit reader written here from the layout statement;
+* Sec. II-A / Fig. 2: the residual width ceil(log2(2 eps + 1)) (eps = 4 gives
+  4 bits in the paper's toy example);
+* closed forms: an arithmetic progression fits one segment per block with
+  every residual zero; the blob size from the segment counts;
+* brute force on tiny inputs: every segment's slope is feasible, every
+  segment that ends before its block does cannot be extended by one key with
+  any slope, the stored slope is the midpoint of the enumerated feasible set,
+  and the greedy count is at least the minimum over all anchored
+  segmentations (equal when that minimum is 1);
+* hand-derived worked examples under tests/golden/.
+
+The same checks run against deliberately mutated builds of the oracle to
+show that a plausible mistake in it fails at least one of them.
+"""
+from __future__ import annotations
+
+import math
+import os
+
+import numpy as np
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def align16(x: int) -> int:
+    return (x + 15) // 16 * 16
+
+
+def widths_of(v: int) -> int:
+    for nb in (1, 2, 4, 8):
+        if v < (1 << (8 * nb)):
+            return nb
+    raise ValueError(v)
+
+
+def load_golden(name: str) -> dict:
+    out = {"blob": []}
+    in_blob = False
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if not line:
+                continue
+            if in_blob:
+                out["blob"].extend(int(t, 16) for t in line.split())
+                continue
+            key, _, val = line.partition(":")
+            key, val = key.strip(), val.strip()
+            if key == "blob":
+                in_blob = True
+            elif key == "keys":
+                out["keys"] = [int(t) for t in val.split()]
+            else:
+                out[key] = int(val)
+    out["blob"] = np.array(out["blob"], np.uint8)
+    return out
+
+
+def read_codes(blob: np.ndarray, h: dict, b: int, nb: int) -> list:
+    """Codes of block b, read from the LSB-first bit stream of its slab."""
+    w = h["width"]
+    start = h["off_res"] + b * h["res_stride"]
+    slab = int.from_bytes(bytes(blob[start:start + h["res_stride"]]), "little")
+    mask = (1 << w) - 1
+    return [(slab >> (j * w)) & mask for j in range(nb)]
+
+
+# --- the random inputs the checks use ---------------------------------------
+
+def _sorted_keys(rng, n, kb, kind):
+    hi = (1 << (8 * kb)) - 1
+    if kind == "uniform":
+        g = rng.integers(0, 100, n)
+    elif kind == "dups":
+        g = rng.integers(0, 2, n)
+    elif kind == "wide":
+        g = rng.integers(0, 1 << min(20, 8 * kb - 14), n)
+    else:  # bursty: long runs of small gaps with rare large jumps
+        g = rng.integers(0, 5, n)
+        jumps = rng.random(n) < 0.01
+        g[jumps] = rng.integers(1000, 1 << min(24, 8 * kb - 14), int(jumps.sum()))
+    k = np.cumsum(g.astype(np.uint64))
+    room = hi - int(k[-1])  # keys may be shifted up by at most this much
+    where = int(rng.integers(0, 3))
+    if where == 0:
+        base = 0
+    elif where == 1:
+        base = room  # the last key is the largest representable value
+    else:
+        base = int(rng.integers(0, min(room, 2 ** 62) + 1))
+    return (k + np.uint64(base)).astype(np.uint32 if kb == 4 else np.uint64)
+
+
+def random_cases(seed: int, count: int):
+    rng = np.random.default_rng(seed)
+    for _ in range(count):
+        kb = int(rng.choice([4, 8]))
+        log2b = int(rng.integers(6, 13))
+        n = int(rng.choice([1, 2, 63, 64, 65, 1000, 1 << log2b, (1 << log2b) + 1, 5000]))
+        eps = int(rng.choice([0, 1, 3, 7, 15, 63, 255, 4095]))
+        kind = str(rng.choice(["uniform", "dups", "wide", "bursty"]))
+        yield _sorted_keys(rng, n, kb, kind), eps, log2b
+
+
+# --- checks -------------------------------------------------------------------
+
+def check_width(ref):
+    assert ref.width(4) == 4, "Fig. 2: eps = 4 needs 4 bits"
+    for eps, w in ((7, 4), (15, 5), (31, 6), (63, 7), (127, 8), (255, 9), (0, 0)):
+        assert ref.width(eps) == w, (eps, w)
+    for eps in list(range(0, 3000)) + [2 ** k + d for k in range(11, 31) for d in (-1, 0, 1)] + [2 ** 31 - 1]:
+        assert ref.width(eps) == math.ceil(math.log2(2 * eps + 1)), eps
+
+
+def check_roundtrip(ref, seed=1, count=60):
+    for keys, eps, log2b in random_cases(seed, count):
+        blob = ref.compress(keys, eps, log2b)
+        back = ref.decode(blob)
+        assert back.dtype == keys.dtype and np.array_equal(back, keys), (len(keys), eps, log2b)
+
+
+def check_error_bound(ref, seed=2, count=40, frac_bits=20):
+    for keys, eps, log2b in random_cases(seed, count):
+        B = 1 << log2b
+        blob = ref.compress(keys, eps, log2b, frac_bits)
+        h = ref.header(blob)
+        for b in range(0, (len(keys) + B - 1) // B):
+            kk = [int(x) for x in keys[b * B:(b + 1) * B]]
+            st, an, sl = ref.fit_block(np.array(kk, np.uint64), eps, frac_bits)
+            assert int(st[0]) == 0
+            for t in range(len(st)):
+                s = int(st[t])
+                e = int(st[t + 1]) if t + 1 < len(st) else len(kk)
+                assert s < e and int(an[t]) == kk[s]
+                for j in range(s, e):
+                    pred = kk[s] + ((int(sl[t]) * (j - s)) >> frac_bits)
+                    assert abs(kk[j] - pred) <= eps, (b, j, eps)
+            codes = read_codes(blob, h, b, len(kk))
+            assert max(codes) <= 2 * eps
+
+
+def check_arithmetic_progression(ref, frac_bits=20):
+    for g in (0, 1, 3, 64, 1000, 12345):
+        for eps in (0, 7, 63, 5000):
+            for log2b, kb in ((6, 4), (10, 8), (12, 8)):
+                B = 1 << log2b
+                n = 3 * B + 17
+                keys = (np.uint64(11) + np.uint64(g) * np.arange(n, dtype=np.uint64))
+                keys = keys.astype(np.uint32 if kb == 4 else np.uint64)
+                blob = ref.compress(keys, eps, log2b, frac_bits)
+                h = ref.header(blob)
+                assert h["nseg_total"] == h["nblocks"], (g, eps, log2b)
+                for b in range(h["nblocks"]):
+                    nb = min(B, n - b * B)
+                    assert read_codes(blob, h, b, nb) == [eps] * nb, (g, eps, b)
+                _, _, sl = ref.fit_block(keys[:B].astype(np.uint64), eps, frac_bits)
+                A = int(sl[0])
+                # the midpoint lies in [g 2^F, g 2^F + 2^F / (B - 1)), so floor(A d / 2^F) = g d
+                assert g * 2 ** frac_bits <= A and (A - g * 2 ** frac_bits) * (B - 1) < 2 ** frac_bits, (g, eps, A)
+
+
+def check_span_within_eps(ref):
+    rng = np.random.default_rng(5)
+    for eps in (3, 63, 1000):
+        for _ in range(20):
+            k = np.sort(rng.integers(0, eps + 1, 500)).astype(np.uint64) + np.uint64(77)
+            st, _, _ = ref.fit_block(k, eps)
+            assert len(st) == 1, "a block whose key span is <= eps is one segment"
+
+
+def _feasible_masks(kk, s, eps, F, alo, ahi):
+    """For e = s+1 .. n: boolean mask over the integers A in [alo, ahi] of
+    slopes keeping keys s..e-1 within eps (Def. 2), by enumeration."""
+    A = np.arange(alo, ahi + 1, dtype=np.int64)
+    mask = np.ones(len(A), bool)
+    out = {s + 1: mask.copy()}
+    for j in range(s + 1, len(kk)):
+        pred = kk[s] + ((A * (j - s)) >> F)  # arithmetic shift: floor, also for A < 0
+        mask &= np.abs(kk[j] - pred) <= eps
+        out[j + 1] = mask.copy()
+    return A, out
+
+
+def check_bruteforce(ref, seed=3, trials=150):
+    rng = np.random.default_rng(seed)
+    greedy_above_min = 0
+    for trial in range(trials):
+        F = int(rng.choice([0, 1, 2, 4]))
+        eps = int(rng.integers(0, 4))
+        n = int(rng.integers(1, 13))
+        kk = [int(x) for x in np.cumsum(rng.integers(0, int(rng.choice([3, 8, 20])), n))]
+        alo, ahi = -((eps + 2) << F), (max(kk) - min(kk) + eps + 2) << F
+        masks = {}
+        for s in range(n):
+            Avals, masks[s] = _feasible_masks(kk, s, eps, F, alo, ahi)
+        nonneg = Avals >= 0
+
+        st, an, sl = ref.fit_block(np.array(kk, np.uint64), eps, F)
+        bounds = [int(x) for x in st] + [n]
+        assert bounds[0] == 0 and all(a < b for a, b in zip(bounds, bounds[1:]))
+        for t in range(len(st)):
+            s, e, A = bounds[t], bounds[t + 1], int(sl[t])
+            assert int(an[t]) == kk[s]
+            if e - s == 1:
+                assert A == 0
+            else:
+                feas = Avals[masks[s][e]]
+                assert len(feas) and alo < feas[0] and feas[-1] < ahi, "enumeration range too small"
+                assert np.array_equal(feas, np.arange(feas[0], feas[-1] + 1)), "feasible set is an interval"
+                assert A == max(0, (int(feas[0]) + int(feas[-1])) // 2), (kk, eps, F, s, e, A)
+                assert (masks[s][e] & nonneg).any(), "the segment must admit a slope >= 0"
+            if e < n:
+                assert not (masks[s][e + 1] & nonneg).any(), ("segment could be extended", kk, eps, F, s, e)
+
+        # minimum number of anchored segments with slopes >= 0, by dynamic programming
+        INF = 10 ** 9
+        dp = [0] + [INF] * n
+        for e in range(1, n + 1):
+            for s in range(e):
+                if (masks[s][e] & nonneg).any():
+                    dp[e] = min(dp[e], dp[s] + 1)
+        assert len(st) >= dp[n]
+        if dp[n] == 1:
+            assert len(st) == 1
+        greedy_above_min += len(st) > dp[n]
+    return greedy_above_min
+
+
+def check_cap_boundary(ref, frac_bits=20):
+    cap = 1 << (64 - frac_bits)
+    for eps in (0, 5):
+        joined = np.array([0, cap - 2 - eps], np.uint64)  # D + eps + 1 = cap - 1
+        split = np.array([0, cap - 1 - eps], np.uint64)   # D + eps + 1 = cap
+        assert len(ref.fit_block(joined, eps, frac_bits)[0]) == 1
+        assert len(ref.fit_block(split, eps, frac_bits)[0]) == 2
+    huge = np.cumsum(np.full(300, 1 << 45, dtype=np.uint64))
+    st, _, sl = ref.fit_block(huge, 3, frac_bits)
+    assert len(st) == 300 and not sl.any()
+    assert np.array_equal(ref.decode(ref.compress(huge, 3, 8, frac_bits)), huge)
+
+
+def check_blob_size(ref, seed=4, count=30):
+    for keys, eps, log2b in random_cases(seed, count):
+        B = 1 << log2b
+        kb = keys.dtype.itemsize
+        w = math.ceil(math.log2(2 * eps + 1))
+        nblocks = (len(keys) + B - 1) // B
+        stride = align16((B * w + 7) // 8)
+        size = 128 + align16(nblocks * kb) + 16 * nblocks + nblocks * stride
+        nseg_total = 0
+        for b in range(nblocks):
+            kk = keys[b * B:(b + 1) * B].astype(np.uint64)
+            st, an, sl = ref.fit_block(kk, eps)
+            m = len(st)
+            nseg_total += m
+            ab = widths_of(int(an.max() - an[0]))
+            sb = widths_of(int(sl.max()))
+            size += align16(2 * m) + align16(ab * m) + align16(sb * m)
+        blob = ref.compress(keys, eps, log2b)
+        h = ref.header(blob)
+        assert len(blob) == size == h["blob_bytes"]
+        assert h["nseg_total"] == nseg_total and h["nblocks"] == nblocks and h["n"] == len(keys)
+        assert h["off_dir"] == 128 + align16(nblocks * kb)
+        assert h["off_res"] == h["off_dir"] + 16 * nblocks and h["res_stride"] == stride
+
+
+def check_byte_widths(ref):
+    # anchor deltas 255 / 256 and 65535 / 65536 sit on either side of a width step
+    for delta, ab in ((255, 1), (256, 2), (65535, 2), (65536, 4), (2 ** 32 - 1, 4), (2 ** 32, 8)):
+        keys = np.array([0, 0, delta], np.uint64)  # eps 0: the jump starts a new segment
+        blob = ref.compress(keys, 0, 6)
+        h = ref.header(blob)
+        assert h["nseg_total"] == 2
+        assert int(blob[h["off_dir"] + 14]) == ab, (delta, ab)
+
+
+def check_golden(ref):
+    for name in ("ap4_eps1.txt", "break4_eps1.txt"):
+        g = load_golden(name)
+        keys = np.array(g["keys"], np.uint32 if g["key_bytes"] == 4 else np.uint64)
+        blob = ref.compress(keys, g["eps"], g["log2_block"], g["frac_bits"])
+        assert np.array_equal(blob, g["blob"]), name
+        assert np.array_equal(ref.decode(g["blob"]), keys), name
+
+
+ALL_CHECKS = [check_width, check_golden, check_roundtrip, check_error_bound,
+              check_arithmetic_progression, check_span_within_eps, check_bruteforce,
+              check_cap_boundary, check_blob_size, check_byte_widths]
+
+
+def run_quick(ref) -> str:
+    """Run every check with small counts; return the name of the first that fails, or ''."""
+    quick = [
+        (check_width, {}), (check_golden, {}), (check_roundtrip, {"count": 25}),
+        (check_error_bound, {"count": 12}), (check_arithmetic_progression, {}),
+        (check_span_within_eps, {}), (check_bruteforce, {"trials": 200}),
+        (check_cap_boundary, {}), (check_blob_size, {"count": 12}), (check_byte_widths, {}),
+    ]
+    for fn, kw in quick:
+        try:
+            fn(ref, **kw)
+        except Exception:  # an assertion, an oracle error status, or a malformed result
+            return fn.__name__
+    return ""
