@@ -1,0 +1,232 @@
+"""Benchmark of the learned compressor's hot path on one MI355X.
+
+Workload: 100,000,000 sorted distinct uint64 keys, floor(2^40 x / M) with
+x ~ lognormal(0, 2) (M the largest of the first 1e8 draws), de-duplicated;
+blocks of 1024 keys; eps swept over {15, 63, 255}.  One step is the whole
+path: for every eps, compress (fit + pack + scan + emit) and decompress;
+then, on the eps = 63 blob, one decompress_range over the middle half of the
+keys, 10M random access(i) and 1M lower_bound(q) with q uniform over the key
+range.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line.  `value` is decoded GB/s = sum(n * 8) / sum(decode
+kernel time) over the eps sweep, each decode timed with HIP events on the
+stream it runs on.  The CPU baseline times the oracle's plain C decoder on
+a bounded prefix of the same keys, single-threaded.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "decoded GB/s + lookups/s vs plain per-list kernel; comp. ratio; p99 latency"
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(host_keys, eps: int, budget_s: float = 12.0):
+    """Oracle decode (plain C, one thread) on a prefix of the workload."""
+    import numpy as np
+    import oracle
+
+    n_probe = min(len(host_keys), 1 << 20)
+    blob = oracle.compress(host_keys[:n_probe], eps, 10)
+    t0 = time.perf_counter()
+    oracle.decode(blob)
+    per_key = (time.perf_counter() - t0) / n_probe
+    n_s = int(min(len(host_keys), max(n_probe, budget_s / 2 / max(per_key, 1e-9))))
+    n_s -= n_s % 1024 if n_s > 1024 else 0
+    sample = np.ascontiguousarray(host_keys[:n_s])
+    t0 = time.perf_counter()
+    blob = oracle.compress(sample, eps, 10)
+    t_enc = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    out = oracle.decode(blob)
+    t_dec = time.perf_counter() - t0
+    assert np.array_equal(out, sample)
+    return {
+        "value": round(n_s * 8 / t_dec / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+        "sample": f"first {n_s} keys of the workload, eps={eps}, B=1024; oracle decode "
+                  f"{t_dec:.2f} s, oracle compress {t_enc:.2f} s ({n_s * 8 / t_enc / 1e9:.4f} GB/s)",
+        "compress_GBps": round(n_s * 8 / t_enc / 1e9, 4),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=100_000_000)
+    ap.add_argument("--eps", type=str, default="15,63,255")
+    ap.add_argument("--access", type=int, default=10_000_000)
+    ap.add_argument("--lower-bound", type=int, default=1_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path is "
+              "single-GPU here. Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2412_10770_amd import lc, workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    eps_list = [int(e) for e in args.eps.split(",")]
+    t0 = time.perf_counter()
+    keys = workloads.lognormal_distinct(args.n, device=dev)
+    torch.cuda.synchronize()
+    n = keys.numel()
+    log(f"generated {n} keys in {time.perf_counter() - t0:.1f} s")
+
+    # buffers (allocated once, outside the timed region)
+    blobs, wss = {}, None
+    max_ws = 0
+    for e in eps_list:
+        bmax, ws_bytes = lc.compress_bound(n, 8, e)
+        blobs[e] = torch.empty(bmax, dtype=torch.uint8, device=dev)
+        max_ws = max(max_ws, ws_bytes)
+    wss = torch.empty(max_ws, dtype=torch.uint8, device=dev)
+    nbytes = torch.zeros(len(eps_list), dtype=torch.int64, device=dev)
+    flags = torch.zeros(1, dtype=torch.int32, device=dev)
+    out = torch.empty(n, dtype=torch.int64, device=dev)
+    acc_idx = workloads.uniform_indices(args.access, n, seed=workloads.SEED_BASE + 102, device=dev)
+    acc_out = torch.empty(args.access, dtype=torch.int64, device=dev)
+    lo_k, hi_k = int(keys[0]), int(keys[-1])
+    lb_q = workloads.uniform_keys(args.lower_bound, lo_k, hi_k, seed=workloads.SEED_BASE + 103, device=dev)
+    lb_out = torch.empty(args.lower_bound, dtype=torch.int64, device=dev)
+    r_begin, r_end = n // 4, n // 4 + n // 2
+    r_out = torch.empty(r_end - r_begin, dtype=torch.int64, device=dev)
+
+    # one untimed compress per eps to learn the blob layout (headers)
+    infos = {}
+    for k, e in enumerate(eps_list):
+        lc.compress_async(keys, e, blobs[e], wss, nbytes[k:k + 1], flags)
+    torch.cuda.synchronize()
+    assert int(flags.item()) == 0, "keys not sorted"
+    for e in eps_list:
+        infos[e] = lc.Blob.from_device(blobs[e])
+    ref_eps = 63 if 63 in eps_list else eps_list[0]
+    bref = infos[ref_eps]
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    def step(timed: bool):
+        rec = {}
+        for k, e in enumerate(eps_list):
+            b = infos[e]
+            e0, e1, e2 = ev(), ev(), ev()
+            e0.record()
+            lc.compress_async(keys, e, blobs[e], wss, nbytes[k:k + 1], flags)
+            e1.record()
+            lc.decompress(lc.Blob(blobs[e], b.info), out=out)
+            e2.record()
+            rec[e] = (e0, e1, e2)
+        q0, q1, q2, q3 = ev(), ev(), ev(), ev()
+        q0.record()
+        lc.decompress_range(bref, r_begin, r_end, out=r_out)
+        q1.record()
+        lc.access(bref, acc_idx, out=acc_out, flags=flags, check=False)
+        q2.record()
+        lc.lower_bound(bref, lb_q, out=lb_out)
+        q3.record()
+        rec["q"] = (q0, q1, q2, q3)
+        return rec
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    # correctness of the timed configuration: identity round trip
+    lc.decompress(bref, out=out)
+    torch.cuda.synchronize()
+    assert torch.equal(out, keys), "round trip failed"
+    log(f"warmup done ({args.warmup} steps); timing {args.steps} steps")
+
+    recs = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        recs.append(step(True))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    log(f"timed region {wall:.3f} s")
+    assert int(flags.item()) == 0
+
+    per_eps = {}
+    dec_ms_total, dec_bytes_total, dec_alg_bytes = 0.0, 0.0, []
+    for e in eps_list:
+        enc = [r[e][0].elapsed_time(r[e][1]) for r in recs]
+        dec = [r[e][1].elapsed_time(r[e][2]) for r in recs]
+        b = infos[e]
+        dms = float(np.mean(dec))
+        per_eps[str(e)] = {
+            "ratio": round(b.ratio, 5), "bits_per_key": round(b.bits_per_key, 4),
+            "blob_bytes": b.nbytes, "nseg_total": b.info.nseg_total,
+            "paper_size_formula_bits_per_key": round((96 * b.info.nseg_total + n * b.info.width) / n, 4),
+            "decode_ms": round(dms, 4), "decode_GBps": round(n * 8 / dms / 1e6, 2),
+            "compress_ms": round(float(np.mean(enc)), 4),
+            "compress_GBps": round(n * 8 / float(np.mean(enc)) / 1e6, 2),
+        }
+        dec_ms_total += sum(dec)
+        dec_bytes_total += n * 8 * len(dec)
+        dec_alg_bytes.append(b.nbytes + n * 8)
+    value = dec_bytes_total / (dec_ms_total / 1e3) / 1e9
+    dec_avg_ms = dec_ms_total / (len(eps_list) * len(recs))
+    achieved = float(np.mean(dec_alg_bytes)) / (dec_avg_ms / 1e3) / 1e9
+    rng_ms = float(np.mean([r["q"][0].elapsed_time(r["q"][1]) for r in recs]))
+    acc_ms = float(np.mean([r["q"][1].elapsed_time(r["q"][2]) for r in recs]))
+    lb_ms = float(np.mean([r["q"][2].elapsed_time(r["q"][3]) for r in recs]))
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{n} sorted distinct uint64 keys, floor(2^40 x / M), x ~ lognormal(0, 2); "
+                        f"blocks of 1024; eps swept over {eps_list}; per step: compress + decompress "
+                        f"per eps, decompress_range of {r_end - r_begin} keys, {args.access} access, "
+                        f"{args.lower_bound} lower_bound on the eps={ref_eps} blob",
+            "n": n, "key_bytes": 8, "log2_block": 10, "eps": eps_list,
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+            "kernel": "decode_kernel<8>",
+            "bytes_per_launch": int(np.mean(dec_alg_bytes)), "avg_launch_ms": round(dec_avg_ms, 4),
+        },
+        "per_eps": per_eps,
+        "decompress_range_GBps": round((r_end - r_begin) * 8 / rng_ms / 1e6, 2),
+        "access_lookups_per_s": round(args.access / acc_ms * 1e3, 1),
+        "lower_bound_lookups_per_s": round(args.lower_bound / lb_ms * 1e3, 1),
+        "paper_cpu_context": {"lc-simd": "6.535 GiB/s decode, Xeon Gold 6430, CCNews (Fig. 3a)"},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a prefix of the keys")
+        host = workloads.as_numpy(keys)
+        result["cpu_baseline"] = cpu_baseline(host, ref_eps)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

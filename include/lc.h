@@ -1,0 +1,148 @@
+/*
+ * lc.h -- C ABI of the MI355X (gfx950) learned compressor for sorted integer
+ * keys (arXiv 2412.10770, "Learned Data Compression: Challenges and
+ * Opportunities for the Future").
+ *
+ * The library encodes a sorted key list K (Def. 1) as an error-bounded
+ * piecewise linear model plus bit-packed residuals (Def. 2, Eq. 1, Sec. II-A)
+ * and answers queries on the compressed form.  Every entry point works on
+ * device memory and only enqueues work on the given stream; nothing here
+ * allocates device memory, synchronises, or keeps state between calls (the
+ * library is reentrant).  The caller owns every buffer.
+ *
+ * Conventions shared by all entry points:
+ *   - keys are unsigned integers of key_bytes = 4 or 8 bytes, little-endian,
+ *     in non-decreasing order (duplicates allowed); indices are 0-based;
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream);
+ *   - the return value is 0 (LC_OK) or a negative LC_E* code, detected on the
+ *     host before anything is enqueued (nothing is enqueued on error);
+ *   - data-dependent problems found on the device are OR-ed into a caller
+ *     provided 32-bit flag word (LC_FLAG_*), which the caller zeroes.
+ *
+ * Blob v1 (the compressed form, little-endian, every region 16-byte aligned,
+ * every pad byte zero):
+ *   header (128 B): magic "LCB1", version 1, key_bytes, log2_block, frac_bits
+ *     F, residual width w, eps, n, nblocks, nseg_total, max_nseg, the byte
+ *     offsets of the four regions below, res_stride, blob_bytes;
+ *   first_keys[nblocks]   the first key of every block of B = 2^log2_block keys;
+ *   dir[nblocks]          16 B each: segment-area offset, segment count,
+ *                         key count - 1, anchor and slope byte widths;
+ *   residual slabs        block b at off_res + b*res_stride, code j of the
+ *                         block in bits [j*w, j*w + w) of an LSB-first stream;
+ *   segment areas         per block: u16 start[], anchor - first_key[] and
+ *                         slope A[] (1, 2, 4 or 8 bytes each).
+ * Key i = b*B + j decodes as
+ *   anchor[t] + floor(A[t] * (j - start[t]) / 2^F) + code_j - eps  (mod 2^64)
+ * with t the last segment of block b starting at or before j, i.e. the
+ * paper's K[i] = floor(f(i)) + Delta[i] with an anchored fixed-point f.
+ */
+#ifndef LC_H
+#define LC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lc_status;
+
+#define LC_OK 0
+#define LC_EINVAL (-1)   /* null pointer, bad parameter, bad range, n too large */
+#define LC_ENOSPC (-2)   /* blob_cap or ws_bytes below what lc_compress_bound gives */
+#define LC_EFORMAT (-3)  /* header: bad magic/version or inconsistent fields */
+#define LC_EDEVICE (-4)  /* a kernel launch failed (hipGetLastError after launch) */
+
+#define LC_FLAG_UNSORTED 1u /* compress: keys not non-decreasing; blob is invalid */
+#define LC_FLAG_RANGE 2u    /* access: an index >= n; its output slot is 0 */
+
+#define LC_DEFAULT_LOG2_BLOCK 10
+#define LC_DEFAULT_FRAC_BITS 20
+#define LC_MAX_EPS 0x7FFFFFFFu
+#define LC_HEADER_BYTES 128
+
+/* Encoder parameters.
+ *   key_bytes  4 or 8
+ *   log2_block 6..12 (block size B = 2^log2_block keys; segments never cross
+ *              a block)
+ *   frac_bits  0..32, fractional bits F of the fixed-point slope A / 2^F
+ *              (LC_DEFAULT_FRAC_BITS = 20)
+ *   eps        0..LC_MAX_EPS, the error bound of Def. 2; residuals take
+ *              w = ceil(log2(2 eps + 1)) bits each (Sec. II-A) */
+typedef struct lc_params {
+    uint8_t key_bytes;
+    uint8_t log2_block;
+    uint8_t frac_bits;
+    uint8_t reserved; /* must be 0 */
+    uint32_t eps;
+} lc_params;
+
+/* Host-side copy of a blob's header fields (filled by lc_info). */
+typedef struct lc_blob_info {
+    uint32_t key_bytes, log2_block, frac_bits, width, eps, max_nseg;
+    uint64_t n, nblocks, nseg_total;
+    uint64_t off_first, off_dir, off_res, res_stride, off_seg, blob_bytes;
+} lc_blob_info;
+
+/* Worst-case sizes for compressing n keys with parameters p (host only,
+ * pure).  *blob_max: bytes the blob buffer must hold; *ws_bytes: bytes of the
+ * device workspace lc_compress needs.  Either output pointer may be NULL.
+ * Errors: LC_EINVAL (bad p, p NULL, n > 2^40). */
+lc_status lc_compress_bound(uint64_t n, const lc_params* p, uint64_t* blob_max,
+                            uint64_t* ws_bytes);
+
+/* Enc of Def. 1: compress n keys at d_keys (device, key_bytes each, sorted)
+ * into d_blob (device, blob_cap bytes, 16-byte aligned).  The fit follows
+ * Def. 2 / Eq. 1 per block: greedy anchored segments with an integer slope,
+ * residuals bit-packed at ceil(log2(2 eps + 1)) bits (Sec. II-A).
+ * d_ws: device workspace of ws_bytes (16-byte aligned), contents scratch.
+ * d_blob_bytes: device u64 receiving the blob size (may be NULL).
+ * d_flags: device u32 flag word (required); LC_FLAG_UNSORTED is OR-ed in
+ * when the keys are not sorted, in which case the blob must not be used.
+ * The blob is byte-for-byte deterministic.  Asynchronous on `stream`.
+ * Errors: LC_EINVAL, LC_ENOSPC (blob_cap / ws_bytes too small), LC_EDEVICE. */
+lc_status lc_compress(const void* d_keys, uint64_t n, const lc_params* p, void* d_blob,
+                      uint64_t blob_cap, void* d_ws, uint64_t ws_bytes, uint64_t* d_blob_bytes,
+                      uint32_t* d_flags, void* stream);
+
+/* Parse and check a blob header from host memory (at least 128 bytes, the
+ * first bytes of the blob).  Pure host code.
+ * Errors: LC_EINVAL (NULL), LC_EFORMAT (magic, version or fields). */
+lc_status lc_info(const void* h_header, uint64_t header_bytes, lc_blob_info* out);
+
+/* Dec of Def. 1: write all n keys (key_bytes each) to d_out (device, 16-byte
+ * aligned).  d_blob is the device blob described by info.
+ * Errors: LC_EINVAL (NULL pointer, info inconsistent), LC_EDEVICE. */
+lc_status lc_decompress(const void* d_blob, const lc_blob_info* info, void* d_out,
+                        void* stream);
+
+/* Dec restricted to [begin, end): d_out[i - begin] = K[i] (key_bytes each,
+ * d_out aligned to key_bytes).  0 <= begin <= end <= n, else LC_EINVAL.
+ * An empty range enqueues nothing. */
+lc_status lc_decompress_range(const void* d_blob, const lc_blob_info* info, uint64_t begin,
+                              uint64_t end, void* d_out, void* stream);
+
+/* Random access on the compressed form: d_out[q] = K[d_idx[q]] for
+ * q < m (d_idx: device u64[m]; d_out: device, key_bytes each).  An index
+ * >= n writes 0 and ORs LC_FLAG_RANGE into *d_flags (device u32, required).
+ * Errors: LC_EINVAL, LC_EDEVICE. */
+lc_status lc_access(const void* d_blob, const lc_blob_info* info, const uint64_t* d_idx,
+                    uint64_t m, void* d_out, uint32_t* d_flags, void* stream);
+
+/* lower_bound on the compressed form: d_pos[q] = the smallest i in [0, n]
+ * with K[i] >= d_q[q] (n when every key is smaller), for q < m.  d_q holds m
+ * keys of key_bytes each; d_pos is device u64[m].  Blocks are located through
+ * first_keys and segments through their anchors, the segment-level pruning of
+ * Sec. III-A.  Cannot fail on valid input.
+ * Errors: LC_EINVAL, LC_EDEVICE. */
+lc_status lc_lower_bound(const void* d_blob, const lc_blob_info* info, const void* d_q,
+                         uint64_t m, uint64_t* d_pos, void* stream);
+
+/* Static description of a status code. */
+const char* lc_strerror(lc_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LC_H */

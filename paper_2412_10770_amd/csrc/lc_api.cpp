@@ -1,0 +1,243 @@
+// C ABI of the learned compressor (declared in include/lc.h): argument
+// checks, blob layout, workspace carving and kernel launches.  All checks that
+// can fail happen before anything is enqueued.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "lc.h"
+#include "lc_launch.h"
+
+#define LC_API extern "C" __attribute__((visibility("default")))
+
+namespace {
+
+constexpr uint64_t kMaxKeys = 1ull << 40;
+constexpr uint32_t kMagic = 0x3142434Cu;
+
+// Residual width: the smallest w with 2^w >= 2 eps + 1.
+uint32_t residual_width(uint32_t eps)
+{
+    const uint64_t span = 2ull * eps + 1;
+    uint32_t w = 0;
+    while ((1ull << w) < span) w++;
+    return w;
+}
+
+lc_status check_params(const lc_params* p)
+{
+    if (!p) return LC_EINVAL;
+    if (p->key_bytes != 4 && p->key_bytes != 8) return LC_EINVAL;
+    if (p->log2_block < 6 || p->log2_block > 12) return LC_EINVAL;
+    if (p->frac_bits > 32 || p->reserved != 0) return LC_EINVAL;
+    if (p->eps > LC_MAX_EPS) return LC_EINVAL;
+    return LC_OK;
+}
+
+// Fixed part of the layout (everything but the segment areas).
+lc::Layout fixed_layout(uint64_t n, const lc_params* p)
+{
+    lc::Layout L{};
+    const uint64_t B = 1ull << p->log2_block;
+    L.n = n;
+    L.nblocks = (n + B - 1) / B;
+    L.kb = p->key_bytes;
+    L.log2b = p->log2_block;
+    L.F = p->frac_bits;
+    L.eps = p->eps;
+    L.w = residual_width(p->eps);
+    L.res_stride = lc::align16((B * L.w + 7) / 8);
+    L.off_first = lc::kHeaderBytes;
+    L.off_dir = L.off_first + lc::align16(L.nblocks * L.kb);
+    L.off_res = L.off_dir + 16 * L.nblocks;
+    L.off_seg = L.off_res + L.nblocks * L.res_stride;
+    L.max_nseg = 0;
+    return L;
+}
+
+struct WsPlan {
+    uint64_t blk, tiles, start, delta, slope, total;
+};
+
+WsPlan plan_workspace(const lc::Layout& L)
+{
+    const uint64_t recs = L.nblocks << L.log2b;
+    WsPlan w;
+    w.blk = 0;
+    w.tiles = w.blk + lc::align16(L.nblocks * sizeof(lc::BlockInfo));
+    w.start = w.tiles + lc::align16(lc::ntiles_of(L.nblocks) * sizeof(lc::TileSum));
+    w.delta = w.start + lc::align16(recs * 2);
+    w.slope = w.delta + recs * 8;
+    w.total = w.slope + recs * 8;
+    if (w.total == 0) w.total = 16;
+    return w;
+}
+
+uint64_t worst_blob(const lc::Layout& L)
+{
+    const uint64_t B = 1ull << L.log2b;
+    const uint64_t seg_area = lc::align16(2 * B) + 2 * lc::align16(8 * B);
+    return L.off_seg + L.nblocks * seg_area;
+}
+
+uint64_t rd(const uint8_t* p, int nbytes)
+{
+    uint64_t v = 0;
+    for (int i = 0; i < nbytes; i++) v |= (uint64_t)p[i] << (8 * i);
+    return v;
+}
+
+// Layout of a parsed blob, re-checked (the info struct comes from the caller).
+lc_status layout_of(const lc_blob_info* info, lc::Layout* L)
+{
+    if (!info) return LC_EINVAL;
+    lc_params p{};
+    p.key_bytes = (uint8_t)info->key_bytes;
+    p.log2_block = (uint8_t)info->log2_block;
+    p.frac_bits = (uint8_t)info->frac_bits;
+    p.eps = info->eps;
+    if (info->key_bytes > 8 || info->log2_block > 12 || info->frac_bits > 32) return LC_EINVAL;
+    if (check_params(&p) != LC_OK || info->n > kMaxKeys) return LC_EINVAL;
+    *L = fixed_layout(info->n, &p);
+    if (L->w != info->width || L->nblocks != info->nblocks || L->off_first != info->off_first ||
+        L->off_dir != info->off_dir || L->off_res != info->off_res || L->res_stride != info->res_stride ||
+        L->off_seg != info->off_seg)
+        return LC_EINVAL;
+    if (info->n && (info->max_nseg == 0 || info->max_nseg > (1u << info->log2_block))) return LC_EINVAL;
+    L->max_nseg = info->max_nseg;
+    return LC_OK;
+}
+
+}  // namespace
+
+LC_API lc_status lc_compress_bound(uint64_t n, const lc_params* p, uint64_t* blob_max, uint64_t* ws_bytes)
+{
+    lc_status st = check_params(p);
+    if (st != LC_OK) return st;
+    if (n > kMaxKeys) return LC_EINVAL;
+    const lc::Layout L = fixed_layout(n, p);
+    if (blob_max) *blob_max = worst_blob(L);
+    if (ws_bytes) *ws_bytes = plan_workspace(L).total;
+    return LC_OK;
+}
+
+LC_API lc_status lc_compress(const void* d_keys, uint64_t n, const lc_params* p, void* d_blob, uint64_t blob_cap,
+                             void* d_ws, uint64_t ws_bytes, uint64_t* d_blob_bytes, uint32_t* d_flags,
+                             void* stream)
+{
+    lc_status st = check_params(p);
+    if (st != LC_OK) return st;
+    if (n > kMaxKeys || !d_blob || !d_flags || (n && (!d_keys || !d_ws))) return LC_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(d_blob) & 15) || (reinterpret_cast<uintptr_t>(d_ws) & 15) ||
+        (reinterpret_cast<uintptr_t>(d_keys) & (p->key_bytes - 1)))
+        return LC_EINVAL;
+    const lc::Layout L = fixed_layout(n, p);
+    const WsPlan w = plan_workspace(L);
+    if (blob_cap < worst_blob(L)) return LC_ENOSPC;
+    if (n && ws_bytes < w.total) return LC_ENOSPC;
+    uint8_t* ws = static_cast<uint8_t*>(d_ws);
+    lc::Workspace W{};
+    if (n) {
+        W.blk = reinterpret_cast<lc::BlockInfo*>(ws + w.blk);
+        W.tiles = reinterpret_cast<lc::TileSum*>(ws + w.tiles);
+        W.seg_start = reinterpret_cast<uint16_t*>(ws + w.start);
+        W.seg_delta = reinterpret_cast<uint64_t*>(ws + w.delta);
+        W.seg_A = reinterpret_cast<uint64_t*>(ws + w.slope);
+    }
+    hipError_t e = lc::launch_compress(d_keys, L, static_cast<uint8_t*>(d_blob), W, d_blob_bytes, d_flags,
+                                       static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LC_OK : LC_EDEVICE;
+}
+
+LC_API lc_status lc_info(const void* h_header, uint64_t header_bytes, lc_blob_info* out)
+{
+    if (!h_header || !out) return LC_EINVAL;
+    if (header_bytes < LC_HEADER_BYTES) return LC_EFORMAT;
+    const uint8_t* h = static_cast<const uint8_t*>(h_header);
+    if (rd(h, 4) != kMagic || rd(h + 4, 2) != 1) return LC_EFORMAT;
+    lc_blob_info I{};
+    I.key_bytes = h[6];
+    I.log2_block = h[7];
+    I.frac_bits = h[8];
+    I.width = h[9];
+    I.eps = (uint32_t)rd(h + 12, 4);
+    I.n = rd(h + 16, 8);
+    I.nblocks = rd(h + 24, 8);
+    I.nseg_total = rd(h + 32, 8);
+    I.max_nseg = (uint32_t)rd(h + 40, 4);
+    I.off_first = rd(h + 48, 8);
+    I.off_dir = rd(h + 56, 8);
+    I.off_res = rd(h + 64, 8);
+    I.res_stride = rd(h + 72, 8);
+    I.off_seg = rd(h + 80, 8);
+    I.blob_bytes = rd(h + 88, 8);
+    lc::Layout L;
+    if (layout_of(&I, &L) != LC_OK) return LC_EFORMAT;
+    if (I.blob_bytes < I.off_seg || I.nseg_total < I.nblocks || I.nseg_total > I.n) return LC_EFORMAT;
+    *out = I;
+    return LC_OK;
+}
+
+LC_API lc_status lc_decompress(const void* d_blob, const lc_blob_info* info, void* d_out, void* stream)
+{
+    lc::Layout L;
+    if (!d_blob || layout_of(info, &L) != LC_OK) return LC_EINVAL;
+    if (L.n == 0) return LC_OK;
+    if (!d_out || (reinterpret_cast<uintptr_t>(d_out) & 15)) return LC_EINVAL;
+    hipError_t e = lc::launch_decode(static_cast<const uint8_t*>(d_blob), L, 0, L.n, d_out,
+                                     static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LC_OK : LC_EDEVICE;
+}
+
+LC_API lc_status lc_decompress_range(const void* d_blob, const lc_blob_info* info, uint64_t begin, uint64_t end,
+                                     void* d_out, void* stream)
+{
+    lc::Layout L;
+    if (!d_blob || layout_of(info, &L) != LC_OK) return LC_EINVAL;
+    if (begin > end || end > L.n) return LC_EINVAL;
+    if (begin == end) return LC_OK;
+    if (!d_out || (reinterpret_cast<uintptr_t>(d_out) & (L.kb - 1))) return LC_EINVAL;
+    hipError_t e = lc::launch_decode(static_cast<const uint8_t*>(d_blob), L, begin, end, d_out,
+                                     static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LC_OK : LC_EDEVICE;
+}
+
+LC_API lc_status lc_access(const void* d_blob, const lc_blob_info* info, const uint64_t* d_idx, uint64_t m,
+                           void* d_out, uint32_t* d_flags, void* stream)
+{
+    lc::Layout L;
+    if (!d_blob || layout_of(info, &L) != LC_OK) return LC_EINVAL;
+    if (m == 0) return LC_OK;
+    if (!d_idx || !d_out || !d_flags || (reinterpret_cast<uintptr_t>(d_out) & (L.kb - 1)) ||
+        (reinterpret_cast<uintptr_t>(d_idx) & 7))
+        return LC_EINVAL;
+    hipError_t e = lc::launch_access(static_cast<const uint8_t*>(d_blob), L, d_idx, m, d_out, d_flags,
+                                     static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LC_OK : LC_EDEVICE;
+}
+
+LC_API lc_status lc_lower_bound(const void* d_blob, const lc_blob_info* info, const void* d_q, uint64_t m,
+                                uint64_t* d_pos, void* stream)
+{
+    lc::Layout L;
+    if (!d_blob || layout_of(info, &L) != LC_OK) return LC_EINVAL;
+    if (m == 0) return LC_OK;
+    if (!d_q || !d_pos || (reinterpret_cast<uintptr_t>(d_q) & (L.kb - 1)) ||
+        (reinterpret_cast<uintptr_t>(d_pos) & 7))
+        return LC_EINVAL;
+    hipError_t e = lc::launch_lower_bound(static_cast<const uint8_t*>(d_blob), L, d_q, m, d_pos,
+                                          static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LC_OK : LC_EDEVICE;
+}
+
+LC_API const char* lc_strerror(lc_status s)
+{
+    switch (s) {
+    case LC_OK: return "ok";
+    case LC_EINVAL: return "invalid argument";
+    case LC_ENOSPC: return "buffer too small";
+    case LC_EFORMAT: return "not a valid blob header";
+    case LC_EDEVICE: return "kernel launch failed";
+    default: return "unknown status";
+    }
+}

@@ -1,0 +1,832 @@
+// HIP kernels of the learned compressor, written for gfx950 (CDNA4, wave64).
+//
+// Encode (Def. 1 Enc, Def. 2 / Eq. 1 fit, Sec. II-A residual packing):
+//   fit_pack     one wave per key block: greedy anchored integer cone, wave
+//                prefix max/min + ballot over 64 candidate keys at a time,
+//                residual codes OR-ed into an LDS slab, slab stored to the blob
+//   tile_reduce  per 256 blocks: segment-area bytes, segment counts
+//   tile_scan    one workgroup: exclusive scan over tiles, header, blob size
+//   dir_emit     per 256 blocks: in-tile scan -> directory entries
+//   seg_emit     one wave per block: segment SoA in 16-byte chunks
+// Decode (Def. 1 Dec, K[i] = floor(f(i)) + Delta[i]):
+//   decode       one workgroup per block: segment table and residual slab
+//                staged in LDS, 16-byte coalesced stores; also serves ranges
+//   access       one lane per query, K[i] from the compressed block
+//   lower_bound  one lane per query: first_keys -> segment anchors -> search
+//                inside one segment (the segment pruning of Sec. III-A)
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lc_launch.h"
+
+namespace lc {
+namespace {
+
+constexpr uint32_t kMagic = 0x3142434Cu;  // "LCB1"
+constexpr uint32_t kVersion = 1;
+constexpr uint32_t kFlagUnsorted = 1u;
+constexpr uint32_t kFlagRange = 2u;
+constexpr uint64_t kMaxGrid = 1ull << 22;  // workgroups per launch; larger jobs loop
+
+__device__ __forceinline__ uint64_t a16(uint64_t x) { return (x + 15) & ~uint64_t(15); }
+
+__device__ __forceinline__ uint32_t byte_width(uint64_t v)
+{
+    return v < (1ull << 8) ? 1u : v < (1ull << 16) ? 2u : v < (1ull << 32) ? 4u : 8u;
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
+
+// Element t of a little-endian array of `width`-byte unsigned integers whose
+// base is aligned to `width`.
+__device__ __forceinline__ uint64_t load_w(const uint8_t* base, uint32_t t, uint32_t width)
+{
+    switch (width) {
+    case 1: return base[t];
+    case 2: return reinterpret_cast<const uint16_t*>(base)[t];
+    case 4: return reinterpret_cast<const uint32_t*>(base)[t];
+    default: return reinterpret_cast<const uint64_t*>(base)[t];
+    }
+}
+
+template <int KB>
+__device__ __forceinline__ uint64_t load_key(const void* p, uint64_t i)
+{
+    if constexpr (KB == 4) return reinterpret_cast<const uint32_t*>(p)[i];
+    else return reinterpret_cast<const uint64_t*>(p)[i];
+}
+
+template <int KB>
+__device__ __forceinline__ void store_key(void* p, uint64_t i, uint64_t v)
+{
+    if constexpr (KB == 4) reinterpret_cast<uint32_t*>(p)[i] = static_cast<uint32_t>(v);
+    else reinterpret_cast<uint64_t*>(p)[i] = v;
+}
+
+// Inclusive scans across the 64 lanes of a wave.
+__device__ __forceinline__ uint64_t wave_incl_max(uint64_t v)
+{
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint64_t t = __shfl_up(v, o, 64);
+        if (lane >= (uint32_t)o) v = v > t ? v : t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_min(uint64_t v)
+{
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint64_t t = __shfl_up(v, o, 64);
+        if (lane >= (uint32_t)o) v = v < t ? v : t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_sum(uint64_t v)
+{
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint64_t t = __shfl_up(v, o, 64);
+        if (lane >= (uint32_t)o) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_max(uint64_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        uint64_t t = __shfl_xor(v, o, 64);
+        v = v > t ? v : t;
+    }
+    return v;
+}
+
+// Exclusive sum over the threads of a workgroup of NT threads (NT % 64 == 0).
+// Returns the exclusive prefix; *total receives the workgroup sum.
+template <int NT>
+__device__ __forceinline__ uint64_t block_excl_sum(uint64_t v, uint64_t* total)
+{
+    __shared__ uint64_t s_w[NT / 64];
+    const uint32_t lane = lane_id(), wave = threadIdx.x / 64;
+    uint64_t incl = wave_incl_sum(v);
+    if (lane == 63) s_w[wave] = incl;
+    __syncthreads();
+    uint64_t before = 0, all = 0;
+    for (uint32_t k = 0; k < NT / 64; k++) {
+        uint64_t x = s_w[k];
+        if (k < wave) before += x;
+        all += x;
+    }
+    __syncthreads();
+    *total = all;
+    return before + incl - v;
+}
+
+// Largest power of two <= x (x >= 1).
+__device__ __forceinline__ uint32_t pow2_floor(uint32_t x) { return 1u << (31 - __clz(x)); }
+
+// ---------------------------------------------------------------------------
+// Encode
+// ---------------------------------------------------------------------------
+
+// One wave (64 threads) per block.  LDS: keys u64[B], slopes u64[B],
+// starts u16[B], slab u32[res_stride / 4 + 2].
+template <int KB>
+__global__ __launch_bounds__(64) void fit_pack_kernel(const void* __restrict__ keys, Layout L,
+                                                       uint8_t* __restrict__ blob, Workspace ws,
+                                                       uint32_t* __restrict__ flags, uint64_t blk0)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    const uint32_t B = 1u << L.log2b;
+    uint64_t* s_keys = reinterpret_cast<uint64_t*>(smem);
+    uint64_t* s_A = s_keys + B;
+    uint16_t* s_start = reinterpret_cast<uint16_t*>(s_A + B);
+    uint32_t* s_slab = reinterpret_cast<uint32_t*>(s_start + B);
+    const uint32_t slab_words = (uint32_t)(L.res_stride / 4);
+
+    const uint32_t lane = threadIdx.x;
+    const uint64_t b = blk0 + blockIdx.x;
+    const uint64_t base = b << L.log2b;
+    const uint32_t nb = (uint32_t)((L.n - base) < B ? (L.n - base) : B);
+
+    for (uint32_t j = lane; j < nb; j += 64) s_keys[j] = load_key<KB>(keys, base + j);
+    for (uint32_t i = lane; i < slab_words + 2; i += 64) s_slab[i] = 0;
+    __syncthreads();
+
+    // Keys must be non-decreasing, across the block boundary too.
+    bool unsorted = false;
+    for (uint32_t j = lane; j < nb; j += 64) {
+        uint64_t prev = j ? s_keys[j - 1] : (b ? load_key<KB>(keys, base - 1) : 0);
+        unsorted |= s_keys[j] < prev;
+    }
+    if (__ballot(unsorted) != 0 && lane == 0) atomicOr(flags, kFlagUnsorted);
+
+    // Greedy anchored cone.  For candidate key e of the segment starting at s
+    // (d = e - s, D = K[e] - K[s]) the integer slopes A with
+    // |K[e] - (K[s] + floor(A d / 2^F))| <= eps form
+    //   [ceil((D - eps) 2^F / d), floor(((D + eps + 1) 2^F - 1) / d)].
+    // The running intersection is tracked as
+    //   P = 1 + (largest non-negative lower end), 0 when there is none,
+    //   M = smallest magnitude of the negative lower ends (lower end = -M),
+    //   H = smallest upper end,
+    // 64 candidates at a time by wave prefix scans; the segment ends at the
+    // first candidate where the intersection is empty or D + eps + 1 reaches
+    // 2^(64 - F).  Stored slope: floor((lo + hi) / 2) clamped to >= 0.
+    const uint64_t eps = L.eps;
+    const uint32_t F = L.F;
+    const uint64_t lim = F == 0 ? (~0ull - eps) : ((1ull << (64 - F)) - eps - 1);
+    uint32_t s = 0, nseg = 0;
+    uint64_t maxA = 0;
+    while (s < nb) {
+        const uint64_t anchor = s_keys[s];
+        uint64_t runP = 0, runH = ~0ull, runM = ~0ull;
+        uint64_t Pf, Hf, Mf;
+        uint32_t e0 = s + 1, e_end;
+        for (;;) {
+            if (e0 >= nb) {
+                e_end = nb;
+                Pf = runP; Hf = runH; Mf = runM;
+                break;
+            }
+            const uint32_t e = e0 + lane;
+            const bool valid = e < nb;
+            uint64_t P = 0, H = ~0ull, M = ~0ull;
+            bool capped = false;
+            if (valid) {
+                const uint64_t d = e - s;
+                const uint64_t D = s_keys[e] - anchor;
+                capped = D >= lim;
+                if (!capped) {
+                    if (D >= eps) {
+                        const uint64_t x = (D - eps) << F;
+                        const uint64_t q = x / d;
+                        P = q + (q * d != x) + 1;
+                    } else {
+                        M = ((eps - D) << F) / d;
+                    }
+                    H = (((D + eps + 1) << F) - 1) / d;
+                }
+            }
+            P = wave_incl_max(P);
+            H = wave_incl_min(H);
+            M = wave_incl_min(M);
+            P = P > runP ? P : runP;
+            H = H < runH ? H : runH;
+            M = M < runM ? M : runM;
+            const bool fail = valid && (capped || (P != 0 && P - 1 > H));
+            const uint64_t fm = __ballot(fail);
+            if (fm != 0) {
+                const int f = __ffsll((unsigned long long)fm) - 1;
+                e_end = e0 + f;
+                if (f > 0) {
+                    Pf = __shfl(P, f - 1, 64);
+                    Hf = __shfl(H, f - 1, 64);
+                    Mf = __shfl(M, f - 1, 64);
+                } else {
+                    Pf = runP; Hf = runH; Mf = runM;
+                }
+                break;
+            }
+            const uint32_t last = (nb - 1 - e0) < 63u ? (nb - 1 - e0) : 63u;
+            runP = __shfl(P, last, 64);
+            runH = __shfl(H, last, 64);
+            runM = __shfl(M, last, 64);
+            e0 += 64;
+        }
+        uint64_t A = 0;
+        if (e_end > s + 1) {
+            if (Pf != 0) {
+                const uint64_t lo = Pf - 1;
+                A = lo + (Hf - lo) / 2;
+            } else {
+                A = Hf >= Mf ? (Hf - Mf) / 2 : 0;  // floor((-M + H) / 2), clamped
+            }
+        }
+        if (lane == 0) {
+            s_start[nseg] = (uint16_t)s;
+            s_A[nseg] = A;
+        }
+        maxA = A > maxA ? A : maxA;
+        nseg++;
+        s = e_end;
+    }
+    __syncthreads();
+
+    // Residual codes (offset by eps) packed LSB-first into the LDS slab.
+    const uint32_t w = L.w;
+    if (w != 0) {
+        const uint64_t wmask = (w >= 64) ? ~0ull : ((1ull << w) - 1);
+        const uint32_t pw = pow2_floor(nseg);
+        for (uint32_t j = lane; j < nb; j += 64) {
+            uint32_t t = 0;
+            for (uint32_t step = pw; step; step >>= 1)
+                if (t + step < nseg && s_start[t + step] <= j) t += step;
+            const uint32_t st = s_start[t];
+            const uint64_t pred = s_keys[st] + ((s_A[t] * (uint64_t)(j - st)) >> F);
+            const uint64_t code = (s_keys[j] - pred + eps) & wmask;
+            const uint64_t bitpos = (uint64_t)j * w;
+            const uint32_t wd = (uint32_t)(bitpos >> 5), sh = (uint32_t)(bitpos & 31);
+            const uint64_t v = code << sh;
+            atomicOr(&s_slab[wd], (uint32_t)v);
+            if (sh + w > 32) atomicOr(&s_slab[wd + 1], (uint32_t)(v >> 32));
+        }
+    }
+    __syncthreads();
+
+    uint4* dst = reinterpret_cast<uint4*>(blob + L.off_res + b * L.res_stride);
+    const uint4* src = reinterpret_cast<const uint4*>(s_slab);
+    for (uint32_t c = lane; c < slab_words / 4; c += 64) dst[c] = src[c];
+
+    const uint64_t first = s_keys[0];
+    if (lane == 0) store_key<KB>(blob + L.off_first, b, first);
+
+    const uint64_t rec = b << L.log2b;
+    for (uint32_t t = lane; t < nseg; t += 64) {
+        const uint32_t st = s_start[t];
+        ws.seg_start[rec + t] = (uint16_t)st;
+        ws.seg_delta[rec + t] = s_keys[st] - first;
+        ws.seg_A[rec + t] = s_A[t];
+    }
+    if (lane == 0) {
+        const uint64_t maxd = s_keys[s_start[nseg - 1]] - first;
+        const uint32_t ab = byte_width(maxd), sb = byte_width(maxA);
+        BlockInfo bi;
+        bi.nseg = nseg;
+        bi.seg_bytes = (uint32_t)(a16(2ull * nseg) + a16((uint64_t)ab * nseg) + a16((uint64_t)sb * nseg));
+        bi.nkeys = nb;
+        bi.ab = (uint8_t)ab;
+        bi.sb = (uint8_t)sb;
+        bi.pad = 0;
+        ws.blk[b] = bi;
+    }
+}
+
+// Sums over tiles of kTileBlocks blocks.
+__global__ __launch_bounds__(256) void tile_reduce_kernel(Workspace ws, uint64_t nblocks, uint64_t tile0)
+{
+    const uint64_t tile = tile0 + blockIdx.x;
+    const uint64_t b = tile * kTileBlocks + threadIdx.x;
+    uint64_t bytes = 0, nseg = 0, mx = 0;
+    if (b < nblocks) {
+        const BlockInfo bi = ws.blk[b];
+        bytes = bi.seg_bytes;
+        nseg = bi.nseg;
+        mx = bi.nseg;
+    }
+    uint64_t tb, tn;
+    block_excl_sum<256>(bytes, &tb);
+    block_excl_sum<256>(nseg, &tn);
+    __shared__ uint64_t s_mx[4];
+    const uint64_t wm = wave_max(mx);
+    if (lane_id() == 0) s_mx[threadIdx.x / 64] = wm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t m = s_mx[0];
+        for (int k = 1; k < 4; k++) m = s_mx[k] > m ? s_mx[k] : m;
+        TileSum t;
+        t.bytes = tb;
+        t.nseg = tn;
+        t.off = 0;
+        t.max_nseg = (uint32_t)m;
+        t.pad = 0;
+        ws.tiles[tile] = t;
+    }
+}
+
+// One workgroup: exclusive scan of tile bytes, totals, header, blob size,
+// zero padding after first_keys.
+__global__ __launch_bounds__(1024) void tile_scan_kernel(Workspace ws, Layout L, uint8_t* __restrict__ blob,
+                                                         uint64_t* __restrict__ d_blob_bytes)
+{
+    const uint64_t ntiles = (L.nblocks + kTileBlocks - 1) / kTileBlocks;
+    uint64_t carry = 0, nseg_total = 0, max_nseg = 0;
+    for (uint64_t t0 = 0; t0 < ntiles; t0 += 1024) {
+        const uint64_t t = t0 + threadIdx.x;
+        uint64_t v = 0, ns = 0, mx = 0;
+        if (t < ntiles) {
+            const TileSum ts = ws.tiles[t];
+            v = ts.bytes;
+            ns = ts.nseg;
+            mx = ts.max_nseg;
+        }
+        uint64_t tot, tot_ns;
+        const uint64_t ex = block_excl_sum<1024>(v, &tot);
+        block_excl_sum<1024>(ns, &tot_ns);
+        if (t < ntiles) ws.tiles[t].off = carry + ex;
+        carry += tot;
+        nseg_total += tot_ns;
+        __shared__ uint64_t s_mx[16];
+        const uint64_t wm = wave_max(mx);
+        if (lane_id() == 0) s_mx[threadIdx.x / 64] = wm;
+        __syncthreads();
+        for (int k = 0; k < 16; k++) max_nseg = s_mx[k] > max_nseg ? s_mx[k] : max_nseg;
+        __syncthreads();
+    }
+    const uint64_t blob_bytes = L.off_seg + carry;
+    if (threadIdx.x == 0) {
+        uint32_t h[32];
+        for (int k = 0; k < 32; k++) h[k] = 0;
+        h[0] = kMagic;
+        h[1] = kVersion | (L.kb << 16) | (L.log2b << 24);
+        h[2] = L.F | (L.w << 8);
+        h[3] = L.eps;
+        h[4] = (uint32_t)L.n;            h[5] = (uint32_t)(L.n >> 32);
+        h[6] = (uint32_t)L.nblocks;      h[7] = (uint32_t)(L.nblocks >> 32);
+        h[8] = (uint32_t)nseg_total;     h[9] = (uint32_t)(nseg_total >> 32);
+        h[10] = (uint32_t)max_nseg;      h[11] = 0;
+        h[12] = (uint32_t)L.off_first;   h[13] = (uint32_t)(L.off_first >> 32);
+        h[14] = (uint32_t)L.off_dir;     h[15] = (uint32_t)(L.off_dir >> 32);
+        h[16] = (uint32_t)L.off_res;     h[17] = (uint32_t)(L.off_res >> 32);
+        h[18] = (uint32_t)L.res_stride;  h[19] = (uint32_t)(L.res_stride >> 32);
+        h[20] = (uint32_t)L.off_seg;     h[21] = (uint32_t)(L.off_seg >> 32);
+        h[22] = (uint32_t)blob_bytes;    h[23] = (uint32_t)(blob_bytes >> 32);
+        uint4* hd = reinterpret_cast<uint4*>(blob);
+        for (int k = 0; k < 8; k++) hd[k] = make_uint4(h[4 * k], h[4 * k + 1], h[4 * k + 2], h[4 * k + 3]);
+        if (d_blob_bytes) *d_blob_bytes = blob_bytes;
+    }
+    // zero the pad between first_keys and the directory
+    const uint64_t fk_end = L.off_first + L.nblocks * L.kb;
+    if (threadIdx.x < L.off_dir - fk_end) blob[fk_end + threadIdx.x] = 0;
+}
+
+// Directory entries: one thread per block, 256 blocks (one tile) per workgroup.
+__global__ __launch_bounds__(256) void dir_emit_kernel(Workspace ws, Layout L, uint8_t* __restrict__ blob,
+                                                       uint64_t tile0)
+{
+    const uint64_t tile = tile0 + blockIdx.x;
+    const uint64_t b = tile * kTileBlocks + threadIdx.x;
+    BlockInfo bi = {};
+    if (b < L.nblocks) bi = ws.blk[b];
+    uint64_t tot;
+    const uint64_t ex = block_excl_sum<256>(bi.seg_bytes, &tot);
+    if (b < L.nblocks) {
+        const uint64_t seg_off = L.off_seg + ws.tiles[tile].off + ex;
+        const uint32_t w3 = (bi.nkeys - 1) | ((uint32_t)bi.ab << 16) | ((uint32_t)bi.sb << 24);
+        reinterpret_cast<uint4*>(blob + L.off_dir)[b] =
+            make_uint4((uint32_t)seg_off, (uint32_t)(seg_off >> 32), bi.nseg, w3);
+    }
+}
+
+// 16 bytes of a little-endian array of `width`-byte values: entries
+// [c * 16 / width, (c + 1) * 16 / width), zero past n.
+template <typename T>
+__device__ __forceinline__ uint4 pack_chunk(const T* vals, uint32_t n, uint32_t c, uint32_t width)
+{
+    const uint32_t per = 16 / width;
+    const uint64_t mask = width == 8 ? ~0ull : ((1ull << (8 * width)) - 1);
+    uint64_t lo = 0, hi = 0;
+    for (uint32_t k = 0; k < per; k++) {
+        const uint32_t idx = c * per + k;
+        const uint64_t v = idx < n ? ((uint64_t)vals[idx] & mask) : 0;
+        const uint32_t bit = k * width * 8;
+        if (bit < 64) lo |= v << bit;
+        else hi |= v << (bit - 64);
+    }
+    return make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
+}
+
+// Segment areas: one wave per block, four blocks per workgroup.
+__global__ __launch_bounds__(256) void seg_emit_kernel(Workspace ws, Layout L, uint8_t* __restrict__ blob,
+                                                       uint64_t blk0)
+{
+    const uint64_t b = blk0 + (uint64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    if (b >= L.nblocks) return;
+    const uint32_t lane = lane_id();
+    const uint4 dv = reinterpret_cast<const uint4*>(blob + L.off_dir)[b];
+    const uint64_t seg_off = dv.x | ((uint64_t)dv.y << 32);
+    const uint32_t n = dv.z;
+    const uint32_t ab = (dv.w >> 16) & 0xFF, sb = dv.w >> 24;
+    const uint64_t rec = b << L.log2b;
+    uint4* out = reinterpret_cast<uint4*>(blob + seg_off);
+    const uint32_t c_start = (uint32_t)(a16(2ull * n) / 16);
+    const uint32_t c_anchor = (uint32_t)(a16((uint64_t)ab * n) / 16);
+    const uint32_t c_slope = (uint32_t)(a16((uint64_t)sb * n) / 16);
+    for (uint32_t c = lane; c < c_start; c += 64) out[c] = pack_chunk(ws.seg_start + rec, n, c, 2);
+    out += c_start;
+    for (uint32_t c = lane; c < c_anchor; c += 64) out[c] = pack_chunk(ws.seg_delta + rec, n, c, ab);
+    out += c_anchor;
+    for (uint32_t c = lane; c < c_slope; c += 64) out[c] = pack_chunk(ws.seg_A + rec, n, c, sb);
+}
+
+// ---------------------------------------------------------------------------
+// Decode
+// ---------------------------------------------------------------------------
+
+struct DecodeArgs {
+    Layout L;
+    uint64_t begin, end;   // key range, global indices
+    uint64_t b_first;      // first block of this launch
+    uint64_t nblk;         // blocks in this launch
+    uint64_t per_xcd;      // ceil(grid / 8): consecutive blocks handled by one XCD
+    uint32_t vec;          // 1: outputs of key groups of 16 bytes are 16-byte aligned
+};
+
+// Segments whose model is staged in LDS; a block with more segments (sparse
+// tails: up to B / 2 two-key segments) reads its model from global memory.
+constexpr uint32_t kSegCap = 192;
+
+__host__ __device__ constexpr uint64_t decode_lds_bytes(uint32_t log2b, uint64_t res_stride)
+{
+    return (uint64_t)kSegCap * 18 + (8ull << log2b) / 32 + res_stride + 8;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_sum32(uint32_t v)
+{
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(v, o, 64);
+        if (lane >= (uint32_t)o) v += t;
+    }
+    return v;
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// One wave per block.  The block's segment starts become an LDS bitmap with
+// per-word prefix popcounts, so the segment of key j is found in O(1):
+//   t = prefix[j / 32] + popcount(bits[j / 32] & mask(j % 32)) - 1.
+// The model (start, anchor, slope) of up to kSegCap segments and the residual
+// slab are staged in LDS.  Lane l decodes the groups of V = 16 / KB keys
+// starting at V * (l + 64 i): each store instruction of the wave writes 1 KB
+// of contiguous output.  Workgroup w runs on XCD w % 8, so blocks are
+// assigned XCD-major: each XCD walks a contiguous run of blocks.
+template <int KB, bool RANGE>
+__global__ __launch_bounds__(64) void decode_kernel(const uint8_t* __restrict__ blob, DecodeArgs a,
+                                                     void* __restrict__ out)
+{
+    constexpr uint32_t V = 16 / KB;
+    const uint64_t rel = (uint64_t)(blockIdx.x % 8) * a.per_xcd + blockIdx.x / 8;
+    if (rel >= a.nblk) return;
+    const uint64_t b = a.b_first + rel;
+    const Layout& L = a.L;
+    const uint32_t lane = threadIdx.x;
+    const uint32_t nwords = (1u << L.log2b) >> 5;
+    const uint32_t slab_words = (uint32_t)(L.res_stride / 4);
+
+    extern __shared__ __align__(16) uint8_t smem[];
+    uint64_t* s_anchor = reinterpret_cast<uint64_t*>(smem);
+    uint64_t* s_A = s_anchor + kSegCap;
+    uint32_t* s_bm = reinterpret_cast<uint32_t*>(s_A + kSegCap);
+    uint32_t* s_pre = s_bm + nwords;
+    uint16_t* s_start = reinterpret_cast<uint16_t*>(s_pre + nwords);
+    uint32_t* s_slab = reinterpret_cast<uint32_t*>(s_start + kSegCap);
+
+    // residual slab: its address does not depend on the directory
+    const uint4* src = reinterpret_cast<const uint4*>(blob + L.off_res + b * L.res_stride);
+    for (uint32_t c = lane; c < slab_words / 4; c += 64) reinterpret_cast<uint4*>(s_slab)[c] = src[c];
+    if (lane < 2) s_slab[slab_words + lane] = 0;
+    for (uint32_t w = lane; w < nwords; w += 64) s_bm[w] = 0;
+
+    const uint4 dv = reinterpret_cast<const uint4*>(blob + L.off_dir)[b];
+    const uint64_t seg_off = dv.x | ((uint64_t)dv.y << 32);
+    const uint32_t nseg = dv.z ? dv.z : 1u;
+    const uint32_t nkeys = (dv.w & 0xFFFF) + 1;
+    const uint32_t ab = (dv.w >> 16) & 0xFF, sb = dv.w >> 24;
+    const uint64_t first = load_key<KB>(blob + L.off_first, b);
+    const uint16_t* g_start = reinterpret_cast<const uint16_t*>(blob + seg_off);
+    const uint8_t* g_an = blob + seg_off + a16(2ull * nseg);
+    const uint8_t* g_sl = g_an + a16((uint64_t)ab * nseg);
+    const bool staged = nseg <= kSegCap;
+    __syncthreads();
+
+    for (uint32_t t = lane; t < nseg; t += 64) {
+        const uint32_t st = g_start[t] & ((1u << L.log2b) - 1);
+        atomicOr(&s_bm[st >> 5], 1u << (st & 31));
+        if (staged) {
+            s_start[t] = (uint16_t)st;
+            s_anchor[t] = first + load_w(g_an, t, ab);
+            s_A[t] = load_w(g_sl, t, sb);
+        }
+    }
+    __syncthreads();
+    uint32_t carry = 0;
+    for (uint32_t w0 = 0; w0 < nwords; w0 += 64) {
+        const uint32_t w = w0 + lane;
+        const uint32_t c = w < nwords ? __popc(s_bm[w]) : 0u;
+        const uint32_t incl = wave_incl_sum32(c);
+        if (w < nwords) s_pre[w] = carry + incl - c;
+        carry += __shfl(incl, 63, 64);
+    }
+    __syncthreads();
+
+    const uint32_t F = L.F, w = L.w;
+    const uint64_t eps = L.eps;
+    const uint64_t wmask = (1ull << w) - 1;  // w <= 32
+    const uint64_t i0 = b << L.log2b;
+    uint32_t jlo = 0, jhi = nkeys;
+    uint64_t obase = i0;  // out index of key j is obase + j (mod 2^64)
+    if constexpr (RANGE) {
+        jlo = (uint32_t)((a.begin > i0 ? a.begin : i0) - i0);
+        const uint64_t iend = i0 + nkeys < a.end ? i0 + nkeys : a.end;
+        jhi = (uint32_t)(iend - i0);
+        obase = i0 - a.begin;
+    }
+
+    uint32_t cur_t = ~0u, cur_start = 0;
+    uint64_t cur_anchor = 0, cur_A = 0;
+    auto model = [&](uint32_t t) {
+        if (t == cur_t) return;
+        cur_t = t;
+        if (staged) {
+            cur_start = s_start[t];
+            cur_anchor = s_anchor[t];
+            cur_A = s_A[t];
+        } else {
+            cur_start = g_start[t];
+            cur_anchor = first + load_w(g_an, t, ab);
+            cur_A = load_w(g_sl, t, sb);
+        }
+    };
+    auto key_at = [&](uint32_t j) {
+        const uint64_t pred = cur_anchor + ((cur_A * (uint64_t)(j - cur_start)) >> F);
+        const uint64_t bitpos = (uint64_t)j * w;
+        const uint32_t wd = (uint32_t)(bitpos >> 5), sh = (uint32_t)(bitpos & 31);
+        const uint64_t win = (uint64_t)s_slab[wd] | ((uint64_t)s_slab[wd + 1] << 32);
+        return pred + ((win >> sh) & wmask) - eps;
+    };
+
+    if (!RANGE || a.vec) {
+        for (uint32_t g = lane * V; g < jhi; g += 64 * V) {
+            if (RANGE && g + V <= jlo) continue;
+            const uint32_t bits = s_bm[g >> 5];
+            uint32_t t = s_pre[g >> 5] + __popc(bits & (0xFFFFFFFFu >> (31 - (g & 31)))) - 1;
+            uint64_t v[V];
+#pragma unroll
+            for (uint32_t k = 0; k < V; k++) {
+                const uint32_t j = g + k;
+                if (k) t += (bits >> (j & 31)) & 1u;
+                model(t);
+                v[k] = key_at(j);
+            }
+            if (g >= jlo && g + V <= jhi) {
+                u32x4 q;
+                if constexpr (KB == 8) {
+                    q = u32x4{(uint32_t)v[0], (uint32_t)(v[0] >> 32), (uint32_t)v[1], (uint32_t)(v[1] >> 32)};
+                } else {
+                    q = u32x4{(uint32_t)v[0], (uint32_t)v[1], (uint32_t)v[2], (uint32_t)v[3]};
+                }
+                __builtin_nontemporal_store(q, reinterpret_cast<u32x4*>(out) + (obase + g) / V);
+            } else {
+#pragma unroll
+                for (uint32_t k = 0; k < V; k++)
+                    if (g + k >= jlo && g + k < jhi) store_key<KB>(out, obase + g + k, v[k]);
+            }
+        }
+    } else {
+        for (uint32_t j = jlo + lane; j < jhi; j += 64) {
+            const uint32_t bits = s_bm[j >> 5];
+            model(s_pre[j >> 5] + __popc(bits & (0xFFFFFFFFu >> (31 - (j & 31)))) - 1);
+            store_key<KB>(out, obase + j, key_at(j));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Point queries
+// ---------------------------------------------------------------------------
+
+struct BlockView {
+    uint64_t seg_off;
+    uint32_t nseg, nkeys, ab, sb;
+};
+
+__device__ __forceinline__ BlockView block_view(const uint8_t* blob, const Layout& L, uint64_t b)
+{
+    const uint4 dv = reinterpret_cast<const uint4*>(blob + L.off_dir)[b];
+    BlockView v;
+    v.seg_off = dv.x | ((uint64_t)dv.y << 32);
+    v.nseg = dv.z;
+    v.nkeys = (dv.w & 0xFFFF) + 1;
+    v.ab = (dv.w >> 16) & 0xFF;
+    v.sb = dv.w >> 24;
+    return v;
+}
+
+// Residual code j of block b, read straight from the blob.
+__device__ __forceinline__ uint64_t code_at(const uint8_t* blob, const Layout& L, uint64_t b, uint32_t j)
+{
+    if (L.w == 0) return 0;
+    const uint64_t bitpos = (uint64_t)j * L.w;
+    const uint32_t* slab = reinterpret_cast<const uint32_t*>(blob + L.off_res + b * L.res_stride);
+    const uint32_t wd = (uint32_t)(bitpos >> 5), sh = (uint32_t)(bitpos & 31);
+    uint64_t win = slab[wd];
+    if (sh + L.w > 32) win |= (uint64_t)slab[wd + 1] << 32;
+    return (win >> sh) & ((1ull << L.w) - 1);
+}
+
+template <int KB>
+__global__ __launch_bounds__(256) void access_kernel(const uint8_t* __restrict__ blob, Layout L,
+                                                     const uint64_t* __restrict__ idx, uint64_t m,
+                                                     void* __restrict__ out, uint32_t* __restrict__ flags)
+{
+    bool bad = false;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < m; q += stride) {
+        const uint64_t i = idx[q];
+        if (i >= L.n) {
+            store_key<KB>(out, q, 0);
+            bad = true;
+            continue;
+        }
+        const uint64_t b = i >> L.log2b;
+        const uint32_t j = (uint32_t)(i & ((1ull << L.log2b) - 1));
+        const BlockView v = block_view(blob, L, b);
+        const uint16_t* st = reinterpret_cast<const uint16_t*>(blob + v.seg_off);
+        uint32_t t = 0;
+        for (uint32_t step = pow2_floor(v.nseg); step; step >>= 1)
+            if (t + step < v.nseg && st[t + step] <= j) t += step;
+        const uint8_t* an = blob + v.seg_off + a16(2ull * v.nseg);
+        const uint8_t* sl = an + a16((uint64_t)v.ab * v.nseg);
+        const uint64_t anchor = load_key<KB>(blob + L.off_first, b) + load_w(an, t, v.ab);
+        const uint64_t A = load_w(sl, t, v.sb);
+        const uint64_t key = anchor + ((A * (uint64_t)(j - st[t])) >> L.F) + code_at(blob, L, b, j) - L.eps;
+        store_key<KB>(out, q, key);
+    }
+    if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(flags, kFlagRange);
+}
+
+template <int KB>
+__global__ __launch_bounds__(256) void lower_bound_kernel(const uint8_t* __restrict__ blob, Layout L,
+                                                          const void* __restrict__ qs, uint64_t m,
+                                                          uint64_t* __restrict__ pos)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint8_t* fk = blob + L.off_first;
+    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < m; q += stride) {
+        const uint64_t x = load_key<KB>(qs, q);
+        if (L.n == 0 || load_key<KB>(fk, 0) >= x) {
+            pos[q] = 0;
+            continue;
+        }
+        // last block whose first key is < x
+        uint64_t b = 0;
+        for (uint64_t step = 1ull << (63 - __clzll((long long)L.nblocks)); step; step >>= 1)
+            if (b + step < L.nblocks && load_key<KB>(fk, b + step) < x) b += step;
+        const BlockView v = block_view(blob, L, b);
+        const uint16_t* st = reinterpret_cast<const uint16_t*>(blob + v.seg_off);
+        const uint8_t* an = blob + v.seg_off + a16(2ull * v.nseg);
+        const uint8_t* sl = an + a16((uint64_t)v.ab * v.nseg);
+        const uint64_t first = load_key<KB>(fk, b);
+        // last segment whose anchor (its first key) is < x
+        uint32_t t = 0;
+        for (uint32_t step = pow2_floor(v.nseg); step; step >>= 1)
+            if (t + step < v.nseg && first + load_w(an, t + step, v.ab) < x) t += step;
+        const uint32_t s = st[t];
+        const uint32_t e = t + 1 < v.nseg ? st[t + 1] : v.nkeys;
+        const uint64_t anchor = first + load_w(an, t, v.ab);
+        const uint64_t A = load_w(sl, t, v.sb);
+        // keys s+1 .. e-1 of the segment: first one >= x, else e
+        uint32_t lo = s + 1, hi = e;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            uint64_t k = anchor + ((A * (uint64_t)(mid - s)) >> L.F) + code_at(blob, L, b, mid) - L.eps;
+            if constexpr (KB == 4) k &= 0xFFFFFFFFull;
+            if (k >= x) hi = mid;
+            else lo = mid + 1;
+        }
+        pos[q] = (b << L.log2b) + lo;
+    }
+}
+
+inline uint32_t query_grid(uint64_t m)
+{
+    const uint64_t g = (m + 255) / 256;
+    return (uint32_t)(g < 8192 ? (g ? g : 1) : 8192);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_compress(const void* d_keys, const Layout& L, uint8_t* d_blob, const Workspace& ws,
+                           uint64_t* d_blob_bytes, uint32_t* d_flags, hipStream_t stream)
+{
+    const uint64_t B = 1ull << L.log2b;
+    if (L.nblocks) {
+        const size_t lds = B * 8 + B * 8 + B * 2 + L.res_stride + 8;
+        auto k = L.kb == 4 ? fit_pack_kernel<4> : fit_pack_kernel<8>;
+        if (lds > 65536) {
+            hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        for (uint64_t b0 = 0; b0 < L.nblocks; b0 += kMaxGrid) {
+            const uint64_t nb = L.nblocks - b0 < kMaxGrid ? L.nblocks - b0 : kMaxGrid;
+            hipLaunchKernelGGL(k, dim3((uint32_t)nb), dim3(64), lds, stream, d_keys, L, d_blob, ws, d_flags, b0);
+        }
+        const uint64_t nt = ntiles_of(L.nblocks);
+        for (uint64_t t0 = 0; t0 < nt; t0 += kMaxGrid) {
+            const uint64_t g = nt - t0 < kMaxGrid ? nt - t0 : kMaxGrid;
+            hipLaunchKernelGGL(tile_reduce_kernel, dim3((uint32_t)g), dim3(256), 0, stream, ws, L.nblocks, t0);
+        }
+    }
+    hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, stream, ws, L, d_blob, d_blob_bytes);
+    if (L.nblocks) {
+        const uint64_t nt = ntiles_of(L.nblocks);
+        for (uint64_t t0 = 0; t0 < nt; t0 += kMaxGrid) {
+            const uint64_t g = nt - t0 < kMaxGrid ? nt - t0 : kMaxGrid;
+            hipLaunchKernelGGL(dir_emit_kernel, dim3((uint32_t)g), dim3(256), 0, stream, ws, L, d_blob, t0);
+        }
+        const uint64_t groups = (L.nblocks + 3) / 4;
+        for (uint64_t g0 = 0; g0 < groups; g0 += kMaxGrid) {
+            const uint64_t g = groups - g0 < kMaxGrid ? groups - g0 : kMaxGrid;
+            hipLaunchKernelGGL(seg_emit_kernel, dim3((uint32_t)g), dim3(256), 0, stream, ws, L, d_blob, g0 * 4);
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_decode(const uint8_t* d_blob, const Layout& L, uint64_t begin, uint64_t end, void* d_out,
+                         hipStream_t stream)
+{
+    if (begin >= end) return hipSuccess;
+    const uint64_t b_lo = begin >> L.log2b, b_hi = (end - 1) >> L.log2b;
+    const size_t lds = decode_lds_bytes(L.log2b, L.res_stride);
+    const bool range = !(begin == 0 && end == L.n);
+    auto k = L.kb == 4 ? (range ? decode_kernel<4, true> : decode_kernel<4, false>)
+                       : (range ? decode_kernel<8, true> : decode_kernel<8, false>);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    for (uint64_t b0 = b_lo; b0 <= b_hi; b0 += kMaxGrid) {
+        DecodeArgs a;
+        a.L = L;
+        a.begin = begin;
+        a.end = end;
+        a.b_first = b0;
+        a.nblk = (b_hi + 1 - b0) < kMaxGrid ? (b_hi + 1 - b0) : kMaxGrid;
+        a.per_xcd = (a.nblk + 7) / 8;
+        a.vec = (begin % (16 / L.kb)) == 0 && (reinterpret_cast<uintptr_t>(d_out) % 16) == 0;
+        hipLaunchKernelGGL(k, dim3((uint32_t)(a.per_xcd * 8)), dim3(64), lds, stream, d_blob, a, d_out);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_access(const uint8_t* d_blob, const Layout& L, const uint64_t* d_idx, uint64_t m, void* d_out,
+                         uint32_t* d_flags, hipStream_t stream)
+{
+    if (m == 0) return hipSuccess;
+    auto k = L.kb == 4 ? access_kernel<4> : access_kernel<8>;
+    hipLaunchKernelGGL(k, dim3(query_grid(m)), dim3(256), 0, stream, d_blob, L, d_idx, m, d_out, d_flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_lower_bound(const uint8_t* d_blob, const Layout& L, const void* d_q, uint64_t m, uint64_t* d_pos,
+                              hipStream_t stream)
+{
+    if (m == 0) return hipSuccess;
+    auto k = L.kb == 4 ? lower_bound_kernel<4> : lower_bound_kernel<8>;
+    hipLaunchKernelGGL(k, dim3(query_grid(m)), dim3(256), 0, stream, d_blob, L, d_q, m, d_pos);
+    return hipGetLastError();
+}
+
+}  // namespace lc

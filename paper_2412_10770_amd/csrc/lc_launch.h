@@ -1,0 +1,57 @@
+// Internal interface between the C ABI (lc_api.cpp) and the kernels
+// (lc_kernels.hip).  Not installed; the public interface is include/lc.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lc {
+
+// Byte layout of one blob v1 plus the encoder parameters, as kernel arguments.
+struct Layout {
+    uint64_t n, nblocks;
+    uint64_t off_first, off_dir, off_res, res_stride, off_seg;
+    uint32_t kb, log2b, F, w, eps, max_nseg;
+};
+
+// Per-block result of the fit kernel, read by the scan and emit kernels.
+struct BlockInfo {
+    uint32_t nseg;
+    uint32_t seg_bytes;  // bytes of the block's segment area
+    uint32_t nkeys;
+    uint8_t ab, sb;      // anchor-delta and slope byte widths
+    uint16_t pad;
+};
+
+// Per-tile (256 blocks) sums and, after the tile scan, the tile's offset.
+struct TileSum {
+    uint64_t bytes, nseg, off;
+    uint32_t max_nseg, pad;
+};
+
+// Device workspace of lc_compress, carved from the caller's buffer.
+struct Workspace {
+    BlockInfo* blk;       // [nblocks]
+    TileSum* tiles;       // [ntiles]
+    uint16_t* seg_start;  // [nblocks * B]: segment starts, block-major
+    uint64_t* seg_delta;  // [nblocks * B]: anchor - first key of the block
+    uint64_t* seg_A;      // [nblocks * B]: fixed-point slopes
+};
+
+constexpr uint32_t kTileBlocks = 256;
+constexpr uint64_t kHeaderBytes = 128;
+
+inline uint64_t align16(uint64_t x) { return (x + 15) & ~uint64_t(15); }
+inline uint64_t ntiles_of(uint64_t nblocks) { return (nblocks + kTileBlocks - 1) / kTileBlocks; }
+
+// Kernel launchers; each returns the hipError_t of its last launch.
+hipError_t launch_compress(const void* d_keys, const Layout& L, uint8_t* d_blob, const Workspace& ws,
+                           uint64_t* d_blob_bytes, uint32_t* d_flags, hipStream_t stream);
+hipError_t launch_decode(const uint8_t* d_blob, const Layout& L, uint64_t begin, uint64_t end,
+                         void* d_out, hipStream_t stream);
+hipError_t launch_access(const uint8_t* d_blob, const Layout& L, const uint64_t* d_idx, uint64_t m,
+                         void* d_out, uint32_t* d_flags, hipStream_t stream);
+hipError_t launch_lower_bound(const uint8_t* d_blob, const Layout& L, const void* d_q, uint64_t m,
+                              uint64_t* d_pos, hipStream_t stream);
+
+}  // namespace lc

@@ -1,0 +1,259 @@
+"""Python binding of the C ABI in include/lc.h (ctypes; marshalling only).
+
+PyTorch provides device memory and the stream; every step of encoding,
+decoding and querying runs in the HIP kernels of ``liblc.so``.  There is no
+fallback: if the library is not built, importing this module raises.
+
+Keys travel as 1-D contiguous device tensors holding the unsigned bit
+patterns: ``torch.int32``/``torch.uint32`` for 4-byte keys and
+``torch.int64``/``torch.uint64`` for 8-byte keys.  Decoded keys come back as
+``torch.int32`` / ``torch.int64`` bit patterns.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch  # noqa: F401  (loads the HIP runtime liblc.so binds to)
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblc.so")
+
+LC_OK = 0
+LC_EINVAL = -1
+LC_ENOSPC = -2
+LC_EFORMAT = -3
+LC_EDEVICE = -4
+LC_FLAG_UNSORTED = 1
+LC_FLAG_RANGE = 2
+HEADER_BYTES = 128
+DEFAULT_LOG2_BLOCK = 10
+DEFAULT_FRAC_BITS = 20
+
+EXPORTED = ("lc_compress_bound", "lc_compress", "lc_info", "lc_decompress", "lc_decompress_range",
+            "lc_access", "lc_lower_bound", "lc_strerror")
+
+
+class lc_params(ctypes.Structure):
+    _fields_ = [("key_bytes", ctypes.c_uint8), ("log2_block", ctypes.c_uint8),
+                ("frac_bits", ctypes.c_uint8), ("reserved", ctypes.c_uint8), ("eps", ctypes.c_uint32)]
+
+
+class lc_blob_info(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint32) for f in
+                ("key_bytes", "log2_block", "frac_bits", "width", "eps", "max_nseg")] + \
+               [(f, ctypes.c_uint64) for f in
+                ("n", "nblocks", "nseg_total", "off_first", "off_dir", "off_res", "res_stride",
+                 "off_seg", "blob_bytes")]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u64, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32
+    P, I = ctypes.POINTER(lc_params), ctypes.POINTER(lc_blob_info)
+    sig = {
+        "lc_compress_bound": [u64, P, ctypes.POINTER(u64), ctypes.POINTER(u64)],
+        "lc_compress": [vp, u64, P, vp, u64, vp, u64, vp, vp, vp],
+        "lc_info": [vp, u64, I],
+        "lc_decompress": [vp, I, vp, vp],
+        "lc_decompress_range": [vp, I, u64, u64, vp, vp],
+        "lc_access": [vp, I, vp, u64, vp, vp, vp],
+        "lc_lower_bound": [vp, I, vp, u64, vp, vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int32
+    L.lc_strerror.argtypes = [ctypes.c_int32]
+    L.lc_strerror.restype = ctypes.c_char_p
+    return L
+
+
+lib = _load()
+
+
+class LcError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+        self.code = code
+
+
+def strerror(code: int) -> str:
+    return lib.lc_strerror(code).decode()
+
+
+def _check(rc: int, what: str):
+    if rc != LC_OK:
+        raise LcError(rc, what)
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _key_bytes(t: torch.Tensor) -> int:
+    if t.dtype in (torch.int32, torch.uint32):
+        return 4
+    if t.dtype in (torch.int64, torch.uint64):
+        return 8
+    raise TypeError(f"keys must be 4- or 8-byte integers, got {t.dtype}")
+
+
+def _dev(t: torch.Tensor, what: str):
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous device tensor")
+
+
+def key_dtype(key_bytes: int) -> torch.dtype:
+    return torch.int32 if key_bytes == 4 else torch.int64
+
+
+def params(key_bytes: int, eps: int, log2_block: int = DEFAULT_LOG2_BLOCK,
+           frac_bits: int = DEFAULT_FRAC_BITS) -> lc_params:
+    return lc_params(key_bytes, log2_block, frac_bits, 0, eps)
+
+
+def compress_bound(n: int, key_bytes: int, eps: int, log2_block: int = DEFAULT_LOG2_BLOCK,
+                   frac_bits: int = DEFAULT_FRAC_BITS):
+    """(blob_max, ws_bytes): worst-case blob size and workspace size."""
+    blob_max, ws = ctypes.c_uint64(), ctypes.c_uint64()
+    p = params(key_bytes, eps, log2_block, frac_bits)
+    _check(lib.lc_compress_bound(n, ctypes.byref(p), ctypes.byref(blob_max), ctypes.byref(ws)),
+           "lc_compress_bound")
+    return blob_max.value, ws.value
+
+
+def info(header) -> lc_blob_info:
+    """Parse a blob header (host bytes / numpy / CPU tensor, >= 128 bytes)."""
+    if isinstance(header, torch.Tensor):
+        header = header.detach().cpu().contiguous().numpy()
+    buf = bytes(memoryview(header).cast("B")[:HEADER_BYTES]) if not isinstance(header, bytes) else header
+    out = lc_blob_info()
+    raw = ctypes.create_string_buffer(buf, len(buf))
+    _check(lib.lc_info(ctypes.cast(raw, ctypes.c_void_p), len(buf), ctypes.byref(out)), "lc_info")
+    return out
+
+
+@dataclass
+class Blob:
+    """A compressed key list resident in device memory."""
+    data: torch.Tensor   # uint8, exactly info.blob_bytes long
+    info: lc_blob_info
+
+    @property
+    def n(self) -> int:
+        return self.info.n
+
+    @property
+    def key_bytes(self) -> int:
+        return self.info.key_bytes
+
+    @property
+    def nbytes(self) -> int:
+        return self.info.blob_bytes
+
+    @property
+    def ratio(self) -> float:
+        """size(K^c) / size(K) (Def. 1), counting every blob byte."""
+        return self.nbytes / max(1, self.n * self.key_bytes)
+
+    @property
+    def bits_per_key(self) -> float:
+        return 8.0 * self.nbytes / max(1, self.n)
+
+    @classmethod
+    def from_device(cls, data: torch.Tensor) -> "Blob":
+        inf = info(data[:HEADER_BYTES].cpu())
+        return cls(data[:inf.blob_bytes], inf)
+
+
+def compress_async(keys: torch.Tensor, eps: int, blob: torch.Tensor, workspace: torch.Tensor,
+                   blob_bytes: torch.Tensor, flags: torch.Tensor, log2_block: int = DEFAULT_LOG2_BLOCK,
+                   frac_bits: int = DEFAULT_FRAC_BITS, stream=None):
+    """Enqueue lc_compress into caller-provided buffers; no synchronisation."""
+    _dev(keys, "keys")
+    kb = _key_bytes(keys)
+    p = params(kb, eps, log2_block, frac_bits)
+    _check(lib.lc_compress(ctypes.c_void_p(keys.data_ptr()), keys.numel(), ctypes.byref(p),
+                           ctypes.c_void_p(blob.data_ptr()), blob.numel(),
+                           ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                           ctypes.c_void_p(blob_bytes.data_ptr()), ctypes.c_void_p(flags.data_ptr()),
+                           _stream(stream)), "lc_compress")
+
+
+def compress(keys: torch.Tensor, eps: int, log2_block: int = DEFAULT_LOG2_BLOCK,
+             frac_bits: int = DEFAULT_FRAC_BITS, stream=None) -> Blob:
+    """Enc of Def. 1 on the GPU; synchronises to learn the blob size."""
+    _dev(keys, "keys")
+    kb = _key_bytes(keys)
+    blob_max, ws_bytes = compress_bound(keys.numel(), kb, eps, log2_block, frac_bits)
+    dev = keys.device
+    blob = torch.empty(blob_max, dtype=torch.uint8, device=dev)
+    ws = torch.empty(max(ws_bytes, 16), dtype=torch.uint8, device=dev)
+    nbytes = torch.zeros(1, dtype=torch.int64, device=dev)
+    flags = torch.zeros(1, dtype=torch.int32, device=dev)
+    compress_async(keys, eps, blob, ws, nbytes, flags, log2_block, frac_bits, stream)
+    if int(flags.item()) & LC_FLAG_UNSORTED:
+        raise LcError(LC_EINVAL, "lc_compress: keys are not sorted (LC_FLAG_UNSORTED)")
+    size = int(nbytes.item())
+    del ws
+    data = blob[:size].clone()
+    return Blob(data, info(data[:HEADER_BYTES].cpu()))
+
+
+def decompress(blob: Blob, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Dec of Def. 1: all n keys."""
+    if out is None:
+        out = torch.empty(blob.n, dtype=key_dtype(blob.key_bytes), device=blob.data.device)
+    _check(lib.lc_decompress(ctypes.c_void_p(blob.data.data_ptr()), ctypes.byref(blob.info),
+                             ctypes.c_void_p(out.data_ptr()), _stream(stream)), "lc_decompress")
+    return out
+
+
+def decompress_range(blob: Blob, begin: int, end: int, out: torch.Tensor | None = None,
+                     stream=None) -> torch.Tensor:
+    """Keys [begin, end)."""
+    if out is None:
+        out = torch.empty(max(0, end - begin), dtype=key_dtype(blob.key_bytes), device=blob.data.device)
+    _check(lib.lc_decompress_range(ctypes.c_void_p(blob.data.data_ptr()), ctypes.byref(blob.info),
+                                   begin, end, ctypes.c_void_p(out.data_ptr()), _stream(stream)),
+           "lc_decompress_range")
+    return out
+
+
+def access(blob: Blob, idx: torch.Tensor, out: torch.Tensor | None = None,
+           flags: torch.Tensor | None = None, stream=None, check: bool = True) -> torch.Tensor:
+    """K[idx[q]] for every q.  With check=True, synchronises and raises on an index >= n."""
+    _dev(idx, "idx")
+    if idx.dtype not in (torch.int64, torch.uint64):
+        raise TypeError("idx must be a 64-bit integer tensor")
+    if out is None:
+        out = torch.empty(idx.numel(), dtype=key_dtype(blob.key_bytes), device=idx.device)
+    own_flags = flags is None
+    if own_flags:
+        flags = torch.zeros(1, dtype=torch.int32, device=idx.device)
+    _check(lib.lc_access(ctypes.c_void_p(blob.data.data_ptr()), ctypes.byref(blob.info),
+                         ctypes.c_void_p(idx.data_ptr()), idx.numel(), ctypes.c_void_p(out.data_ptr()),
+                         ctypes.c_void_p(flags.data_ptr()), _stream(stream)), "lc_access")
+    if check and own_flags and int(flags.item()) & LC_FLAG_RANGE:
+        raise LcError(LC_EINVAL, "lc_access: an index is >= n (LC_FLAG_RANGE)")
+    return out
+
+
+def lower_bound(blob: Blob, q: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """First i with K[i] >= q (n if none), as int64."""
+    _dev(q, "q")
+    if _key_bytes(q) != blob.key_bytes:
+        raise TypeError("queries must have the blob's key width")
+    if out is None:
+        out = torch.empty(q.numel(), dtype=torch.int64, device=q.device)
+    _check(lib.lc_lower_bound(ctypes.c_void_p(blob.data.data_ptr()), ctypes.byref(blob.info),
+                              ctypes.c_void_p(q.data_ptr()), q.numel(), ctypes.c_void_p(out.data_ptr()),
+                              _stream(stream)), "lc_lower_bound")
+    return out

@@ -1,0 +1,107 @@
+"""The C ABI library loads and exports what include/lc.h declares; host-side
+argument checks (no GPU needed: every call here fails before any enqueue)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "lc.h")).read()
+    return sorted(set(re.findall(r"^(?:lc_status|const char\*)\s+(lc_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lc():
+    from paper_2412_10770_amd import lc as mod
+    return mod
+
+
+def test_header_declares_the_five_operations():
+    names = _declared()
+    for op in ("lc_compress", "lc_decompress", "lc_decompress_range", "lc_access", "lc_lower_bound"):
+        assert op in names
+
+
+def test_library_exports_every_declared_symbol(lc):
+    raw = ctypes.CDLL(lc.LIB_PATH)
+    for name in _declared():
+        assert hasattr(raw, name), name
+    assert sorted(lc.EXPORTED) == _declared()
+
+
+def test_strerror(lc):
+    assert lc.strerror(0) == "ok"
+    for code in (-1, -2, -3, -4):
+        assert lc.strerror(code) not in ("", "unknown status")
+
+
+def test_compress_bound(lc):
+    for n, kb, eps, log2b in ((0, 4, 0, 6), (1, 8, 63, 10), (10 ** 8, 8, 255, 10), (1000, 4, 7, 12)):
+        blob_max, ws = lc.compress_bound(n, kb, eps, log2b)
+        B = 1 << log2b
+        nblocks = -(-n // B)
+        w = int(np.ceil(np.log2(2 * eps + 1)))
+        stride = -(-(-(-B * w // 8)) // 16) * 16
+        fixed = 128 + -(-nblocks * kb // 16) * 16 + 16 * nblocks + nblocks * stride
+        assert blob_max >= fixed + nblocks * 48
+        assert ws >= 18 * nblocks * B
+    for bad in ((3, 10, 20, 0), (8, 5, 20, 0), (8, 13, 20, 0), (8, 10, 33, 0), (8, 10, 20, 2 ** 31)):
+        p = lc.lc_params(bad[0], bad[1], bad[2], 0, bad[3])
+        a, b = ctypes.c_uint64(), ctypes.c_uint64()
+        assert lc.lib.lc_compress_bound(10, ctypes.byref(p), ctypes.byref(a), ctypes.byref(b)) == lc.LC_EINVAL
+    p = lc.params(8, 63)
+    assert lc.lib.lc_compress_bound(2 ** 41, ctypes.byref(p), None, None) == lc.LC_EINVAL
+
+
+def test_info_parses_oracle_headers(lc):
+    rng = np.random.default_rng(3)
+    for kb, eps, log2b, n in ((4, 63, 10, 5000), (8, 0, 6, 1), (8, 4095, 12, 9000), (4, 7, 8, 0)):
+        keys = np.cumsum(rng.integers(0, 50, n)).astype(np.uint32 if kb == 4 else np.uint64)
+        blob = oracle.compress(keys, eps, log2b)
+        inf = lc.info(blob[:128])
+        h = oracle.header(blob)
+        for f in oracle.HEADER_FIELDS:
+            assert getattr(inf, f if f != "width" else "width") == h[f], f
+
+
+def test_info_rejects_bad_headers(lc):
+    blob = oracle.compress(np.arange(0, 3000, 2, dtype=np.uint64), 15, 9)
+    for off, val in ((0, 0), (4, 9), (6, 3), (7, 5), (9, 1), (24, 7), (56, 1)):
+        bad = blob[:128].copy()
+        bad[off] = val
+        with pytest.raises(lc.LcError) as e:
+            lc.info(bad)
+        assert e.value.code == lc.LC_EFORMAT, off
+    with pytest.raises(lc.LcError):
+        lc.info(blob[:64])
+
+
+def test_entry_points_reject_bad_arguments_before_any_launch(lc):
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails its checks first
+    p = lc.params(8, 63)
+    assert lc.lib.lc_compress(fake, 10, None, fake, 1 << 20, fake, 1 << 20, null, fake, null) == lc.LC_EINVAL
+    assert lc.lib.lc_compress(fake, 10, ctypes.byref(p), null, 1 << 20, fake, 1 << 20, null, fake, null) == lc.LC_EINVAL
+    assert lc.lib.lc_compress(fake, 10, ctypes.byref(p), fake, 1 << 20, fake, 1 << 20, null, null, null) == lc.LC_EINVAL
+    assert lc.lib.lc_compress(fake, 10, ctypes.byref(p), fake, 16, fake, 1 << 20, null, fake, null) == lc.LC_ENOSPC
+    assert lc.lib.lc_compress(fake, 10, ctypes.byref(p), fake, 1 << 20, fake, 16, null, fake, null) == lc.LC_ENOSPC
+    assert lc.lib.lc_compress(ctypes.c_void_p(0x1001), 10, ctypes.byref(p), fake, 1 << 20, fake, 1 << 20, null,
+                              fake, null) == lc.LC_EINVAL
+    blob = oracle.compress(np.arange(0, 30000, 3, dtype=np.uint64), 63, 10)
+    inf = lc.info(blob[:128])
+    assert lc.lib.lc_decompress_range(fake, ctypes.byref(inf), 5, 4, fake, null) == lc.LC_EINVAL
+    assert lc.lib.lc_decompress_range(fake, ctypes.byref(inf), 0, inf.n + 1, fake, null) == lc.LC_EINVAL
+    assert lc.lib.lc_decompress_range(fake, ctypes.byref(inf), 7, 7, fake, null) == lc.LC_OK  # empty: no-op
+    assert lc.lib.lc_decompress(fake, ctypes.byref(inf), ctypes.c_void_p(0x1008), null) == lc.LC_EINVAL
+    assert lc.lib.lc_access(fake, ctypes.byref(inf), fake, 5, fake, null, null) == lc.LC_EINVAL
+    assert lc.lib.lc_access(fake, ctypes.byref(inf), fake, 0, fake, null, null) == lc.LC_OK
+    assert lc.lib.lc_lower_bound(null, ctypes.byref(inf), fake, 5, fake, null) == lc.LC_EINVAL
+    inf.off_seg += 16  # info no longer consistent with the layout rules
+    assert lc.lib.lc_decompress(fake, ctypes.byref(inf), fake, null) == lc.LC_EINVAL

@@ -1,0 +1,184 @@
+"""HIP path against the CPU oracle, through the C ABI.
+
+Integer work, so the bar is bit-exact everywhere: the GPU blob equals the
+oracle's blob byte for byte, each side decodes the other's blob to K, and
+decompress_range / access / lower_bound equal the plain definitions
+(K[b:e], K[i], numpy.searchsorted(..., 'left')).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import oracle_pins as P
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lc():
+    from paper_2412_10770_amd import lc as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def wl():
+    from paper_2412_10770_amd import workloads
+    return workloads
+
+
+def _to_dev(keys: np.ndarray) -> torch.Tensor:
+    signed = keys.view(np.int32 if keys.dtype.itemsize == 4 else np.int64)
+    return torch.from_numpy(signed.copy()).to(DEV)
+
+
+def _host(t: torch.Tensor, kb: int) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint32 if kb == 4 else np.uint64)
+
+
+def check_all(lc, keys: np.ndarray, eps: int, log2b: int, rng, nq: int = 2000, frac_bits: int = 20):
+    kb = keys.dtype.itemsize
+    n = len(keys)
+    _say(f"case n={n} kb={kb} eps={eps} log2b={log2b} F={frac_bits}")
+    want = oracle.compress(keys, eps, log2b, frac_bits)
+    d = _to_dev(keys)
+    blob = lc.compress(d, eps, log2b, frac_bits)
+    got = blob.data.cpu().numpy()
+    if not np.array_equal(got, want):
+        h = oracle.header(want)
+        first = int(np.flatnonzero(got[:len(want)] != want[:len(got)])[0]) if min(len(got), len(want)) else -1
+        raise AssertionError(f"blob mismatch: sizes {len(got)} vs {len(want)}, first byte {first}, header {h}")
+    # both decoders on both blobs
+    assert np.array_equal(_host(lc.decompress(blob), kb), keys)
+    assert np.array_equal(oracle.decode(got), keys)
+    ob = lc.Blob.from_device(torch.from_numpy(want).to(DEV))
+    assert np.array_equal(_host(lc.decompress(ob), kb), keys)
+    if n == 0:
+        return blob
+    # ranges: aligned, unaligned, single key, whole list
+    ranges = [(0, n), (0, 1), (n - 1, n)]
+    for _ in range(6):
+        a = int(rng.integers(0, n))
+        b = int(rng.integers(a, n + 1))
+        ranges.append((a, b))
+    for a, b in ranges:
+        assert np.array_equal(_host(lc.decompress_range(blob, a, b), kb), keys[a:b]), (a, b)
+    # access
+    idx = rng.integers(0, n, nq).astype(np.int64)
+    idx[:3] = [0, n - 1, n // 2]
+    acc = lc.access(blob, torch.from_numpy(idx).to(DEV))
+    assert np.array_equal(_host(acc, kb), oracle.access(keys, idx))
+    # lower_bound: keys, neighbours, extremes, random
+    top = (1 << (8 * kb)) - 1
+    cand = [0, top, int(keys[0]), int(keys[-1])]
+    cand += [int(x) for x in keys[rng.integers(0, n, nq // 4)]]
+    cand += [min(top, int(x) + 1) for x in keys[rng.integers(0, n, nq // 4)]]
+    cand += [max(0, int(x) - 1) for x in keys[rng.integers(0, n, nq // 4)]]
+    lo, hi = int(keys[0]), int(keys[-1])
+    cand += [lo + int(v) for v in rng.integers(0, max(1, min(hi - lo + 1, 2 ** 62)), nq // 4)]
+    q = np.array(cand, dtype=keys.dtype)
+    pos = lc.lower_bound(blob, _to_dev(q)).cpu().numpy().astype(np.uint64)
+    assert np.array_equal(pos, oracle.lower_bound(keys, q))
+    return blob
+
+
+def test_random_small_cases(lc):
+    rng = np.random.default_rng(11)
+    for keys, eps, log2b in P.random_cases(seed=21, count=50):
+        check_all(lc, keys, eps, log2b, rng)
+
+
+@pytest.mark.parametrize("frac_bits", [0, 8, 32])
+def test_other_frac_bits(lc, frac_bits):
+    rng = np.random.default_rng(frac_bits)
+    for keys, eps, log2b in P.random_cases(seed=30 + frac_bits, count=8):
+        check_all(lc, keys, eps, log2b, rng, frac_bits=frac_bits)
+
+
+def test_edge_lists(lc, wl):
+    rng = np.random.default_rng(12)
+    for name, keys in wl.edge_lists():
+        for eps in (0, 1, 63, 2 ** 31 - 1):
+            for log2b in (6, 10, 12):
+                check_all(lc, keys, eps, log2b, rng, nq=200)
+
+
+def test_golden_blobs_on_gpu(lc):
+    for name in ("ap4_eps1.txt", "break4_eps1.txt"):
+        g = P.load_golden(name)
+        keys = np.array(g["keys"], np.uint32 if g["key_bytes"] == 4 else np.uint64)
+        blob = lc.compress(_to_dev(keys), g["eps"], g["log2_block"], g["frac_bits"])
+        assert np.array_equal(blob.data.cpu().numpy(), g["blob"]), name
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 1023, 1024, 1025, 4096 * 3 + 5])
+def test_block_edges(lc, n):
+    rng = np.random.default_rng(n)
+    keys = np.cumsum(rng.integers(1, 65, n)).astype(np.uint64)
+    for log2b in (6, 10, 12):
+        check_all(lc, keys, 63, log2b, rng, nq=300)
+
+
+def test_long_segments_and_singletons(lc):
+    rng = np.random.default_rng(5)
+    ap = (np.uint64(3) + np.uint64(17) * np.arange(50_000, dtype=np.uint64))
+    check_all(lc, ap, 0, 12, rng)           # one segment per 4096-key block
+    cap = np.cumsum(np.full(9000, 1 << 45, dtype=np.uint64))
+    check_all(lc, cap, 3, 12, rng)          # every key its own segment
+    check_all(lc, np.full(10_000, 123, np.uint32), 5, 10, rng)
+
+
+def test_determinism(lc):
+    rng = np.random.default_rng(1)
+    keys = np.cumsum(rng.integers(0, 1000, 300_000)).astype(np.uint64)
+    d = _to_dev(keys)
+    a = lc.compress(d, 63).data
+    b = lc.compress(d, 63).data
+    assert torch.equal(a, b)
+
+
+def test_unsorted_flag(lc):
+    keys = np.arange(5000, dtype=np.uint64) * np.uint64(7)
+    for pos in (0, 1, 1023, 1024, 2500, 4999):
+        bad = keys.copy()
+        if pos == 0:
+            bad[0] = bad[1] + 1
+        else:
+            bad[pos] = bad[pos - 1] - 1
+        with pytest.raises(lc.LcError):
+            lc.compress(_to_dev(bad), 15)
+
+
+def test_access_out_of_range_flag(lc):
+    keys = np.arange(3000, dtype=np.uint32) * np.uint32(5)
+    blob = lc.compress(_to_dev(keys), 7)
+    idx = torch.tensor([0, 2999, 3000, 2 ** 40], dtype=torch.int64, device=DEV)
+    flags = torch.zeros(1, dtype=torch.int32, device=DEV)
+    out = lc.access(blob, idx, flags=flags)
+    assert int(flags.item()) == lc.LC_FLAG_RANGE
+    assert out.cpu().tolist() == [0, 2999 * 5, 0, 0]
+    with pytest.raises(lc.LcError):
+        lc.access(blob, idx)
+
+
+def test_configs_reduced(lc, wl):
+    """The benchmark recipes at sizes the oracle finishes in seconds."""
+    rng = np.random.default_rng(2)
+    keys = wl.as_numpy(wl.uniform_gaps(1_000_000, device="cpu"))
+    check_all(lc, keys, 63, 10, rng, nq=100_000)  # the 1M uint32 workload, at full size
+    keys = wl.as_numpy(wl.lognormal_distinct(2_000_000, device="cpu"))
+    for eps in (15, 63, 255):
+        check_all(lc, keys, eps, 10, rng, nq=20_000)
+    keys = wl.as_numpy(wl.heterogeneous_runs(2_000_000, device="cpu", run_lo=1e3, run_hi=1e5))
+    check_all(lc, keys, 63, 10, rng, nq=20_000)
+    keys = wl.as_numpy(wl.lognormal_gaps(2_000_000, device="cpu"))
+    for eps in (255, 1023):
+        check_all(lc, keys, eps, 10, rng, nq=20_000)
