@@ -22,8 +22,9 @@
  * Blob v1 (the compressed form, little-endian, every region 16-byte aligned,
  * every pad byte zero):
  *   header (128 B): magic "LCB1", version 1, key_bytes, log2_block, frac_bits
- *     F, residual width w, eps, n, nblocks, nseg_total, max_nseg, the byte
- *     offsets of the four regions below, res_stride, blob_bytes;
+ *     F, residual width w, eps, n, nblocks, nseg_total, max_nseg,
+ *     max_seg_bytes, the byte offsets of the four regions below, res_stride,
+ *     blob_bytes;
  *   first_keys[nblocks]   the first key of every block of B = 2^log2_block keys;
  *   dir[nblocks]          16 B each: segment-area offset, segment count,
  *                         key count - 1, anchor and slope byte widths;
@@ -79,7 +80,10 @@ typedef struct lc_params {
 
 /* Host-side copy of a blob's header fields (filled by lc_info). */
 typedef struct lc_blob_info {
-    uint32_t key_bytes, log2_block, frac_bits, width, eps, max_nseg;
+    uint32_t key_bytes, log2_block, frac_bits, width, eps;
+    uint32_t max_nseg;      /* most segments in one block */
+    uint32_t max_seg_bytes; /* largest segment area of one block (sizes decode's LDS) */
+    uint32_t reserved;
     uint64_t n, nblocks, nseg_total;
     uint64_t off_first, off_dir, off_res, res_stride, off_seg, blob_bytes;
 } lc_blob_info;

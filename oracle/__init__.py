@@ -33,7 +33,7 @@ REF_ENOSPC = -2
 REF_EFORMAT = -3
 REF_EUNSORTED = -5
 
-HEADER_FIELDS = ("key_bytes", "log2_block", "frac_bits", "width", "eps", "max_nseg", "n",
+HEADER_FIELDS = ("key_bytes", "log2_block", "frac_bits", "width", "eps", "max_nseg", "max_seg_bytes", "n",
                  "nblocks", "nseg_total", "off_first", "off_dir", "off_res", "res_stride",
                  "off_seg", "blob_bytes")
 
@@ -128,7 +128,7 @@ class Ref:
 
     def header(self, blob) -> dict:
         b = np.ascontiguousarray(blob, dtype=np.uint8)
-        f = np.zeros(15, np.uint64)
+        f = np.zeros(16, np.uint64)
         rc = self.L.lcref_header(_u8p(b), len(b), f.ctypes.data)
         if rc != REF_OK:
             raise OracleError(rc, "header")

@@ -49,7 +49,8 @@
  *     10 u16 0                          12 u32 eps
  *     16 u64 n                          24 u64 nblocks = ceil(n / B)
  *     32 u64 nseg_total                 40 u32 max_nseg (largest per block)
- *     44 u32 0                          48 u64 off_first (= 128)
+ *     44 u32 max_seg_bytes (largest segment area of a block)
+ *                                       48 u64 off_first (= 128)
  *     56 u64 off_dir                    64 u64 off_res
  *     72 u64 res_stride                 80 u64 off_seg
  *     88 u64 blob_bytes                 96..127 zero
@@ -254,6 +255,7 @@ int lcref_compress(const void* keys, uint64_t n, int kb, int log2_block, uint32_
     }
     uint64_t nseg_total = 0;
     uint32_t max_nseg = 0;
+    uint64_t max_area = 0;
     for (uint64_t b = 0; b < nblocks; b++) {
         uint64_t base = b * B;
         uint32_t nb = (uint32_t)((n - base) < B ? (n - base) : B);
@@ -282,8 +284,10 @@ int lcref_compress(const void* keys, uint64_t n, int kb, int log2_block, uint32_
             if (slopes[base + t] > maxa) maxa = slopes[base + t];
         }
         uint64_t m = nseg[b];
-        total += align16(2 * m) + align16((uint64_t)byte_width(maxd) * m) +
-                 align16((uint64_t)byte_width(maxa) * m);
+        uint64_t area = align16(2 * m) + align16((uint64_t)byte_width(maxd) * m) +
+                        align16((uint64_t)byte_width(maxa) * m);
+        total += area;
+        if (area > max_area) max_area = area;
     }
     *out_bytes = total;
     if (cap < total || out == NULL) {
@@ -304,6 +308,7 @@ int lcref_compress(const void* keys, uint64_t n, int kb, int log2_block, uint32_
     put_le(out + 24, nblocks, 8);
     put_le(out + 32, nseg_total, 8);
     put_le(out + 40, max_nseg, 4);
+    put_le(out + 44, max_area, 4);
     put_le(out + 48, off_first, 8);
     put_le(out + 56, off_dir, 8);
     put_le(out + 64, off_res, 8);
@@ -366,7 +371,7 @@ int lcref_compress(const void* keys, uint64_t n, int kb, int log2_block, uint32_
 
 /* Header fields, parsed and checked against the layout rules. */
 typedef struct {
-    uint32_t kb, log2_block, F, w, eps, max_nseg;
+    uint32_t kb, log2_block, F, w, eps, max_nseg, max_seg_bytes;
     uint64_t n, nblocks, nseg_total, off_first, off_dir, off_res, res_stride, off_seg, bytes;
 } ref_header;
 
@@ -383,6 +388,7 @@ static int parse_header(const uint8_t* blob, uint64_t avail, ref_header* h)
     h->nblocks = get_le(blob + 24, 8);
     h->nseg_total = get_le(blob + 32, 8);
     h->max_nseg = (uint32_t)get_le(blob + 40, 4);
+    h->max_seg_bytes = (uint32_t)get_le(blob + 44, 4);
     h->off_first = get_le(blob + 48, 8);
     h->off_dir = get_le(blob + 56, 8);
     h->off_res = get_le(blob + 64, 8);
@@ -424,6 +430,7 @@ int lcref_decode(const uint8_t* blob, uint64_t avail, void* out, uint64_t out_ca
         if (!(sb == 1 || sb == 2 || sb == 4 || sb == 8)) return REF_EFORMAT;
         uint64_t area = align16(2ull * m) + align16((uint64_t)ab * m) + align16((uint64_t)sb * m);
         if (seg_off < h.off_seg || seg_off + area > h.bytes) return REF_EFORMAT;
+        if (m > h.max_nseg || area > h.max_seg_bytes) return REF_EFORMAT;
         const uint8_t* st = blob + seg_off;
         const uint8_t* an = st + align16(2ull * m);
         const uint8_t* sl = an + align16((uint64_t)ab * m);
@@ -451,15 +458,15 @@ int lcref_decode(const uint8_t* blob, uint64_t avail, void* out, uint64_t out_ca
     return REF_OK;
 }
 
-/* Header fields for tests: writes 15 u64 values in the order of ref_header. */
+/* Header fields for tests: writes 16 u64 values in the order of ref_header. */
 int lcref_header(const uint8_t* blob, uint64_t avail, uint64_t* fields)
 {
     ref_header h;
     int rc = parse_header(blob, avail, &h);
     if (rc != REF_OK) return rc;
-    uint64_t v[15] = {h.kb, h.log2_block, h.F, h.w, h.eps, h.max_nseg, h.n, h.nblocks,
-                      h.nseg_total, h.off_first, h.off_dir, h.off_res, h.res_stride,
-                      h.off_seg, h.bytes};
+    uint64_t v[16] = {h.kb, h.log2_block, h.F, h.w, h.eps, h.max_nseg, h.max_seg_bytes, h.n,
+                      h.nblocks, h.nseg_total, h.off_first, h.off_dir, h.off_res,
+                      h.res_stride, h.off_seg, h.bytes};
     memcpy(fields, v, sizeof v);
     return REF_OK;
 }

@@ -103,8 +103,13 @@ lc_status layout_of(const lc_blob_info* info, lc::Layout* L)
         L->off_dir != info->off_dir || L->off_res != info->off_res || L->res_stride != info->res_stride ||
         L->off_seg != info->off_seg)
         return LC_EINVAL;
-    if (info->n && (info->max_nseg == 0 || info->max_nseg > (1u << info->log2_block))) return LC_EINVAL;
+    const uint64_t B = 1ull << info->log2_block;
+    if (info->n && (info->max_nseg == 0 || info->max_nseg > B)) return LC_EINVAL;
+    if (info->n && (info->max_seg_bytes < 48 || info->max_seg_bytes > lc::align16(2 * B) + 2 * lc::align16(8 * B) ||
+                    info->max_seg_bytes % 16))
+        return LC_EINVAL;
     L->max_nseg = info->max_nseg;
+    L->max_seg_bytes = info->max_seg_bytes;
     return LC_OK;
 }
 
@@ -165,6 +170,7 @@ LC_API lc_status lc_info(const void* h_header, uint64_t header_bytes, lc_blob_in
     I.nblocks = rd(h + 24, 8);
     I.nseg_total = rd(h + 32, 8);
     I.max_nseg = (uint32_t)rd(h + 40, 4);
+    I.max_seg_bytes = (uint32_t)rd(h + 44, 4);
     I.off_first = rd(h + 48, 8);
     I.off_dir = rd(h + 56, 8);
     I.off_res = rd(h + 64, 8);

@@ -39,7 +39,8 @@ __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
 
 // Element t of a little-endian array of `width`-byte unsigned integers whose
 // base is aligned to `width`.
-__device__ __forceinline__ uint64_t load_w(const uint8_t* base, uint32_t t, uint32_t width)
+template <typename P8>
+__device__ __forceinline__ uint64_t load_w(P8 base, uint32_t t, uint32_t width)
 {
     switch (width) {
     case 1: return base[t];
@@ -312,29 +313,35 @@ __global__ __launch_bounds__(256) void tile_reduce_kernel(Workspace ws, uint64_t
 {
     const uint64_t tile = tile0 + blockIdx.x;
     const uint64_t b = tile * kTileBlocks + threadIdx.x;
-    uint64_t bytes = 0, nseg = 0, mx = 0;
+    uint64_t bytes = 0, nseg = 0;
     if (b < nblocks) {
         const BlockInfo bi = ws.blk[b];
         bytes = bi.seg_bytes;
         nseg = bi.nseg;
-        mx = bi.nseg;
     }
     uint64_t tb, tn;
     block_excl_sum<256>(bytes, &tb);
     block_excl_sum<256>(nseg, &tn);
-    __shared__ uint64_t s_mx[4];
-    const uint64_t wm = wave_max(mx);
-    if (lane_id() == 0) s_mx[threadIdx.x / 64] = wm;
+    // maxima of the segment count (low half) and segment-area bytes (high half)
+    __shared__ uint64_t s_mx[2][4];
+    const uint64_t mn = wave_max(nseg), mb = wave_max(bytes);
+    if (lane_id() == 0) {
+        s_mx[0][threadIdx.x / 64] = mn;
+        s_mx[1][threadIdx.x / 64] = mb;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint64_t m = s_mx[0];
-        for (int k = 1; k < 4; k++) m = s_mx[k] > m ? s_mx[k] : m;
+        uint64_t m0 = 0, m1 = 0;
+        for (int k = 0; k < 4; k++) {
+            m0 = s_mx[0][k] > m0 ? s_mx[0][k] : m0;
+            m1 = s_mx[1][k] > m1 ? s_mx[1][k] : m1;
+        }
         TileSum t;
         t.bytes = tb;
         t.nseg = tn;
         t.off = 0;
-        t.max_nseg = (uint32_t)m;
-        t.pad = 0;
+        t.max_nseg = (uint32_t)m0;
+        t.max_seg_bytes = (uint32_t)m1;
         ws.tiles[tile] = t;
     }
 }
@@ -345,15 +352,16 @@ __global__ __launch_bounds__(1024) void tile_scan_kernel(Workspace ws, Layout L,
                                                          uint64_t* __restrict__ d_blob_bytes)
 {
     const uint64_t ntiles = (L.nblocks + kTileBlocks - 1) / kTileBlocks;
-    uint64_t carry = 0, nseg_total = 0, max_nseg = 0;
+    uint64_t carry = 0, nseg_total = 0, max_nseg = 0, max_area = 0;
     for (uint64_t t0 = 0; t0 < ntiles; t0 += 1024) {
         const uint64_t t = t0 + threadIdx.x;
-        uint64_t v = 0, ns = 0, mx = 0;
+        uint64_t v = 0, ns = 0, mx = 0, ma = 0;
         if (t < ntiles) {
             const TileSum ts = ws.tiles[t];
             v = ts.bytes;
             ns = ts.nseg;
             mx = ts.max_nseg;
+            ma = ts.max_seg_bytes;
         }
         uint64_t tot, tot_ns;
         const uint64_t ex = block_excl_sum<1024>(v, &tot);
@@ -361,11 +369,17 @@ __global__ __launch_bounds__(1024) void tile_scan_kernel(Workspace ws, Layout L,
         if (t < ntiles) ws.tiles[t].off = carry + ex;
         carry += tot;
         nseg_total += tot_ns;
-        __shared__ uint64_t s_mx[16];
-        const uint64_t wm = wave_max(mx);
-        if (lane_id() == 0) s_mx[threadIdx.x / 64] = wm;
+        __shared__ uint64_t s_mx[2][16];
+        const uint64_t wm = wave_max(mx), wa = wave_max(ma);
+        if (lane_id() == 0) {
+            s_mx[0][threadIdx.x / 64] = wm;
+            s_mx[1][threadIdx.x / 64] = wa;
+        }
         __syncthreads();
-        for (int k = 0; k < 16; k++) max_nseg = s_mx[k] > max_nseg ? s_mx[k] : max_nseg;
+        for (int k = 0; k < 16; k++) {
+            max_nseg = s_mx[0][k] > max_nseg ? s_mx[0][k] : max_nseg;
+            max_area = s_mx[1][k] > max_area ? s_mx[1][k] : max_area;
+        }
         __syncthreads();
     }
     const uint64_t blob_bytes = L.off_seg + carry;
@@ -379,7 +393,7 @@ __global__ __launch_bounds__(1024) void tile_scan_kernel(Workspace ws, Layout L,
         h[4] = (uint32_t)L.n;            h[5] = (uint32_t)(L.n >> 32);
         h[6] = (uint32_t)L.nblocks;      h[7] = (uint32_t)(L.nblocks >> 32);
         h[8] = (uint32_t)nseg_total;     h[9] = (uint32_t)(nseg_total >> 32);
-        h[10] = (uint32_t)max_nseg;      h[11] = 0;
+        h[10] = (uint32_t)max_nseg;      h[11] = (uint32_t)max_area;
         h[12] = (uint32_t)L.off_first;   h[13] = (uint32_t)(L.off_first >> 32);
         h[14] = (uint32_t)L.off_dir;     h[15] = (uint32_t)(L.off_dir >> 32);
         h[16] = (uint32_t)L.off_res;     h[17] = (uint32_t)(L.off_res >> 32);
@@ -465,15 +479,30 @@ struct DecodeArgs {
     uint64_t nblk;         // blocks in this launch
     uint64_t per_xcd;      // ceil(grid / 8): consecutive blocks handled by one XCD
     uint32_t vec;          // 1: outputs of key groups of 16 bytes are 16-byte aligned
+    uint32_t raw_cap;      // LDS bytes for a staged segment area
 };
 
-// Segments whose model is staged in LDS; a block with more segments (sparse
-// tails: up to B / 2 two-key segments) reads its model from global memory.
-constexpr uint32_t kSegCap = 192;
+// A block's segment area is staged raw in LDS when it fits kSegRawMax bytes
+// (the LDS reserved is the blob's largest area if smaller: a header field).
+// A small cap keeps many waves resident; blocks over it -- sparse stretches
+// where most segments hold two keys -- are decoded segment-parallel from
+// global memory instead.
+#ifndef LC_DECODE_RAW_CAP
+#define LC_DECODE_RAW_CAP 4096
+#endif
+constexpr uint32_t kSegRawMax = LC_DECODE_RAW_CAP;
+// 16-byte chunks per lane loaded before the first wait (slab, segment area).
+constexpr uint32_t kSlabBatch = 4;
+constexpr uint32_t kSegBatch = 4;
 
-__host__ __device__ constexpr uint64_t decode_lds_bytes(uint32_t log2b, uint64_t res_stride)
+__host__ __device__ constexpr uint32_t decode_raw_cap(uint32_t max_seg_bytes)
 {
-    return (uint64_t)kSegCap * 18 + (8ull << log2b) / 32 + res_stride + 8;
+    return ((max_seg_bytes < kSegRawMax ? max_seg_bytes : kSegRawMax) + 15) & ~15u;
+}
+
+__host__ __device__ constexpr uint64_t decode_lds_bytes(uint32_t log2b, uint64_t res_stride, uint32_t raw_cap)
+{
+    return (uint64_t)raw_cap + 16 + (8ull << log2b) / 32 + res_stride + 16;
 }
 
 __device__ __forceinline__ uint32_t wave_incl_sum32(uint32_t v)
@@ -489,19 +518,161 @@ __device__ __forceinline__ uint32_t wave_incl_sum32(uint32_t v)
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-// One wave per block.  The block's segment starts become an LDS bitmap with
-// per-word prefix popcounts, so the segment of key j is found in O(1):
-//   t = prefix[j / 32] + popcount(bits[j / 32] & mask(j % 32)) - 1.
-// The model (start, anchor, slope) of up to kSegCap segments and the residual
-// slab are staged in LDS.  Lane l decodes the groups of V = 16 / KB keys
-// starting at V * (l + 64 i): each store instruction of the wave writes 1 KB
-// of contiguous output.  Workgroup w runs on XCD w % 8, so blocks are
-// assigned XCD-major: each XCD walks a contiguous run of blocks.
+// Per-block decode context.
+struct BlockCtx {
+    uint64_t first, eps, obase;
+    uint32_t F, w, ab, sb, jlo, jhi, vec;
+    const uint32_t* s_slab;
+    const uint32_t* s_bm;
+    const uint32_t* s_pre;
+};
+
+template <uint32_t W, typename P8>
+__device__ __forceinline__ uint64_t load_fixed(P8 base, uint32_t t)
+{
+    if constexpr (W == 1) return base[t];
+    else if constexpr (W == 2) return reinterpret_cast<const uint16_t*>(base)[t];
+    else if constexpr (W == 4) return reinterpret_cast<const uint32_t*>(base)[t];
+    else return reinterpret_cast<const uint64_t*>(base)[t];
+}
+
+// floor(A * d / 2^F) with d < 2^13; a 32 x 32 -> 64-bit product when the
+// block's slopes fit in 4 bytes.
+template <uint32_t SB>
+__device__ __forceinline__ uint64_t slope_term(uint64_t A, uint32_t d, uint32_t F)
+{
+    if constexpr (SB <= 4) return ((uint64_t)(uint32_t)A * d) >> F;
+    else return (A * d) >> F;
+}
+
+// Decodes keys [jlo, jhi) of one block whose model arrays (u16 start[],
+// anchor-first_key[] of AB bytes, A[] of SB bytes) are read through
+// `start`, `an`, `sl` -- LDS copies for staged blocks, the blob otherwise.
+// AB / SB are the block's byte widths (0: read at the runtime widths).
+template <int KB, bool RANGE, uint32_t AB, uint32_t SB, typename P16, typename P8>
+__device__ __forceinline__ void decode_keys(const BlockCtx& c, P16 start, P8 an, P8 sl, void* __restrict__ out)
+{
+    constexpr uint32_t V = 16 / KB;
+    const uint32_t lane = lane_id();
+    const uint64_t wmask = (1ull << c.w) - 1;  // w <= 32
+    auto anchor_of = [&](uint32_t t) -> uint64_t {
+        if constexpr (AB != 0) return load_fixed<AB>(an, t);
+        else return load_w(an, t, c.ab);
+    };
+    auto slope_of = [&](uint32_t t) -> uint64_t {
+        if constexpr (SB != 0) return load_fixed<SB>(sl, t);
+        else return load_w(sl, t, c.sb);
+    };
+    auto key_at = [&](uint32_t j, uint32_t t) {
+        const uint32_t d = j - start[t];
+        const uint64_t pred = c.first + anchor_of(t) + slope_term<SB == 0 ? 8 : SB>(slope_of(t), d, c.F);
+        const uint32_t bitpos = j * c.w;
+        const uint32_t wd = bitpos >> 5, sh = bitpos & 31;
+        const uint64_t win = (uint64_t)c.s_slab[wd] | ((uint64_t)c.s_slab[wd + 1] << 32);
+        return pred + ((win >> sh) & wmask) - c.eps;
+    };
+    auto seg_of = [&](uint32_t j) {
+        const uint32_t bits = c.s_bm[j >> 5];
+        return c.s_pre[j >> 5] + __popc(bits & (0xFFFFFFFFu >> (31 - (j & 31)))) - 1;
+    };
+
+    if (!RANGE || c.vec) {
+        for (uint32_t g = lane * V; g < c.jhi; g += 64 * V) {
+            if (RANGE && g + V <= c.jlo) continue;
+            const uint32_t bits = c.s_bm[g >> 5];
+            uint32_t t = seg_of(g);
+            uint64_t v[V];
+#pragma unroll
+            for (uint32_t k = 0; k < V; k++) {
+                const uint32_t j = g + k;
+                if (k) t += (bits >> (j & 31)) & 1u;
+                v[k] = key_at(j, t);
+            }
+            if (g >= c.jlo && g + V <= c.jhi) {
+                u32x4 q;
+                if constexpr (KB == 8) {
+                    q = u32x4{(uint32_t)v[0], (uint32_t)(v[0] >> 32), (uint32_t)v[1], (uint32_t)(v[1] >> 32)};
+                } else {
+                    q = u32x4{(uint32_t)v[0], (uint32_t)v[1], (uint32_t)v[2], (uint32_t)v[3]};
+                }
+                __builtin_nontemporal_store(q, reinterpret_cast<u32x4*>(out) + (c.obase + g) / V);
+            } else {
+#pragma unroll
+                for (uint32_t k = 0; k < V; k++)
+                    if (g + k >= c.jlo && g + k < c.jhi) store_key<KB>(out, c.obase + g + k, v[k]);
+            }
+        }
+    } else {
+        for (uint32_t j = c.jlo + lane; j < c.jhi; j += 64) store_key<KB>(out, c.obase + j, key_at(j, seg_of(j)));
+    }
+}
+
+// Staged blocks: dispatch once per block on the (anchor, slope) widths so the
+// per-key loop has no width branches.
+template <int KB, bool RANGE>
+__device__ __forceinline__ void decode_staged(const BlockCtx& c, const uint8_t* s_raw, uint32_t off_an,
+                                              uint32_t off_sl, void* __restrict__ out)
+{
+    const uint16_t* st = reinterpret_cast<const uint16_t*>(s_raw);
+    const uint8_t* an = s_raw + off_an;
+    const uint8_t* sl = s_raw + off_sl;
+#define LC_DECODE_CASE(A_, S_) \
+    case (A_) * 16 + (S_): decode_keys<KB, RANGE, A_, S_>(c, st, an, sl, out); return;
+    switch (c.ab * 16 + c.sb) {
+        LC_DECODE_CASE(1, 1) LC_DECODE_CASE(1, 2) LC_DECODE_CASE(1, 4) LC_DECODE_CASE(1, 8)
+        LC_DECODE_CASE(2, 1) LC_DECODE_CASE(2, 2) LC_DECODE_CASE(2, 4) LC_DECODE_CASE(2, 8)
+        LC_DECODE_CASE(4, 1) LC_DECODE_CASE(4, 2) LC_DECODE_CASE(4, 4) LC_DECODE_CASE(4, 8)
+        LC_DECODE_CASE(8, 1) LC_DECODE_CASE(8, 2) LC_DECODE_CASE(8, 4) LC_DECODE_CASE(8, 8)
+        default: decode_keys<KB, RANGE, 0, 0>(c, st, an, sl, out); return;
+    }
+#undef LC_DECODE_CASE
+}
+
+// Blocks whose segment area is not staged: one lane per segment, keys of
+// the segment decoded in order.  Model loads are coalesced across lanes;
+// most segments here hold one or two keys.
+template <int KB, bool RANGE>
+__device__ __forceinline__ void decode_segments(const BlockCtx& c, const uint8_t* __restrict__ g_seg,
+                                                uint32_t nseg, uint32_t nkeys, uint32_t off_an, uint32_t off_sl,
+                                                void* __restrict__ out)
+{
+    const uint32_t lane = lane_id();
+    const uint16_t* g_start = reinterpret_cast<const uint16_t*>(g_seg);
+    const uint64_t wmask = (1ull << c.w) - 1;
+    for (uint32_t t = lane; t < nseg; t += 64) {
+        const uint32_t s = g_start[t];
+        const uint32_t e = t + 1 < nseg ? g_start[t + 1] : nkeys;
+        const uint64_t anchor = c.first + load_w(g_seg + off_an, t, c.ab);
+        const uint64_t A = load_w(g_seg + off_sl, t, c.sb);
+        const uint32_t j0 = s > c.jlo ? s : c.jlo, j1 = e < c.jhi ? e : c.jhi;
+        for (uint32_t j = j0; j < j1; j++) {
+            const uint64_t pred = anchor + ((A * (uint64_t)(j - s)) >> c.F);
+            const uint32_t bitpos = j * c.w;
+            const uint32_t wd = bitpos >> 5, sh = bitpos & 31;
+            const uint64_t win = (uint64_t)c.s_slab[wd] | ((uint64_t)c.s_slab[wd + 1] << 32);
+            store_key<KB>(out, c.obase + j, pred + ((win >> sh) & wmask) - c.eps);
+        }
+    }
+}
+
+// One wave per block.
+//  1. Coalesced 16-byte loads of the residual slab (its address needs only
+//     b) and of the raw segment area (once the directory entry is in), all
+//     unconditional with clamped chunk indices -- every load stays inside
+//     the blob; a slab of width 0 reads the first chunk of the segment areas
+//     -- so all are in flight before the first wait; they land in LDS.
+//  2. The segment starts become an LDS bitmap with per-word prefix
+//     popcounts, so the segment of key j is found in O(1):
+//       t = prefix[j / 32] + popcount(bits[j / 32] & mask(j % 32)) - 1.
+//  3. Lane l decodes the groups of V = 16 / KB keys starting at
+//     V * (l + 64 i); each store instruction of the wave writes 1 KB of
+//     contiguous output (non-temporal: the output is not re-read here).
+// Workgroup w runs on XCD w % 8, so blocks are assigned XCD-major: each XCD
+// walks a contiguous run of blocks (and of directory and segment bytes).
 template <int KB, bool RANGE>
 __global__ __launch_bounds__(64) void decode_kernel(const uint8_t* __restrict__ blob, DecodeArgs a,
                                                      void* __restrict__ out)
 {
-    constexpr uint32_t V = 16 / KB;
     const uint64_t rel = (uint64_t)(blockIdx.x % 8) * a.per_xcd + blockIdx.x / 8;
     if (rel >= a.nblk) return;
     const uint64_t b = a.b_first + rel;
@@ -509,20 +680,22 @@ __global__ __launch_bounds__(64) void decode_kernel(const uint8_t* __restrict__ 
     const uint32_t lane = threadIdx.x;
     const uint32_t nwords = (1u << L.log2b) >> 5;
     const uint32_t slab_words = (uint32_t)(L.res_stride / 4);
+    const uint32_t nch_slab = slab_words / 4;
+    const uint32_t raw_cap = a.raw_cap;
 
     extern __shared__ __align__(16) uint8_t smem[];
-    uint64_t* s_anchor = reinterpret_cast<uint64_t*>(smem);
-    uint64_t* s_A = s_anchor + kSegCap;
-    uint32_t* s_bm = reinterpret_cast<uint32_t*>(s_A + kSegCap);
-    uint32_t* s_pre = s_bm + nwords;
-    uint16_t* s_start = reinterpret_cast<uint16_t*>(s_pre + nwords);
-    uint32_t* s_slab = reinterpret_cast<uint32_t*>(s_start + kSegCap);
+    uint8_t* s_raw = smem;                                                 // raw_cap
+    uint4* s_trash = reinterpret_cast<uint4*>(smem + raw_cap);             // 16 B
+    uint32_t* s_slab = reinterpret_cast<uint32_t*>(smem + raw_cap + 16);   // slab_words + 4
+    uint32_t* s_bm = s_slab + slab_words + 4;                              // nwords
+    uint32_t* s_pre = s_bm + nwords;                                       // nwords
 
-    // residual slab: its address does not depend on the directory
-    const uint4* src = reinterpret_cast<const uint4*>(blob + L.off_res + b * L.res_stride);
-    for (uint32_t c = lane; c < slab_words / 4; c += 64) reinterpret_cast<uint4*>(s_slab)[c] = src[c];
-    if (lane < 2) s_slab[slab_words + lane] = 0;
-    for (uint32_t w = lane; w < nwords; w += 64) s_bm[w] = 0;
+    const uint32_t last_slab = nch_slab ? nch_slab - 1 : 0u;
+    const uint4* g_slab = reinterpret_cast<const uint4*>(blob + L.off_res + b * L.res_stride);
+    const uint4 fs0 = g_slab[lane < last_slab ? lane : last_slab];
+    const uint4 fs1 = g_slab[lane + 64 < last_slab ? lane + 64 : last_slab];
+    const uint4 fs2 = g_slab[lane + 128 < last_slab ? lane + 128 : last_slab];
+    const uint4 fs3 = g_slab[lane + 192 < last_slab ? lane + 192 : last_slab];
 
     const uint4 dv = reinterpret_cast<const uint4*>(blob + L.off_dir)[b];
     const uint64_t seg_off = dv.x | ((uint64_t)dv.y << 32);
@@ -530,102 +703,84 @@ __global__ __launch_bounds__(64) void decode_kernel(const uint8_t* __restrict__ 
     const uint32_t nkeys = (dv.w & 0xFFFF) + 1;
     const uint32_t ab = (dv.w >> 16) & 0xFF, sb = dv.w >> 24;
     const uint64_t first = load_key<KB>(blob + L.off_first, b);
-    const uint16_t* g_start = reinterpret_cast<const uint16_t*>(blob + seg_off);
-    const uint8_t* g_an = blob + seg_off + a16(2ull * nseg);
-    const uint8_t* g_sl = g_an + a16((uint64_t)ab * nseg);
-    const bool staged = nseg <= kSegCap;
+    const uint32_t off_an = (uint32_t)a16(2ull * nseg);
+    const uint32_t off_sl = off_an + (uint32_t)a16((uint64_t)ab * nseg);
+    const uint32_t seg_bytes = off_sl + (uint32_t)a16((uint64_t)sb * nseg);
+    const bool staged = seg_bytes <= raw_cap;
+    const uint8_t* g_seg = blob + seg_off;
+
+    const uint32_t nch_seg = staged ? seg_bytes / 16 : 0u;
+    const uint32_t last_seg = nch_seg ? nch_seg - 1 : 0u;
+    const uint4* g_raw = reinterpret_cast<const uint4*>(g_seg);
+    const uint4 fg0 = g_raw[lane < last_seg ? lane : last_seg];
+    const uint4 fg1 = g_raw[lane + 64 < last_seg ? lane + 64 : last_seg];
+    const uint4 fg2 = g_raw[lane + 128 < last_seg ? lane + 128 : last_seg];
+    const uint4 fg3 = g_raw[lane + 192 < last_seg ? lane + 192 : last_seg];
+    {
+        // stores unconditional too (lanes past the end write a trash slot),
+        // so the compiler cannot sink each load into its own guarded store
+        uint4* ss = reinterpret_cast<uint4*>(s_slab);
+        uint4* sr = reinterpret_cast<uint4*>(s_raw);
+        *(lane < nch_slab ? ss + lane : s_trash) = fs0;
+        *(lane + 64 < nch_slab ? ss + lane + 64 : s_trash) = fs1;
+        *(lane + 128 < nch_slab ? ss + lane + 128 : s_trash) = fs2;
+        *(lane + 192 < nch_slab ? ss + lane + 192 : s_trash) = fs3;
+        *(lane < nch_seg ? sr + lane : s_trash) = fg0;
+        *(lane + 64 < nch_seg ? sr + lane + 64 : s_trash) = fg1;
+        *(lane + 128 < nch_seg ? sr + lane + 128 : s_trash) = fg2;
+        *(lane + 192 < nch_seg ? sr + lane + 192 : s_trash) = fg3;
+    }
+    for (uint32_t c = lane + 64 * kSegBatch; c < nch_seg; c += 64)  // areas over 4 KB
+        reinterpret_cast<uint4*>(s_raw)[c] = g_raw[c];
+    for (uint32_t c = lane + 64 * kSlabBatch; c < nch_slab; c += 64)  // slabs over 4 KB
+        reinterpret_cast<uint4*>(s_slab)[c] = g_slab[c];
+    if (lane < 4) s_slab[slab_words + lane] = 0;
+    for (uint32_t w = lane; w < nwords; w += 64) s_bm[w] = 0;
     __syncthreads();
 
+    BlockCtx c;
+    c.first = first;
+    c.eps = L.eps;
+    c.F = L.F;
+    c.w = L.w;
+    c.ab = ab;
+    c.sb = sb;
+    c.s_slab = s_slab;
+    c.s_bm = s_bm;
+    c.s_pre = s_pre;
+    c.vec = a.vec;
+    const uint64_t i0 = b << L.log2b;
+    c.jlo = 0;
+    c.jhi = nkeys;
+    c.obase = i0;  // out index of key j is obase + j (mod 2^64)
+    if constexpr (RANGE) {
+        c.jlo = (uint32_t)((a.begin > i0 ? a.begin : i0) - i0);
+        const uint64_t iend = i0 + nkeys < a.end ? i0 + nkeys : a.end;
+        c.jhi = (uint32_t)(iend - i0);
+        c.obase = i0 - a.begin;
+    }
+    if (!staged) {
+        decode_segments<KB, RANGE>(c, g_seg, nseg, nkeys, off_an, off_sl, out);
+        return;
+    }
+
+    const uint32_t smask = (1u << L.log2b) - 1;
+    const uint16_t* st16 = reinterpret_cast<const uint16_t*>(s_raw);
     for (uint32_t t = lane; t < nseg; t += 64) {
-        const uint32_t st = g_start[t] & ((1u << L.log2b) - 1);
+        const uint32_t st = st16[t] & smask;
         atomicOr(&s_bm[st >> 5], 1u << (st & 31));
-        if (staged) {
-            s_start[t] = (uint16_t)st;
-            s_anchor[t] = first + load_w(g_an, t, ab);
-            s_A[t] = load_w(g_sl, t, sb);
-        }
     }
     __syncthreads();
     uint32_t carry = 0;
     for (uint32_t w0 = 0; w0 < nwords; w0 += 64) {
         const uint32_t w = w0 + lane;
-        const uint32_t c = w < nwords ? __popc(s_bm[w]) : 0u;
-        const uint32_t incl = wave_incl_sum32(c);
-        if (w < nwords) s_pre[w] = carry + incl - c;
+        const uint32_t cnt = w < nwords ? __popc(s_bm[w]) : 0u;
+        const uint32_t incl = wave_incl_sum32(cnt);
+        if (w < nwords) s_pre[w] = carry + incl - cnt;
         carry += __shfl(incl, 63, 64);
     }
     __syncthreads();
-
-    const uint32_t F = L.F, w = L.w;
-    const uint64_t eps = L.eps;
-    const uint64_t wmask = (1ull << w) - 1;  // w <= 32
-    const uint64_t i0 = b << L.log2b;
-    uint32_t jlo = 0, jhi = nkeys;
-    uint64_t obase = i0;  // out index of key j is obase + j (mod 2^64)
-    if constexpr (RANGE) {
-        jlo = (uint32_t)((a.begin > i0 ? a.begin : i0) - i0);
-        const uint64_t iend = i0 + nkeys < a.end ? i0 + nkeys : a.end;
-        jhi = (uint32_t)(iend - i0);
-        obase = i0 - a.begin;
-    }
-
-    uint32_t cur_t = ~0u, cur_start = 0;
-    uint64_t cur_anchor = 0, cur_A = 0;
-    auto model = [&](uint32_t t) {
-        if (t == cur_t) return;
-        cur_t = t;
-        if (staged) {
-            cur_start = s_start[t];
-            cur_anchor = s_anchor[t];
-            cur_A = s_A[t];
-        } else {
-            cur_start = g_start[t];
-            cur_anchor = first + load_w(g_an, t, ab);
-            cur_A = load_w(g_sl, t, sb);
-        }
-    };
-    auto key_at = [&](uint32_t j) {
-        const uint64_t pred = cur_anchor + ((cur_A * (uint64_t)(j - cur_start)) >> F);
-        const uint64_t bitpos = (uint64_t)j * w;
-        const uint32_t wd = (uint32_t)(bitpos >> 5), sh = (uint32_t)(bitpos & 31);
-        const uint64_t win = (uint64_t)s_slab[wd] | ((uint64_t)s_slab[wd + 1] << 32);
-        return pred + ((win >> sh) & wmask) - eps;
-    };
-
-    if (!RANGE || a.vec) {
-        for (uint32_t g = lane * V; g < jhi; g += 64 * V) {
-            if (RANGE && g + V <= jlo) continue;
-            const uint32_t bits = s_bm[g >> 5];
-            uint32_t t = s_pre[g >> 5] + __popc(bits & (0xFFFFFFFFu >> (31 - (g & 31)))) - 1;
-            uint64_t v[V];
-#pragma unroll
-            for (uint32_t k = 0; k < V; k++) {
-                const uint32_t j = g + k;
-                if (k) t += (bits >> (j & 31)) & 1u;
-                model(t);
-                v[k] = key_at(j);
-            }
-            if (g >= jlo && g + V <= jhi) {
-                u32x4 q;
-                if constexpr (KB == 8) {
-                    q = u32x4{(uint32_t)v[0], (uint32_t)(v[0] >> 32), (uint32_t)v[1], (uint32_t)(v[1] >> 32)};
-                } else {
-                    q = u32x4{(uint32_t)v[0], (uint32_t)v[1], (uint32_t)v[2], (uint32_t)v[3]};
-                }
-                __builtin_nontemporal_store(q, reinterpret_cast<u32x4*>(out) + (obase + g) / V);
-            } else {
-#pragma unroll
-                for (uint32_t k = 0; k < V; k++)
-                    if (g + k >= jlo && g + k < jhi) store_key<KB>(out, obase + g + k, v[k]);
-            }
-        }
-    } else {
-        for (uint32_t j = jlo + lane; j < jhi; j += 64) {
-            const uint32_t bits = s_bm[j >> 5];
-            model(s_pre[j >> 5] + __popc(bits & (0xFFFFFFFFu >> (31 - (j & 31)))) - 1);
-            store_key<KB>(out, obase + j, key_at(j));
-        }
-    }
+    decode_staged<KB, RANGE>(c, s_raw, off_an, off_sl, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -789,7 +944,8 @@ hipError_t launch_decode(const uint8_t* d_blob, const Layout& L, uint64_t begin,
 {
     if (begin >= end) return hipSuccess;
     const uint64_t b_lo = begin >> L.log2b, b_hi = (end - 1) >> L.log2b;
-    const size_t lds = decode_lds_bytes(L.log2b, L.res_stride);
+    const uint32_t raw_cap = decode_raw_cap(L.max_seg_bytes);
+    const size_t lds = decode_lds_bytes(L.log2b, L.res_stride, raw_cap);
     const bool range = !(begin == 0 && end == L.n);
     auto k = L.kb == 4 ? (range ? decode_kernel<4, true> : decode_kernel<4, false>)
                        : (range ? decode_kernel<8, true> : decode_kernel<8, false>);
@@ -806,6 +962,7 @@ hipError_t launch_decode(const uint8_t* d_blob, const Layout& L, uint64_t begin,
         a.nblk = (b_hi + 1 - b0) < kMaxGrid ? (b_hi + 1 - b0) : kMaxGrid;
         a.per_xcd = (a.nblk + 7) / 8;
         a.vec = (begin % (16 / L.kb)) == 0 && (reinterpret_cast<uintptr_t>(d_out) % 16) == 0;
+        a.raw_cap = raw_cap;
         hipLaunchKernelGGL(k, dim3((uint32_t)(a.per_xcd * 8)), dim3(64), lds, stream, d_blob, a, d_out);
     }
     return hipGetLastError();

@@ -11,7 +11,7 @@ namespace lc {
 struct Layout {
     uint64_t n, nblocks;
     uint64_t off_first, off_dir, off_res, res_stride, off_seg;
-    uint32_t kb, log2b, F, w, eps, max_nseg;
+    uint32_t kb, log2b, F, w, eps, max_nseg, max_seg_bytes;
 };
 
 // Per-block result of the fit kernel, read by the scan and emit kernels.
@@ -26,7 +26,7 @@ struct BlockInfo {
 // Per-tile (256 blocks) sums and, after the tile scan, the tile's offset.
 struct TileSum {
     uint64_t bytes, nseg, off;
-    uint32_t max_nseg, pad;
+    uint32_t max_nseg, max_seg_bytes;
 };
 
 // Device workspace of lc_compress, carved from the caller's buffer.

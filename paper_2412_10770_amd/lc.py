@@ -42,7 +42,8 @@ class lc_params(ctypes.Structure):
 
 class lc_blob_info(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint32) for f in
-                ("key_bytes", "log2_block", "frac_bits", "width", "eps", "max_nseg")] + \
+                ("key_bytes", "log2_block", "frac_bits", "width", "eps", "max_nseg", "max_seg_bytes",
+                 "reserved")] + \
                [(f, ctypes.c_uint64) for f in
                 ("n", "nblocks", "nseg_total", "off_first", "off_dir", "off_res", "res_stride",
                  "off_seg", "blob_bytes")]

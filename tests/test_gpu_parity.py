@@ -182,3 +182,34 @@ def test_configs_reduced(lc, wl):
     keys = wl.as_numpy(wl.lognormal_gaps(2_000_000, device="cpu"))
     for eps in (255, 1023):
         check_all(lc, keys, eps, 10, rng, nq=20_000)
+
+
+def _width_combo_lists():
+    """Lists whose 64-key blocks cover all 16 (anchor bytes, slope bytes) pairs."""
+    rng = np.random.default_rng(0)
+    out = []
+    for _ in range(400):
+        F = int(rng.choice([0, 4, 12, 20]))
+        eps = int(rng.choice([0, 1, 7, 255]))
+        scale = int(rng.choice([0, 1, 3, 8, 16, 24, 33, 40]))
+        gaps = rng.integers(0, 2 ** scale + 1, 512).astype(np.uint64)
+        if rng.random() < 0.3:
+            gaps[rng.random(512) < 0.05] = np.uint64(2 ** int(rng.integers(20, 46)))
+        out.append((np.cumsum(gaps).astype(np.uint64), eps, F))
+    out.append((np.arange(0, 64 * 5000, 5000, dtype=np.uint64), 0, 20))
+    out.append((np.concatenate([np.arange(0, 3 * 4100, 4100),
+                                30000 + np.arange(0, 61 * 4100, 4100)]).astype(np.uint64), 0, 20))
+    return out
+
+
+def test_width_combinations(lc):
+    """Decode has a specialised loop per (anchor, slope) byte width; cover all 16."""
+    rng = np.random.default_rng(9)
+    seen = set()
+    for keys, eps, F in _width_combo_lists():
+        blob = oracle.compress(keys, eps, 6, F)
+        h = oracle.header(blob)
+        d = blob[h["off_dir"]:h["off_dir"] + 16 * h["nblocks"]].reshape(-1, 16)
+        seen |= set(zip(d[:, 14].tolist(), d[:, 15].tolist()))
+        check_all(lc, keys, eps, 6, rng, nq=64, frac_bits=F)
+    assert seen == {(a, s) for a in (1, 2, 4, 8) for s in (1, 2, 4, 8)}, sorted(seen)
