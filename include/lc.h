@@ -56,6 +56,7 @@ typedef int32_t lc_status;
 
 #define LC_FLAG_UNSORTED 1u /* compress: keys not non-decreasing; blob is invalid */
 #define LC_FLAG_RANGE 2u    /* access: an index >= n; its output slot is 0 */
+#define LC_FLAG_INTERNAL 4u /* compress: an internal step limit was hit; blob invalid (a bug) */
 
 #define LC_DEFAULT_LOG2_BLOCK 10
 #define LC_DEFAULT_FRAC_BITS 20

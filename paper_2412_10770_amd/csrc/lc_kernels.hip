@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "lc_launch.h"
 
 namespace lc {
@@ -136,175 +138,257 @@ __device__ __forceinline__ uint32_t pow2_floor(uint32_t x) { return 1u << (31 - 
 // Encode
 // ---------------------------------------------------------------------------
 
-// One wave (64 threads) per block.  LDS: keys u64[B], slopes u64[B],
-// starts u16[B], slab u32[res_stride / 4 + 2].
+// DPP row shift / broadcast of a 32-bit value (lanes whose source lies
+// outside the row read 0; callers only use lanes with a valid source).
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v)
+{
+    return (uint64_t)dpp32<CTRL>((uint32_t)v) | ((uint64_t)dpp32<CTRL>((uint32_t)(v >> 32)) << 32);
+}
+
+// Inclusive max / min scans of u64 across the wave with DPP: row_shr 1, 2,
+// 4, 8 inside each row of 16 lanes, then row_bcast 15 and row_bcast 31
+// carry row totals into the rows above.
+template <bool MAX>
+__device__ __forceinline__ uint64_t wave_scan64(uint64_t v)
+{
+    const uint32_t lane = lane_id(), rl = lane & 15;
+    auto op = [](uint64_t a, uint64_t b) { return MAX ? (a > b ? a : b) : (a < b ? a : b); };
+    uint64_t u;
+    u = dpp64<0x111>(v); if (rl >= 1) v = op(v, u);
+    u = dpp64<0x112>(v); if (rl >= 2) v = op(v, u);
+    u = dpp64<0x114>(v); if (rl >= 4) v = op(v, u);
+    u = dpp64<0x118>(v); if (rl >= 8) v = op(v, u);
+    u = dpp64<0x142>(v); if ((lane & 31) >= 16) v = op(v, u);
+    u = dpp64<0x143>(v); if (lane >= 32) v = op(v, u);
+    return v;
+}
+
+// floor(x / d) (and x mod d) for 1 <= d <= 4096 and any u64 x, with
+// inv = recip(d) (relative error far below 2^-33): 32-bit halves, each
+// quotient estimated in FP64 to within 1 and corrected once from its
+// remainder.
+// 1 / d to nearly full FP64 precision: the hardware reciprocal is an
+// approximation, refined by one Newton-Raphson step (squares its error).
+__device__ __forceinline__ double recip(uint32_t d)
+{
+    const double dd = (double)d;
+    const double r0 = __builtin_amdgcn_rcp(dd);
+    return __builtin_fma(r0, __builtin_fma(-dd, r0, 1.0), r0);
+}
+
+__device__ __forceinline__ uint64_t div_small(uint64_t x, uint32_t d, double inv, uint32_t* rem = nullptr)
+{
+    const uint32_t xh = (uint32_t)(x >> 32), xl = (uint32_t)x;
+    const double eh = (double)xh * inv;  // clamped: the estimate may pass 2^32 - 1 by a hair
+    uint32_t qh = (uint32_t)(eh < 4294967295.0 ? eh : 4294967295.0);
+    const int64_t rh0 = (int64_t)xh - (int64_t)qh * d;
+    qh = qh - (rh0 < 0) + (rh0 >= (int64_t)d);  // the estimate is within 1 of the quotient
+    const int64_t rh = (int64_t)xh - (int64_t)qh * d;
+    const uint64_t y = ((uint64_t)rh << 32) | xl;  // < d * 2^32 <= 2^44: exact in FP64
+    const double el = (double)y * inv;
+    uint32_t ql = (uint32_t)(el < 4294967295.0 ? el : 4294967295.0);
+    const int64_t rl0 = (int64_t)y - (int64_t)ql * d;
+    const int32_t c = (rl0 >= (int64_t)d) - (rl0 < 0);
+    ql += c;
+    if (rem) *rem = (uint32_t)(rl0 - (int64_t)c * d);
+    return ((uint64_t)qh << 32) | ql;
+}
+
+// Inclusive max / min scan of u64 inside each row of 16 lanes (DPP row_shr).
+template <bool MAX>
+__device__ __forceinline__ uint64_t row_scan64(uint64_t v)
+{
+    const uint32_t rl = lane_id() & 15;
+    auto op = [](uint64_t a, uint64_t b) { return MAX ? (a > b ? a : b) : (a < b ? a : b); };
+    uint64_t u;
+    u = dpp64<0x111>(v); if (rl >= 1) v = op(v, u);
+    u = dpp64<0x112>(v); if (rl >= 2) v = op(v, u);
+    u = dpp64<0x114>(v); if (rl >= 4) v = op(v, u);
+    u = dpp64<0x118>(v); if (rl >= 8) v = op(v, u);
+    return v;
+}
+
+// Fit step limit per row: a row advances its candidate window by 16 keys or
+// closes a segment every step, so 2 * B + 64 steps always suffice; hitting
+// the limit would mean an internal error, flagged instead of looping on.
+constexpr uint32_t kFlagInternal = 4u;
+
+// Four blocks per wave, one per row of 16 lanes (row r of workgroup w: block
+// 4 w + r).  LDS: the four residual slabs (u32[res_stride / 4 + 2] each);
+// keys are read from global memory (each block's 1024 keys stay in L1/L2
+// while the row works on them).
+//
+// Greedy anchored cone.  For candidate key e of the segment starting at s
+// (d = e - s, D = K[e] - K[s]) the integer slopes A with
+// |K[e] - (K[s] + floor(A d / 2^F))| <= eps form
+//   [ceil((D - eps) 2^F / d), floor(((D + eps + 1) 2^F - 1) / d)].
+// The running intersection is tracked as
+//   P = 1 + (largest non-negative lower end), 0 while there is none,
+//   H = smallest upper end (never negative: keys are sorted),
+// for 16 candidates per step by DPP row scans; the segment ends at the first
+// candidate where the intersection is empty or D + eps + 1 reaches
+// 2^(64 - F).  Stored slope: floor((lo + hi) / 2) clamped to >= 0.  When a
+// segment closes with P = 0 every lower end is negative (all its keys lie
+// within eps of the anchor, which happens only for a block's last segment);
+// only then is lo = -min_e floor((eps - D) 2^F / d) computed, in one more
+// pass over the segment.  Each segment's residual codes (offset by eps) are
+// then OR-ed into the row's LDS slab, LSB first, and its record (start,
+// anchor - first key, A) goes to the workspace.
 template <int KB>
 __global__ __launch_bounds__(64) void fit_pack_kernel(const void* __restrict__ keys, Layout L,
                                                        uint8_t* __restrict__ blob, Workspace ws,
                                                        uint32_t* __restrict__ flags, uint64_t blk0)
 {
+    using KT = typename std::conditional<KB == 4, uint32_t, uint64_t>::type;
     extern __shared__ __align__(16) uint8_t smem[];
     const uint32_t B = 1u << L.log2b;
-    uint64_t* s_keys = reinterpret_cast<uint64_t*>(smem);
-    uint64_t* s_A = s_keys + B;
-    uint16_t* s_start = reinterpret_cast<uint16_t*>(s_A + B);
-    uint32_t* s_slab = reinterpret_cast<uint32_t*>(s_start + B);
     const uint32_t slab_words = (uint32_t)(L.res_stride / 4);
+    const uint32_t slab_pitch = slab_words + 4;  // words; keeps every slab 16-byte aligned
+    const uint32_t lane = threadIdx.x, row = lane >> 4, r = lane & 15;
+    uint32_t* s_slab = reinterpret_cast<uint32_t*>(smem) + row * slab_pitch;
 
-    const uint32_t lane = threadIdx.x;
-    const uint64_t b = blk0 + blockIdx.x;
-    const uint64_t base = b << L.log2b;
-    const uint32_t nb = (uint32_t)((L.n - base) < B ? (L.n - base) : B);
-
-    for (uint32_t j = lane; j < nb; j += 64) s_keys[j] = load_key<KB>(keys, base + j);
-    for (uint32_t i = lane; i < slab_words + 2; i += 64) s_slab[i] = 0;
+    for (uint32_t i = lane; i < 4 * slab_pitch; i += 64) reinterpret_cast<uint32_t*>(smem)[i] = 0;
     __syncthreads();
+
+    const uint64_t b = blk0 + (uint64_t)blockIdx.x * 4 + row;
+    const uint64_t base = b << L.log2b;
+    const uint32_t nb = b < L.nblocks ? (uint32_t)((L.n - base) < B ? (L.n - base) : B) : 0u;
+    const KT* K = reinterpret_cast<const KT*>(keys) + (b < L.nblocks ? base : 0);
 
     // Keys must be non-decreasing, across the block boundary too.
     bool unsorted = false;
-    for (uint32_t j = lane; j < nb; j += 64) {
-        uint64_t prev = j ? s_keys[j - 1] : (b ? load_key<KB>(keys, base - 1) : 0);
-        unsorted |= s_keys[j] < prev;
+    for (uint32_t j = r; j < nb; j += 16) {
+        const KT prev = j ? K[j - 1] : (b ? K[-1] : KT(0));
+        unsorted |= K[j] < prev;
     }
     if (__ballot(unsorted) != 0 && lane == 0) atomicOr(flags, kFlagUnsorted);
 
-    // Greedy anchored cone.  For candidate key e of the segment starting at s
-    // (d = e - s, D = K[e] - K[s]) the integer slopes A with
-    // |K[e] - (K[s] + floor(A d / 2^F))| <= eps form
-    //   [ceil((D - eps) 2^F / d), floor(((D + eps + 1) 2^F - 1) / d)].
-    // The running intersection is tracked as
-    //   P = 1 + (largest non-negative lower end), 0 when there is none,
-    //   M = smallest magnitude of the negative lower ends (lower end = -M),
-    //   H = smallest upper end,
-    // 64 candidates at a time by wave prefix scans; the segment ends at the
-    // first candidate where the intersection is empty or D + eps + 1 reaches
-    // 2^(64 - F).  Stored slope: floor((lo + hi) / 2) clamped to >= 0.
     const uint64_t eps = L.eps;
-    const uint32_t F = L.F;
+    const uint32_t F = L.F, w = L.w;
+    const uint64_t wmask = (1ull << w) - 1;  // w <= 32
     const uint64_t lim = F == 0 ? (~0ull - eps) : ((1ull << (64 - F)) - eps - 1);
-    uint32_t s = 0, nseg = 0;
-    uint64_t maxA = 0;
-    while (s < nb) {
-        const uint64_t anchor = s_keys[s];
-        uint64_t runP = 0, runH = ~0ull, runM = ~0ull;
-        uint64_t Pf, Hf, Mf;
-        uint32_t e0 = s + 1, e_end;
-        for (;;) {
-            if (e0 >= nb) {
-                e_end = nb;
-                Pf = runP; Hf = runH; Mf = runM;
-                break;
-            }
-            const uint32_t e = e0 + lane;
-            const bool valid = e < nb;
-            uint64_t P = 0, H = ~0ull, M = ~0ull;
-            bool capped = false;
-            if (valid) {
-                const uint64_t d = e - s;
-                const uint64_t D = s_keys[e] - anchor;
-                capped = D >= lim;
-                if (!capped) {
-                    if (D >= eps) {
-                        const uint64_t x = (D - eps) << F;
-                        const uint64_t q = x / d;
-                        P = q + (q * d != x) + 1;
-                    } else {
-                        M = ((eps - D) << F) / d;
-                    }
-                    H = (((D + eps + 1) << F) - 1) / d;
-                }
-            }
-            P = wave_incl_max(P);
-            H = wave_incl_min(H);
-            M = wave_incl_min(M);
-            P = P > runP ? P : runP;
-            H = H < runH ? H : runH;
-            M = M < runM ? M : runM;
-            const bool fail = valid && (capped || (P != 0 && P - 1 > H));
-            const uint64_t fm = __ballot(fail);
-            if (fm != 0) {
-                const int f = __ffsll((unsigned long long)fm) - 1;
-                e_end = e0 + f;
-                if (f > 0) {
-                    Pf = __shfl(P, f - 1, 64);
-                    Hf = __shfl(H, f - 1, 64);
-                    Mf = __shfl(M, f - 1, 64);
-                } else {
-                    Pf = runP; Hf = runH; Mf = runM;
-                }
-                break;
-            }
-            const uint32_t last = (nb - 1 - e0) < 63u ? (nb - 1 - e0) : 63u;
-            runP = __shfl(P, last, 64);
-            runH = __shfl(H, last, 64);
-            runM = __shfl(M, last, 64);
-            e0 += 64;
-        }
-        uint64_t A = 0;
-        if (e_end > s + 1) {
-            if (Pf != 0) {
-                const uint64_t lo = Pf - 1;
-                A = lo + (Hf - lo) / 2;
-            } else {
-                A = Hf >= Mf ? (Hf - Mf) / 2 : 0;  // floor((-M + H) / 2), clamped
-            }
-        }
-        if (lane == 0) {
-            s_start[nseg] = (uint16_t)s;
-            s_A[nseg] = A;
-        }
-        maxA = A > maxA ? A : maxA;
-        nseg++;
-        s = e_end;
-    }
-    __syncthreads();
-
-    // Residual codes (offset by eps) packed LSB-first into the LDS slab.
-    const uint32_t w = L.w;
-    if (w != 0) {
-        const uint64_t wmask = (w >= 64) ? ~0ull : ((1ull << w) - 1);
-        const uint32_t pw = pow2_floor(nseg);
-        for (uint32_t j = lane; j < nb; j += 64) {
-            uint32_t t = 0;
-            for (uint32_t step = pw; step; step >>= 1)
-                if (t + step < nseg && s_start[t + step] <= j) t += step;
-            const uint32_t st = s_start[t];
-            const uint64_t pred = s_keys[st] + ((s_A[t] * (uint64_t)(j - st)) >> F);
-            const uint64_t code = (s_keys[j] - pred + eps) & wmask;
-            const uint64_t bitpos = (uint64_t)j * w;
-            const uint32_t wd = (uint32_t)(bitpos >> 5), sh = (uint32_t)(bitpos & 31);
-            const uint64_t v = code << sh;
-            atomicOr(&s_slab[wd], (uint32_t)v);
-            if (sh + w > 32) atomicOr(&s_slab[wd + 1], (uint32_t)(v >> 32));
-        }
-    }
-    __syncthreads();
-
-    uint4* dst = reinterpret_cast<uint4*>(blob + L.off_res + b * L.res_stride);
-    const uint4* src = reinterpret_cast<const uint4*>(s_slab);
-    for (uint32_t c = lane; c < slab_words / 4; c += 64) dst[c] = src[c];
-
-    const uint64_t first = s_keys[0];
-    if (lane == 0) store_key<KB>(blob + L.off_first, b, first);
-
+    const uint64_t first = nb ? (uint64_t)K[0] : 0;
     const uint64_t rec = b << L.log2b;
-    for (uint32_t t = lane; t < nseg; t += 64) {
-        const uint32_t st = s_start[t];
-        ws.seg_start[rec + t] = (uint16_t)st;
-        ws.seg_delta[rec + t] = s_keys[st] - first;
-        ws.seg_A[rec + t] = s_A[t];
+    const uint32_t row_lane0 = row * 16;
+
+    uint32_t s = 0, nseg = 0, e0 = 1;
+    uint64_t anchor = first, runP = 0, runH = ~0ull, maxA = 0;
+    for (uint32_t step = 0; __ballot(s < nb) != 0; step++) {
+        if (step >= 2 * B + 64) {
+            if (lane == 0) atomicOr(flags, kFlagInternal);
+            break;
+        }
+        const bool open = s < nb;
+        const uint32_t e = e0 + r;
+        const bool valid = open && e < nb;
+        uint64_t P = 0, H = ~0ull;
+        bool capped = false;
+        if (valid) {
+            const uint32_t d = e - s;
+            const uint64_t D = (uint64_t)K[e] - anchor;
+            capped = D >= lim;
+            if (!capped) {
+                const double inv = recip(d);
+                if (D >= eps) {
+                    uint32_t rem;
+                    const uint64_t q = div_small((D - eps) << F, d, inv, &rem);
+                    P = q + (rem != 0) + 1;  // 1 + ceil((D - eps) 2^F / d)
+                }
+                H = div_small(((D + eps + 1) << F) - 1, d, inv);
+            }
+        }
+        P = row_scan64<true>(P);
+        H = row_scan64<false>(H);
+        P = P > runP ? P : runP;
+        H = H < runH ? H : runH;
+        const bool fail = valid && (capped || (P != 0 && P - 1 > H));
+        const uint32_t fm = (uint32_t)(__ballot(fail) >> row_lane0) & 0xFFFFu;
+        // f: candidates of this step that join the segment
+        const uint32_t avail = e0 < nb ? (nb - e0 < 16 ? nb - e0 : 16u) : 0u;
+        const uint32_t f = fm ? (uint32_t)__builtin_ctz(fm) : avail;
+        const uint32_t src = row_lane0 + (f ? f - 1 : 0);
+        const uint64_t Pl = __shfl(P, src, 64), Hl = __shfl(H, src, 64);
+        const uint64_t Pf = f ? Pl : runP, Hf = f ? Hl : runH;
+        const bool closes = open && (fm != 0 || e0 + 16 >= nb);
+        if (open && !closes) {
+            runP = Pf;
+            runH = Hf;
+            e0 += 16;
+        }
+        if (closes) {
+            const uint32_t e_end = e0 + f;
+            uint64_t A = 0;
+            if (e_end > s + 1) {
+                if (Pf != 0) {
+                    const uint64_t lo = Pf - 1;
+                    A = lo + (Hf - lo) / 2;
+                } else {
+                    // all lower ends negative: lo = -M, M = min floor((eps - D) 2^F / d)
+                    uint64_t M = ~0ull;
+                    for (uint32_t j = s + 1 + r; j < e_end; j += 16) {
+                        const uint32_t d = j - s;
+                        const uint64_t D = (uint64_t)K[j] - anchor;
+                        const uint64_t m = div_small((eps - D) << F, d, recip(d));
+                        M = m < M ? m : M;
+                    }
+                    for (int o = 8; o > 0; o >>= 1) {
+                        const uint64_t t = __shfl_xor(M, o, 16);
+                        M = t < M ? t : M;
+                    }
+                    A = Hf >= M ? (Hf - M) / 2 : 0;  // floor((-M + H) / 2), clamped
+                }
+            }
+            if (r == 0) {
+                ws.seg_start[rec + nseg] = (uint16_t)s;
+                ws.seg_delta[rec + nseg] = anchor - first;
+                ws.seg_A[rec + nseg] = A;
+            }
+            if (w != 0) {
+                for (uint32_t j = s + r; j < e_end; j += 16) {
+                    const uint64_t pred = anchor + ((A * (uint64_t)(j - s)) >> F);
+                    const uint64_t code = ((uint64_t)K[j] - pred + eps) & wmask;
+                    const uint32_t bitpos = j * w;
+                    const uint32_t wd = bitpos >> 5, sh = bitpos & 31;
+                    const uint64_t v = code << sh;
+                    atomicOr(&s_slab[wd], (uint32_t)v);
+                    if (sh + w > 32) atomicOr(&s_slab[wd + 1], (uint32_t)(v >> 32));
+                }
+            }
+            maxA = A > maxA ? A : maxA;
+            nseg++;
+            s = e_end;
+            e0 = s + 1;
+            runP = 0;
+            runH = ~0ull;
+            if (s < nb) anchor = K[s];
+        }
     }
-    if (lane == 0) {
-        const uint64_t maxd = s_keys[s_start[nseg - 1]] - first;
-        const uint32_t ab = byte_width(maxd), sb = byte_width(maxA);
-        BlockInfo bi;
-        bi.nseg = nseg;
-        bi.seg_bytes = (uint32_t)(a16(2ull * nseg) + a16((uint64_t)ab * nseg) + a16((uint64_t)sb * nseg));
-        bi.nkeys = nb;
-        bi.ab = (uint8_t)ab;
-        bi.sb = (uint8_t)sb;
-        bi.pad = 0;
-        ws.blk[b] = bi;
+    __syncthreads();
+
+    if (nb) {
+        uint4* dst = reinterpret_cast<uint4*>(blob + L.off_res + b * L.res_stride);
+        const uint4* src4 = reinterpret_cast<const uint4*>(s_slab);
+        for (uint32_t c = r; c < slab_words / 4; c += 16) dst[c] = src4[c];
+        if (r == 0) {
+            store_key<KB>(blob + L.off_first, b, first);
+            const uint64_t maxd = ws.seg_delta[rec + nseg - 1];
+            const uint32_t ab = byte_width(maxd), sb = byte_width(maxA);
+            BlockInfo bi;
+            bi.nseg = nseg;
+            bi.seg_bytes = (uint32_t)(a16(2ull * nseg) + a16((uint64_t)ab * nseg) + a16((uint64_t)sb * nseg));
+            bi.nkeys = nb;
+            bi.ab = (uint8_t)ab;
+            bi.sb = (uint8_t)sb;
+            bi.pad = 0;
+            ws.blk[b] = bi;
+        }
     }
 }
 
@@ -905,17 +989,13 @@ inline uint32_t query_grid(uint64_t m)
 hipError_t launch_compress(const void* d_keys, const Layout& L, uint8_t* d_blob, const Workspace& ws,
                            uint64_t* d_blob_bytes, uint32_t* d_flags, hipStream_t stream)
 {
-    const uint64_t B = 1ull << L.log2b;
     if (L.nblocks) {
-        const size_t lds = B * 8 + B * 8 + B * 2 + L.res_stride + 8;
+        const size_t lds = 4 * (L.res_stride + 16);
         auto k = L.kb == 4 ? fit_pack_kernel<4> : fit_pack_kernel<8>;
-        if (lds > 65536) {
-            hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (e != hipSuccess) return e;
-        }
-        for (uint64_t b0 = 0; b0 < L.nblocks; b0 += kMaxGrid) {
-            const uint64_t nb = L.nblocks - b0 < kMaxGrid ? L.nblocks - b0 : kMaxGrid;
-            hipLaunchKernelGGL(k, dim3((uint32_t)nb), dim3(64), lds, stream, d_keys, L, d_blob, ws, d_flags, b0);
+        const uint64_t groups = (L.nblocks + 3) / 4;
+        for (uint64_t g0 = 0; g0 < groups; g0 += kMaxGrid) {
+            const uint64_t ng = groups - g0 < kMaxGrid ? groups - g0 : kMaxGrid;
+            hipLaunchKernelGGL(k, dim3((uint32_t)ng), dim3(64), lds, stream, d_keys, L, d_blob, ws, d_flags, g0 * 4);
         }
         const uint64_t nt = ntiles_of(L.nblocks);
         for (uint64_t t0 = 0; t0 < nt; t0 += kMaxGrid) {

@@ -27,6 +27,7 @@ LC_EFORMAT = -3
 LC_EDEVICE = -4
 LC_FLAG_UNSORTED = 1
 LC_FLAG_RANGE = 2
+LC_FLAG_INTERNAL = 4
 HEADER_BYTES = 128
 DEFAULT_LOG2_BLOCK = 10
 DEFAULT_FRAC_BITS = 20
@@ -200,8 +201,11 @@ def compress(keys: torch.Tensor, eps: int, log2_block: int = DEFAULT_LOG2_BLOCK,
     nbytes = torch.zeros(1, dtype=torch.int64, device=dev)
     flags = torch.zeros(1, dtype=torch.int32, device=dev)
     compress_async(keys, eps, blob, ws, nbytes, flags, log2_block, frac_bits, stream)
-    if int(flags.item()) & LC_FLAG_UNSORTED:
+    fl = int(flags.item())
+    if fl & LC_FLAG_UNSORTED:
         raise LcError(LC_EINVAL, "lc_compress: keys are not sorted (LC_FLAG_UNSORTED)")
+    if fl & LC_FLAG_INTERNAL:
+        raise LcError(LC_EDEVICE, "lc_compress: internal step limit hit (LC_FLAG_INTERNAL)")
     size = int(nbytes.item())
     del ws
     data = blob[:size].clone()
