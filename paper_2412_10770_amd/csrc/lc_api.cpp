@@ -105,11 +105,13 @@ lc_status layout_of(const lc_blob_info* info, lc::Layout* L)
         return LC_EINVAL;
     const uint64_t B = 1ull << info->log2_block;
     if (info->n && (info->max_nseg == 0 || info->max_nseg > B)) return LC_EINVAL;
+    if (info->blob_bytes < L->off_seg) return LC_EINVAL;
     if (info->n && (info->max_seg_bytes < 48 || info->max_seg_bytes > lc::align16(2 * B) + 2 * lc::align16(8 * B) ||
                     info->max_seg_bytes % 16))
         return LC_EINVAL;
     L->max_nseg = info->max_nseg;
     L->max_seg_bytes = info->max_seg_bytes;
+    L->blob_bytes = info->blob_bytes;
     return LC_OK;
 }
 

@@ -566,22 +566,26 @@ struct DecodeArgs {
     uint32_t raw_cap;      // LDS bytes for a staged segment area
 };
 
-// A block's segment area is staged raw in LDS when it fits kSegRawMax bytes
-// (the LDS reserved is the blob's largest area if smaller: a header field).
-// A small cap keeps many waves resident; blocks over it -- sparse stretches
-// where most segments hold two keys -- are decoded segment-parallel from
-// global memory instead.
-#ifndef LC_DECODE_RAW_CAP
-#define LC_DECODE_RAW_CAP 4096
-#endif
-constexpr uint32_t kSegRawMax = LC_DECODE_RAW_CAP;
+// A block's segment area is staged raw in LDS.  The main decode launch
+// reserves at most kSegRawSmall bytes for it (less when the blob's largest
+// area, a header field, is smaller), which keeps ~29 waves resident per CU;
+// it skips the few blocks with larger areas -- sparse stretches where most
+// segments hold two keys.  A second launch, only when such blocks exist,
+// finds them 64 directory entries per wave and decodes them the same way
+// with up to kSegRawMax bytes of LDS; areas beyond that (possible only for
+// 4096-key blocks) are decoded segment-parallel from global memory.
+constexpr uint32_t kSegRawSmall = 4096;
+constexpr uint32_t kSegRawMax = 32768;
+constexpr uint32_t kBigPerWave = 4;
+constexpr uint32_t kTouchGrid = 8192;
+constexpr uint64_t kTouchMinBytes = 1ull << 20;  // below this the touch pass costs more than it saves
 // 16-byte chunks per lane loaded before the first wait (slab, segment area).
 constexpr uint32_t kSlabBatch = 4;
 constexpr uint32_t kSegBatch = 4;
 
-__host__ __device__ constexpr uint32_t decode_raw_cap(uint32_t max_seg_bytes)
+__host__ __device__ constexpr uint32_t decode_raw_cap(uint32_t max_seg_bytes, uint32_t cap)
 {
-    return ((max_seg_bytes < kSegRawMax ? max_seg_bytes : kSegRawMax) + 15) & ~15u;
+    return ((max_seg_bytes < cap ? max_seg_bytes : cap) + 15) & ~15u;
 }
 
 __host__ __device__ constexpr uint64_t decode_lds_bytes(uint32_t log2b, uint64_t res_stride, uint32_t raw_cap)
@@ -751,21 +755,32 @@ __device__ __forceinline__ void decode_segments(const BlockCtx& c, const uint8_t
 //  3. Lane l decodes the groups of V = 16 / KB keys starting at
 //     V * (l + 64 i); each store instruction of the wave writes 1 KB of
 //     contiguous output (non-temporal: the output is not re-read here).
-// Workgroup w runs on XCD w % 8, so blocks are assigned XCD-major: each XCD
-// walks a contiguous run of blocks (and of directory and segment bytes).
-template <int KB, bool RANGE>
-__global__ __launch_bounds__(64) void decode_kernel(const uint8_t* __restrict__ blob, DecodeArgs a,
-                                                     void* __restrict__ out)
+// Streams bytes [lo, hi) of the blob through the caches (wide coalesced
+// reads whose values are discarded), so that the decode that follows finds
+// them in the 256 MB on-die cache: its reads form a dependent chain per
+// block (directory entry -> segment area), so it is bound by memory latency
+// when they come from HBM, while this pass reads at full bandwidth.
+__global__ __launch_bounds__(256) void touch_kernel(const uint8_t* __restrict__ blob, uint64_t lo, uint64_t hi)
 {
-    const uint64_t rel = (uint64_t)(blockIdx.x % 8) * a.per_xcd + blockIdx.x / 8;
-    if (rel >= a.nblk) return;
-    const uint64_t b = a.b_first + rel;
+    const uint4* p = reinterpret_cast<const uint4*>(blob + lo);
+    const uint64_t n = (hi - lo) / 16;
+    uint32_t acc = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+        const uint4 v = p[i];
+        acc ^= v.x ^ v.y ^ v.z ^ v.w;
+    }
+    asm volatile("" ::"v"(acc));  // keeps the loads; no instruction is emitted
+}
+
+template <int KB, bool RANGE>
+__device__ __forceinline__ void decode_block(const uint8_t* __restrict__ blob, const DecodeArgs& a, uint64_t b,
+                                             uint32_t raw_cap, bool skip_big, void* __restrict__ out)
+{
     const Layout& L = a.L;
     const uint32_t lane = threadIdx.x;
     const uint32_t nwords = (1u << L.log2b) >> 5;
     const uint32_t slab_words = (uint32_t)(L.res_stride / 4);
     const uint32_t nch_slab = slab_words / 4;
-    const uint32_t raw_cap = a.raw_cap;
 
     extern __shared__ __align__(16) uint8_t smem[];
     uint8_t* s_raw = smem;                                                 // raw_cap
@@ -791,6 +806,7 @@ __global__ __launch_bounds__(64) void decode_kernel(const uint8_t* __restrict__ 
     const uint32_t off_sl = off_an + (uint32_t)a16((uint64_t)ab * nseg);
     const uint32_t seg_bytes = off_sl + (uint32_t)a16((uint64_t)sb * nseg);
     const bool staged = seg_bytes <= raw_cap;
+    if (skip_big && !staged) return;  // left to the big-block launch
     const uint8_t* g_seg = blob + seg_off;
 
     const uint32_t nch_seg = staged ? seg_bytes / 16 : 0u;
@@ -865,6 +881,46 @@ __global__ __launch_bounds__(64) void decode_kernel(const uint8_t* __restrict__ 
     }
     __syncthreads();
     decode_staged<KB, RANGE>(c, s_raw, off_an, off_sl, out);
+}
+
+// Main launch: one wave per block, blocks with areas over the small cap
+// skipped.  Workgroup w runs on XCD w % 8, so blocks are assigned XCD-major:
+// each XCD walks a contiguous run of blocks (and of directory and segment
+// bytes).
+template <int KB, bool RANGE>
+__global__ __launch_bounds__(64) void decode_kernel(const uint8_t* __restrict__ blob, DecodeArgs a,
+                                                     void* __restrict__ out)
+{
+    const uint64_t rel = (uint64_t)(blockIdx.x % 8) * a.per_xcd + blockIdx.x / 8;
+    if (rel >= a.nblk) return;
+    decode_block<KB, RANGE>(blob, a, a.b_first + rel, a.raw_cap, true, out);
+}
+
+// Big-block launch: wave w checks the directory entries of blocks
+// [4 w, 4 w + 4) of the launch and decodes, one after another, those whose
+// segment area exceeds the main launch's cap (small_cap).  Big blocks sit
+// together (sparse stretches of the key range), so few per wave keeps the
+// launch balanced.
+template <int KB, bool RANGE>
+__global__ __launch_bounds__(64) void decode_big_kernel(const uint8_t* __restrict__ blob, DecodeArgs a,
+                                                         uint32_t small_cap, void* __restrict__ out)
+{
+    const uint64_t rel = (uint64_t)blockIdx.x * kBigPerWave + threadIdx.x;
+    bool big = false;
+    if (threadIdx.x < kBigPerWave && rel < a.nblk) {
+        const uint4 dv = reinterpret_cast<const uint4*>(blob + a.L.off_dir)[a.b_first + rel];
+        const uint32_t nseg = dv.z ? dv.z : 1u;
+        const uint32_t ab = (dv.w >> 16) & 0xFF, sb = dv.w >> 24;
+        const uint64_t bytes = a16(2ull * nseg) + a16((uint64_t)ab * nseg) + a16((uint64_t)sb * nseg);
+        big = bytes > small_cap;
+    }
+    uint64_t m = __ballot(big);
+    while (m) {
+        const uint32_t k = (uint32_t)__ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        decode_block<KB, RANGE>(blob, a, a.b_first + (uint64_t)blockIdx.x * kBigPerWave + k, a.raw_cap, false, out);
+        __syncthreads();  // LDS is reused by the next block
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1024,14 +1080,35 @@ hipError_t launch_decode(const uint8_t* d_blob, const Layout& L, uint64_t begin,
 {
     if (begin >= end) return hipSuccess;
     const uint64_t b_lo = begin >> L.log2b, b_hi = (end - 1) >> L.log2b;
-    const uint32_t raw_cap = decode_raw_cap(L.max_seg_bytes);
-    const size_t lds = decode_lds_bytes(L.log2b, L.res_stride, raw_cap);
+    const uint32_t small_cap = decode_raw_cap(L.max_seg_bytes, kSegRawSmall);
+    const uint32_t big_cap = decode_raw_cap(L.max_seg_bytes, kSegRawMax);
+    const size_t lds_small = decode_lds_bytes(L.log2b, L.res_stride, small_cap);
+    const size_t lds_big = decode_lds_bytes(L.log2b, L.res_stride, big_cap);
     const bool range = !(begin == 0 && end == L.n);
     auto k = L.kb == 4 ? (range ? decode_kernel<4, true> : decode_kernel<4, false>)
                        : (range ? decode_kernel<8, true> : decode_kernel<8, false>);
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
+    auto kb = L.kb == 4 ? (range ? decode_big_kernel<4, true> : decode_big_kernel<4, false>)
+                        : (range ? decode_big_kernel<8, true> : decode_big_kernel<8, false>);
+    hipError_t e;
+    if (lds_small > 65536 &&
+        (e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_small)) != hipSuccess)
+        return e;
+    if (big_cap > small_cap && lds_big > 65536 &&
+        (e = hipFuncSetAttribute((const void*)kb, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_big)) != hipSuccess)
+        return e;
+    // Stage the compressed bytes the decode will read in the on-die cache:
+    // the whole tail of the blob for a full decode; the directory entries and
+    // slabs of the blocks touched for a range (its segment areas are found
+    // only through the directory).
+    if (!range) {
+        hipLaunchKernelGGL(touch_kernel, dim3(kTouchGrid), dim3(256), 0, stream, d_blob, L.off_dir, L.blob_bytes);
+    } else {
+        const uint64_t d_lo = L.off_dir + 16 * b_lo, d_hi = L.off_dir + 16 * (b_hi + 1);
+        const uint64_t r_lo = L.off_res + b_lo * L.res_stride, r_hi = L.off_res + (b_hi + 1) * L.res_stride;
+        if (d_hi - d_lo + r_hi - r_lo >= kTouchMinBytes) {
+            hipLaunchKernelGGL(touch_kernel, dim3(kTouchGrid), dim3(256), 0, stream, d_blob, d_lo, d_hi);
+            hipLaunchKernelGGL(touch_kernel, dim3(kTouchGrid), dim3(256), 0, stream, d_blob, r_lo, r_hi);
+        }
     }
     for (uint64_t b0 = b_lo; b0 <= b_hi; b0 += kMaxGrid) {
         DecodeArgs a;
@@ -1042,8 +1119,13 @@ hipError_t launch_decode(const uint8_t* d_blob, const Layout& L, uint64_t begin,
         a.nblk = (b_hi + 1 - b0) < kMaxGrid ? (b_hi + 1 - b0) : kMaxGrid;
         a.per_xcd = (a.nblk + 7) / 8;
         a.vec = (begin % (16 / L.kb)) == 0 && (reinterpret_cast<uintptr_t>(d_out) % 16) == 0;
-        a.raw_cap = raw_cap;
-        hipLaunchKernelGGL(k, dim3((uint32_t)(a.per_xcd * 8)), dim3(64), lds, stream, d_blob, a, d_out);
+        a.raw_cap = small_cap;
+        hipLaunchKernelGGL(k, dim3((uint32_t)(a.per_xcd * 8)), dim3(64), lds_small, stream, d_blob, a, d_out);
+        if (big_cap > small_cap) {
+            a.raw_cap = big_cap;
+            hipLaunchKernelGGL(kb, dim3((uint32_t)((a.nblk + kBigPerWave - 1) / kBigPerWave)), dim3(64), lds_big,
+                               stream, d_blob, a, small_cap, d_out);
+        }
     }
     return hipGetLastError();
 }

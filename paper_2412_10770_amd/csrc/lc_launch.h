@@ -10,7 +10,7 @@ namespace lc {
 // Byte layout of one blob v1 plus the encoder parameters, as kernel arguments.
 struct Layout {
     uint64_t n, nblocks;
-    uint64_t off_first, off_dir, off_res, res_stride, off_seg;
+    uint64_t off_first, off_dir, off_res, res_stride, off_seg, blob_bytes;
     uint32_t kb, log2b, F, w, eps, max_nseg, max_seg_bytes;
 };
 
