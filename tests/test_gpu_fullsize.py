@@ -1,0 +1,115 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times (blocks of 1024 keys, F = 20).
+
+The oracle cannot encode 1e8 keys in a test's time, so these checks use:
+  * properties that hold at any size -- decode(compress(K)) == K exactly
+    (Def. 1), directory offsets equal to the prefix sums of the per-block
+    segment areas, and the blob size equal to its closed form;
+  * sampled outputs the oracle computes one by one -- a block's bytes depend
+    only on its keys, so the oracle compresses each sampled block on its own
+    and its slab, segment area and directory fields must equal the GPU
+    blob's;
+  * sampled queries against the plain definitions (K[i], K[b:e],
+    searchsorted(K, q, 'left')).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def a16(x):
+    return (x + 15) // 16 * 16
+
+
+def check_fullsize(lc, keys: torch.Tensor, eps: int, n_access: int, n_lb: int, seed: int):
+    n = keys.numel()
+    kb = keys.element_size()
+    _say(f"full-size case n={n} kb={kb} eps={eps}")
+    blob = lc.compress(keys, eps)  # log2_block 10, F 20: the benchmark's configuration
+    h = blob.info
+    B = 1 << h.log2_block
+    assert h.n == n and h.nblocks == (n + B - 1) // B
+
+    out = lc.decompress(blob)
+    assert torch.equal(out, keys), "round trip (Def. 1)"
+    del out
+
+    data = blob.data.cpu().numpy()
+    dirs = data[h.off_dir:h.off_dir + 16 * h.nblocks].reshape(-1, 16)
+    seg_off = dirs[:, 0:8].copy().view(np.uint64).ravel().astype(np.int64)
+    nseg = dirs[:, 8:12].copy().view(np.uint32).ravel().astype(np.int64)
+    nk = dirs[:, 12:14].copy().view(np.uint16).ravel().astype(np.int64) + 1
+    ab = dirs[:, 14].astype(np.int64)
+    sb = dirs[:, 15].astype(np.int64)
+    area = a16(2 * nseg) + a16(ab * nseg) + a16(sb * nseg)
+    assert np.array_equal(seg_off, h.off_seg + np.concatenate([[0], np.cumsum(area)[:-1]]))
+    assert h.blob_bytes == h.off_seg + int(area.sum()) == len(data)
+    assert h.nseg_total == int(nseg.sum()) and h.max_nseg == int(nseg.max())
+    assert h.max_seg_bytes == int(area.max())
+    assert np.all(nk[:-1] == B) and nk[-1] == n - (h.nblocks - 1) * B
+
+    rng = np.random.default_rng(seed)
+    host = keys.cpu().numpy().view(np.uint32 if kb == 4 else np.uint64)
+    picks = set(rng.choice(h.nblocks, size=min(48, h.nblocks), replace=False).tolist())
+    picks |= {0, h.nblocks - 1, int(np.argmax(nseg)), int(np.argmax(area))}
+    for b in sorted(picks):
+        kk = host[b * B:(b + 1) * B]
+        one = oracle.compress(kk, eps, h.log2_block)
+        oh = oracle.header(one)
+        od = one[oh["off_dir"]:oh["off_dir"] + 16]
+        assert np.array_equal(od[8:16], dirs[b, 8:16]), b
+        assert np.array_equal(one[oh["off_res"]:oh["off_res"] + h.res_stride],
+                              data[h.off_res + b * h.res_stride:h.off_res + (b + 1) * h.res_stride]), b
+        assert np.array_equal(one[oh["off_seg"]:oh["blob_bytes"]], data[seg_off[b]:seg_off[b] + area[b]]), b
+        assert int.from_bytes(bytes(data[h.off_first + b * kb:h.off_first + (b + 1) * kb]), "little") == int(kk[0])
+
+    g = torch.Generator(device=DEV)
+    g.manual_seed(seed)
+    idx = torch.randint(0, n, (n_access,), device=DEV, generator=g)
+    assert torch.equal(lc.access(blob, idx), keys[idx])
+    lo, hi = int(host[0]), int(host[-1])
+    q = torch.randint(lo, hi + 2, (n_lb,), device=DEV, generator=g, dtype=torch.int64).to(keys.dtype)
+    want = torch.searchsorted(keys, q, side="left")
+    assert torch.equal(lc.lower_bound(blob, q), want)
+    for _ in range(4):
+        a = int(rng.integers(0, n))
+        e = int(min(n, a + rng.integers(1, 5_000_000)))
+        assert torch.equal(lc.decompress_range(blob, a, e), keys[a:e]), (a, e)
+    assert torch.equal(lc.decompress_range(blob, n // 4, n // 4 + n // 2), keys[n // 4:n // 4 + n // 2])
+    return blob
+
+
+@pytest.fixture(scope="module")
+def lc():
+    from paper_2412_10770_amd import lc as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def wl():
+    from paper_2412_10770_amd import workloads
+    return workloads
+
+
+def test_lognormal_100m(lc, wl):
+    """100M distinct uint64 keys, lognormal(0, 2) scaled to 2^40; eps 15 / 63 / 255."""
+    keys = wl.lognormal_distinct(100_000_000, device=DEV)
+    for eps in (15, 63, 255):
+        check_fullsize(lc, keys, eps, n_access=1_000_000, n_lb=1_000_000, seed=eps)
+
+
+def test_heterogeneous_runs_200m(lc, wl):
+    """200M uint64 keys, alternating dense / Zipf(1.2) runs; eps 63; 10M access, 1M lower_bound."""
+    keys = wl.heterogeneous_runs(200_000_000, device=DEV)
+    check_fullsize(lc, keys, 63, n_access=10_000_000, n_lb=1_000_000, seed=3)
