@@ -57,6 +57,10 @@ typedef int32_t lc_status;
 #define LC_FLAG_UNSORTED 1u /* compress: keys not non-decreasing; blob is invalid */
 #define LC_FLAG_RANGE 2u    /* access: an index >= n; its output slot is 0 */
 #define LC_FLAG_INTERNAL 4u /* compress: an internal step limit was hit; blob invalid (a bug) */
+#define LC_FLAG_BADLIST 8u  /* batch: a list's keys, blob slot or output lie outside the buffers
+                               given, or its eps exceeds the plan's max_eps (the list was skipped),
+                               or a block's directory entry is inconsistent with its layout (the
+                               block was skipped) */
 
 #define LC_DEFAULT_LOG2_BLOCK 10
 #define LC_DEFAULT_FRAC_BITS 20
@@ -142,6 +146,97 @@ lc_status lc_access(const void* d_blob, const lc_blob_info* info, const uint64_t
  * Errors: LC_EINVAL, LC_EDEVICE. */
 lc_status lc_lower_bound(const void* d_blob, const lc_blob_info* info, const void* d_q,
                          uint64_t m, uint64_t* d_pos, void* stream);
+
+/* ---- Batches of lists ----------------------------------------------------
+ * Many sorted lists (e.g. the posting lists of an inverted index, Sec. III-A)
+ * compressed or decompressed together: one launch runs the fit over every
+ * (list, block) work item, so the cost of a step no longer grows with the
+ * number of lists.  Every list gets an ordinary blob v1 in a slot of one
+ * buffer: a list's blob is byte-for-byte what lc_compress gives for it.  All
+ * lists share key_bytes, log2_block and frac_bits; each has its own eps.
+ *
+ * The table of lists lives in device memory for the kernels (d_lists) and is
+ * prepared on the host by lc_batch_plan.  Every list is checked on the device
+ * against the buffers given (key range, blob slot, output range, eps <=
+ * max_eps); a list that fails is skipped and LC_FLAG_BADLIST is OR-ed into
+ * d_stats[0].
+ */
+
+#define LC_BATCH_MAX_CANDIDATES 8
+
+/* One list of a batch (64 bytes). */
+typedef struct lc_batch_list {
+    uint64_t key_off;   /* index of the list's first key in the concatenated keys (compress)
+                           and in the concatenated output (decompress) */
+    uint64_t n;         /* keys in the list (may be 0) */
+    uint64_t blob_off;  /* byte offset of the list's blob slot in the batch buffer (lc_batch_plan) */
+    uint64_t blob_cap;  /* bytes of the slot: the list's lc_compress_bound at max_eps (lc_batch_plan) */
+    uint64_t block_off; /* blocks of all earlier lists (lc_batch_plan) */
+    uint64_t group_off; /* 4-block groups of all earlier lists (lc_batch_plan) */
+    uint32_t eps;       /* the list's error bound, <= max_eps */
+    uint32_t reserved[3];
+} lc_batch_list;
+
+/* Parameters shared by the lists of a batch. */
+typedef struct lc_batch_params {
+    uint8_t key_bytes, log2_block, frac_bits, reserved; /* as lc_params */
+    uint32_t nlists;       /* >= 1 */
+    uint32_t max_eps;      /* the largest eps any list may take; sizes the slots */
+    uint32_t reserved2;
+    uint64_t total_blocks; /* set by lc_batch_plan */
+    uint64_t total_groups; /* set by lc_batch_plan */
+    uint64_t blob_bytes;   /* set by lc_batch_plan: bytes of the batch buffer */
+    uint64_t ws_bytes;     /* set by lc_batch_plan: bytes of the device workspace */
+} lc_batch_params;
+
+/* Host, pure: fill blob_off, blob_cap, block_off and group_off of
+ * h_lists[0 .. p->nlists) (slots packed in list order, each its list's
+ * worst-case size at p->max_eps) and p's totals.  key_off, n and eps are
+ * left as given.  Errors: LC_EINVAL (bad parameters, NULL). */
+lc_status lc_batch_plan(lc_batch_params* p, lc_batch_list* h_lists);
+
+/* Compress every list.  d_keys: nkeys concatenated keys; d_lists: device
+ * copy of the planned table; d_blob: blob_cap bytes (>= p->blob_bytes);
+ * d_ws: p->ws_bytes of workspace; d_sizes: device u64[nlists] receiving each
+ * list's blob size; d_stats: device u32[2] the caller zeroes: [0] flags
+ * (LC_FLAG_*), [1] the largest max_seg_bytes of any list (for
+ * lc_batch_decompress).  Three launches: the fit over all work items, a scan
+ * per list (directory and header), the segment areas.  Asynchronous.
+ * Errors: LC_EINVAL, LC_ENOSPC (blob_cap / ws_bytes), LC_EDEVICE. */
+lc_status lc_batch_compress(const void* d_keys, uint64_t nkeys, const lc_batch_list* d_lists,
+                            const lc_batch_params* p, void* d_blob, uint64_t blob_cap, void* d_ws,
+                            uint64_t ws_bytes, uint64_t* d_sizes, uint32_t* d_stats, void* stream);
+
+/* Size pass of the eps autotuner: the exact blob size every list would have
+ * at each candidate eps, without writing any blob: d_sizes[c * nlists + l]
+ * for candidate h_cands[c] (~0 for a list that does not fit the buffers).
+ * h_cands: ncand (1 .. LC_BATCH_MAX_CANDIDATES) strictly increasing values
+ * <= p->max_eps.  One fit launch over all (candidate, work item) pairs and
+ * one scan launch.  d_sizes: device u64[ncand * nlists]; other buffers as
+ * lc_batch_compress (no blob). */
+lc_status lc_batch_sizes(const void* d_keys, uint64_t nkeys, const lc_batch_list* d_lists,
+                         const lc_batch_params* p, const uint32_t* h_cands, uint32_t ncand, void* d_ws,
+                         uint64_t ws_bytes, uint64_t* d_sizes, uint32_t* d_stats, void* stream);
+
+/* Autotuner step: for every list l set d_lists[l].eps to the candidate
+ * h_cands[c] with the smallest d_sizes[c * nlists + l] (the sizes of
+ * lc_batch_sizes run once per candidate); ties go to the smaller eps.
+ * h_cands: ncand (1 .. LC_BATCH_MAX_CANDIDATES) strictly increasing values
+ * <= p->max_eps.  One launch, no host synchronisation. */
+lc_status lc_batch_pick_eps(lc_batch_list* d_lists, const lc_batch_params* p, const uint64_t* d_sizes,
+                            const uint32_t* h_cands, uint32_t ncand, void* stream);
+
+/* Decompress every list of a batch buffer written by lc_batch_compress with
+ * the same table (a list's eps must be the one its blob was written with):
+ * list l's keys go to d_out + key_off * key_bytes (nout keys in all; d_out
+ * aligned to the key width).  max_seg_bytes: d_stats[1] of that compress; it
+ * sizes the on-chip staging of segment areas (any value decodes correctly,
+ * smaller ones more slowly).  d_stats: device u32 flag word
+ * (LC_FLAG_BADLIST).  Blob contents are trusted as written by the compress.
+ * Errors: LC_EINVAL, LC_EDEVICE. */
+lc_status lc_batch_decompress(const void* d_blob, uint64_t blob_cap, const lc_batch_list* d_lists,
+                              const lc_batch_params* p, uint32_t max_seg_bytes, void* d_out, uint64_t nout,
+                              uint32_t* d_stats, void* stream);
 
 /* Static description of a status code. */
 const char* lc_strerror(lc_status s);

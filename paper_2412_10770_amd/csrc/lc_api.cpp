@@ -115,6 +115,82 @@ lc_status layout_of(const lc_blob_info* info, lc::Layout* L)
     return LC_OK;
 }
 
+constexpr uint64_t kBlockInfoBytes = sizeof(lc::BlockInfo);
+
+lc_status check_batch(const lc_batch_params* p)
+{
+    if (!p || p->nlists == 0 || p->reserved2 != 0) return LC_EINVAL;
+    lc_params q{};
+    q.key_bytes = p->key_bytes;
+    q.log2_block = p->log2_block;
+    q.frac_bits = p->frac_bits;
+    q.reserved = p->reserved;
+    q.eps = p->max_eps;
+    return check_params(&q);
+}
+
+// Batch workspace: block infos for up to LC_BATCH_MAX_CANDIDATES size passes,
+// then the segment records of every block (start, anchor delta, slope).
+struct BatchWs {
+    uint64_t blk, start, delta, slope, total;
+};
+
+BatchWs plan_batch_ws(uint64_t total_blocks, uint32_t log2b)
+{
+    const uint64_t recs = total_blocks << log2b;
+    BatchWs w;
+    w.blk = 0;
+    w.start = lc::align16(LC_BATCH_MAX_CANDIDATES * total_blocks * kBlockInfoBytes);
+    w.delta = w.start + lc::align16(recs * 2);
+    w.slope = w.delta + recs * 8;
+    w.total = w.slope + recs * 8;
+    if (w.total == 0) w.total = 16;
+    return w;
+}
+
+lc::BatchArgs batch_args(const lc_batch_params* p, uint64_t nkeys, uint64_t blob_cap)
+{
+    lc::BatchArgs a{};
+    a.kb = p->key_bytes;
+    a.log2b = p->log2_block;
+    a.F = p->frac_bits;
+    a.nlists = p->nlists;
+    a.max_eps = p->max_eps;
+    a.total_blocks = p->total_blocks;
+    a.total_groups = p->total_groups;
+    a.nkeys = nkeys;
+    a.blob_cap = blob_cap;
+    return a;
+}
+
+bool misaligned(const void* ptr, uintptr_t a) { return (reinterpret_cast<uintptr_t>(ptr) & (a - 1)) != 0; }
+
+// Shared checks of lc_batch_compress / lc_batch_sizes.
+lc_status check_batch_fit(const void* d_keys, const lc_batch_list* d_lists, const lc_batch_params* p, void* d_ws,
+                          uint64_t ws_bytes, uint64_t* d_sizes, uint32_t* d_stats, lc::Workspace* W)
+{
+    lc_status st = check_batch(p);
+    if (st != LC_OK) return st;
+    if (p->total_blocks > (kMaxKeys >> p->log2_block) * p->nlists || p->total_groups > p->total_blocks)
+        return LC_EINVAL;
+    if (!d_lists || !d_stats || misaligned(d_lists, 8) || misaligned(d_stats, 4) ||
+        (d_sizes && misaligned(d_sizes, 8)))
+        return LC_EINVAL;
+    if (p->total_blocks && (!d_keys || !d_ws || misaligned(d_keys, p->key_bytes) || misaligned(d_ws, 16)))
+        return LC_EINVAL;
+    const BatchWs w = plan_batch_ws(p->total_blocks, p->log2_block);
+    if (p->total_blocks && ws_bytes < w.total) return LC_ENOSPC;
+    uint8_t* ws = static_cast<uint8_t*>(d_ws);
+    *W = lc::Workspace{};
+    if (p->total_blocks) {
+        W->blk = reinterpret_cast<lc::BlockInfo*>(ws + w.blk);
+        W->seg_start = reinterpret_cast<uint16_t*>(ws + w.start);
+        W->seg_delta = reinterpret_cast<uint64_t*>(ws + w.delta);
+        W->seg_A = reinterpret_cast<uint64_t*>(ws + w.slope);
+    }
+    return LC_OK;
+}
+
 }  // namespace
 
 LC_API lc_status lc_compress_bound(uint64_t n, const lc_params* p, uint64_t* blob_max, uint64_t* ws_bytes)
@@ -191,7 +267,7 @@ LC_API lc_status lc_decompress(const void* d_blob, const lc_blob_info* info, voi
     lc::Layout L;
     if (!d_blob || layout_of(info, &L) != LC_OK) return LC_EINVAL;
     if (L.n == 0) return LC_OK;
-    if (!d_out || (reinterpret_cast<uintptr_t>(d_out) & 15)) return LC_EINVAL;
+    if (!d_out || (reinterpret_cast<uintptr_t>(d_out) & (L.kb - 1))) return LC_EINVAL;
     hipError_t e = lc::launch_decode(static_cast<const uint8_t*>(d_blob), L, 0, L.n, d_out,
                                      static_cast<hipStream_t>(stream));
     return e == hipSuccess ? LC_OK : LC_EDEVICE;
@@ -235,6 +311,105 @@ LC_API lc_status lc_lower_bound(const void* d_blob, const lc_blob_info* info, co
         return LC_EINVAL;
     hipError_t e = lc::launch_lower_bound(static_cast<const uint8_t*>(d_blob), L, d_q, m, d_pos,
                                           static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LC_OK : LC_EDEVICE;
+}
+
+LC_API lc_status lc_batch_plan(lc_batch_params* p, lc_batch_list* h_lists)
+{
+    lc_status st = check_batch(p);
+    if (st != LC_OK) return st;
+    if (!h_lists) return LC_EINVAL;
+    lc_params q{};
+    q.key_bytes = p->key_bytes;
+    q.log2_block = p->log2_block;
+    q.frac_bits = p->frac_bits;
+    q.eps = p->max_eps;
+    uint64_t blob = 0, blocks = 0, groups = 0;
+    for (uint32_t l = 0; l < p->nlists; l++) {
+        lc_batch_list& li = h_lists[l];
+        if (li.n > kMaxKeys) return LC_EINVAL;
+        const lc::Layout L = fixed_layout(li.n, &q);
+        const uint64_t cap = worst_blob(L);
+        li.blob_off = blob;
+        li.blob_cap = cap;
+        li.block_off = blocks;
+        li.group_off = groups;
+        blob += cap;
+        blocks += L.nblocks;
+        groups += (L.nblocks + 3) / 4;
+        if (blob >> 62) return LC_EINVAL;
+    }
+    p->total_blocks = blocks;
+    p->total_groups = groups;
+    p->blob_bytes = blob;
+    p->ws_bytes = plan_batch_ws(blocks, p->log2_block).total;
+    return LC_OK;
+}
+
+LC_API lc_status lc_batch_compress(const void* d_keys, uint64_t nkeys, const lc_batch_list* d_lists,
+                                   const lc_batch_params* p, void* d_blob, uint64_t blob_cap, void* d_ws,
+                                   uint64_t ws_bytes, uint64_t* d_sizes, uint32_t* d_stats, void* stream)
+{
+    lc::Workspace W;
+    lc_status st = check_batch_fit(d_keys, d_lists, p, d_ws, ws_bytes, d_sizes, d_stats, &W);
+    if (st != LC_OK) return st;
+    if (!d_blob || misaligned(d_blob, 16)) return LC_EINVAL;
+    if (blob_cap < p->blob_bytes) return LC_ENOSPC;
+    const lc::BatchArgs a = batch_args(p, nkeys, blob_cap);
+    hipError_t e = lc::launch_batch_compress(d_keys, d_lists, a, nullptr, 0, static_cast<uint8_t*>(d_blob), W, d_sizes,
+                                             d_stats, false, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LC_OK : LC_EDEVICE;
+}
+
+static lc_status check_cands(const lc_batch_params* p, const uint32_t* h_cands, uint32_t ncand)
+{
+    if (!h_cands || ncand == 0 || ncand > LC_BATCH_MAX_CANDIDATES) return LC_EINVAL;
+    for (uint32_t k = 0; k < ncand; k++) {
+        if (h_cands[k] > p->max_eps) return LC_EINVAL;
+        if (k && h_cands[k] <= h_cands[k - 1]) return LC_EINVAL;
+    }
+    return LC_OK;
+}
+
+LC_API lc_status lc_batch_sizes(const void* d_keys, uint64_t nkeys, const lc_batch_list* d_lists,
+                                const lc_batch_params* p, const uint32_t* h_cands, uint32_t ncand, void* d_ws,
+                                uint64_t ws_bytes, uint64_t* d_sizes, uint32_t* d_stats, void* stream)
+{
+    lc::Workspace W;
+    lc_status st = check_batch_fit(d_keys, d_lists, p, d_ws, ws_bytes, d_sizes, d_stats, &W);
+    if (st != LC_OK) return st;
+    if (!d_sizes || (st = check_cands(p, h_cands, ncand)) != LC_OK) return LC_EINVAL;
+    const lc::BatchArgs a = batch_args(p, nkeys, ~0ull);
+    hipError_t e = lc::launch_batch_compress(d_keys, d_lists, a, h_cands, ncand, nullptr, W, d_sizes, d_stats, true,
+                                             static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LC_OK : LC_EDEVICE;
+}
+
+LC_API lc_status lc_batch_pick_eps(lc_batch_list* d_lists, const lc_batch_params* p, const uint64_t* d_sizes,
+                                   const uint32_t* h_cands, uint32_t ncand, void* stream)
+{
+    lc_status st = check_batch(p);
+    if (st != LC_OK) return st;
+    if (!d_lists || !d_sizes || misaligned(d_lists, 8) || misaligned(d_sizes, 8)) return LC_EINVAL;
+    if ((st = check_cands(p, h_cands, ncand)) != LC_OK) return st;
+    hipError_t e = lc::launch_batch_pick(d_lists, p->nlists, d_sizes, h_cands, ncand, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LC_OK : LC_EDEVICE;
+}
+
+LC_API lc_status lc_batch_decompress(const void* d_blob, uint64_t blob_cap, const lc_batch_list* d_lists,
+                                     const lc_batch_params* p, uint32_t max_seg_bytes, void* d_out, uint64_t nout,
+                                     uint32_t* d_stats, void* stream)
+{
+    lc_status st = check_batch(p);
+    if (st != LC_OK) return st;
+    if (p->total_blocks > (kMaxKeys >> p->log2_block) * p->nlists || p->total_groups > p->total_blocks)
+        return LC_EINVAL;
+    if (!d_lists || !d_stats || misaligned(d_lists, 8) || misaligned(d_stats, 4)) return LC_EINVAL;
+    if (p->total_blocks == 0) return LC_OK;
+    if (!d_blob || !d_out || misaligned(d_blob, 16) || misaligned(d_out, p->key_bytes)) return LC_EINVAL;
+    const lc::BatchArgs a = batch_args(p, nout, blob_cap);
+    hipError_t e = lc::launch_batch_decode(static_cast<const uint8_t*>(d_blob), d_lists, a, max_seg_bytes, d_out,
+                                           d_stats, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? LC_OK : LC_EDEVICE;
 }
 

@@ -28,6 +28,7 @@ constexpr uint32_t kMagic = 0x3142434Cu;  // "LCB1"
 constexpr uint32_t kVersion = 1;
 constexpr uint32_t kFlagUnsorted = 1u;
 constexpr uint32_t kFlagRange = 2u;
+constexpr uint32_t kFlagBadList = 8u;  // batch: a list outside the buffers, or a corrupt directory entry
 constexpr uint64_t kMaxGrid = 1ull << 22;  // workgroups per launch; larger jobs loop
 
 __device__ __forceinline__ uint64_t a16(uint64_t x) { return (x + 15) & ~uint64_t(15); }
@@ -241,10 +242,13 @@ constexpr uint32_t kFlagInternal = 4u;
 // pass over the segment.  Each segment's residual codes (offset by eps) are
 // then OR-ed into the row's LDS slab, LSB first, and its record (start,
 // anchor - first key, A) goes to the workspace.
-template <int KB>
-__global__ __launch_bounds__(64) void fit_pack_kernel(const void* __restrict__ keys, Layout L,
-                                                       uint8_t* __restrict__ blob, Workspace ws,
-                                                       uint32_t* __restrict__ flags, uint64_t blk0)
+// Fits blocks blk0 .. blk0 + 3 of one list (layout L; keys, blob and
+// workspace pointers already offset to the list).  SIZES: only the per-block
+// segment counts and widths are produced (BlockInfo), nothing else is
+// written -- the autotuner's size pass.
+template <int KB, bool SIZES>
+__device__ __forceinline__ void fit_rows(const void* __restrict__ keys, const Layout& L, uint8_t* __restrict__ blob,
+                                         const Workspace& ws, uint32_t* __restrict__ flags, uint64_t blk0)
 {
     using KT = typename std::conditional<KB == 4, uint32_t, uint64_t>::type;
     extern __shared__ __align__(16) uint8_t smem[];
@@ -257,7 +261,7 @@ __global__ __launch_bounds__(64) void fit_pack_kernel(const void* __restrict__ k
     for (uint32_t i = lane; i < 4 * slab_pitch; i += 64) reinterpret_cast<uint32_t*>(smem)[i] = 0;
     __syncthreads();
 
-    const uint64_t b = blk0 + (uint64_t)blockIdx.x * 4 + row;
+    const uint64_t b = blk0 + row;
     const uint64_t base = b << L.log2b;
     const uint32_t nb = b < L.nblocks ? (uint32_t)((L.n - base) < B ? (L.n - base) : B) : 0u;
     const KT* K = reinterpret_cast<const KT*>(keys) + (b < L.nblocks ? base : 0);
@@ -279,7 +283,7 @@ __global__ __launch_bounds__(64) void fit_pack_kernel(const void* __restrict__ k
     const uint32_t row_lane0 = row * 16;
 
     uint32_t s = 0, nseg = 0, e0 = 1;
-    uint64_t anchor = first, runP = 0, runH = ~0ull, maxA = 0;
+    uint64_t anchor = first, runP = 0, runH = ~0ull, maxA = 0, maxd = 0;
     for (uint32_t step = 0; __ballot(s < nb) != 0; step++) {
         if (step >= 2 * B + 64) {
             if (lane == 0) atomicOr(flags, kFlagInternal);
@@ -345,12 +349,12 @@ __global__ __launch_bounds__(64) void fit_pack_kernel(const void* __restrict__ k
                     A = Hf >= M ? (Hf - M) / 2 : 0;  // floor((-M + H) / 2), clamped
                 }
             }
-            if (r == 0) {
+            if (!SIZES && r == 0) {
                 ws.seg_start[rec + nseg] = (uint16_t)s;
                 ws.seg_delta[rec + nseg] = anchor - first;
                 ws.seg_A[rec + nseg] = A;
             }
-            if (w != 0) {
+            if (!SIZES && w != 0) {
                 for (uint32_t j = s + r; j < e_end; j += 16) {
                     const uint64_t pred = anchor + ((A * (uint64_t)(j - s)) >> F);
                     const uint64_t code = ((uint64_t)K[j] - pred + eps) & wmask;
@@ -362,6 +366,7 @@ __global__ __launch_bounds__(64) void fit_pack_kernel(const void* __restrict__ k
                 }
             }
             maxA = A > maxA ? A : maxA;
+            maxd = anchor - first;
             nseg++;
             s = e_end;
             e0 = s + 1;
@@ -373,13 +378,14 @@ __global__ __launch_bounds__(64) void fit_pack_kernel(const void* __restrict__ k
     __syncthreads();
 
     if (nb) {
-        uint4* dst = reinterpret_cast<uint4*>(blob + L.off_res + b * L.res_stride);
-        const uint4* src4 = reinterpret_cast<const uint4*>(s_slab);
-        for (uint32_t c = r; c < slab_words / 4; c += 16) dst[c] = src4[c];
+        if (!SIZES) {
+            uint4* dst = reinterpret_cast<uint4*>(blob + L.off_res + b * L.res_stride);
+            const uint4* src4 = reinterpret_cast<const uint4*>(s_slab);
+            for (uint32_t c = r; c < slab_words / 4; c += 16) dst[c] = src4[c];
+        }
         if (r == 0) {
-            store_key<KB>(blob + L.off_first, b, first);
-            const uint64_t maxd = ws.seg_delta[rec + nseg - 1];
-            const uint32_t ab = byte_width(maxd), sb = byte_width(maxA);
+            if (!SIZES) store_key<KB>(blob + L.off_first, b, first);
+            const uint32_t ab = byte_width(maxd), sb = byte_width(maxA);  // anchors grow with t
             BlockInfo bi;
             bi.nseg = nseg;
             bi.seg_bytes = (uint32_t)(a16(2ull * nseg) + a16((uint64_t)ab * nseg) + a16((uint64_t)sb * nseg));
@@ -390,6 +396,14 @@ __global__ __launch_bounds__(64) void fit_pack_kernel(const void* __restrict__ k
             ws.blk[b] = bi;
         }
     }
+}
+
+template <int KB>
+__global__ __launch_bounds__(64) void fit_pack_kernel(const void* __restrict__ keys, Layout L,
+                                                       uint8_t* __restrict__ blob, Workspace ws,
+                                                       uint32_t* __restrict__ flags, uint64_t blk0)
+{
+    fit_rows<KB, false>(keys, L, blob, ws, flags, blk0 + (uint64_t)blockIdx.x * 4);
 }
 
 // Sums over tiles of kTileBlocks blocks.
@@ -430,6 +444,30 @@ __global__ __launch_bounds__(256) void tile_reduce_kernel(Workspace ws, uint64_t
     }
 }
 
+// The 128-byte header of blob v1 (one thread).
+__device__ __forceinline__ void write_header(uint8_t* __restrict__ blob, const Layout& L, uint64_t nseg_total,
+                                             uint64_t max_nseg, uint64_t max_area, uint64_t blob_bytes)
+{
+    uint32_t h[32];
+    for (int k = 0; k < 32; k++) h[k] = 0;
+    h[0] = kMagic;
+    h[1] = kVersion | (L.kb << 16) | (L.log2b << 24);
+    h[2] = L.F | (L.w << 8);
+    h[3] = L.eps;
+    h[4] = (uint32_t)L.n;            h[5] = (uint32_t)(L.n >> 32);
+    h[6] = (uint32_t)L.nblocks;      h[7] = (uint32_t)(L.nblocks >> 32);
+    h[8] = (uint32_t)nseg_total;     h[9] = (uint32_t)(nseg_total >> 32);
+    h[10] = (uint32_t)max_nseg;      h[11] = (uint32_t)max_area;
+    h[12] = (uint32_t)L.off_first;   h[13] = (uint32_t)(L.off_first >> 32);
+    h[14] = (uint32_t)L.off_dir;     h[15] = (uint32_t)(L.off_dir >> 32);
+    h[16] = (uint32_t)L.off_res;     h[17] = (uint32_t)(L.off_res >> 32);
+    h[18] = (uint32_t)L.res_stride;  h[19] = (uint32_t)(L.res_stride >> 32);
+    h[20] = (uint32_t)L.off_seg;     h[21] = (uint32_t)(L.off_seg >> 32);
+    h[22] = (uint32_t)blob_bytes;    h[23] = (uint32_t)(blob_bytes >> 32);
+    uint4* hd = reinterpret_cast<uint4*>(blob);
+    for (int k = 0; k < 8; k++) hd[k] = make_uint4(h[4 * k], h[4 * k + 1], h[4 * k + 2], h[4 * k + 3]);
+}
+
 // One workgroup: exclusive scan of tile bytes, totals, header, blob size,
 // zero padding after first_keys.
 __global__ __launch_bounds__(1024) void tile_scan_kernel(Workspace ws, Layout L, uint8_t* __restrict__ blob,
@@ -468,24 +506,7 @@ __global__ __launch_bounds__(1024) void tile_scan_kernel(Workspace ws, Layout L,
     }
     const uint64_t blob_bytes = L.off_seg + carry;
     if (threadIdx.x == 0) {
-        uint32_t h[32];
-        for (int k = 0; k < 32; k++) h[k] = 0;
-        h[0] = kMagic;
-        h[1] = kVersion | (L.kb << 16) | (L.log2b << 24);
-        h[2] = L.F | (L.w << 8);
-        h[3] = L.eps;
-        h[4] = (uint32_t)L.n;            h[5] = (uint32_t)(L.n >> 32);
-        h[6] = (uint32_t)L.nblocks;      h[7] = (uint32_t)(L.nblocks >> 32);
-        h[8] = (uint32_t)nseg_total;     h[9] = (uint32_t)(nseg_total >> 32);
-        h[10] = (uint32_t)max_nseg;      h[11] = (uint32_t)max_area;
-        h[12] = (uint32_t)L.off_first;   h[13] = (uint32_t)(L.off_first >> 32);
-        h[14] = (uint32_t)L.off_dir;     h[15] = (uint32_t)(L.off_dir >> 32);
-        h[16] = (uint32_t)L.off_res;     h[17] = (uint32_t)(L.off_res >> 32);
-        h[18] = (uint32_t)L.res_stride;  h[19] = (uint32_t)(L.res_stride >> 32);
-        h[20] = (uint32_t)L.off_seg;     h[21] = (uint32_t)(L.off_seg >> 32);
-        h[22] = (uint32_t)blob_bytes;    h[23] = (uint32_t)(blob_bytes >> 32);
-        uint4* hd = reinterpret_cast<uint4*>(blob);
-        for (int k = 0; k < 8; k++) hd[k] = make_uint4(h[4 * k], h[4 * k + 1], h[4 * k + 2], h[4 * k + 3]);
+        write_header(blob, L, nseg_total, max_nseg, max_area, blob_bytes);
         if (d_blob_bytes) *d_blob_bytes = blob_bytes;
     }
     // zero the pad between first_keys and the directory
@@ -529,12 +550,27 @@ __device__ __forceinline__ uint4 pack_chunk(const T* vals, uint32_t n, uint32_t 
     return make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
 }
 
-// Segment areas: one wave per block, four blocks per workgroup.
-__global__ __launch_bounds__(256) void seg_emit_kernel(Workspace ws, Layout L, uint8_t* __restrict__ blob,
-                                                       uint64_t blk0)
+// Is directory entry dv of block b consistent with layout L and a blob of
+// `bytes` bytes?  Key count as the layout says, 1 <= nseg <= keys, byte
+// widths in {1, 2, 4, 8}, the segment area 16-byte aligned inside
+// [off_seg, bytes).  Decoders check it before following the offset.
+__device__ __forceinline__ bool dir_ok(const uint4& dv, const Layout& L, uint64_t b, uint64_t bytes)
 {
-    const uint64_t b = blk0 + (uint64_t)blockIdx.x * 4 + threadIdx.x / 64;
-    if (b >= L.nblocks) return;
+    const uint64_t seg_off = dv.x | ((uint64_t)dv.y << 32);
+    const uint64_t left = L.n - (b << L.log2b);
+    const uint32_t want = left < (1ull << L.log2b) ? (uint32_t)left : (1u << L.log2b);
+    const uint32_t nseg = dv.z, nkeys = (dv.w & 0xFFFF) + 1;
+    const uint32_t ab = (dv.w >> 16) & 0xFF, sb = dv.w >> 24;
+    const bool widths = ab && sb && ab <= 8 && sb <= 8 && !(ab & (ab - 1)) && !(sb & (sb - 1));
+    const uint64_t area = a16(2ull * nseg) + a16((uint64_t)ab * nseg) + a16((uint64_t)sb * nseg);
+    return nkeys == want && nseg >= 1 && nseg <= nkeys && widths && (seg_off & 15) == 0 && seg_off >= L.off_seg &&
+           seg_off <= bytes && area <= bytes - seg_off;
+}
+
+// Segment area of block b (one wave): the records in the workspace packed at
+// the block's widths into 16-byte chunks at the directory's offset.
+__device__ __forceinline__ void emit_block(const Workspace& ws, const Layout& L, uint8_t* __restrict__ blob, uint64_t b)
+{
     const uint32_t lane = lane_id();
     const uint4 dv = reinterpret_cast<const uint4*>(blob + L.off_dir)[b];
     const uint64_t seg_off = dv.x | ((uint64_t)dv.y << 32);
@@ -552,6 +588,15 @@ __global__ __launch_bounds__(256) void seg_emit_kernel(Workspace ws, Layout L, u
     for (uint32_t c = lane; c < c_slope; c += 64) out[c] = pack_chunk(ws.seg_A + rec, n, c, sb);
 }
 
+// Segment areas: one wave per block, four blocks per workgroup.
+__global__ __launch_bounds__(256) void seg_emit_kernel(Workspace ws, Layout L, uint8_t* __restrict__ blob,
+                                                       uint64_t blk0)
+{
+    const uint64_t b = blk0 + (uint64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    if (b >= L.nblocks) return;
+    emit_block(ws, L, blob, b);
+}
+
 // ---------------------------------------------------------------------------
 // Decode
 // ---------------------------------------------------------------------------
@@ -562,8 +607,9 @@ struct DecodeArgs {
     uint64_t b_first;      // first block of this launch
     uint64_t nblk;         // blocks in this launch
     uint64_t per_xcd;      // ceil(grid / 8): consecutive blocks handled by one XCD
-    uint32_t vec;          // 1: outputs of key groups of 16 bytes are 16-byte aligned
     uint32_t raw_cap;      // LDS bytes for a staged segment area
+    uint64_t bytes;        // bytes of the blob (or of its slot): directory offsets must stay inside
+    uint32_t* flags;       // where a corrupt directory entry is reported (may be null)
 };
 
 // A block's segment area is staged raw in LDS.  The main decode launch
@@ -609,7 +655,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // Per-block decode context.
 struct BlockCtx {
     uint64_t first, eps, obase;
-    uint32_t F, w, ab, sb, jlo, jhi, vec;
+    uint32_t F, w, ab, sb, jlo, jhi;
     const uint32_t* s_slab;
     const uint32_t* s_bm;
     const uint32_t* s_pre;
@@ -664,34 +710,38 @@ __device__ __forceinline__ void decode_keys(const BlockCtx& c, P16 start, P8 an,
         return c.s_pre[j >> 5] + __popc(bits & (0xFFFFFFFFu >> (31 - (j & 31)))) - 1;
     };
 
-    if (!RANGE || c.vec) {
-        for (uint32_t g = lane * V; g < c.jhi; g += 64 * V) {
-            if (RANGE && g + V <= c.jlo) continue;
-            const uint32_t bits = c.s_bm[g >> 5];
-            uint32_t t = seg_of(g);
-            uint64_t v[V];
+    // Groups of V keys whose output lands on a 16-byte boundary start at
+    // j = j0 (mod V); keys [0, j0) of the block are stored one by one.  A
+    // group may straddle two bitmap words when j0 != 0, hence the 64-bit
+    // window of the bitmap.
+    const uint32_t j0 = (uint32_t)(0 - (reinterpret_cast<uintptr_t>(out) / KB + c.obase)) & (V - 1);
+    if (lane < j0 && lane >= c.jlo && lane < c.jhi) store_key<KB>(out, c.obase + lane, key_at(lane, seg_of(lane)));
+    for (uint32_t g = j0 + lane * V; g < c.jhi; g += 64 * V) {
+        if (RANGE && g + V <= c.jlo) continue;
+        const uint32_t wb = g >> 5;
+        const uint64_t bits = (uint64_t)c.s_bm[wb] | ((uint64_t)c.s_bm[wb + 1] << 32);
+        uint32_t t = c.s_pre[wb] + __popc((uint32_t)bits & (0xFFFFFFFFu >> (31 - (g & 31)))) - 1;
+        uint64_t v[V];
 #pragma unroll
-            for (uint32_t k = 0; k < V; k++) {
-                const uint32_t j = g + k;
-                if (k) t += (bits >> (j & 31)) & 1u;
-                v[k] = key_at(j, t);
-            }
-            if (g >= c.jlo && g + V <= c.jhi) {
-                u32x4 q;
-                if constexpr (KB == 8) {
-                    q = u32x4{(uint32_t)v[0], (uint32_t)(v[0] >> 32), (uint32_t)v[1], (uint32_t)(v[1] >> 32)};
-                } else {
-                    q = u32x4{(uint32_t)v[0], (uint32_t)v[1], (uint32_t)v[2], (uint32_t)v[3]};
-                }
-                __builtin_nontemporal_store(q, reinterpret_cast<u32x4*>(out) + (c.obase + g) / V);
-            } else {
-#pragma unroll
-                for (uint32_t k = 0; k < V; k++)
-                    if (g + k >= c.jlo && g + k < c.jhi) store_key<KB>(out, c.obase + g + k, v[k]);
-            }
+        for (uint32_t k = 0; k < V; k++) {
+            const uint32_t j = g + k;
+            if (k) t += (uint32_t)(bits >> (j - (wb << 5))) & 1u;
+            v[k] = key_at(j, t);
         }
-    } else {
-        for (uint32_t j = c.jlo + lane; j < c.jhi; j += 64) store_key<KB>(out, c.obase + j, key_at(j, seg_of(j)));
+        if (g >= c.jlo && g + V <= c.jhi) {
+            u32x4 q;
+            if constexpr (KB == 8) {
+                q = u32x4{(uint32_t)v[0], (uint32_t)(v[0] >> 32), (uint32_t)v[1], (uint32_t)(v[1] >> 32)};
+            } else {
+                q = u32x4{(uint32_t)v[0], (uint32_t)v[1], (uint32_t)v[2], (uint32_t)v[3]};
+            }
+            __builtin_nontemporal_store(q, reinterpret_cast<u32x4*>(reinterpret_cast<uint8_t*>(out) +
+                                                                     (c.obase + g) * KB));
+        } else {
+#pragma unroll
+            for (uint32_t k = 0; k < V; k++)
+                if (g + k >= c.jlo && g + k < c.jhi) store_key<KB>(out, c.obase + g + k, v[k]);
+        }
     }
 }
 
@@ -743,18 +793,6 @@ __device__ __forceinline__ void decode_segments(const BlockCtx& c, const uint8_t
     }
 }
 
-// One wave per block.
-//  1. Coalesced 16-byte loads of the residual slab (its address needs only
-//     b) and of the raw segment area (once the directory entry is in), all
-//     unconditional with clamped chunk indices -- every load stays inside
-//     the blob; a slab of width 0 reads the first chunk of the segment areas
-//     -- so all are in flight before the first wait; they land in LDS.
-//  2. The segment starts become an LDS bitmap with per-word prefix
-//     popcounts, so the segment of key j is found in O(1):
-//       t = prefix[j / 32] + popcount(bits[j / 32] & mask(j % 32)) - 1.
-//  3. Lane l decodes the groups of V = 16 / KB keys starting at
-//     V * (l + 64 i); each store instruction of the wave writes 1 KB of
-//     contiguous output (non-temporal: the output is not re-read here).
 // Streams bytes [lo, hi) of the blob through the caches (wide coalesced
 // reads whose values are discarded), so that the decode that follows finds
 // them in the 256 MB on-die cache: its reads form a dependent chain per
@@ -772,6 +810,19 @@ __global__ __launch_bounds__(256) void touch_kernel(const uint8_t* __restrict__ 
     asm volatile("" ::"v"(acc));  // keeps the loads; no instruction is emitted
 }
 
+// One wave per block.
+//  1. Coalesced 16-byte loads of the residual slab (its address needs only
+//     b) and of the raw segment area (once the directory entry is in), all
+//     unconditional with clamped chunk indices -- every load stays inside
+//     the blob; a slab of width 0 reads the first chunk of the segment areas
+//     -- so all are in flight before the first wait; they land in LDS.
+//  2. The segment starts become an LDS bitmap with per-word prefix
+//     popcounts, so the segment of key j is found in O(1):
+//       t = prefix[j / 32] + popcount(bits[j / 32] & mask(j % 32)) - 1.
+//  3. Lane l decodes the groups of V = 16 / KB keys starting at
+//     j0 + V * (l + 64 i), j0 chosen so that every group's output is
+//     16-byte aligned; each store instruction of the wave writes 1 KB of
+//     contiguous output (non-temporal: the output is not re-read here).
 template <int KB, bool RANGE>
 __device__ __forceinline__ void decode_block(const uint8_t* __restrict__ blob, const DecodeArgs& a, uint64_t b,
                                              uint32_t raw_cap, bool skip_big, void* __restrict__ out)
@@ -805,6 +856,10 @@ __device__ __forceinline__ void decode_block(const uint8_t* __restrict__ blob, c
     const uint32_t off_an = (uint32_t)a16(2ull * nseg);
     const uint32_t off_sl = off_an + (uint32_t)a16((uint64_t)ab * nseg);
     const uint32_t seg_bytes = off_sl + (uint32_t)a16((uint64_t)sb * nseg);
+    if (!dir_ok(dv, L, b, a.bytes)) {  // corrupt blob: skip the block
+        if (a.flags && lane == 0) atomicOr(a.flags, kFlagBadList);
+        return;
+    }
     const bool staged = seg_bytes <= raw_cap;
     if (skip_big && !staged) return;  // left to the big-block launch
     const uint8_t* g_seg = blob + seg_off;
@@ -848,7 +903,6 @@ __device__ __forceinline__ void decode_block(const uint8_t* __restrict__ blob, c
     c.s_slab = s_slab;
     c.s_bm = s_bm;
     c.s_pre = s_pre;
-    c.vec = a.vec;
     const uint64_t i0 = b << L.log2b;
     c.jlo = 0;
     c.jhi = nkeys;
@@ -1030,10 +1084,347 @@ __global__ __launch_bounds__(256) void lower_bound_kernel(const uint8_t* __restr
     }
 }
 
+// ---------------------------------------------------------------------------
+// Batches of lists
+// ---------------------------------------------------------------------------
+
+constexpr uint32_t kMaxCands = 8;
+
+// Candidate error bounds of a size pass (kernel argument).
+struct Cands {
+    uint32_t eps[kMaxCands];
+    uint32_t n;
+};
+
+// Blob v1 layout of a list of n keys at eps (mirrors the host's layout).
+__device__ __forceinline__ Layout list_layout(const BatchArgs& a, uint64_t n, uint32_t eps)
+{
+    Layout L;
+    const uint64_t B = 1ull << a.log2b;
+    L.n = n;
+    L.nblocks = (n + B - 1) >> a.log2b;
+    L.kb = a.kb;
+    L.log2b = a.log2b;
+    L.F = a.F;
+    L.eps = eps;
+    L.w = eps ? 64 - __clzll((long long)(2ull * eps)) : 0u;  // smallest w with 2^w > 2 eps
+    L.res_stride = a16((B * L.w + 7) / 8);
+    L.off_first = kHeaderBytes;
+    L.off_dir = L.off_first + a16(L.nblocks * a.kb);
+    L.off_res = L.off_dir + 16 * L.nblocks;
+    L.off_seg = L.off_res + L.nblocks * L.res_stride;
+    L.max_nseg = 0;
+    L.max_seg_bytes = 0;
+    L.blob_bytes = 0;
+    return L;
+}
+
+// Does list li fit the buffers of the batch?  Keys (or outputs) [key_off,
+// key_off + n) inside the a.nkeys given, its blocks and 4-block groups inside
+// the plan's totals, eps <= max_eps and, when the blob is used, a 16-byte
+// aligned slot inside the buffer that holds the list's worst-case blob.
+__device__ __forceinline__ bool list_fits(const lc_batch_list& li, const BatchArgs& a, const Layout& L,
+                                          uint32_t eps, bool use_blob)
+{
+    const uint64_t B = 1ull << a.log2b;
+    bool ok = li.n <= a.nkeys && li.key_off <= a.nkeys - li.n && eps <= a.max_eps && li.n <= (1ull << 40);
+    ok = ok && li.block_off <= a.total_blocks && L.nblocks <= a.total_blocks - li.block_off;
+    ok = ok && li.group_off <= a.total_groups && (L.nblocks + 3) / 4 <= a.total_groups - li.group_off;
+    if (use_blob) {
+        const uint64_t worst = L.off_seg + L.nblocks * (a16(2 * B) + 2 * a16(8 * B));
+        ok = ok && (li.blob_off & 15) == 0 && li.blob_off <= a.blob_cap && li.blob_cap <= a.blob_cap - li.blob_off &&
+             worst <= li.blob_cap;
+    }
+    return ok;
+}
+
+// The list owning item x: the last l with off(l) <= x.  Offsets are
+// non-decreasing in a planned table (empty lists repeat their successor's).
+template <bool BY_GROUP>
+__device__ __forceinline__ uint32_t find_list(const lc_batch_list* __restrict__ lists, uint32_t nlists, uint64_t x)
+{
+    uint32_t lo = 0, hi = nlists;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        const uint64_t off = BY_GROUP ? lists[mid].group_off : lists[mid].block_off;
+        if (off <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Workspace of one list: block infos and segment records at its block offset.
+__device__ __forceinline__ Workspace list_ws(const Workspace& ws, uint64_t block_off, uint32_t log2b, uint64_t blk_off)
+{
+    Workspace w;
+    w.blk = ws.blk + blk_off;
+    w.tiles = nullptr;
+    const uint64_t rec = block_off << log2b;
+    w.seg_start = ws.seg_start ? ws.seg_start + rec : nullptr;
+    w.seg_delta = ws.seg_delta ? ws.seg_delta + rec : nullptr;
+    w.seg_A = ws.seg_A ? ws.seg_A + rec : nullptr;
+    return w;
+}
+
+// Fit over every (list, 4-block group) work item of the batch, one wave per
+// item.  SIZES: the size pass, once per candidate eps (item index
+// c * total_groups + g), block infos only.
+template <int KB, bool SIZES>
+__global__ __launch_bounds__(64) void batch_fit_kernel(const void* __restrict__ keys,
+                                                       const lc_batch_list* __restrict__ lists, BatchArgs a,
+                                                       Cands cands, uint8_t* __restrict__ blob, Workspace ws,
+                                                       uint32_t* __restrict__ stats, uint64_t item0)
+{
+    const uint64_t item = item0 + blockIdx.x;
+    const uint64_t cand = SIZES ? item / a.total_groups : 0;
+    const uint64_t g = SIZES ? item % a.total_groups : item;
+    const uint32_t l = find_list<true>(lists, a.nlists, g);
+    const lc_batch_list li = lists[l];
+    const uint32_t eps = SIZES ? cands.eps[cand] : li.eps;
+    const Layout L = list_layout(a, li.n, eps);
+    const uint64_t local = g - li.group_off;
+    if (!list_fits(li, a, L, eps, !SIZES) || local >= (L.nblocks + 3) / 4) {
+        if (threadIdx.x == 0) atomicOr(stats, kFlagBadList);
+        return;
+    }
+    const Workspace w = list_ws(ws, li.block_off, a.log2b, cand * a.total_blocks + li.block_off);
+    const uint8_t* k = reinterpret_cast<const uint8_t*>(keys) + li.key_off * KB;
+    fit_rows<KB, SIZES>(k, L, SIZES ? nullptr : blob + li.blob_off, w, stats, local * 4);
+}
+
+template <int NT>
+__device__ __forceinline__ uint64_t block_max(uint64_t v)
+{
+    __shared__ uint64_t s_m[NT / 64];
+    v = wave_max(v);
+    if (lane_id() == 0) s_m[threadIdx.x / 64] = v;
+    __syncthreads();
+    uint64_t m = 0;
+    for (uint32_t k = 0; k < NT / 64; k++) m = s_m[k] > m ? s_m[k] : m;
+    __syncthreads();
+    return m;
+}
+
+// One workgroup per list (per candidate and list for the size pass): scan
+// of the blocks' segment-area bytes, then (unless SIZES) the directory, the
+// header and the first-key padding of the list's blob.  sizes[c * nlists + l]
+// receives the blob size (~0 for a list that does not fit the buffers).
+template <bool SIZES>
+__global__ __launch_bounds__(256) void batch_scan_kernel(const lc_batch_list* __restrict__ lists, BatchArgs a,
+                                                         Cands cands, uint8_t* __restrict__ blob, Workspace ws,
+                                                         uint64_t* __restrict__ sizes, uint32_t* __restrict__ stats,
+                                                         uint64_t item0)
+{
+    const uint64_t item = item0 + blockIdx.x;
+    const uint32_t l = (uint32_t)(item % a.nlists);
+    const uint64_t cand = item / a.nlists;
+    const lc_batch_list li = lists[l];
+    const uint32_t eps = SIZES ? cands.eps[cand] : li.eps;
+    const Layout L = list_layout(a, li.n, eps);
+    if (!list_fits(li, a, L, eps, !SIZES)) {
+        if (threadIdx.x == 0) {
+            atomicOr(stats, kFlagBadList);
+            if (sizes) sizes[item] = ~0ull;
+        }
+        return;
+    }
+    const BlockInfo* blk = ws.blk + cand * a.total_blocks + li.block_off;
+    uint8_t* out = SIZES ? nullptr : blob + li.blob_off;
+    uint64_t carry = 0, nseg_total = 0, max_nseg = 0, max_area = 0;
+    for (uint64_t b0 = 0; b0 < L.nblocks; b0 += 256) {
+        const uint64_t b = b0 + threadIdx.x;
+        BlockInfo bi = {};
+        bool bad = false;
+        if (b < L.nblocks) {
+            bi = blk[b];
+            // block infos of a planned table were all written by the fit
+            const uint64_t left = L.n - (b << L.log2b);
+            const uint32_t want = left < (1ull << L.log2b) ? (uint32_t)left : (1u << L.log2b);
+            const uint32_t ab = bi.ab, sb = bi.sb;
+            bad = bi.nkeys != want || bi.nseg < 1 || bi.nseg > want || !ab || !sb || ab > 8 || sb > 8 ||
+                  (ab & (ab - 1)) || (sb & (sb - 1)) ||
+                  bi.seg_bytes != a16(2ull * bi.nseg) + a16((uint64_t)ab * bi.nseg) + a16((uint64_t)sb * bi.nseg);
+            if (bad) bi = BlockInfo{};
+        }
+        if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(stats, kFlagBadList);
+        uint64_t tot, tot_n;
+        const uint64_t ex = block_excl_sum<256>(bi.seg_bytes, &tot);
+        block_excl_sum<256>(bi.nseg, &tot_n);
+        if (!SIZES && b < L.nblocks) {
+            const uint64_t seg_off = L.off_seg + carry + ex;
+            const uint32_t w3 = (bi.nkeys - 1) | ((uint32_t)bi.ab << 16) | ((uint32_t)bi.sb << 24);
+            reinterpret_cast<uint4*>(out + L.off_dir)[b] = make_uint4((uint32_t)seg_off, (uint32_t)(seg_off >> 32),
+                                                                      bi.nseg, w3);
+        }
+        carry += tot;
+        nseg_total += tot_n;
+        max_nseg = b < L.nblocks && bi.nseg > max_nseg ? bi.nseg : max_nseg;
+        max_area = b < L.nblocks && bi.seg_bytes > max_area ? bi.seg_bytes : max_area;
+    }
+    max_nseg = block_max<256>(max_nseg);
+    max_area = block_max<256>(max_area);
+    const uint64_t blob_bytes = L.off_seg + carry;
+    if (threadIdx.x == 0) {
+        if (sizes) sizes[item] = blob_bytes;
+        if (!SIZES) {
+            write_header(out, L, nseg_total, max_nseg, max_area, blob_bytes);
+            atomicMax(stats + 1, (uint32_t)max_area);
+        }
+    }
+    if (!SIZES) {
+        const uint64_t fk_end = L.off_first + L.nblocks * L.kb;
+        if (threadIdx.x < L.off_dir - fk_end) out[fk_end + threadIdx.x] = 0;
+    }
+}
+
+// Segment areas of every block of the batch: one wave per block.
+__global__ __launch_bounds__(256) void batch_emit_kernel(const lc_batch_list* __restrict__ lists, BatchArgs a,
+                                                         uint8_t* __restrict__ blob, Workspace ws, uint64_t blk0)
+{
+    const uint64_t gb = blk0 + (uint64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    if (gb >= a.total_blocks) return;
+    const uint32_t l = find_list<false>(lists, a.nlists, gb);
+    const lc_batch_list li = lists[l];
+    const Layout L = list_layout(a, li.n, li.eps);
+    const uint64_t b = gb - li.block_off;
+    if (!list_fits(li, a, L, li.eps, true) || b >= L.nblocks) return;  // flagged by the fit
+    const uint4 dv = reinterpret_cast<const uint4*>(blob + li.blob_off + L.off_dir)[b];
+    if (!dir_ok(dv, L, b, li.blob_cap)) return;  // flagged by the scan
+    emit_block(list_ws(ws, li.block_off, a.log2b, li.block_off), L, blob + li.blob_off, b);
+}
+
+// Decode of every block of the batch, one wave per block, XCD-major as the
+// single-list decode; blocks whose segment area exceeds raw_cap are left to
+// batch_decode_big_kernel.  List l's keys go to out + key_off * KB.
+template <int KB>
+__device__ __forceinline__ bool batch_block(const lc_batch_list* __restrict__ lists, const BatchArgs& a, uint64_t gb,
+                                            lc_batch_list* li, Layout* L, uint64_t* b)
+{
+    const uint32_t l = find_list<false>(lists, a.nlists, gb);
+    *li = lists[l];
+    *L = list_layout(a, li->n, li->eps);
+    *b = gb - li->block_off;
+    return list_fits(*li, a, *L, li->eps, true) && *b < L->nblocks;
+}
+
+template <int KB>
+__global__ __launch_bounds__(64) void batch_decode_kernel(const uint8_t* __restrict__ blob,
+                                                          const lc_batch_list* __restrict__ lists, BatchArgs a,
+                                                          uint64_t blk0, uint64_t nblk, uint64_t per_xcd,
+                                                          uint32_t raw_cap, bool skip_big, void* __restrict__ out,
+                                                          uint32_t* __restrict__ stats)
+{
+    const uint64_t rel = (uint64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (rel >= nblk) return;
+    lc_batch_list li;
+    DecodeArgs d{};
+    uint64_t b;
+    if (!batch_block<KB>(lists, a, blk0 + rel, &li, &d.L, &b)) {
+        if (threadIdx.x == 0) atomicOr(stats, kFlagBadList);
+        return;
+    }
+    d.begin = 0;
+    d.end = li.n;
+    d.raw_cap = raw_cap;
+    d.bytes = li.blob_cap;
+    d.flags = stats;
+    decode_block<KB, true>(blob + li.blob_off, d, b, raw_cap, skip_big,
+                           reinterpret_cast<uint8_t*>(out) + li.key_off * KB);
+}
+
+template <int KB>
+__global__ __launch_bounds__(64) void batch_decode_big_kernel(const uint8_t* __restrict__ blob,
+                                                              const lc_batch_list* __restrict__ lists, BatchArgs a,
+                                                              uint64_t blk0, uint64_t nblk, uint32_t small_cap,
+                                                              uint32_t raw_cap, void* __restrict__ out,
+                                                              uint32_t* __restrict__ stats)
+{
+    const uint64_t rel = (uint64_t)blockIdx.x * kBigPerWave + threadIdx.x;
+    bool big = false;
+    if (threadIdx.x < kBigPerWave && rel < nblk) {
+        lc_batch_list li;
+        Layout L;
+        uint64_t b;
+        if (batch_block<KB>(lists, a, blk0 + rel, &li, &L, &b)) {
+            const uint4 dv = reinterpret_cast<const uint4*>(blob + li.blob_off + L.off_dir)[b];
+            const uint32_t nseg = dv.z ? dv.z : 1u;
+            const uint32_t ab = (dv.w >> 16) & 0xFF, sb = dv.w >> 24;
+            big = a16(2ull * nseg) + a16((uint64_t)ab * nseg) + a16((uint64_t)sb * nseg) > small_cap;
+        }
+    }
+    uint64_t m = __ballot(big);
+    while (m) {
+        const uint32_t k = (uint32_t)__ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        lc_batch_list li;
+        DecodeArgs d{};
+        uint64_t b;
+        batch_block<KB>(lists, a, blk0 + (uint64_t)blockIdx.x * kBigPerWave + k, &li, &d.L, &b);
+        d.begin = 0;
+        d.end = li.n;
+        d.raw_cap = raw_cap;
+        d.bytes = li.blob_cap;
+        d.flags = stats;
+        decode_block<KB, true>(blob + li.blob_off, d, b, raw_cap, false,
+                               reinterpret_cast<uint8_t*>(out) + li.key_off * KB);
+        __syncthreads();  // LDS is reused by the next block
+    }
+}
+
+// eps of list l := the candidate with the smallest size (ties: the smaller
+// eps, i.e. the earlier candidate).
+__global__ __launch_bounds__(256) void batch_pick_kernel(lc_batch_list* __restrict__ lists, uint32_t nlists,
+                                                         const uint64_t* __restrict__ sizes, Cands cands)
+{
+    const uint32_t l = blockIdx.x * 256 + threadIdx.x;
+    if (l >= nlists) return;
+    uint32_t best = 0;
+    for (uint32_t c = 1; c < cands.n; c++)
+        if (sizes[(uint64_t)c * nlists + l] < sizes[(uint64_t)best * nlists + l]) best = c;
+    lists[l].eps = cands.eps[best];
+}
+
 inline uint32_t query_grid(uint64_t m)
 {
     const uint64_t g = (m + 255) / 256;
     return (uint32_t)(g < 8192 ? (g ? g : 1) : 8192);
+}
+
+
+hipError_t launch_batch_fit(const void* d_keys, const lc_batch_list* d_lists, const BatchArgs& a, const Cands& c,
+                            uint8_t* d_blob, const Workspace& ws, uint64_t* d_sizes, uint32_t* d_stats, bool sizes_only,
+                            hipStream_t stream)
+{
+    const uint32_t ncand = sizes_only ? c.n : 1u;
+    uint32_t eps_max = 0;
+    for (uint32_t k = 0; k < (sizes_only ? c.n : 0u); k++) eps_max = c.eps[k] > eps_max ? c.eps[k] : eps_max;
+    if (!sizes_only) eps_max = a.max_eps;
+    uint32_t w = 0;
+    while ((1ull << w) < 2ull * eps_max + 1) w++;
+    const uint64_t res_stride = align16(((1ull << a.log2b) * w + 7) / 8);
+    const size_t lds = 4 * (res_stride + 16);
+    const uint64_t items = a.total_groups * ncand;
+    auto k = a.kb == 4 ? (sizes_only ? batch_fit_kernel<4, true> : batch_fit_kernel<4, false>)
+                       : (sizes_only ? batch_fit_kernel<8, true> : batch_fit_kernel<8, false>);
+    for (uint64_t i0 = 0; i0 < items; i0 += kMaxGrid) {
+        const uint64_t g = items - i0 < kMaxGrid ? items - i0 : kMaxGrid;
+        hipLaunchKernelGGL(k, dim3((uint32_t)g), dim3(64), lds, stream, d_keys, d_lists, a, c, d_blob, ws, d_stats, i0);
+    }
+    const uint64_t scans = (uint64_t)a.nlists * ncand;
+    auto ks = sizes_only ? batch_scan_kernel<true> : batch_scan_kernel<false>;
+    for (uint64_t i0 = 0; i0 < scans; i0 += kMaxGrid) {
+        const uint64_t g = scans - i0 < kMaxGrid ? scans - i0 : kMaxGrid;
+        hipLaunchKernelGGL(ks, dim3((uint32_t)g), dim3(256), 0, stream, d_lists, a, c, d_blob, ws, d_sizes, d_stats, i0);
+    }
+    if (!sizes_only) {
+        const uint64_t groups = (a.total_blocks + 3) / 4;
+        for (uint64_t g0 = 0; g0 < groups; g0 += kMaxGrid) {
+            const uint64_t g = groups - g0 < kMaxGrid ? groups - g0 : kMaxGrid;
+            hipLaunchKernelGGL(batch_emit_kernel, dim3((uint32_t)g), dim3(256), 0, stream, d_lists, a, d_blob, ws,
+                               g0 * 4);
+        }
+    }
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -1041,6 +1432,58 @@ inline uint32_t query_grid(uint64_t m)
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+
+hipError_t launch_batch_compress(const void* d_keys, const lc_batch_list* d_lists, const BatchArgs& a, const uint32_t* cands,
+                                 uint32_t ncand, uint8_t* d_blob, const Workspace& ws, uint64_t* d_sizes,
+                                 uint32_t* d_stats, bool sizes_only, hipStream_t stream)
+{
+    Cands c{};
+    c.n = ncand;
+    for (uint32_t k = 0; k < ncand && k < kMaxCands; k++) c.eps[k] = cands[k];
+    return launch_batch_fit(d_keys, d_lists, a, c, d_blob, ws, d_sizes, d_stats, sizes_only, stream);
+}
+
+hipError_t launch_batch_pick(lc_batch_list* d_lists, uint32_t nlists, const uint64_t* d_sizes, const uint32_t* cands,
+                             uint32_t ncand, hipStream_t stream)
+{
+    Cands c{};
+    c.n = ncand;
+    for (uint32_t k = 0; k < ncand && k < kMaxCands; k++) c.eps[k] = cands[k];
+    hipLaunchKernelGGL(batch_pick_kernel, dim3((nlists + 255) / 256), dim3(256), 0, stream, d_lists, nlists, d_sizes, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_decode(const uint8_t* d_blob, const lc_batch_list* d_lists, const BatchArgs& a,
+                               uint32_t max_seg_bytes, void* d_out, uint32_t* d_stats, hipStream_t stream)
+{
+    if (a.total_blocks == 0) return hipSuccess;
+    uint32_t w = 0;
+    while ((1ull << w) < 2ull * a.max_eps + 1) w++;
+    const uint64_t res_stride = align16(((1ull << a.log2b) * w + 7) / 8);
+    const uint32_t small_cap = decode_raw_cap(max_seg_bytes, kSegRawSmall);
+    const uint32_t big_cap = decode_raw_cap(max_seg_bytes, kSegRawMax);
+    const size_t lds_small = decode_lds_bytes(a.log2b, res_stride, small_cap);
+    const size_t lds_big = decode_lds_bytes(a.log2b, res_stride, big_cap);
+    auto k = a.kb == 4 ? batch_decode_kernel<4> : batch_decode_kernel<8>;
+    auto kbig = a.kb == 4 ? batch_decode_big_kernel<4> : batch_decode_big_kernel<8>;
+    hipError_t e;
+    if (lds_small > 65536 &&
+        (e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_small)) != hipSuccess)
+        return e;
+    if (big_cap > small_cap && lds_big > 65536 &&
+        (e = hipFuncSetAttribute((const void*)kbig, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_big)) != hipSuccess)
+        return e;
+    for (uint64_t b0 = 0; b0 < a.total_blocks; b0 += kMaxGrid) {
+        const uint64_t nblk = a.total_blocks - b0 < kMaxGrid ? a.total_blocks - b0 : kMaxGrid;
+        const uint64_t per_xcd = (nblk + 7) / 8;
+        hipLaunchKernelGGL(k, dim3((uint32_t)(per_xcd * 8)), dim3(64), lds_small, stream, d_blob, d_lists, a, b0, nblk,
+                           per_xcd, small_cap, big_cap > small_cap, d_out, d_stats);
+        if (big_cap > small_cap)
+            hipLaunchKernelGGL(kbig, dim3((uint32_t)((nblk + kBigPerWave - 1) / kBigPerWave)), dim3(64), lds_big, stream,
+                               d_blob, d_lists, a, b0, nblk, small_cap, big_cap, d_out, d_stats);
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_compress(const void* d_keys, const Layout& L, uint8_t* d_blob, const Workspace& ws,
                            uint64_t* d_blob_bytes, uint32_t* d_flags, hipStream_t stream)
@@ -1118,8 +1561,9 @@ hipError_t launch_decode(const uint8_t* d_blob, const Layout& L, uint64_t begin,
         a.b_first = b0;
         a.nblk = (b_hi + 1 - b0) < kMaxGrid ? (b_hi + 1 - b0) : kMaxGrid;
         a.per_xcd = (a.nblk + 7) / 8;
-        a.vec = (begin % (16 / L.kb)) == 0 && (reinterpret_cast<uintptr_t>(d_out) % 16) == 0;
         a.raw_cap = small_cap;
+        a.bytes = L.blob_bytes;
+        a.flags = nullptr;
         hipLaunchKernelGGL(k, dim3((uint32_t)(a.per_xcd * 8)), dim3(64), lds_small, stream, d_blob, a, d_out);
         if (big_cap > small_cap) {
             a.raw_cap = big_cap;

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "lc.h"
+
 namespace lc {
 
 // Byte layout of one blob v1 plus the encoder parameters, as kernel arguments.
@@ -44,6 +46,15 @@ constexpr uint64_t kHeaderBytes = 128;
 inline uint64_t align16(uint64_t x) { return (x + 15) & ~uint64_t(15); }
 inline uint64_t ntiles_of(uint64_t nblocks) { return (nblocks + kTileBlocks - 1) / kTileBlocks; }
 
+// Parameters of a batch of lists, as kernel arguments.
+struct BatchArgs {
+    uint32_t kb, log2b, F, nlists, max_eps;
+    uint32_t pad;
+    uint64_t total_blocks, total_groups;
+    uint64_t nkeys;         // keys in the concatenated key (compress) / output (decompress) array
+    uint64_t blob_cap;      // bytes of the batch buffer
+};
+
 // Kernel launchers; each returns the hipError_t of its last launch.
 hipError_t launch_compress(const void* d_keys, const Layout& L, uint8_t* d_blob, const Workspace& ws,
                            uint64_t* d_blob_bytes, uint32_t* d_flags, hipStream_t stream);
@@ -53,5 +64,14 @@ hipError_t launch_access(const uint8_t* d_blob, const Layout& L, const uint64_t*
                          void* d_out, uint32_t* d_flags, hipStream_t stream);
 hipError_t launch_lower_bound(const uint8_t* d_blob, const Layout& L, const void* d_q, uint64_t m,
                               uint64_t* d_pos, hipStream_t stream);
+
+// Batch fit, scan and emit (sizes_only: the size pass over cands[0 .. ncand)).
+hipError_t launch_batch_compress(const void* d_keys, const lc_batch_list* d_lists, const BatchArgs& a,
+                                 const uint32_t* cands, uint32_t ncand, uint8_t* d_blob, const Workspace& ws,
+                                 uint64_t* d_sizes, uint32_t* d_stats, bool sizes_only, hipStream_t stream);
+hipError_t launch_batch_pick(lc_batch_list* d_lists, uint32_t nlists, const uint64_t* d_sizes, const uint32_t* cands,
+                             uint32_t ncand, hipStream_t stream);
+hipError_t launch_batch_decode(const uint8_t* d_blob, const lc_batch_list* d_lists, const BatchArgs& a,
+                               uint32_t max_seg_bytes, void* d_out, uint32_t* d_stats, hipStream_t stream);
 
 }  // namespace lc

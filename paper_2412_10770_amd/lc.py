@@ -15,6 +15,7 @@ import ctypes
 import os
 from dataclasses import dataclass
 
+import numpy as np
 import torch  # noqa: F401  (loads the HIP runtime liblc.so binds to)
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -28,12 +29,15 @@ LC_EDEVICE = -4
 LC_FLAG_UNSORTED = 1
 LC_FLAG_RANGE = 2
 LC_FLAG_INTERNAL = 4
+LC_FLAG_BADLIST = 8
+BATCH_MAX_CANDIDATES = 8
 HEADER_BYTES = 128
 DEFAULT_LOG2_BLOCK = 10
 DEFAULT_FRAC_BITS = 20
 
 EXPORTED = ("lc_compress_bound", "lc_compress", "lc_info", "lc_decompress", "lc_decompress_range",
-            "lc_access", "lc_lower_bound", "lc_strerror")
+            "lc_access", "lc_lower_bound", "lc_batch_plan", "lc_batch_compress", "lc_batch_sizes",
+            "lc_batch_pick_eps", "lc_batch_decompress", "lc_strerror")
 
 
 class lc_params(ctypes.Structure):
@@ -48,6 +52,19 @@ class lc_blob_info(ctypes.Structure):
                [(f, ctypes.c_uint64) for f in
                 ("n", "nblocks", "nseg_total", "off_first", "off_dir", "off_res", "res_stride",
                  "off_seg", "blob_bytes")]
+
+
+class lc_batch_params(ctypes.Structure):
+    _fields_ = [("key_bytes", ctypes.c_uint8), ("log2_block", ctypes.c_uint8), ("frac_bits", ctypes.c_uint8),
+                ("reserved", ctypes.c_uint8), ("nlists", ctypes.c_uint32), ("max_eps", ctypes.c_uint32),
+                ("reserved2", ctypes.c_uint32)] + \
+               [(f, ctypes.c_uint64) for f in ("total_blocks", "total_groups", "blob_bytes", "ws_bytes")]
+
+
+# struct lc_batch_list, one 64-byte record per list
+BATCH_LIST_DTYPE = np.dtype([("key_off", "<u8"), ("n", "<u8"), ("blob_off", "<u8"), ("blob_cap", "<u8"),
+                             ("block_off", "<u8"), ("group_off", "<u8"), ("eps", "<u4"), ("reserved", "<u4", (3,))])
+assert BATCH_LIST_DTYPE.itemsize == 64
 
 
 def _load():
@@ -65,6 +82,11 @@ def _load():
         "lc_decompress_range": [vp, I, u64, u64, vp, vp],
         "lc_access": [vp, I, vp, u64, vp, vp, vp],
         "lc_lower_bound": [vp, I, vp, u64, vp, vp],
+        "lc_batch_plan": [ctypes.POINTER(lc_batch_params), vp],
+        "lc_batch_compress": [vp, u64, vp, ctypes.POINTER(lc_batch_params), vp, u64, vp, u64, vp, vp, vp],
+        "lc_batch_sizes": [vp, u64, vp, ctypes.POINTER(lc_batch_params), vp, u32, vp, u64, vp, vp, vp],
+        "lc_batch_pick_eps": [vp, ctypes.POINTER(lc_batch_params), vp, vp, u32, vp],
+        "lc_batch_decompress": [vp, u64, vp, ctypes.POINTER(lc_batch_params), u32, vp, u64, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -261,4 +283,142 @@ def lower_bound(blob: Blob, q: torch.Tensor, out: torch.Tensor | None = None, st
     _check(lib.lc_lower_bound(ctypes.c_void_p(blob.data.data_ptr()), ctypes.byref(blob.info),
                               ctypes.c_void_p(q.data_ptr()), q.numel(), ctypes.c_void_p(out.data_ptr()),
                               _stream(stream)), "lc_lower_bound")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Batches of lists
+# ---------------------------------------------------------------------------
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def batch_plan(lengths, eps, key_bytes: int, max_eps: int | None = None, log2_block: int = DEFAULT_LOG2_BLOCK,
+               frac_bits: int = DEFAULT_FRAC_BITS, key_offsets=None):
+    """lc_batch_plan: (lc_batch_params, host table) for lists of the given
+    lengths, stored one after another in the key array unless key_offsets is
+    given.  eps: one value or one per list; max_eps sizes the blob slots."""
+    lengths = np.asarray(lengths, dtype=np.uint64).ravel()
+    nl = lengths.size
+    table = np.zeros(nl, dtype=BATCH_LIST_DTYPE)
+    table["n"] = lengths
+    if key_offsets is None:
+        key_offsets = np.concatenate([[0], np.cumsum(lengths, dtype=np.uint64)[:-1]]) if nl else lengths
+    table["key_off"] = np.asarray(key_offsets, dtype=np.uint64)
+    table["eps"] = np.broadcast_to(np.asarray(eps, dtype=np.uint32), (nl,))
+    if max_eps is None:
+        max_eps = int(table["eps"].max()) if nl else 0
+    p = lc_batch_params(key_bytes, log2_block, frac_bits, 0, nl, max_eps, 0, 0, 0, 0, 0)
+    _check(lib.lc_batch_plan(ctypes.byref(p), table.ctypes.data_as(ctypes.c_void_p)), "lc_batch_plan")
+    return p, table
+
+
+def batch_sizes_async(keys, lists, p, cands, ws, sizes, stats, stream=None):
+    """Enqueue lc_batch_sizes: sizes[c * nlists + l] for every candidate eps."""
+    cand = (ctypes.c_uint32 * len(cands))(*cands)
+    _check(lib.lc_batch_sizes(_ptr(keys), keys.numel(), _ptr(lists), ctypes.byref(p), cand, len(cands),
+                              _ptr(ws), ws.numel(), _ptr(sizes), _ptr(stats), _stream(stream)), "lc_batch_sizes")
+
+
+def batch_pick_eps_async(lists, p, sizes, cands, stream=None):
+    """Enqueue lc_batch_pick_eps: every list's eps := its argmin-size candidate."""
+    cand = (ctypes.c_uint32 * len(cands))(*cands)
+    _check(lib.lc_batch_pick_eps(_ptr(lists), ctypes.byref(p), _ptr(sizes), cand, len(cands), _stream(stream)),
+           "lc_batch_pick_eps")
+
+
+def batch_compress_async(keys, lists, p, blob, ws, sizes, stats, stream=None):
+    """Enqueue lc_batch_compress into caller-provided buffers."""
+    _check(lib.lc_batch_compress(_ptr(keys), keys.numel(), _ptr(lists), ctypes.byref(p), _ptr(blob), blob.numel(),
+                                 _ptr(ws), ws.numel(), _ptr(sizes), _ptr(stats), _stream(stream)),
+           "lc_batch_compress")
+
+
+def batch_decompress_async(blob, lists, p, max_seg_bytes: int, out, stats, stream=None):
+    """Enqueue lc_batch_decompress into out (all lists, at their key offsets)."""
+    _check(lib.lc_batch_decompress(_ptr(blob), blob.numel(), _ptr(lists), ctypes.byref(p), max_seg_bytes,
+                                   _ptr(out), out.numel(), _ptr(stats), _stream(stream)), "lc_batch_decompress")
+
+
+@dataclass
+class Batch:
+    """A batch of compressed lists: one blob v1 per list, in slots of one buffer."""
+    params: lc_batch_params
+    table: np.ndarray       # host copy of the list table (eps as compressed)
+    lists: torch.Tensor     # device copy (uint8, 64 bytes per list)
+    data: torch.Tensor      # the batch buffer (uint8)
+    sizes: np.ndarray       # blob bytes per list
+    max_seg_bytes: int
+    nkeys: int              # keys in the concatenated array
+
+    @property
+    def key_bytes(self) -> int:
+        return self.params.key_bytes
+
+    @property
+    def nbytes(self) -> int:
+        """Bytes of all list blobs (the slots' unused tails not counted)."""
+        return int(self.sizes.sum())
+
+    @property
+    def eps(self) -> np.ndarray:
+        return self.table["eps"].copy()
+
+    def blob(self, l: int) -> Blob:
+        off, size = int(self.table["blob_off"][l]), int(self.sizes[l])
+        data = self.data[off:off + size]
+        return Blob(data, info(data[:HEADER_BYTES].cpu()))
+
+
+def _raise_flags(fl: int, what: str):
+    if fl & LC_FLAG_UNSORTED:
+        raise LcError(LC_EINVAL, f"{what}: a list is not sorted (LC_FLAG_UNSORTED)")
+    if fl & LC_FLAG_BADLIST:
+        raise LcError(LC_EINVAL, f"{what}: a list does not fit the buffers (LC_FLAG_BADLIST)")
+    if fl & LC_FLAG_INTERNAL:
+        raise LcError(LC_EDEVICE, f"{what}: internal step limit hit (LC_FLAG_INTERNAL)")
+
+
+def batch_compress(keys: torch.Tensor, lengths, eps=None, candidates=None, log2_block: int = DEFAULT_LOG2_BLOCK,
+                   frac_bits: int = DEFAULT_FRAC_BITS, stream=None, check: bool = True) -> Batch:
+    """Compress the lists stored one after another in keys.  Either eps (one
+    value or one per list) or candidates (the autotuner picks each list's eps
+    among them by exact blob size, ties to the smaller)."""
+    _dev(keys, "keys")
+    kb = _key_bytes(keys)
+    if (eps is None) == (candidates is None):
+        raise ValueError("give exactly one of eps and candidates")
+    cands = sorted(set(int(c) for c in candidates)) if candidates is not None else None
+    p, table = batch_plan(lengths, cands[0] if cands else eps, kb, max(cands) if cands else None, log2_block,
+                          frac_bits)
+    dev = keys.device
+    nl = p.nlists
+    lists = torch.from_numpy(table.view(np.uint8).copy()).to(dev)
+    ws = torch.empty(max(p.ws_bytes, 16), dtype=torch.uint8, device=dev)
+    stats = torch.zeros(2, dtype=torch.int32, device=dev)
+    if cands:
+        csizes = torch.empty(len(cands) * nl, dtype=torch.int64, device=dev)
+        batch_sizes_async(keys, lists, p, cands, ws, csizes, stats, stream)
+        batch_pick_eps_async(lists, p, csizes, cands, stream)
+    blob = torch.empty(max(p.blob_bytes, 16), dtype=torch.uint8, device=dev)
+    sizes = torch.empty(nl, dtype=torch.int64, device=dev)
+    batch_compress_async(keys, lists, p, blob, ws, sizes, stats, stream)
+    st = stats.cpu().numpy()
+    if check:
+        _raise_flags(int(st[0]), "lc_batch_compress")
+    del ws
+    final = lists.cpu().numpy().view(BATCH_LIST_DTYPE).copy()
+    return Batch(p, final, lists, blob, sizes.cpu().numpy().astype(np.uint64), int(st[1]) & 0xFFFFFFFF,
+                 keys.numel())
+
+
+def batch_decompress(batch: Batch, out: torch.Tensor | None = None, stream=None, check: bool = True) -> torch.Tensor:
+    """All lists of the batch, at their key offsets (the layout compressed)."""
+    if out is None:
+        out = torch.empty(batch.nkeys, dtype=key_dtype(batch.key_bytes), device=batch.data.device)
+    stats = torch.zeros(1, dtype=torch.int32, device=out.device)
+    batch_decompress_async(batch.data, batch.lists, batch.params, batch.max_seg_bytes, out, stats, stream)
+    if check:
+        _raise_flags(int(stats.item()), "lc_batch_decompress")
     return out

@@ -24,6 +24,11 @@ Recipes (sizes are parameters; the full sizes are the defaults):
   draw gaps uniform in [1, 4], sparse runs Zipf(1.2) gaps capped at 2^20
   (200,000,000 uint64 keys).
 * ``lognormal_gaps``: gaps max(1, ceil(lognormal(3, 1.5))), uint64.
+* ``posting_lists``: a batch of uint32 lists shaped like the posting lists
+  of an inverted index: 4096 lists whose lengths follow the power law
+  P(L) ~ L^-1.1 truncated to [100, 10^6] (inverse CDF, floored; about
+  3e8 keys in all), each list starting at 0 with geometric gaps (support
+  1, 2, ...) of mean m, m = exp(U[ln 2, ln 2000]) drawn per list.
 * queries: ``uniform_indices`` (i uniform in [0, n)) and ``uniform_keys``
   (q uniform over [lo, hi]).
 """
@@ -133,6 +138,43 @@ def lognormal_gaps(n: int, seed: int = SEED_BASE + 5, device="cpu", mu: float = 
     if n:
         gaps[0] = 0
     return torch.cumsum(gaps, 0)
+
+
+def posting_lengths(nlists: int = 4096, seed: int = SEED_BASE + 6, lo: float = 100, hi: float = 1e6,
+                    s: float = 1.1) -> np.ndarray:
+    """List lengths from the power law L^-s truncated to [lo, hi] (inverse CDF, floored)."""
+    rng = np.random.default_rng(seed)
+    u = rng.random(nlists)
+    a = 1.0 - s
+    x = (lo ** a + u * (hi ** a - lo ** a)) ** (1.0 / a)
+    return np.clip(np.floor(x), lo, hi).astype(np.int64)
+
+
+def posting_lists(nlists: int = 4096, seed: int = SEED_BASE + 6, device="cpu", lo: float = 100,
+                  hi: float = 1e6, s: float = 1.1, mean_lo: float = 2.0, mean_hi: float = 2000.0):
+    """(keys, lengths): the lists stored one after another as one uint32 key
+    tensor (int32 bit patterns), and the host array of their lengths."""
+    lengths = posting_lengths(nlists, seed, lo, hi, s)
+    rng = np.random.default_rng(seed + 1)
+    means = np.exp(rng.uniform(math.log(mean_lo), math.log(mean_hi), nlists))
+    n = int(lengths.sum())
+    g = _gen(seed + 2, device)
+    lens_t = torch.from_numpy(lengths).to(device)
+    # per-key log(1 - p), p = 1 / m, for inverse-CDF geometric draws
+    lq = torch.from_numpy(np.log1p(-1.0 / means)).to(device).repeat_interleave(lens_t)
+    u = torch.rand(n, dtype=torch.float64, device=device, generator=g)
+    gaps = torch.floor(torch.log1p(-u) / lq).to(torch.int64) + 1
+    del u, lq
+    starts = torch.cumsum(lens_t, 0) - lens_t
+    gaps[starts[lengths > 0]] = 0  # every list starts at 0
+    keys = torch.cumsum(gaps, 0)
+    del gaps
+    # restart the running sum at each list
+    base = keys[starts[lengths > 0]]
+    keys -= base.repeat_interleave(lens_t[lengths > 0])
+    if n and int(keys.max()) >= 1 << 32:
+        raise ValueError("a list exceeds the uint32 key range")
+    return keys.to(torch.int32), lengths
 
 
 def uniform_indices(m: int, n: int, seed: int, device="cpu") -> torch.Tensor:

@@ -99,9 +99,70 @@ def test_entry_points_reject_bad_arguments_before_any_launch(lc):
     assert lc.lib.lc_decompress_range(fake, ctypes.byref(inf), 5, 4, fake, null) == lc.LC_EINVAL
     assert lc.lib.lc_decompress_range(fake, ctypes.byref(inf), 0, inf.n + 1, fake, null) == lc.LC_EINVAL
     assert lc.lib.lc_decompress_range(fake, ctypes.byref(inf), 7, 7, fake, null) == lc.LC_OK  # empty: no-op
-    assert lc.lib.lc_decompress(fake, ctypes.byref(inf), ctypes.c_void_p(0x1008), null) == lc.LC_EINVAL
+    assert lc.lib.lc_decompress(fake, ctypes.byref(inf), ctypes.c_void_p(0x1004), null) == lc.LC_EINVAL
     assert lc.lib.lc_access(fake, ctypes.byref(inf), fake, 5, fake, null, null) == lc.LC_EINVAL
     assert lc.lib.lc_access(fake, ctypes.byref(inf), fake, 0, fake, null, null) == lc.LC_OK
     assert lc.lib.lc_lower_bound(null, ctypes.byref(inf), fake, 5, fake, null) == lc.LC_EINVAL
     inf.off_seg += 16  # info no longer consistent with the layout rules
     assert lc.lib.lc_decompress(fake, ctypes.byref(inf), fake, null) == lc.LC_EINVAL
+
+
+def test_batch_plan(lc):
+    """lc_batch_plan is host code: slots, block and group offsets, totals."""
+    lengths = [0, 5, 1024, 1025, 100_000, 0, 64]
+    for kb, log2b in ((4, 10), (8, 6), (4, 12)):
+        p, t = lc.batch_plan(lengths, 7, kb, max_eps=127, log2_block=log2b)
+        B = 1 << log2b
+        nb = np.array([-(-n // B) for n in lengths])
+        assert list(t["key_off"]) == list(np.concatenate([[0], np.cumsum(lengths)[:-1]]))
+        assert list(t["block_off"]) == list(np.concatenate([[0], np.cumsum(nb)[:-1]]))
+        ng = (nb + 3) // 4
+        assert list(t["group_off"]) == list(np.concatenate([[0], np.cumsum(ng)[:-1]]))
+        caps = [lc.compress_bound(n, kb, 127, log2b)[0] for n in lengths]
+        assert list(t["blob_cap"]) == caps
+        assert list(t["blob_off"]) == list(np.concatenate([[0], np.cumsum(caps)[:-1]]))
+        assert all(int(o) % 16 == 0 for o in t["blob_off"])
+        assert p.total_blocks == nb.sum() and p.total_groups == ng.sum() and p.blob_bytes == sum(caps)
+        assert p.ws_bytes >= 18 * p.total_blocks * B + 8 * 16 * p.total_blocks
+        assert list(t["eps"]) == [7] * len(lengths)
+
+
+def test_batch_bad_args(lc):
+    """Batch entry points reject bad parameters before any launch."""
+    P = ctypes.byref
+    t = np.zeros(2, dtype=lc.BATCH_LIST_DTYPE)
+    t["n"] = [10, 20]
+    good = lc.lc_batch_params(4, 10, 20, 0, 2, 31, 0, 0, 0, 0, 0)
+    tp = t.ctypes.data_as(ctypes.c_void_p)
+    for bad in (lc.lc_batch_params(3, 10, 20, 0, 2, 31, 0, 0, 0, 0, 0),
+                lc.lc_batch_params(4, 5, 20, 0, 2, 31, 0, 0, 0, 0, 0),
+                lc.lc_batch_params(4, 10, 33, 0, 2, 31, 0, 0, 0, 0, 0),
+                lc.lc_batch_params(4, 10, 20, 0, 0, 31, 0, 0, 0, 0, 0),
+                lc.lc_batch_params(4, 10, 20, 0, 2, 2 ** 31, 0, 0, 0, 0, 0)):
+        assert lc.lib.lc_batch_plan(P(bad), tp) == lc.LC_EINVAL
+    assert lc.lib.lc_batch_plan(P(good), None) == lc.LC_EINVAL
+    assert lc.lib.lc_batch_plan(P(good), tp) == lc.LC_OK
+    fake = ctypes.c_void_p(1 << 20)  # never dereferenced: every call below fails its checks first
+    cands = (ctypes.c_uint32 * 3)(7, 31, 127)
+    # null table / stats
+    assert lc.lib.lc_batch_compress(fake, 30, None, P(good), fake, 1 << 30, fake, 1 << 30, fake, fake, None) == lc.LC_EINVAL
+    assert lc.lib.lc_batch_compress(fake, 30, fake, P(good), fake, 1 << 30, fake, 1 << 30, fake, None, None) == lc.LC_EINVAL
+    # buffers too small
+    assert lc.lib.lc_batch_compress(fake, 30, fake, P(good), fake, good.blob_bytes - 16, fake, 1 << 30, fake, fake,
+                                    None) == lc.LC_ENOSPC
+    assert lc.lib.lc_batch_compress(fake, 30, fake, P(good), fake, 1 << 30, fake, good.ws_bytes - 16, fake, fake,
+                                    None) == lc.LC_ENOSPC
+    # misaligned blob
+    assert lc.lib.lc_batch_compress(fake, 30, fake, P(good), ctypes.c_void_p((1 << 20) + 8), 1 << 30, fake, 1 << 30,
+                                    fake, fake, None) == lc.LC_EINVAL
+    # candidates: above max_eps, not increasing, too many, none
+    for cs in ((7, 31, 127), (31, 7), tuple(range(9)), ()):
+        arr = (ctypes.c_uint32 * max(1, len(cs)))(*cs)
+        assert lc.lib.lc_batch_sizes(fake, 30, fake, P(good), arr, len(cs), fake, 1 << 30, fake, fake,
+                                     None) == lc.LC_EINVAL
+        assert lc.lib.lc_batch_pick_eps(fake, P(good), fake, arr, len(cs), None) == lc.LC_EINVAL
+    assert lc.lib.lc_batch_sizes(fake, 30, fake, P(good), cands, 3, fake, 1 << 30, None, fake, None) == lc.LC_EINVAL
+    # decompress: misaligned output, null table
+    assert lc.lib.lc_batch_decompress(fake, 1 << 30, fake, P(good), 4096, ctypes.c_void_p((1 << 20) + 2), 30, fake,
+                                      None) == lc.LC_EINVAL
+    assert lc.lib.lc_batch_decompress(fake, 1 << 30, None, P(good), 4096, fake, 30, fake, None) == lc.LC_EINVAL

@@ -1,0 +1,189 @@
+"""Batches of lists on the GPU against the CPU oracle, through the C ABI.
+
+A batch gives every list an ordinary blob v1, so the bar is the single-list
+one: each list's blob equals the oracle's blob of that list, byte for byte,
+and the batch decode returns every list's keys at its offset.  The eps
+autotuner must pick, per list, the candidate whose oracle blob is smallest
+(ties to the smaller eps), and its size pass must equal the oracle's sizes.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+CANDS = (7, 31, 127)
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lc():
+    from paper_2412_10770_amd import lc as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def wl():
+    from paper_2412_10770_amd import workloads
+    return workloads
+
+
+def _concat(lists, kb):
+    dt = np.uint32 if kb == 4 else np.uint64
+    cat = np.concatenate([np.asarray(x, dtype=dt) for x in lists]) if lists else np.zeros(0, dt)
+    return torch.from_numpy(cat.view(np.int32 if kb == 4 else np.int64).copy()).to(DEV), cat
+
+
+def _host(t, kb):
+    return t.cpu().numpy().view(np.uint32 if kb == 4 else np.uint64)
+
+
+def _mixed_lists(rng, kb, count):
+    """Lists of every edge length (empty, one key, block +- 1) and gap shape."""
+    top = (1 << (8 * kb)) - 1
+    lens = [0, 1, 2, 63, 64, 65, 1023, 1024, 1025, 4096, 5000]
+    lens += [int(x) for x in rng.integers(1, 6000, count - len(lens))]
+    out = []
+    for i, n in enumerate(lens):
+        kind = i % 5
+        if kind == 0:
+            gaps = rng.integers(1, 65, n)
+        elif kind == 1:
+            gaps = rng.geometric(1.0 / float(np.exp(rng.uniform(np.log(2), np.log(2000)))), n)
+        elif kind == 2:
+            gaps = np.full(n, int(rng.integers(0, 1000)))          # arithmetic progression
+        elif kind == 3:
+            gaps = rng.integers(0, 3, n)                             # duplicates
+        else:
+            gaps = rng.integers(0, max(1, top // max(n, 1) // 2), n)  # sparse, wide keys
+        start = int(rng.integers(0, 1 << 16))
+        keys = start + np.cumsum(gaps.astype(np.uint64), dtype=np.uint64) if n else np.zeros(0, np.uint64)
+        keys = np.minimum(keys, np.uint64(top))
+        out.append(np.sort(keys).astype(np.uint32 if kb == 4 else np.uint64))
+    return out
+
+
+def _check_batch(lc, batch, lists, eps, log2b, frac_bits, kb):
+    for l, keys in enumerate(lists):
+        want = oracle.compress(keys, int(eps[l]), log2b, frac_bits)
+        got = batch.blob(l).data.cpu().numpy()
+        assert int(batch.sizes[l]) == len(want), (l, len(keys), int(eps[l]))
+        assert np.array_equal(got, want), (l, len(keys), int(eps[l]))
+    out = lc.batch_decompress(batch)
+    cat = np.concatenate(lists) if lists else np.zeros(0)
+    assert np.array_equal(_host(out, kb), cat)
+
+
+@pytest.mark.parametrize("kb,log2b,frac_bits", [(4, 10, 20), (8, 10, 20), (4, 6, 20), (8, 12, 32), (8, 8, 0)])
+def test_fixed_eps_per_list(lc, kb, log2b, frac_bits):
+    rng = np.random.default_rng(100 + kb + log2b)
+    lists = _mixed_lists(rng, kb, 40)
+    eps = rng.choice([0, 1, 7, 31, 63, 127, 1000, 65535], len(lists)).astype(np.uint32)
+    _say(f"batch fixed eps kb={kb} log2b={log2b} F={frac_bits} lists={len(lists)}")
+    keys, _ = _concat(lists, kb)
+    batch = lc.batch_compress(keys, [len(x) for x in lists], eps=eps, log2_block=log2b, frac_bits=frac_bits)
+    assert np.array_equal(batch.eps, eps)
+    _check_batch(lc, batch, lists, eps, log2b, frac_bits, kb)
+    # a list's blob is an ordinary blob: the single-list queries work on it
+    l = max(range(len(lists)), key=lambda i: len(lists[i]))
+    b = batch.blob(l)
+    idx = torch.from_numpy(rng.integers(0, len(lists[l]), 500).astype(np.int64)).to(DEV)
+    assert np.array_equal(_host(lc.access(b, idx), kb), lists[l][idx.cpu().numpy()])
+
+
+@pytest.mark.parametrize("kb", [4, 8])
+def test_autotune_picks_the_oracle_argmin(lc, kb):
+    rng = np.random.default_rng(200 + kb)
+    lists = _mixed_lists(rng, kb, 30)
+    _say(f"batch autotune kb={kb} lists={len(lists)}")
+    keys, _ = _concat(lists, kb)
+    lengths = [len(x) for x in lists]
+    # the size pass itself
+    p, table = lc.batch_plan(lengths, CANDS[0], kb, max(CANDS))
+    d_lists = torch.from_numpy(table.view(np.uint8).copy()).to(DEV)
+    ws = torch.empty(p.ws_bytes, dtype=torch.uint8, device=DEV)
+    sizes = torch.empty(len(CANDS) * len(lists), dtype=torch.int64, device=DEV)
+    stats = torch.zeros(2, dtype=torch.int32, device=DEV)
+    lc.batch_sizes_async(keys, d_lists, p, CANDS, ws, sizes, stats)
+    got_sizes = sizes.cpu().numpy().reshape(len(CANDS), len(lists))
+    assert int(stats[0].item()) == 0
+    want_sizes = np.array([[len(oracle.compress(x, e, 10, 20)) for x in lists] for e in CANDS])
+    assert np.array_equal(got_sizes, want_sizes)
+    best = np.array([CANDS[int(np.argmin(want_sizes[:, l]))] for l in range(len(lists))], dtype=np.uint32)
+    batch = lc.batch_compress(keys, lengths, candidates=CANDS)
+    assert np.array_equal(batch.eps, best)
+    _check_batch(lc, batch, lists, best, 10, 20, kb)
+
+
+def test_bad_list_is_flagged_and_skipped(lc):
+    rng = np.random.default_rng(7)
+    lists = _mixed_lists(rng, 4, 12)
+    keys, _ = _concat(lists, 4)
+    lengths = np.array([len(x) for x in lists], dtype=np.uint64)
+    offs = np.concatenate([[0], np.cumsum(lengths)[:-1]]).astype(np.uint64)
+    bad = 9
+    offs_bad = offs.copy()
+    offs_bad[bad] = keys.numel() - lengths[bad] + 1  # one key past the end
+    p, table = lc.batch_plan(lengths, 31, 4, key_offsets=offs_bad)
+    d_lists = torch.from_numpy(table.view(np.uint8).copy()).to(DEV)
+    ws = torch.empty(p.ws_bytes, dtype=torch.uint8, device=DEV)
+    blob = torch.zeros(p.blob_bytes, dtype=torch.uint8, device=DEV)
+    sizes = torch.zeros(len(lists), dtype=torch.int64, device=DEV)
+    stats = torch.zeros(2, dtype=torch.int32, device=DEV)
+    lc.batch_compress_async(keys, d_lists, p, blob, ws, sizes, stats)
+    st = stats.cpu().numpy()
+    assert st[0] == lc.LC_FLAG_BADLIST
+    sz = sizes.cpu().numpy().astype(np.uint64)
+    assert sz[bad] == np.uint64(2 ** 64 - 1)
+    data = blob.cpu().numpy()
+    for l, x in enumerate(lists):
+        if l == bad:
+            continue
+        want = oracle.compress(x, 31, 10, 20)
+        o = int(table["blob_off"][l])
+        assert np.array_equal(data[o:o + len(want)], want), l
+    # decode: the bad list is skipped and flagged, the others land at their offsets
+    out = torch.full((keys.numel(),), -1, dtype=torch.int32, device=DEV)
+    dstats = torch.zeros(1, dtype=torch.int32, device=DEV)
+    lc.batch_decompress_async(blob, d_lists, p, int(st[1]), out, dstats)
+    assert int(dstats.item()) == lc.LC_FLAG_BADLIST
+    h = _host(out, 4)
+    for l, x in enumerate(lists):
+        if l != bad:
+            assert np.array_equal(h[int(offs[l]):int(offs[l]) + len(x)], x), l
+
+
+def test_unsorted_list_is_flagged(lc):
+    rng = np.random.default_rng(8)
+    lists = _mixed_lists(rng, 8, 12)
+    lists[10] = lists[10].copy()  # 5000 keys
+    lists[10][100], lists[10][101] = lists[10][101] + 1, lists[10][100]
+    keys, _ = _concat(lists, 8)
+    with pytest.raises(lc.LcError, match="not sorted"):
+        lc.batch_compress(keys, [len(x) for x in lists], eps=15)
+
+
+def test_posting_lists_reduced(lc, wl):
+    """The batch workload's recipe at 256 lists of 100 .. 10^5 keys, autotuned."""
+    keys, lengths = wl.posting_lists(256, device=DEV, hi=1e5)
+    _say(f"posting lists reduced: {len(lengths)} lists, {keys.numel()} keys")
+    batch = lc.batch_compress(keys, lengths, candidates=CANDS)
+    out = lc.batch_decompress(batch)
+    assert torch.equal(out, keys)
+    host = _host(keys, 4)
+    offs = np.concatenate([[0], np.cumsum(lengths)[:-1]])
+    rng = np.random.default_rng(9)
+    for l in sorted(set(rng.choice(len(lengths), 24, replace=False).tolist()) | {int(np.argmax(lengths))}):
+        x = host[offs[l]:offs[l] + lengths[l]]
+        sizes = [len(oracle.compress(x, e, 10, 20)) for e in CANDS]
+        e = CANDS[int(np.argmin(sizes))]
+        assert batch.eps[l] == e, l
+        assert np.array_equal(batch.blob(l).data.cpu().numpy(), oracle.compress(x, e, 10, 20)), l

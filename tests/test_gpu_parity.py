@@ -213,3 +213,31 @@ def test_width_combinations(lc):
         seen |= set(zip(d[:, 14].tolist(), d[:, 15].tolist()))
         check_all(lc, keys, eps, 6, rng, nq=64, frac_bits=F)
     assert seen == {(a, s) for a in (1, 2, 4, 8) for s in (1, 2, 4, 8)}, sorted(seen)
+
+
+@pytest.mark.parametrize("kb", [4, 8])
+def test_outputs_at_any_key_offset(lc, kb):
+    """Decoded keys go to outputs aligned only to the key width: every group
+    of keys is stored where its output address is 16-byte aligned, the rest
+    key by key."""
+    rng = np.random.default_rng(40 + kb)
+    keys = np.cumsum(rng.integers(1, 300, 20_000)).astype(np.uint32 if kb == 4 else np.uint64)
+    d = _to_dev(keys)
+    blob = lc.compress(d, 31)
+    n = len(keys)
+    dt = torch.int32 if kb == 4 else torch.int64
+    for shift in range(16 // kb):
+        _say(f"output shift {shift} kb={kb}")
+        buf = torch.full((n + 8,), -1, dtype=dt, device=DEV)
+        out = buf[shift:shift + n]
+        lc.decompress(blob, out=out)
+        h = _host(buf, kb)
+        assert np.array_equal(h[shift:shift + n], keys)
+        assert np.all(h[:shift] == h.dtype.type(-1 & ((1 << (8 * kb)) - 1)))
+        assert np.all(h[shift + n:] == h.dtype.type(-1 & ((1 << (8 * kb)) - 1)))
+        for a, b in ((1, 1030), (3, n), (1024, 2049), (5, 6), (n - 7, n)):
+            buf.fill_(-1)
+            lc.decompress_range(blob, a, b, out=buf[shift:shift + b - a])
+            h = _host(buf, kb)
+            assert np.array_equal(h[shift:shift + b - a], keys[a:b]), (shift, a, b)
+            assert np.all(h[shift + b - a:] == h.dtype.type(-1 & ((1 << (8 * kb)) - 1))), (shift, a, b)
