@@ -80,6 +80,156 @@ def cpu_baseline(host_keys, eps: int, budget_s: float = 12.0):
     }
 
 
+def bench_batch(dev, steps: int, warmup: int, nlists: int = 4096, cands=(7, 31, 127)):
+    """Posting-list batch: nlists uint32 lists (lengths from the power law
+    L^-1.1 on [100, 10^6], geometric gaps of per-list mean log-uniform in
+    [2, 2000]).  Batched: one size pass over the eps candidates, the on-device
+    pick, compress and decompress, each one launch (or a few) over all lists.
+    Per list: lc_compress + lc_decompress launched once per list at the eps
+    the autotuner chose, so both sides produce identical blobs.  Each side is
+    timed eagerly and replayed from a captured hipGraph."""
+    import numpy as np
+    import torch
+
+    from paper_2412_10770_amd import lc, workloads
+
+    t0 = time.perf_counter()
+    keys, lengths = workloads.posting_lists(nlists, device=dev)
+    torch.cuda.synchronize()
+    n = keys.numel()
+    log(f"batch: generated {nlists} lists, {n} keys in {time.perf_counter() - t0:.1f} s")
+    offs = np.concatenate([[0], np.cumsum(lengths)[:-1]]).astype(np.int64)
+    p, table = lc.batch_plan(lengths, cands[0], 4, max(cands))
+    d_lists = torch.from_numpy(table.view(np.uint8).copy()).to(dev)
+    ws = torch.empty(p.ws_bytes, dtype=torch.uint8, device=dev)
+    blob = torch.empty(p.blob_bytes, dtype=torch.uint8, device=dev)
+    sizes = torch.empty(nlists, dtype=torch.int64, device=dev)
+    csizes = torch.empty(len(cands) * nlists, dtype=torch.int64, device=dev)
+    stats = torch.zeros(2, dtype=torch.int32, device=dev)
+    dstats = torch.zeros(1, dtype=torch.int32, device=dev)
+    out = torch.empty(n, dtype=torch.int32, device=dev)
+
+    # first pass, eager: learns the eps picked per list and the largest segment area
+    lc.batch_sizes_async(keys, d_lists, p, cands, ws, csizes, stats)
+    lc.batch_pick_eps_async(d_lists, p, csizes, cands)
+    lc.batch_compress_async(keys, d_lists, p, blob, ws, sizes, stats)
+    st = stats.cpu().numpy()
+    assert st[0] == 0, f"batch compress flags {st[0]}"
+    max_seg = int(st[1])
+    lc.batch_decompress_async(blob, d_lists, p, max_seg, out, dstats)
+    assert torch.equal(out, keys) and int(dstats.item()) == 0, "batch round trip failed"
+    chosen = d_lists.cpu().numpy().view(lc.BATCH_LIST_DTYPE)["eps"].copy()
+    bsizes = sizes.cpu().numpy()
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    def mark(marks, i):
+        if marks is not None:
+            marks[i].record()
+
+    def batched(marks):
+        stats.zero_()
+        dstats.zero_()
+        mark(marks, 0)
+        lc.batch_sizes_async(keys, d_lists, p, cands, ws, csizes, stats)
+        lc.batch_pick_eps_async(d_lists, p, csizes, cands)
+        mark(marks, 1)
+        lc.batch_compress_async(keys, d_lists, p, blob, ws, sizes, stats)
+        mark(marks, 2)
+        lc.batch_decompress_async(blob, d_lists, p, max_seg, out, dstats)
+        mark(marks, 3)
+
+    # per-list launches into the same slot layout of a second buffer
+    blob2 = torch.empty(p.blob_bytes, dtype=torch.uint8, device=dev)
+    ws2 = torch.empty(max(16, max(lc.compress_bound(int(m), 4, int(e))[1] for m, e in zip(lengths, chosen))),
+                      dtype=torch.uint8, device=dev)
+    nb2 = torch.zeros(nlists, dtype=torch.int64, device=dev)
+    fl2 = torch.zeros(1, dtype=torch.int32, device=dev)
+    out2 = torch.empty(n, dtype=torch.int32, device=dev)
+    kviews = [keys[o:o + m] for o, m in zip(offs, lengths)]
+    oviews = [out2[o:o + m] for o, m in zip(offs, lengths)]
+    bviews = [blob2[int(table["blob_off"][l]):int(table["blob_off"][l] + table["blob_cap"][l])] for l in range(nlists)]
+    for l in range(nlists):
+        lc.compress_async(kviews[l], int(chosen[l]), bviews[l], ws2, nb2[l:l + 1], fl2)
+    torch.cuda.synchronize()
+    assert int(fl2.item()) == 0
+    infos = [lc.Blob.from_device(bviews[l]) for l in range(nlists)]
+    assert np.array_equal(nb2.cpu().numpy(), bsizes), "per-list blob sizes differ from the batch's"
+
+    def per_list(marks):
+        mark(marks, 0)
+        for l in range(nlists):
+            lc.compress_async(kviews[l], int(chosen[l]), bviews[l], ws2, nb2[l:l + 1], fl2)
+        mark(marks, 1)
+        for l in range(nlists):
+            lc.decompress(infos[l], out=oviews[l])
+        mark(marks, 2)
+
+    def run(fn, nmarks, reps, graph, o):
+        g = None
+        if graph:
+            fn(None)  # warm (kernel attributes set outside the capture)
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                fn(None)
+        else:
+            for _ in range(warmup):
+                fn(None)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            o.zero_()  # every run / replay must rewrite the whole output
+            a, b = ev(), ev()
+            marks = None if graph else [ev() for _ in range(nmarks)]
+            a.record()
+            if graph:
+                g.replay()
+            else:
+                fn(marks)
+            b.record()
+            torch.cuda.synchronize()
+            assert torch.equal(o, keys), f"round trip failed ({'graph replay' if graph else 'eager'})"
+            times.append((a.elapsed_time(b), [m0.elapsed_time(m1) for m0, m1 in zip(marks, marks[1:])]
+                          if marks else None))
+        return g, times
+
+    res = {}
+    for name, fn, nm, reps in (("batched", batched, 4, steps), ("per_list", per_list, 3, max(2, steps // 4))):
+        for graph in (False, True):
+            log(f"batch: timing {name} {'graph' if graph else 'eager'}")
+            g, times = run(fn, nm, reps, graph, out if name == "batched" else out2)
+            total = float(np.mean([t[0] for t in times]))
+            entry = {"ms": round(total, 3)}
+            if not graph:
+                ph = np.mean([t[1] for t in times], axis=0)
+                if name == "batched":
+                    entry.update(autotune_ms=round(float(ph[0]), 3), compress_ms=round(float(ph[1]), 3),
+                                 decompress_ms=round(float(ph[2]), 3))
+                else:
+                    entry.update(compress_ms=round(float(ph[0]), 3), decompress_ms=round(float(ph[1]), 3))
+            res[f"{name}_{'graph' if graph else 'eager'}"] = entry
+            del g
+    b, pl = res["batched_eager"], res["per_list_eager"]
+    key_bytes = n * 4
+    return {
+        "workload": f"{nlists} sorted uint32 lists, lengths ~ L^-1.1 on [100, 1e6] ({n} keys), geometric gaps "
+                    f"with per-list mean log-uniform in [2, 2000]; eps per list argmin-size over {list(cands)}",
+        "n": n, "nlists": nlists,
+        "ratio": round(float(bsizes.sum()) / key_bytes, 5),
+        "bits_per_key": round(8.0 * float(bsizes.sum()) / n, 4),
+        "eps_chosen": {str(c): int((chosen == c).sum()) for c in cands},
+        "lists_expanding": int((bsizes > lengths * 4).sum()),
+        "decoded_GBps": {"batched": round(key_bytes / b["decompress_ms"] / 1e6, 2),
+                         "per_list": round(key_bytes / pl["decompress_ms"] / 1e6, 2)},
+        "compress_GBps": {"batched": round(key_bytes / b["compress_ms"] / 1e6, 2),
+                          "per_list": round(key_bytes / pl["compress_ms"] / 1e6, 2)},
+        "step_ms": {k: v["ms"] for k, v in res.items()},
+        "phases_ms": {k: {kk: vv for kk, vv in v.items() if kk != "ms"} for k, v in res.items() if "eager" in k},
+        "note": "batched step = autotune (size pass over the candidates + pick) + compress + decompress; "
+                "per-list step = compress + decompress only (eps given), identical blobs",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +240,8 @@ def main():
     ap.add_argument("--access", type=int, default=10_000_000)
     ap.add_argument("--lower-bound", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the posting-list batch measurement")
+    ap.add_argument("--batch-only", action="store_true", help="only the posting-list batch measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path is "
@@ -103,6 +255,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.batch_only:
+        print(json.dumps(bench_batch(dev, args.steps, args.warmup)), flush=True)
+        return
     eps_list = [int(e) for e in args.eps.split(",")]
     t0 = time.perf_counter()
     keys = workloads.lognormal_distinct(args.n, device=dev)
@@ -252,6 +407,10 @@ def main():
         "lower_bound_lookups_per_s": round(args.lower_bound / lb_ms * 1e3, 1),
         "paper_cpu_context": {"lc-simd": "6.535 GiB/s decode, Xeon Gold 6430, CCNews (Fig. 3a)"},
     }
+    if not args.no_batch:
+        del out, wss, blobs
+        torch.cuda.empty_cache()
+        result["batching"] = bench_batch(dev, args.steps, args.warmup)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a prefix of the keys")
         host = workloads.as_numpy(keys)

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "lc_launch.h"
@@ -1391,6 +1392,37 @@ inline uint32_t query_grid(uint64_t m)
 }
 
 
+// Raises kernel f's dynamic LDS limit to `bytes` (above the default 64 KB)
+// once per device; later calls with no larger need make no runtime call, so
+// launches stay capturable into graphs.
+hipError_t allow_lds(const void* f, size_t bytes)
+{
+    if (bytes <= 65536) return hipSuccess;
+    struct Entry {
+        const void* f;
+        int dev;
+        size_t bytes;
+    };
+    static std::mutex mu;
+    static Entry set[64];
+    static int nset = 0;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(mu);
+    for (int i = 0; i < nset; i++)
+        if (set[i].f == f && set[i].dev == dev && set[i].bytes >= bytes) return hipSuccess;
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    for (int i = 0; i < nset; i++)
+        if (set[i].f == f && set[i].dev == dev) {
+            set[i].bytes = bytes;
+            return hipSuccess;
+        }
+    if (nset < 64) set[nset++] = Entry{f, dev, bytes};
+    return hipSuccess;
+}
+
 hipError_t launch_batch_fit(const void* d_keys, const lc_batch_list* d_lists, const BatchArgs& a, const Cands& c,
                             uint8_t* d_blob, const Workspace& ws, uint64_t* d_sizes, uint32_t* d_stats, bool sizes_only,
                             hipStream_t stream)
@@ -1467,12 +1499,8 @@ hipError_t launch_batch_decode(const uint8_t* d_blob, const lc_batch_list* d_lis
     auto k = a.kb == 4 ? batch_decode_kernel<4> : batch_decode_kernel<8>;
     auto kbig = a.kb == 4 ? batch_decode_big_kernel<4> : batch_decode_big_kernel<8>;
     hipError_t e;
-    if (lds_small > 65536 &&
-        (e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_small)) != hipSuccess)
-        return e;
-    if (big_cap > small_cap && lds_big > 65536 &&
-        (e = hipFuncSetAttribute((const void*)kbig, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_big)) != hipSuccess)
-        return e;
+    if ((e = allow_lds((const void*)k, lds_small)) != hipSuccess) return e;
+    if (big_cap > small_cap && (e = allow_lds((const void*)kbig, lds_big)) != hipSuccess) return e;
     for (uint64_t b0 = 0; b0 < a.total_blocks; b0 += kMaxGrid) {
         const uint64_t nblk = a.total_blocks - b0 < kMaxGrid ? a.total_blocks - b0 : kMaxGrid;
         const uint64_t per_xcd = (nblk + 7) / 8;
@@ -1533,12 +1561,8 @@ hipError_t launch_decode(const uint8_t* d_blob, const Layout& L, uint64_t begin,
     auto kb = L.kb == 4 ? (range ? decode_big_kernel<4, true> : decode_big_kernel<4, false>)
                         : (range ? decode_big_kernel<8, true> : decode_big_kernel<8, false>);
     hipError_t e;
-    if (lds_small > 65536 &&
-        (e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_small)) != hipSuccess)
-        return e;
-    if (big_cap > small_cap && lds_big > 65536 &&
-        (e = hipFuncSetAttribute((const void*)kb, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_big)) != hipSuccess)
-        return e;
+    if ((e = allow_lds((const void*)k, lds_small)) != hipSuccess) return e;
+    if (big_cap > small_cap && (e = allow_lds((const void*)kb, lds_big)) != hipSuccess) return e;
     // Stage the compressed bytes the decode will read in the on-die cache:
     // the whole tail of the blob for a full decode; the directory entries and
     // slabs of the blocks touched for a range (its segment areas are found
