@@ -230,6 +230,87 @@ def bench_batch(dev, steps: int, warmup: int, nlists: int = 4096, cands=(7, 31, 
     }
 
 
+def bench_serve(dev, n: int = 1_000_000_000, qps_points=(1e3, 1e4, 1e5, 1e6, None), arena_bytes: int = 2 << 30,
+                max_batch: int = 1024, max_inflight: int = 4, eps_cands=(15, 63, 255, 1023)):
+    """Request server over a compressed store of n uint64 keys (gaps
+    max(1, ceil(lognormal(3, 1.5)))), eps = the candidate giving the smallest
+    blob.  Poisson request streams at each rate (None: all at time 0, the
+    saturation point): 70% decode_range of length floor(exp(U[0, ln 1e6])),
+    20% access(i), 10% lower_bound(q).  Latency = completion - scheduled
+    arrival.  Unbatched reference: the same server at one request per launch
+    and one launch in flight (plain per-request launches, no host overhead)."""
+    import numpy as np
+    import torch
+
+    from paper_2412_10770_amd import lc, workloads
+
+    t0 = time.perf_counter()
+    keys = workloads.lognormal_gaps(n, seed=workloads.SEED_BASE + 5, device=dev)
+    torch.cuda.synchronize()
+    lo, hi = int(keys[0]), int(keys[-1])
+    log(f"serve: generated {n} keys in {time.perf_counter() - t0:.1f} s")
+    best = None
+    sizes = {}
+    for e in eps_cands:
+        b = lc.compress(keys, e)
+        sizes[e] = b.nbytes
+        if best is None or b.nbytes < best.nbytes:
+            best = b
+        del b
+        torch.cuda.empty_cache()
+    blob = best
+    # the store round-trips (checked in slices to bound the extra memory)
+    step = 100_000_000
+    for s0 in range(0, n, step):
+        e0 = min(n, s0 + step)
+        assert torch.equal(lc.decompress_range(blob, s0, e0), keys[s0:e0]), "store round trip failed"
+    del keys
+    torch.cuda.empty_cache()
+    log(f"serve: store eps={blob.info.eps}, {blob.nbytes / 1e9:.3f} GB ({blob.bits_per_key:.3f} bits/key)")
+
+    def point(srv, qps, count, seed):
+        op, a, b, arr = workloads.request_stream(count, n, lo, hi, qps, seed=seed)
+        res, st = srv.run(lc.requests(op, a, b, arr))
+        assert np.all(res["status"] == 0), "request failed"
+        lat = (res["complete_ns"] - arr.astype(np.int64)) / 1e3
+        span_s = (res["complete_ns"].max() - int(arr.min())) / 1e9
+        out_bytes = float(np.where(op == 1, (b - a) * 8, 8).sum())
+        return {
+            "qps_offered": qps if qps is not None else "saturation",
+            "requests": count,
+            "p50_us": round(float(np.percentile(lat, 50)), 1),
+            "p99_us": round(float(np.percentile(lat, 99)), 1),
+            "qps_achieved": round(count / span_s, 1),
+            "decoded_GBps": round(float(np.where(op == 1, (b - a) * 8, 0).sum()) / span_s / 1e9, 2),
+            "output_GBps": round(out_bytes / span_s / 1e9, 2),
+            "launches": st["launches"], "max_batch_seen": st["max_batch_seen"],
+            "arena_waits": st["arena_waits"], "peak_arena_MB": round(st["peak_arena_bytes"] / 2 ** 20, 1),
+        }
+
+    points = []
+    with lc.Server(blob, arena_bytes, max_batch, max_inflight) as srv:
+        point(srv, None, 2000, seed=1)  # warm
+        for k, qps in enumerate(qps_points):
+            count = 100_000 if qps is None else int(min(100_000, max(1000, qps * 0.25)))
+            log(f"serve: qps={qps or 'saturation'} ({count} requests)")
+            points.append(point(srv, qps, count, seed=100 + k))
+    with lc.Server(blob, arena_bytes, 1, 1) as srv:
+        log("serve: unbatched reference at saturation")
+        unb = point(srv, None, 20_000, seed=200)
+    sat = points[-1]
+    return {
+        "workload": f"{n} sorted uint64 keys, gaps max(1, ceil(lognormal(3, 1.5))); store eps argmin-size over "
+                    f"{list(eps_cands)}; Poisson arrivals, 70% decode_range (length floor(exp(U[0, ln 1e6]))), "
+                    f"20% access, 10% lower_bound; output arena {arena_bytes >> 20} MiB, "
+                    f"{max_batch} requests per launch, {max_inflight} launches in flight",
+        "store": {"eps": blob.info.eps, "bytes": blob.nbytes, "bits_per_key": round(blob.bits_per_key, 4),
+                  "bytes_by_eps": {str(e): v for e, v in sizes.items()}},
+        "points": points,
+        "unbatched_saturation": unb,
+        "saturation_speedup_vs_unbatched": round(sat["qps_achieved"] / unb["qps_achieved"], 2),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -242,6 +323,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the posting-list batch measurement")
     ap.add_argument("--batch-only", action="store_true", help="only the posting-list batch measurement")
+    ap.add_argument("--no-serve", action="store_true", help="skip the request-server measurement")
+    ap.add_argument("--serve-only", action="store_true", help="only the request-server measurement")
+    ap.add_argument("--serve-n", type=int, default=1_000_000_000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path is "
@@ -257,6 +341,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.batch_only:
         print(json.dumps(bench_batch(dev, args.steps, args.warmup)), flush=True)
+        return
+    if args.serve_only:
+        print(json.dumps(bench_serve(dev, args.serve_n)), flush=True)
         return
     eps_list = [int(e) for e in args.eps.split(",")]
     t0 = time.perf_counter()
@@ -411,6 +498,10 @@ def main():
         del out, wss, blobs
         torch.cuda.empty_cache()
         result["batching"] = bench_batch(dev, args.steps, args.warmup)
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        torch.cuda.empty_cache()
+        result["serving"] = bench_serve(dev, args.serve_n)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a prefix of the keys")
         host = workloads.as_numpy(keys)

@@ -238,6 +238,78 @@ lc_status lc_batch_decompress(const void* d_blob, uint64_t blob_cap, const lc_ba
                               const lc_batch_params* p, uint32_t max_seg_bytes, void* d_out, uint64_t nout,
                               uint32_t* d_stats, void* stream);
 
+/* ---- Request server --------------------------------------------------------
+ * A request loop over one device-resident blob with continuous batching:
+ * requests are admitted in arrival order while the output arena (the HBM
+ * budget for results) has room and a launch slot is free; each launch serves
+ * a batch of mixed requests (range decodes, point accesses, lower_bounds) in
+ * one kernel; up to max_inflight launches run concurrently on their own
+ * streams, and a request that arrives while they run joins the next one.  A
+ * request's result is exactly what the single-request entry points give
+ * (lc_decompress_range / lc_access / lc_lower_bound), alone or in any mix.
+ * The decode of Def. 1 restricted to a range, access (Sec. II-B) and
+ * lower_bound (Sec. II-B, III-A) are the operations served.
+ */
+
+#define LC_OP_RANGE 1u       /* keys [a, b): (b - a) * key_bytes output bytes */
+#define LC_OP_ACCESS 2u      /* K[a]: key_bytes output bytes */
+#define LC_OP_LOWER_BOUND 3u /* first i with K[i] >= a (n if none): 8 output bytes (u64) */
+
+/* One request (40 bytes). */
+typedef struct lc_request {
+    uint32_t op;         /* LC_OP_* */
+    uint32_t reserved;
+    uint64_t a, b;       /* operands, as listed at LC_OP_* */
+    uint64_t arrival_ns; /* scheduled arrival, ns after the start of lc_server_run */
+    void* d_dest;        /* optional device pointer: the result is copied there before its
+                            arena space is given back; NULL: discarded */
+} lc_request;
+
+/* What happened to one request (32 bytes); times in ns after the start. */
+typedef struct lc_request_result {
+    int64_t admit_ns;    /* admitted: output space reserved, put into a launch */
+    int64_t launch_ns;   /* its launch was enqueued */
+    int64_t complete_ns; /* its launch (and copy to d_dest) was seen complete */
+    int32_t status;      /* LC_OK; LC_EINVAL (bad op / range / index >= n); LC_ENOSPC (result
+                            larger than the arena); LC_EDEVICE */
+    uint32_t launch;     /* index of the launch that served it */
+} lc_request_result;
+
+typedef struct lc_serve_config {
+    uint32_t max_batch;    /* requests per launch, 1 .. 65536 */
+    uint32_t max_inflight; /* concurrent launches (streams), 1 .. 16 */
+} lc_serve_config;
+
+/* Totals of one lc_server_run. */
+typedef struct lc_serve_stats {
+    uint64_t launches;
+    uint64_t max_batch_seen;  /* most requests in one launch */
+    uint64_t peak_arena_bytes;
+    uint64_t arena_waits;     /* admissions stopped because the arena was full */
+} lc_serve_stats;
+
+typedef struct lc_server lc_server; /* opaque */
+
+/* Creates a server for the blob at d_blob (parsed header `info`) on the
+ * current device.  d_arena: arena_bytes (>= 16) of device memory, 16-byte
+ * aligned, for request outputs -- the HBM budget.  The blob and the arena
+ * stay owned by the caller and must outlive the server.  The server
+ * allocates its streams, events, pinned staging and small device request
+ * tables here (none later).  Errors: LC_EINVAL, LC_EDEVICE. */
+lc_status lc_server_create(const void* d_blob, const lc_blob_info* info, void* d_arena, uint64_t arena_bytes,
+                           const lc_serve_config* cfg, lc_server** out);
+
+/* Serves h_reqs[0 .. n) as they arrive (by arrival_ns, measured from the
+ * call) and returns when all are complete; h_res[i] describes h_reqs[i].
+ * Busy-polls on the calling thread.  stats may be NULL.  Errors: LC_EINVAL
+ * (NULL arguments), LC_EDEVICE (a launch failed: in-flight work is drained,
+ * unserved requests get status LC_EDEVICE). */
+lc_status lc_server_run(lc_server* s, const lc_request* h_reqs, uint64_t n, lc_request_result* h_res,
+                        lc_serve_stats* stats);
+
+/* Waits for the server's streams and frees what lc_server_create allocated. */
+lc_status lc_server_destroy(lc_server* s);
+
 /* Static description of a status code. */
 const char* lc_strerror(lc_status s);
 

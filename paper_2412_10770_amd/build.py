@@ -8,7 +8,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblc.so")
-SOURCES = [os.path.join(CSRC, "lc_kernels.hip"), os.path.join(CSRC, "lc_api.cpp")]
+SOURCES = [os.path.join(CSRC, "lc_kernels.hip"), os.path.join(CSRC, "lc_api.cpp"), os.path.join(CSRC, "lc_serve.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -22,7 +22,8 @@ FLAGS = [
 
 def build(out: str = LIB, extra: list | None = None) -> str:
     tmp = out + ".tmp"
-    cmd = [HIPCC, *FLAGS, *(extra or []), "-x", "hip", SOURCES[0], "-x", "hip", SOURCES[1], "-o", tmp]
+    srcs = [x for src in SOURCES for x in ("-x", "hip", src)]
+    cmd = [HIPCC, *FLAGS, *(extra or []), *srcs, "-o", tmp]
     subprocess.check_call(cmd)
     os.replace(tmp, out)
     return out

@@ -193,6 +193,8 @@ lc_status check_batch_fit(const void* d_keys, const lc_batch_list* d_lists, cons
 
 }  // namespace
 
+lc_status lc::layout_from_info(const lc_blob_info* info, lc::Layout* L) { return layout_of(info, L); }
+
 LC_API lc_status lc_compress_bound(uint64_t n, const lc_params* p, uint64_t* blob_max, uint64_t* ws_bytes)
 {
     lc_status st = check_params(p);

@@ -1011,6 +1011,62 @@ __device__ __forceinline__ uint64_t code_at(const uint8_t* blob, const Layout& L
     return (win >> sh) & ((1ull << L.w) - 1);
 }
 
+// K[i] for i < L.n: directory entry, binary search over the block's u16
+// starts, anchor, slope, one or two slab words.
+template <int KB>
+__device__ __forceinline__ uint64_t access_one(const uint8_t* __restrict__ blob, const Layout& L, uint64_t i)
+{
+    const uint64_t b = i >> L.log2b;
+    const uint32_t j = (uint32_t)(i & ((1ull << L.log2b) - 1));
+    const BlockView v = block_view(blob, L, b);
+    const uint16_t* st = reinterpret_cast<const uint16_t*>(blob + v.seg_off);
+    uint32_t t = 0;
+    for (uint32_t step = pow2_floor(v.nseg); step; step >>= 1)
+        if (t + step < v.nseg && st[t + step] <= j) t += step;
+    const uint8_t* an = blob + v.seg_off + a16(2ull * v.nseg);
+    const uint8_t* sl = an + a16((uint64_t)v.ab * v.nseg);
+    const uint64_t anchor = load_key<KB>(blob + L.off_first, b) + load_w(an, t, v.ab);
+    const uint64_t A = load_w(sl, t, v.sb);
+    return anchor + ((A * (uint64_t)(j - st[t])) >> L.F) + code_at(blob, L, b, j) - L.eps;
+}
+
+// First i with K[i] >= x (L.n if none): binary search over first_keys, then
+// over the block's segment anchors (segment pruning), then over the decoded
+// keys of one segment.
+template <int KB>
+__device__ __forceinline__ uint64_t lower_bound_one(const uint8_t* __restrict__ blob, const Layout& L, uint64_t x)
+{
+    const uint8_t* fk = blob + L.off_first;
+    if (L.n == 0 || load_key<KB>(fk, 0) >= x) return 0;
+    // last block whose first key is < x
+    uint64_t b = 0;
+    for (uint64_t step = 1ull << (63 - __clzll((long long)L.nblocks)); step; step >>= 1)
+        if (b + step < L.nblocks && load_key<KB>(fk, b + step) < x) b += step;
+    const BlockView v = block_view(blob, L, b);
+    const uint16_t* st = reinterpret_cast<const uint16_t*>(blob + v.seg_off);
+    const uint8_t* an = blob + v.seg_off + a16(2ull * v.nseg);
+    const uint8_t* sl = an + a16((uint64_t)v.ab * v.nseg);
+    const uint64_t first = load_key<KB>(fk, b);
+    // last segment whose anchor (its first key) is < x
+    uint32_t t = 0;
+    for (uint32_t step = pow2_floor(v.nseg); step; step >>= 1)
+        if (t + step < v.nseg && first + load_w(an, t + step, v.ab) < x) t += step;
+    const uint32_t s = st[t];
+    const uint32_t e = t + 1 < v.nseg ? st[t + 1] : v.nkeys;
+    const uint64_t anchor = first + load_w(an, t, v.ab);
+    const uint64_t A = load_w(sl, t, v.sb);
+    // keys s+1 .. e-1 of the segment: first one >= x, else e
+    uint32_t lo = s + 1, hi = e;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        uint64_t k = anchor + ((A * (uint64_t)(mid - s)) >> L.F) + code_at(blob, L, b, mid) - L.eps;
+        if constexpr (KB == 4) k &= 0xFFFFFFFFull;
+        if (k >= x) hi = mid;
+        else lo = mid + 1;
+    }
+    return (b << L.log2b) + lo;
+}
+
 template <int KB>
 __global__ __launch_bounds__(256) void access_kernel(const uint8_t* __restrict__ blob, Layout L,
                                                      const uint64_t* __restrict__ idx, uint64_t m,
@@ -1025,19 +1081,7 @@ __global__ __launch_bounds__(256) void access_kernel(const uint8_t* __restrict__
             bad = true;
             continue;
         }
-        const uint64_t b = i >> L.log2b;
-        const uint32_t j = (uint32_t)(i & ((1ull << L.log2b) - 1));
-        const BlockView v = block_view(blob, L, b);
-        const uint16_t* st = reinterpret_cast<const uint16_t*>(blob + v.seg_off);
-        uint32_t t = 0;
-        for (uint32_t step = pow2_floor(v.nseg); step; step >>= 1)
-            if (t + step < v.nseg && st[t + step] <= j) t += step;
-        const uint8_t* an = blob + v.seg_off + a16(2ull * v.nseg);
-        const uint8_t* sl = an + a16((uint64_t)v.ab * v.nseg);
-        const uint64_t anchor = load_key<KB>(blob + L.off_first, b) + load_w(an, t, v.ab);
-        const uint64_t A = load_w(sl, t, v.sb);
-        const uint64_t key = anchor + ((A * (uint64_t)(j - st[t])) >> L.F) + code_at(blob, L, b, j) - L.eps;
-        store_key<KB>(out, q, key);
+        store_key<KB>(out, q, access_one<KB>(blob, L, i));
     }
     if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(flags, kFlagRange);
 }
@@ -1048,41 +1092,47 @@ __global__ __launch_bounds__(256) void lower_bound_kernel(const uint8_t* __restr
                                                           uint64_t* __restrict__ pos)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint8_t* fk = blob + L.off_first;
-    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < m; q += stride) {
-        const uint64_t x = load_key<KB>(qs, q);
-        if (L.n == 0 || load_key<KB>(fk, 0) >= x) {
-            pos[q] = 0;
-            continue;
-        }
-        // last block whose first key is < x
-        uint64_t b = 0;
-        for (uint64_t step = 1ull << (63 - __clzll((long long)L.nblocks)); step; step >>= 1)
-            if (b + step < L.nblocks && load_key<KB>(fk, b + step) < x) b += step;
-        const BlockView v = block_view(blob, L, b);
-        const uint16_t* st = reinterpret_cast<const uint16_t*>(blob + v.seg_off);
-        const uint8_t* an = blob + v.seg_off + a16(2ull * v.nseg);
-        const uint8_t* sl = an + a16((uint64_t)v.ab * v.nseg);
-        const uint64_t first = load_key<KB>(fk, b);
-        // last segment whose anchor (its first key) is < x
-        uint32_t t = 0;
-        for (uint32_t step = pow2_floor(v.nseg); step; step >>= 1)
-            if (t + step < v.nseg && first + load_w(an, t + step, v.ab) < x) t += step;
-        const uint32_t s = st[t];
-        const uint32_t e = t + 1 < v.nseg ? st[t + 1] : v.nkeys;
-        const uint64_t anchor = first + load_w(an, t, v.ab);
-        const uint64_t A = load_w(sl, t, v.sb);
-        // keys s+1 .. e-1 of the segment: first one >= x, else e
-        uint32_t lo = s + 1, hi = e;
-        while (lo < hi) {
+    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < m; q += stride)
+        pos[q] = lower_bound_one<KB>(blob, L, load_key<KB>(qs, q));
+}
+
+// ---------------------------------------------------------------------------
+// Request batches (the server's launches)
+// ---------------------------------------------------------------------------
+
+// One launch serves a batch of requests: waves [0, range_items) decode one
+// block of one range request each (requests found by binary search over
+// item_off), the remaining waves answer 64 point requests each.  Outputs go
+// to the server's arena at each request's offset.
+template <int KB>
+__global__ __launch_bounds__(64) void serve_kernel(const uint8_t* __restrict__ blob, ServeArgs s,
+                                                   const ServeRange* __restrict__ ranges,
+                                                   const ServePoint* __restrict__ points, uint8_t* __restrict__ arena)
+{
+    const uint64_t w = blockIdx.x;
+    if (w < s.range_items) {
+        uint32_t lo = 0, hi = s.nrange;
+        while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) >> 1;
-            uint64_t k = anchor + ((A * (uint64_t)(mid - s)) >> L.F) + code_at(blob, L, b, mid) - L.eps;
-            if constexpr (KB == 4) k &= 0xFFFFFFFFull;
-            if (k >= x) hi = mid;
-            else lo = mid + 1;
+            if (ranges[mid].item_off <= w) lo = mid;
+            else hi = mid;
         }
-        pos[q] = (b << L.log2b) + lo;
+        const ServeRange R = ranges[lo];
+        DecodeArgs d{};
+        d.L = s.L;
+        d.begin = R.a;
+        d.end = R.b;
+        d.raw_cap = s.raw_cap;
+        d.bytes = s.L.blob_bytes;
+        d.flags = nullptr;
+        decode_block<KB, true>(blob, d, (R.a >> s.L.log2b) + (w - R.item_off), s.raw_cap, false, arena + R.out_off);
+        return;
     }
+    const uint64_t q = (w - s.range_items) * 64 + threadIdx.x;
+    if (q >= s.npoint) return;
+    const ServePoint P = points[q];
+    if (P.op == kServeAccess) store_key<KB>(arena + P.out_off, 0, access_one<KB>(blob, s.L, P.key));
+    else *reinterpret_cast<uint64_t*>(arena + P.out_off) = lower_bound_one<KB>(blob, s.L, P.key);
 }
 
 // ---------------------------------------------------------------------------
@@ -1595,6 +1645,22 @@ hipError_t launch_decode(const uint8_t* d_blob, const Layout& L, uint64_t begin,
                                stream, d_blob, a, small_cap, d_out);
         }
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_serve(const uint8_t* d_blob, const ServeArgs& args, const ServeRange* d_ranges,
+                        const ServePoint* d_points, uint8_t* d_arena, hipStream_t stream)
+{
+    ServeArgs s = args;
+    // areas above the small cap decode from global memory (decode_segments)
+    s.raw_cap = decode_raw_cap(s.L.max_seg_bytes, kSegRawSmall);
+    const uint64_t waves = s.range_items + (s.npoint + 63) / 64;
+    if (waves == 0) return hipSuccess;
+    auto k = s.L.kb == 4 ? serve_kernel<4> : serve_kernel<8>;
+    const size_t lds = decode_lds_bytes(s.L.log2b, s.L.res_stride, s.raw_cap);
+    hipError_t e = allow_lds((const void*)k, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3((uint32_t)waves), dim3(64), lds, stream, d_blob, s, d_ranges, d_points, d_arena);
     return hipGetLastError();
 }
 

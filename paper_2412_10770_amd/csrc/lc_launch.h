@@ -55,11 +55,35 @@ struct BatchArgs {
     uint64_t blob_cap;      // bytes of the batch buffer
 };
 
+// A batch of requests for one launch of the server (device tables).
+constexpr uint32_t kServeAccess = 2;       // = LC_OP_ACCESS
+constexpr uint32_t kServeLowerBound = 3;   // = LC_OP_LOWER_BOUND
+struct ServeRange {                        // decode [a, b) to arena + out_off
+    uint64_t a, b, out_off;
+    uint64_t item_off;                     // waves of all earlier range requests of the batch
+};
+struct ServePoint {                        // one access(key) or lower_bound(key) to arena + out_off
+    uint64_t key, out_off;
+    uint32_t op, pad;
+    uint64_t pad2;
+};
+struct ServeArgs {
+    Layout L;
+    uint32_t nrange, npoint;
+    uint64_t range_items;                  // waves of the range requests (one per block touched)
+    uint32_t raw_cap;                      // LDS bytes for a staged segment area (set by launch_serve)
+};
+
+// Layout of a parsed blob header, re-checked (lc_api.cpp).
+lc_status layout_from_info(const lc_blob_info* info, Layout* L);
+
 // Kernel launchers; each returns the hipError_t of its last launch.
 hipError_t launch_compress(const void* d_keys, const Layout& L, uint8_t* d_blob, const Workspace& ws,
                            uint64_t* d_blob_bytes, uint32_t* d_flags, hipStream_t stream);
 hipError_t launch_decode(const uint8_t* d_blob, const Layout& L, uint64_t begin, uint64_t end,
                          void* d_out, hipStream_t stream);
+hipError_t launch_serve(const uint8_t* d_blob, const ServeArgs& s, const ServeRange* d_ranges, const ServePoint* d_points,
+                        uint8_t* d_arena, hipStream_t stream);
 hipError_t launch_access(const uint8_t* d_blob, const Layout& L, const uint64_t* d_idx, uint64_t m,
                          void* d_out, uint32_t* d_flags, hipStream_t stream);
 hipError_t launch_lower_bound(const uint8_t* d_blob, const Layout& L, const void* d_q, uint64_t m,

@@ -37,7 +37,8 @@ DEFAULT_FRAC_BITS = 20
 
 EXPORTED = ("lc_compress_bound", "lc_compress", "lc_info", "lc_decompress", "lc_decompress_range",
             "lc_access", "lc_lower_bound", "lc_batch_plan", "lc_batch_compress", "lc_batch_sizes",
-            "lc_batch_pick_eps", "lc_batch_decompress", "lc_strerror")
+            "lc_batch_pick_eps", "lc_batch_decompress", "lc_server_create", "lc_server_run",
+            "lc_server_destroy", "lc_strerror")
 
 
 class lc_params(ctypes.Structure):
@@ -67,6 +68,23 @@ BATCH_LIST_DTYPE = np.dtype([("key_off", "<u8"), ("n", "<u8"), ("blob_off", "<u8
 assert BATCH_LIST_DTYPE.itemsize == 64
 
 
+class lc_serve_config(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32)]
+
+
+class lc_serve_stats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in ("launches", "max_batch_seen", "peak_arena_bytes", "arena_waits")]
+
+
+# struct lc_request / lc_request_result
+REQUEST_DTYPE = np.dtype([("op", "<u4"), ("reserved", "<u4"), ("a", "<u8"), ("b", "<u8"), ("arrival_ns", "<u8"),
+                          ("d_dest", "<u8")])
+RESULT_DTYPE = np.dtype([("admit_ns", "<i8"), ("launch_ns", "<i8"), ("complete_ns", "<i8"), ("status", "<i4"),
+                         ("launch", "<u4")])
+assert REQUEST_DTYPE.itemsize == 40 and RESULT_DTYPE.itemsize == 32
+OP_RANGE, OP_ACCESS, OP_LOWER_BOUND = 1, 2, 3
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
@@ -87,6 +105,9 @@ def _load():
         "lc_batch_sizes": [vp, u64, vp, ctypes.POINTER(lc_batch_params), vp, u32, vp, u64, vp, vp, vp],
         "lc_batch_pick_eps": [vp, ctypes.POINTER(lc_batch_params), vp, vp, u32, vp],
         "lc_batch_decompress": [vp, u64, vp, ctypes.POINTER(lc_batch_params), u32, vp, u64, vp, vp],
+        "lc_server_create": [vp, I, vp, u64, ctypes.POINTER(lc_serve_config), ctypes.POINTER(vp)],
+        "lc_server_run": [vp, vp, u64, vp, ctypes.POINTER(lc_serve_stats)],
+        "lc_server_destroy": [vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -422,3 +443,66 @@ def batch_decompress(batch: Batch, out: torch.Tensor | None = None, stream=None,
     if check:
         _raise_flags(int(stats.item()), "lc_batch_decompress")
     return out
+
+
+# ---------------------------------------------------------------------------
+# Request server
+# ---------------------------------------------------------------------------
+
+class Server:
+    """Continuous-batching request loop over one device-resident blob (the
+    loop itself runs in liblc.so).  The arena is the HBM budget for results."""
+
+    def __init__(self, blob: Blob, arena_bytes: int = 2 << 30, max_batch: int = 1024, max_inflight: int = 4):
+        self.blob = blob
+        self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=blob.data.device)
+        cfg = lc_serve_config(max_batch, max_inflight)
+        h = ctypes.c_void_p()
+        torch.cuda.synchronize(blob.data.device)  # blob and arena complete before other streams read them
+        _check(lib.lc_server_create(_ptr(blob.data), ctypes.byref(blob.info), _ptr(self.arena), arena_bytes,
+                                    ctypes.byref(cfg), ctypes.byref(h)), "lc_server_create")
+        self._h = h
+
+    def run(self, requests: np.ndarray):
+        """Serve a structured array of REQUEST_DTYPE; returns (results of
+        RESULT_DTYPE, stats dict).  Blocks until every request completed."""
+        req = np.ascontiguousarray(requests, dtype=REQUEST_DTYPE)
+        res = np.zeros(len(req), dtype=RESULT_DTYPE)
+        st = lc_serve_stats()
+        torch.cuda.synchronize(self.blob.data.device)  # d_dest buffers ready
+        rc = lib.lc_server_run(self._h, req.ctypes.data_as(ctypes.c_void_p), len(req),
+                               res.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st))
+        _check(rc, "lc_server_run")
+        return res, {f: getattr(st, f) for f, _ in lc_serve_stats._fields_}
+
+    def close(self):
+        if self._h:
+            lib.lc_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def requests(ops, a, b=None, arrival_ns=None, d_dest=None) -> np.ndarray:
+    """Build a REQUEST_DTYPE array."""
+    ops = np.asarray(ops, dtype=np.uint32)
+    r = np.zeros(len(ops), dtype=REQUEST_DTYPE)
+    r["op"] = ops
+    r["a"] = np.asarray(a, dtype=np.uint64)
+    if b is not None:
+        r["b"] = np.asarray(b, dtype=np.uint64)
+    if arrival_ns is not None:
+        r["arrival_ns"] = np.asarray(arrival_ns, dtype=np.uint64)
+    if d_dest is not None:
+        r["d_dest"] = np.asarray(d_dest, dtype=np.uint64)
+    return r

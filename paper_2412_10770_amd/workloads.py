@@ -29,6 +29,12 @@ Recipes (sizes are parameters; the full sizes are the defaults):
   P(L) ~ L^-1.1 truncated to [100, 10^6] (inverse CDF, floored; about
   3e8 keys in all), each list starting at 0 with geometric gaps (support
   1, 2, ...) of mean m, m = exp(U[ln 2, ln 2000]) drawn per list.
+* ``request_stream``: a serving request stream over a store of n keys:
+  Poisson arrivals at a given rate (exponential inter-arrival times; rate
+  None = all at time 0), 70% range requests of length
+  floor(exp(U[0, ln max_len])) starting uniformly in [0, n - length], 20%
+  access(i) with i uniform, 10% lower_bound(q) with q uniform over the key
+  range.
 * queries: ``uniform_indices`` (i uniform in [0, n)) and ``uniform_keys``
   (q uniform over [lo, hi]).
 """
@@ -175,6 +181,32 @@ def posting_lists(nlists: int = 4096, seed: int = SEED_BASE + 6, device="cpu", l
     if n and int(keys.max()) >= 1 << 32:
         raise ValueError("a list exceeds the uint32 key range")
     return keys.to(torch.int32), lengths
+
+
+def request_stream(count: int, n: int, key_lo: int, key_hi: int, qps: float | None, seed: int,
+                   max_len: int = 1_000_000, mix=(0.7, 0.2, 0.1)):
+    """(op, a, b, arrival_ns) numpy arrays; op 1 = range [a, b), 2 = access(a),
+    3 = lower_bound(a)."""
+    rng = np.random.default_rng(seed)
+    u = rng.random(count)
+    op = np.where(u < mix[0], 1, np.where(u < mix[0] + mix[1], 2, 3)).astype(np.uint32)
+    a = np.zeros(count, dtype=np.uint64)
+    b = np.zeros(count, dtype=np.uint64)
+    rl = np.floor(np.exp(rng.uniform(0.0, math.log(max_len), count))).astype(np.int64)
+    rl = np.minimum(np.maximum(rl, 1), n)
+    start = (rng.random(count) * (n - rl + 1)).astype(np.int64)
+    rng_ = op == 1
+    a[rng_] = start[rng_]
+    b[rng_] = (start + rl)[rng_]
+    acc = op == 2
+    a[acc] = rng.integers(0, n, int(acc.sum()))
+    lb = op == 3
+    a[lb] = rng.integers(key_lo, key_hi + 1, int(lb.sum()), dtype=np.uint64)
+    if qps is None:
+        arrival = np.zeros(count, dtype=np.uint64)
+    else:
+        arrival = np.cumsum(rng.exponential(1e9 / qps, count)).astype(np.uint64)
+    return op, a, b, arrival
 
 
 def uniform_indices(m: int, n: int, seed: int, device="cpu") -> torch.Tensor:
