@@ -613,17 +613,13 @@ struct DecodeArgs {
     uint32_t* flags;       // where a corrupt directory entry is reported (may be null)
 };
 
-// A block's segment area is staged raw in LDS.  The main decode launch
-// reserves at most kSegRawSmall bytes for it (less when the blob's largest
-// area, a header field, is smaller), which keeps ~29 waves resident per CU;
-// it skips the few blocks with larger areas -- sparse stretches where most
-// segments hold two keys.  A second launch, only when such blocks exist,
-// finds them 64 directory entries per wave and decodes them the same way
-// with up to kSegRawMax bytes of LDS; areas beyond that (possible only for
-// 4096-key blocks) are decoded segment-parallel from global memory.
+// A block's segment area is staged raw in LDS when it is at most
+// kSegRawSmall bytes (less when the blob's largest area, a header field, is
+// smaller), which keeps ~29 waves resident per CU.  The few larger areas --
+// sparse stretches where most segments hold two keys -- are not staged: the
+// same wave builds the segment bitmap and decodes the keys reading the model
+// arrays from the blob (cached), so no second launch is needed.
 constexpr uint32_t kSegRawSmall = 4096;
-constexpr uint32_t kSegRawMax = 32768;
-constexpr uint32_t kBigPerWave = 4;
 constexpr uint32_t kTouchGrid = 8192;
 constexpr uint64_t kTouchMinBytes = 1ull << 20;  // below this the touch pass costs more than it saves
 // 16-byte chunks per lane loaded before the first wait (slab, segment area).
@@ -657,6 +653,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 struct BlockCtx {
     uint64_t first, eps, obase;
     uint32_t F, w, ab, sb, jlo, jhi;
+    uint32_t tmax;  // last segment index of the block
     const uint32_t* s_slab;
     const uint32_t* s_bm;
     const uint32_t* s_pre;
@@ -684,7 +681,7 @@ __device__ __forceinline__ uint64_t slope_term(uint64_t A, uint32_t d, uint32_t 
 // anchor-first_key[] of AB bytes, A[] of SB bytes) are read through
 // `start`, `an`, `sl` -- LDS copies for staged blocks, the blob otherwise.
 // AB / SB are the block's byte widths (0: read at the runtime widths).
-template <int KB, bool RANGE, uint32_t AB, uint32_t SB, typename P16, typename P8>
+template <int KB, bool RANGE, bool CLAMP, uint32_t AB, uint32_t SB, typename P16, typename P8>
 __device__ __forceinline__ void decode_keys(const BlockCtx& c, P16 start, P8 an, P8 sl, void* __restrict__ out)
 {
     constexpr uint32_t V = 16 / KB;
@@ -699,6 +696,10 @@ __device__ __forceinline__ void decode_keys(const BlockCtx& c, P16 start, P8 an,
         else return load_w(sl, t, c.sb);
     };
     auto key_at = [&](uint32_t j, uint32_t t) {
+        // keys past the block end in a block's last group (never stored) may
+        // count stray bitmap bits; CLAMP keeps their model reads inside the
+        // arrays when those live in global memory
+        if constexpr (CLAMP) t = t < c.tmax ? t : c.tmax;
         const uint32_t d = j - start[t];
         const uint64_t pred = c.first + anchor_of(t) + slope_term<SB == 0 ? 8 : SB>(slope_of(t), d, c.F);
         const uint32_t bitpos = j * c.w;
@@ -748,7 +749,7 @@ __device__ __forceinline__ void decode_keys(const BlockCtx& c, P16 start, P8 an,
 
 // Staged blocks: dispatch once per block on the (anchor, slope) widths so the
 // per-key loop has no width branches.
-template <int KB, bool RANGE>
+template <int KB, bool RANGE, bool CLAMP>
 __device__ __forceinline__ void decode_staged(const BlockCtx& c, const uint8_t* s_raw, uint32_t off_an,
                                               uint32_t off_sl, void* __restrict__ out)
 {
@@ -756,42 +757,15 @@ __device__ __forceinline__ void decode_staged(const BlockCtx& c, const uint8_t* 
     const uint8_t* an = s_raw + off_an;
     const uint8_t* sl = s_raw + off_sl;
 #define LC_DECODE_CASE(A_, S_) \
-    case (A_) * 16 + (S_): decode_keys<KB, RANGE, A_, S_>(c, st, an, sl, out); return;
+    case (A_) * 16 + (S_): decode_keys<KB, RANGE, CLAMP, A_, S_>(c, st, an, sl, out); return;
     switch (c.ab * 16 + c.sb) {
         LC_DECODE_CASE(1, 1) LC_DECODE_CASE(1, 2) LC_DECODE_CASE(1, 4) LC_DECODE_CASE(1, 8)
         LC_DECODE_CASE(2, 1) LC_DECODE_CASE(2, 2) LC_DECODE_CASE(2, 4) LC_DECODE_CASE(2, 8)
         LC_DECODE_CASE(4, 1) LC_DECODE_CASE(4, 2) LC_DECODE_CASE(4, 4) LC_DECODE_CASE(4, 8)
         LC_DECODE_CASE(8, 1) LC_DECODE_CASE(8, 2) LC_DECODE_CASE(8, 4) LC_DECODE_CASE(8, 8)
-        default: decode_keys<KB, RANGE, 0, 0>(c, st, an, sl, out); return;
+        default: decode_keys<KB, RANGE, CLAMP, 0, 0>(c, st, an, sl, out); return;
     }
 #undef LC_DECODE_CASE
-}
-
-// Blocks whose segment area is not staged: one lane per segment, keys of
-// the segment decoded in order.  Model loads are coalesced across lanes;
-// most segments here hold one or two keys.
-template <int KB, bool RANGE>
-__device__ __forceinline__ void decode_segments(const BlockCtx& c, const uint8_t* __restrict__ g_seg,
-                                                uint32_t nseg, uint32_t nkeys, uint32_t off_an, uint32_t off_sl,
-                                                void* __restrict__ out)
-{
-    const uint32_t lane = lane_id();
-    const uint16_t* g_start = reinterpret_cast<const uint16_t*>(g_seg);
-    const uint64_t wmask = (1ull << c.w) - 1;
-    for (uint32_t t = lane; t < nseg; t += 64) {
-        const uint32_t s = g_start[t];
-        const uint32_t e = t + 1 < nseg ? g_start[t + 1] : nkeys;
-        const uint64_t anchor = c.first + load_w(g_seg + off_an, t, c.ab);
-        const uint64_t A = load_w(g_seg + off_sl, t, c.sb);
-        const uint32_t j0 = s > c.jlo ? s : c.jlo, j1 = e < c.jhi ? e : c.jhi;
-        for (uint32_t j = j0; j < j1; j++) {
-            const uint64_t pred = anchor + ((A * (uint64_t)(j - s)) >> c.F);
-            const uint32_t bitpos = j * c.w;
-            const uint32_t wd = bitpos >> 5, sh = bitpos & 31;
-            const uint64_t win = (uint64_t)c.s_slab[wd] | ((uint64_t)c.s_slab[wd + 1] << 32);
-            store_key<KB>(out, c.obase + j, pred + ((win >> sh) & wmask) - c.eps);
-        }
-    }
 }
 
 // Streams bytes [lo, hi) of the blob through the caches (wide coalesced
@@ -826,7 +800,7 @@ __global__ __launch_bounds__(256) void touch_kernel(const uint8_t* __restrict__ 
 //     contiguous output (non-temporal: the output is not re-read here).
 template <int KB, bool RANGE>
 __device__ __forceinline__ void decode_block(const uint8_t* __restrict__ blob, const DecodeArgs& a, uint64_t b,
-                                             uint32_t raw_cap, bool skip_big, void* __restrict__ out)
+                                             uint32_t raw_cap, void* __restrict__ out)
 {
     const Layout& L = a.L;
     const uint32_t lane = threadIdx.x;
@@ -862,7 +836,6 @@ __device__ __forceinline__ void decode_block(const uint8_t* __restrict__ blob, c
         return;
     }
     const bool staged = seg_bytes <= raw_cap;
-    if (skip_big && !staged) return;  // left to the big-block launch
     const uint8_t* g_seg = blob + seg_off;
 
     const uint32_t nch_seg = staged ? seg_bytes / 16 : 0u;
@@ -904,6 +877,7 @@ __device__ __forceinline__ void decode_block(const uint8_t* __restrict__ blob, c
     c.s_slab = s_slab;
     c.s_bm = s_bm;
     c.s_pre = s_pre;
+    c.tmax = nseg - 1;
     const uint64_t i0 = b << L.log2b;
     c.jlo = 0;
     c.jhi = nkeys;
@@ -914,68 +888,43 @@ __device__ __forceinline__ void decode_block(const uint8_t* __restrict__ blob, c
         c.jhi = (uint32_t)(iend - i0);
         c.obase = i0 - a.begin;
     }
-    if (!staged) {
-        decode_segments<KB, RANGE>(c, g_seg, nseg, nkeys, off_an, off_sl, out);
+    // segment starts -> LDS bitmap + per-word prefix counts
+    auto build_bitmap = [&](const uint16_t* st16) {
+        const uint32_t smask = (1u << L.log2b) - 1;
+        for (uint32_t t = lane; t < nseg; t += 64) {
+            const uint32_t st = st16[t] & smask;
+            atomicOr(&s_bm[st >> 5], 1u << (st & 31));
+        }
+        __syncthreads();
+        uint32_t carry = 0;
+        for (uint32_t w0 = 0; w0 < nwords; w0 += 64) {
+            const uint32_t w = w0 + lane;
+            const uint32_t cnt = w < nwords ? __popc(s_bm[w]) : 0u;
+            const uint32_t incl = wave_incl_sum32(cnt);
+            if (w < nwords) s_pre[w] = carry + incl - cnt;
+            carry += __shfl(incl, 63, 64);
+        }
+        __syncthreads();
+    };
+    if (!staged) {  // model arrays read from the blob (cached), keys decoded as for staged blocks
+        build_bitmap(reinterpret_cast<const uint16_t*>(g_seg));
+        decode_staged<KB, RANGE, true>(c, g_seg, off_an, off_sl, out);
         return;
     }
-
-    const uint32_t smask = (1u << L.log2b) - 1;
-    const uint16_t* st16 = reinterpret_cast<const uint16_t*>(s_raw);
-    for (uint32_t t = lane; t < nseg; t += 64) {
-        const uint32_t st = st16[t] & smask;
-        atomicOr(&s_bm[st >> 5], 1u << (st & 31));
-    }
-    __syncthreads();
-    uint32_t carry = 0;
-    for (uint32_t w0 = 0; w0 < nwords; w0 += 64) {
-        const uint32_t w = w0 + lane;
-        const uint32_t cnt = w < nwords ? __popc(s_bm[w]) : 0u;
-        const uint32_t incl = wave_incl_sum32(cnt);
-        if (w < nwords) s_pre[w] = carry + incl - cnt;
-        carry += __shfl(incl, 63, 64);
-    }
-    __syncthreads();
-    decode_staged<KB, RANGE>(c, s_raw, off_an, off_sl, out);
+    build_bitmap(reinterpret_cast<const uint16_t*>(s_raw));
+    decode_staged<KB, RANGE, false>(c, s_raw, off_an, off_sl, out);
 }
 
-// Main launch: one wave per block, blocks with areas over the small cap
-// skipped.  Workgroup w runs on XCD w % 8, so blocks are assigned XCD-major:
-// each XCD walks a contiguous run of blocks (and of directory and segment
-// bytes).
+// One wave per block.  Workgroup w runs on XCD w % 8, so blocks are
+// assigned XCD-major: each XCD walks a contiguous run of blocks (and of
+// directory and segment bytes).
 template <int KB, bool RANGE>
 __global__ __launch_bounds__(64) void decode_kernel(const uint8_t* __restrict__ blob, DecodeArgs a,
                                                      void* __restrict__ out)
 {
     const uint64_t rel = (uint64_t)(blockIdx.x % 8) * a.per_xcd + blockIdx.x / 8;
     if (rel >= a.nblk) return;
-    decode_block<KB, RANGE>(blob, a, a.b_first + rel, a.raw_cap, true, out);
-}
-
-// Big-block launch: wave w checks the directory entries of blocks
-// [4 w, 4 w + 4) of the launch and decodes, one after another, those whose
-// segment area exceeds the main launch's cap (small_cap).  Big blocks sit
-// together (sparse stretches of the key range), so few per wave keeps the
-// launch balanced.
-template <int KB, bool RANGE>
-__global__ __launch_bounds__(64) void decode_big_kernel(const uint8_t* __restrict__ blob, DecodeArgs a,
-                                                         uint32_t small_cap, void* __restrict__ out)
-{
-    const uint64_t rel = (uint64_t)blockIdx.x * kBigPerWave + threadIdx.x;
-    bool big = false;
-    if (threadIdx.x < kBigPerWave && rel < a.nblk) {
-        const uint4 dv = reinterpret_cast<const uint4*>(blob + a.L.off_dir)[a.b_first + rel];
-        const uint32_t nseg = dv.z ? dv.z : 1u;
-        const uint32_t ab = (dv.w >> 16) & 0xFF, sb = dv.w >> 24;
-        const uint64_t bytes = a16(2ull * nseg) + a16((uint64_t)ab * nseg) + a16((uint64_t)sb * nseg);
-        big = bytes > small_cap;
-    }
-    uint64_t m = __ballot(big);
-    while (m) {
-        const uint32_t k = (uint32_t)__ffsll((unsigned long long)m) - 1;
-        m &= m - 1;
-        decode_block<KB, RANGE>(blob, a, a.b_first + (uint64_t)blockIdx.x * kBigPerWave + k, a.raw_cap, false, out);
-        __syncthreads();  // LDS is reused by the next block
-    }
+    decode_block<KB, RANGE>(blob, a, a.b_first + rel, a.raw_cap, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -1125,7 +1074,7 @@ __global__ __launch_bounds__(64) void serve_kernel(const uint8_t* __restrict__ b
         d.raw_cap = s.raw_cap;
         d.bytes = s.L.blob_bytes;
         d.flags = nullptr;
-        decode_block<KB, true>(blob, d, (R.a >> s.L.log2b) + (w - R.item_off), s.raw_cap, false, arena + R.out_off);
+        decode_block<KB, true>(blob, d, (R.a >> s.L.log2b) + (w - R.item_off), s.raw_cap, arena + R.out_off);
         return;
     }
     const uint64_t q = (w - s.range_items) * 64 + threadIdx.x;
@@ -1345,8 +1294,7 @@ __global__ __launch_bounds__(256) void batch_emit_kernel(const lc_batch_list* __
 }
 
 // Decode of every block of the batch, one wave per block, XCD-major as the
-// single-list decode; blocks whose segment area exceeds raw_cap are left to
-// batch_decode_big_kernel.  List l's keys go to out + key_off * KB.
+// single-list decode.  List l's keys go to out + key_off * KB.
 template <int KB>
 __device__ __forceinline__ bool batch_block(const lc_batch_list* __restrict__ lists, const BatchArgs& a, uint64_t gb,
                                             lc_batch_list* li, Layout* L, uint64_t* b)
@@ -1362,7 +1310,7 @@ template <int KB>
 __global__ __launch_bounds__(64) void batch_decode_kernel(const uint8_t* __restrict__ blob,
                                                           const lc_batch_list* __restrict__ lists, BatchArgs a,
                                                           uint64_t blk0, uint64_t nblk, uint64_t per_xcd,
-                                                          uint32_t raw_cap, bool skip_big, void* __restrict__ out,
+                                                          uint32_t raw_cap, void* __restrict__ out,
                                                           uint32_t* __restrict__ stats)
 {
     const uint64_t rel = (uint64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
@@ -1379,47 +1327,7 @@ __global__ __launch_bounds__(64) void batch_decode_kernel(const uint8_t* __restr
     d.raw_cap = raw_cap;
     d.bytes = li.blob_cap;
     d.flags = stats;
-    decode_block<KB, true>(blob + li.blob_off, d, b, raw_cap, skip_big,
-                           reinterpret_cast<uint8_t*>(out) + li.key_off * KB);
-}
-
-template <int KB>
-__global__ __launch_bounds__(64) void batch_decode_big_kernel(const uint8_t* __restrict__ blob,
-                                                              const lc_batch_list* __restrict__ lists, BatchArgs a,
-                                                              uint64_t blk0, uint64_t nblk, uint32_t small_cap,
-                                                              uint32_t raw_cap, void* __restrict__ out,
-                                                              uint32_t* __restrict__ stats)
-{
-    const uint64_t rel = (uint64_t)blockIdx.x * kBigPerWave + threadIdx.x;
-    bool big = false;
-    if (threadIdx.x < kBigPerWave && rel < nblk) {
-        lc_batch_list li;
-        Layout L;
-        uint64_t b;
-        if (batch_block<KB>(lists, a, blk0 + rel, &li, &L, &b)) {
-            const uint4 dv = reinterpret_cast<const uint4*>(blob + li.blob_off + L.off_dir)[b];
-            const uint32_t nseg = dv.z ? dv.z : 1u;
-            const uint32_t ab = (dv.w >> 16) & 0xFF, sb = dv.w >> 24;
-            big = a16(2ull * nseg) + a16((uint64_t)ab * nseg) + a16((uint64_t)sb * nseg) > small_cap;
-        }
-    }
-    uint64_t m = __ballot(big);
-    while (m) {
-        const uint32_t k = (uint32_t)__ffsll((unsigned long long)m) - 1;
-        m &= m - 1;
-        lc_batch_list li;
-        DecodeArgs d{};
-        uint64_t b;
-        batch_block<KB>(lists, a, blk0 + (uint64_t)blockIdx.x * kBigPerWave + k, &li, &d.L, &b);
-        d.begin = 0;
-        d.end = li.n;
-        d.raw_cap = raw_cap;
-        d.bytes = li.blob_cap;
-        d.flags = stats;
-        decode_block<KB, true>(blob + li.blob_off, d, b, raw_cap, false,
-                               reinterpret_cast<uint8_t*>(out) + li.key_off * KB);
-        __syncthreads();  // LDS is reused by the next block
-    }
+    decode_block<KB, true>(blob + li.blob_off, d, b, raw_cap, reinterpret_cast<uint8_t*>(out) + li.key_off * KB);
 }
 
 // eps of list l := the candidate with the smallest size (ties: the smaller
@@ -1542,23 +1450,16 @@ hipError_t launch_batch_decode(const uint8_t* d_blob, const lc_batch_list* d_lis
     uint32_t w = 0;
     while ((1ull << w) < 2ull * a.max_eps + 1) w++;
     const uint64_t res_stride = align16(((1ull << a.log2b) * w + 7) / 8);
-    const uint32_t small_cap = decode_raw_cap(max_seg_bytes, kSegRawSmall);
-    const uint32_t big_cap = decode_raw_cap(max_seg_bytes, kSegRawMax);
-    const size_t lds_small = decode_lds_bytes(a.log2b, res_stride, small_cap);
-    const size_t lds_big = decode_lds_bytes(a.log2b, res_stride, big_cap);
+    const uint32_t raw_cap = decode_raw_cap(max_seg_bytes, kSegRawSmall);
+    const size_t lds = decode_lds_bytes(a.log2b, res_stride, raw_cap);
     auto k = a.kb == 4 ? batch_decode_kernel<4> : batch_decode_kernel<8>;
-    auto kbig = a.kb == 4 ? batch_decode_big_kernel<4> : batch_decode_big_kernel<8>;
-    hipError_t e;
-    if ((e = allow_lds((const void*)k, lds_small)) != hipSuccess) return e;
-    if (big_cap > small_cap && (e = allow_lds((const void*)kbig, lds_big)) != hipSuccess) return e;
+    hipError_t e = allow_lds((const void*)k, lds);
+    if (e != hipSuccess) return e;
     for (uint64_t b0 = 0; b0 < a.total_blocks; b0 += kMaxGrid) {
         const uint64_t nblk = a.total_blocks - b0 < kMaxGrid ? a.total_blocks - b0 : kMaxGrid;
         const uint64_t per_xcd = (nblk + 7) / 8;
-        hipLaunchKernelGGL(k, dim3((uint32_t)(per_xcd * 8)), dim3(64), lds_small, stream, d_blob, d_lists, a, b0, nblk,
-                           per_xcd, small_cap, big_cap > small_cap, d_out, d_stats);
-        if (big_cap > small_cap)
-            hipLaunchKernelGGL(kbig, dim3((uint32_t)((nblk + kBigPerWave - 1) / kBigPerWave)), dim3(64), lds_big, stream,
-                               d_blob, d_lists, a, b0, nblk, small_cap, big_cap, d_out, d_stats);
+        hipLaunchKernelGGL(k, dim3((uint32_t)(per_xcd * 8)), dim3(64), lds, stream, d_blob, d_lists, a, b0, nblk,
+                           per_xcd, raw_cap, d_out, d_stats);
     }
     return hipGetLastError();
 }
@@ -1601,18 +1502,13 @@ hipError_t launch_decode(const uint8_t* d_blob, const Layout& L, uint64_t begin,
 {
     if (begin >= end) return hipSuccess;
     const uint64_t b_lo = begin >> L.log2b, b_hi = (end - 1) >> L.log2b;
-    const uint32_t small_cap = decode_raw_cap(L.max_seg_bytes, kSegRawSmall);
-    const uint32_t big_cap = decode_raw_cap(L.max_seg_bytes, kSegRawMax);
-    const size_t lds_small = decode_lds_bytes(L.log2b, L.res_stride, small_cap);
-    const size_t lds_big = decode_lds_bytes(L.log2b, L.res_stride, big_cap);
+    const uint32_t raw_cap = decode_raw_cap(L.max_seg_bytes, kSegRawSmall);
+    const size_t lds = decode_lds_bytes(L.log2b, L.res_stride, raw_cap);
     const bool range = !(begin == 0 && end == L.n);
     auto k = L.kb == 4 ? (range ? decode_kernel<4, true> : decode_kernel<4, false>)
                        : (range ? decode_kernel<8, true> : decode_kernel<8, false>);
-    auto kb = L.kb == 4 ? (range ? decode_big_kernel<4, true> : decode_big_kernel<4, false>)
-                        : (range ? decode_big_kernel<8, true> : decode_big_kernel<8, false>);
-    hipError_t e;
-    if ((e = allow_lds((const void*)k, lds_small)) != hipSuccess) return e;
-    if (big_cap > small_cap && (e = allow_lds((const void*)kb, lds_big)) != hipSuccess) return e;
+    hipError_t e = allow_lds((const void*)k, lds);
+    if (e != hipSuccess) return e;
     // Stage the compressed bytes the decode will read in the on-die cache:
     // the whole tail of the blob for a full decode; the directory entries and
     // slabs of the blocks touched for a range (its segment areas are found
@@ -1635,15 +1531,10 @@ hipError_t launch_decode(const uint8_t* d_blob, const Layout& L, uint64_t begin,
         a.b_first = b0;
         a.nblk = (b_hi + 1 - b0) < kMaxGrid ? (b_hi + 1 - b0) : kMaxGrid;
         a.per_xcd = (a.nblk + 7) / 8;
-        a.raw_cap = small_cap;
+        a.raw_cap = raw_cap;
         a.bytes = L.blob_bytes;
         a.flags = nullptr;
-        hipLaunchKernelGGL(k, dim3((uint32_t)(a.per_xcd * 8)), dim3(64), lds_small, stream, d_blob, a, d_out);
-        if (big_cap > small_cap) {
-            a.raw_cap = big_cap;
-            hipLaunchKernelGGL(kb, dim3((uint32_t)((a.nblk + kBigPerWave - 1) / kBigPerWave)), dim3(64), lds_big,
-                               stream, d_blob, a, small_cap, d_out);
-        }
+        hipLaunchKernelGGL(k, dim3((uint32_t)(a.per_xcd * 8)), dim3(64), lds, stream, d_blob, a, d_out);
     }
     return hipGetLastError();
 }

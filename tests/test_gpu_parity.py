@@ -241,3 +241,38 @@ def test_outputs_at_any_key_offset(lc, kb):
             h = _host(buf, kb)
             assert np.array_equal(h[shift:shift + b - a], keys[a:b]), (shift, a, b)
             assert np.all(h[shift + b - a:] == h.dtype.type(-1 & ((1 << (8 * kb)) - 1))), (shift, a, b)
+
+
+@pytest.mark.parametrize("kb", [4, 8])
+def test_sparse_blocks_read_from_global(lc, kb):
+    """Blocks whose segment area exceeds the 4 KB staged in LDS (about two
+    keys per segment) are decoded with the model arrays read from the blob:
+    full decode, ranges at every output phase, and a batch of such lists at
+    odd key offsets, all against the oracle's blob and the keys."""
+    rng = np.random.default_rng(60 + kb)
+    top = (1 << (8 * kb)) - 1
+    n = 9000
+    gaps = rng.integers(1, top // (2 * n), n).astype(np.uint64)
+    gaps[rng.random(n) < 0.3] = 1  # mixed with dense stretches
+    keys = np.cumsum(gaps, dtype=np.uint64).astype(np.uint32 if kb == 4 else np.uint64)
+    _say(f"sparse blocks kb={kb}")
+    blob = check_all(lc, keys, 3, 10, rng, nq=500)
+    h = blob.info
+    data = blob.data.cpu().numpy()
+    dirs = data[h.off_dir:h.off_dir + 16 * h.nblocks].reshape(-1, 16)
+    ns = dirs[:, 8:12].copy().view(np.uint32).ravel().astype(np.int64)
+    area = (2 * ns + 15) // 16 * 16 + (dirs[:, 14] * ns + 15) // 16 * 16 + (dirs[:, 15] * ns + 15) // 16 * 16
+    assert (area > 4096).sum() >= 2, "the case must contain blocks that are not staged"
+    dt = torch.int32 if kb == 4 else torch.int64
+    for shift in range(16 // kb):
+        buf = torch.full((n + 8,), -1, dtype=dt, device=DEV)
+        for a, b in ((1, n), (1023, 3077), (2 + shift, n - 1)):
+            lc.decompress_range(blob, a, b, out=buf[shift:shift + b - a])
+            assert np.array_equal(_host(buf, kb)[shift:shift + b - a], keys[a:b]), (shift, a, b)
+    # batch: three copies at odd offsets (lists after a 1-key and a 3-key list)
+    lists = [keys[:1], keys, keys[:3], keys, keys[5:]]
+    cat = np.concatenate(lists)
+    d = _to_dev(cat)
+    batch = lc.batch_compress(d, [len(x) for x in lists], eps=3)
+    assert np.array_equal(_host(lc.batch_decompress(batch), kb), cat)
+    assert np.array_equal(batch.blob(1).data.cpu().numpy(), oracle.compress(keys, 3, 10))
