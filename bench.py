@@ -230,6 +230,48 @@ def bench_batch(dev, steps: int, warmup: int, nlists: int = 4096, cands=(7, 31, 
     }
 
 
+def bench_lookups(dev, n: int = 200_000_000, eps: int = 63, n_access: int = 10_000_000, n_lb: int = 1_000_000,
+                  reps: int = 10):
+    """Point lookups on the heterogeneous-runs workload: n uint64 keys in
+    alternating dense (gaps 1..4) and Zipf(1.2) runs; eps 63; n_access
+    access(i) with i uniform and n_lb lower_bound(q) with q uniform over the
+    key range, each batch one launch timed with HIP events."""
+    import numpy as np
+    import torch
+
+    from paper_2412_10770_amd import lc, workloads
+
+    keys = workloads.heterogeneous_runs(n, device=dev)
+    blob = lc.compress(keys, eps)
+    idx = workloads.uniform_indices(n_access, n, seed=workloads.SEED_BASE + 104, device=dev)
+    q = workloads.uniform_keys(n_lb, int(keys[0]), int(keys[-1]), seed=workloads.SEED_BASE + 105, device=dev)
+    acc = lc.access(blob, idx)
+    pos = lc.lower_bound(blob, q)
+    assert torch.equal(acc, keys[idx]) and torch.equal(pos, torch.searchsorted(keys, q, side="left"))
+    flags = torch.zeros(1, dtype=torch.int32, device=dev)
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    ta, tl = [], []
+    for _ in range(reps):
+        e0, e1, e2 = ev(), ev(), ev()
+        e0.record()
+        lc.access(blob, idx, out=acc, flags=flags, check=False)
+        e1.record()
+        lc.lower_bound(blob, q, out=pos)
+        e2.record()
+        torch.cuda.synchronize()
+        ta.append(e0.elapsed_time(e1))
+        tl.append(e1.elapsed_time(e2))
+    assert int(flags.item()) == 0
+    return {
+        "workload": f"{n} uint64 keys, alternating dense (gaps U[1,4]) and Zipf(1.2) runs of 1e4..1e6 keys; "
+                    f"eps {eps}; {n_access} access(i), i uniform; {n_lb} lower_bound(q), q uniform over the key range",
+        "bits_per_key": round(blob.bits_per_key, 4),
+        "access_lookups_per_s": round(n_access / float(np.mean(ta)) * 1e3, 1),
+        "lower_bound_lookups_per_s": round(n_lb / float(np.mean(tl)) * 1e3, 1),
+        "access_ms": round(float(np.mean(ta)), 4), "lower_bound_ms": round(float(np.mean(tl)), 4),
+    }
+
+
 def bench_serve(dev, n: int = 1_000_000_000, qps_points=(1e3, 1e4, 1e5, 1e6, None), arena_bytes: int = 2 << 30,
                 max_batch: int = 1024, max_inflight: int = 4, eps_cands=(15, 63, 255, 1023)):
     """Request server over a compressed store of n uint64 keys (gaps
@@ -326,6 +368,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the request-server measurement")
     ap.add_argument("--serve-only", action="store_true", help="only the request-server measurement")
     ap.add_argument("--serve-n", type=int, default=1_000_000_000)
+    ap.add_argument("--no-lookups", action="store_true", help="skip the heterogeneous-runs lookup measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path is "
@@ -494,6 +537,9 @@ def main():
         "lower_bound_lookups_per_s": round(args.lower_bound / lb_ms * 1e3, 1),
         "paper_cpu_context": {"lc-simd": "6.535 GiB/s decode, Xeon Gold 6430, CCNews (Fig. 3a)"},
     }
+    if not args.no_lookups:
+        result["lookups"] = bench_lookups(dev)
+        torch.cuda.empty_cache()
     if not args.no_batch:
         del out, wss, blobs
         torch.cuda.empty_cache()

@@ -113,3 +113,65 @@ def test_heterogeneous_runs_200m(lc, wl):
     """200M uint64 keys, alternating dense / Zipf(1.2) runs; eps 63; 10M access, 1M lower_bound."""
     keys = wl.heterogeneous_runs(200_000_000, device=DEV)
     check_fullsize(lc, keys, 63, n_access=10_000_000, n_lb=1_000_000, seed=3)
+
+
+def test_posting_lists_4096(lc, wl):
+    """The batch workload at full size: 4096 uint32 lists (~2.9e8 keys), eps
+    autotuned over {7, 31, 127}.  Whole-batch round trip; on sampled lists
+    (the longest, the shortest and random ones) the chosen eps equals the
+    argmin of the oracle's exact sizes and the blob equals the oracle's."""
+    cands = (7, 31, 127)
+    keys, lengths = wl.posting_lists(4096, device=DEV)
+    _say(f"posting lists full size: {keys.numel()} keys")
+    batch = lc.batch_compress(keys, lengths, candidates=cands)
+    assert torch.equal(lc.batch_decompress(batch), keys)
+    host = keys.cpu().numpy().view(np.uint32)
+    offs = np.concatenate([[0], np.cumsum(lengths)[:-1]])
+    rng = np.random.default_rng(4096)
+    picks = set(rng.choice(len(lengths), 16, replace=False).tolist())
+    picks |= {int(np.argmax(lengths)), int(np.argmin(lengths))}
+    for l in sorted(picks):
+        x = host[offs[l]:offs[l] + lengths[l]]
+        blobs = [oracle.compress(x, e, 10) for e in cands]
+        best = int(np.argmin([len(b) for b in blobs]))
+        assert batch.eps[l] == cands[best], l
+        assert np.array_equal(batch.blob(l).data.cpu().numpy(), blobs[best]), l
+
+
+def test_serving_store_1e9(lc, wl):
+    """The serving workload at full size: 1e9 uint64 keys with lognormal
+    gaps, stored at the eps with the smallest blob among {15, 63, 255, 1023}
+    (checked against all four sizes); 3000 mixed Poisson requests served with
+    results copied out and compared with the definitions computed by torch
+    from the raw keys on the device (K[a:b], K[i], searchsorted)."""
+    n = 1_000_000_000
+    keys = wl.lognormal_gaps(n, seed=wl.SEED_BASE + 5, device=DEV)
+    _say("serving store 1e9")
+    sizes = {}
+    for e in (15, 63, 255, 1023):
+        b = lc.compress(keys, e)
+        sizes[e] = b.nbytes
+        del b
+        torch.cuda.empty_cache()
+    eps = min(sizes, key=lambda e: (sizes[e], e))
+    blob = lc.compress(keys, eps)
+    assert blob.nbytes == sizes[eps]
+    lo, hi = int(keys[0]), int(keys[-1])
+    op, a, b, arr = wl.request_stream(3000, n, lo, hi, 1e6, seed=77)
+    size = np.where(op == 1, (b - a) * 8, 8).astype(np.int64)
+    off = np.concatenate([[0], np.cumsum((size + 15) // 16 * 16)[:-1]]).astype(np.int64)
+    buf = torch.zeros(int(off[-1] + size[-1] + 16), dtype=torch.uint8, device=DEV)
+    with lc.Server(blob) as srv:
+        res, st = srv.run(lc.requests(op, a, b, arr, buf.data_ptr() + off))
+    torch.cuda.synchronize()
+    assert np.all(res["status"] == 0) and st["launches"] >= 1
+    i64 = torch.int64
+    for i in range(len(op)):
+        seg = buf[int(off[i]):int(off[i] + size[i])].view(i64)
+        if op[i] == 1:
+            assert torch.equal(seg, keys[int(a[i]):int(b[i])]), ("range", i)
+        elif op[i] == 2:
+            assert int(seg[0]) == int(keys[int(a[i])]), ("access", i)
+        else:
+            q = torch.tensor([int(a[i])], dtype=i64, device=DEV)
+            assert int(seg[0]) == int(torch.searchsorted(keys, q, side="left")[0]), ("lower_bound", i)
