@@ -1,19 +1,27 @@
 // HIP kernels of the learned compressor, written for gfx950 (CDNA4, wave64).
 //
 // Encode (Def. 1 Enc, Def. 2 / Eq. 1 fit, Sec. II-A residual packing):
-//   fit_pack     one wave per key block: greedy anchored integer cone, wave
-//                prefix max/min + ballot over 64 candidate keys at a time,
-//                residual codes OR-ed into an LDS slab, slab stored to the blob
+//   fit_pack     four key blocks per wave, one per 16-lane DPP row: greedy
+//                anchored integer cone, row prefix max/min + ballot over 16
+//                candidate keys per step, residual codes OR-ed into an LDS
+//                slab, slab stored to the blob
 //   tile_reduce  per 256 blocks: segment-area bytes, segment counts
 //   tile_scan    one workgroup: exclusive scan over tiles, header, blob size
 //   dir_emit     per 256 blocks: in-tile scan -> directory entries
 //   seg_emit     one wave per block: segment SoA in 16-byte chunks
 // Decode (Def. 1 Dec, K[i] = floor(f(i)) + Delta[i]):
-//   decode       one workgroup per block: segment table and residual slab
-//                staged in LDS, 16-byte coalesced stores; also serves ranges
+//   touch        streams the compressed bytes through the on-die cache
+//   decode       one wave per block: segment table and residual slab staged
+//                in LDS (model arrays read from the blob for large areas),
+//                16-byte coalesced stores; also serves ranges
 //   access       one lane per query, K[i] from the compressed block
 //   lower_bound  one lane per query: first_keys -> segment anchors -> search
 //                inside one segment (the segment pruning of Sec. III-A)
+// Batches of lists: batch_fit / batch_scan / batch_emit / batch_pick /
+//   batch_decode run the same per-block work over all lists of a batch.
+// Request server: serve decodes the range blocks and answers the point
+//   queries of a batch of requests in one launch.
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -21,6 +29,7 @@
 #include <type_traits>
 
 #include "lc_launch.h"
+#include "lc_search.h"
 
 namespace lc {
 namespace {
@@ -960,8 +969,8 @@ __device__ __forceinline__ uint64_t code_at(const uint8_t* blob, const Layout& L
     return (win >> sh) & ((1ull << L.w) - 1);
 }
 
-// K[i] for i < L.n: directory entry, binary search over the block's u16
-// starts, anchor, slope, one or two slab words.
+// K[i] for i < L.n: directory entry, the segment of position j among the
+// block's u16 starts, anchor, slope, one or two slab words.
 template <int KB>
 __device__ __forceinline__ uint64_t access_one(const uint8_t* __restrict__ blob, const Layout& L, uint64_t i)
 {
@@ -969,9 +978,7 @@ __device__ __forceinline__ uint64_t access_one(const uint8_t* __restrict__ blob,
     const uint32_t j = (uint32_t)(i & ((1ull << L.log2b) - 1));
     const BlockView v = block_view(blob, L, b);
     const uint16_t* st = reinterpret_cast<const uint16_t*>(blob + v.seg_off);
-    uint32_t t = 0;
-    for (uint32_t step = pow2_floor(v.nseg); step; step >>= 1)
-        if (t + step < v.nseg && st[t + step] <= j) t += step;
+    const uint32_t t = find_segment(st, v.nseg, v.nkeys, j);
     const uint8_t* an = blob + v.seg_off + a16(2ull * v.nseg);
     const uint8_t* sl = an + a16((uint64_t)v.ab * v.nseg);
     const uint64_t anchor = load_key<KB>(blob + L.off_first, b) + load_w(an, t, v.ab);
@@ -996,7 +1003,9 @@ __device__ __forceinline__ uint64_t lower_bound_one(const uint8_t* __restrict__ 
     const uint8_t* an = blob + v.seg_off + a16(2ull * v.nseg);
     const uint8_t* sl = an + a16((uint64_t)v.ab * v.nseg);
     const uint64_t first = load_key<KB>(fk, b);
-    // last segment whose anchor (its first key) is < x
+    // last segment whose anchor (its first key) is < x (binary search: on
+    // heavy-tailed key distributions the anchors of sparse blocks are too
+    // uneven for a proportional guess to pay off)
     uint32_t t = 0;
     for (uint32_t step = pow2_floor(v.nseg); step; step >>= 1)
         if (t + step < v.nseg && first + load_w(an, t + step, v.ab) < x) t += step;
