@@ -119,8 +119,10 @@ lc_status lc_compress(const void* d_keys, uint64_t n, const lc_params* p, void* 
  * Errors: LC_EINVAL (NULL), LC_EFORMAT (magic, version or fields). */
 lc_status lc_info(const void* h_header, uint64_t header_bytes, lc_blob_info* out);
 
-/* Dec of Def. 1: write all n keys (key_bytes each) to d_out (device, 16-byte
- * aligned).  d_blob is the device blob described by info.
+/* Dec of Def. 1: write all n keys (key_bytes each) to d_out (device, aligned
+ * to key_bytes; 16-byte alignment gives the fastest stores).  d_blob is the
+ * device blob described by info; a directory entry inconsistent with the
+ * layout makes the decoder skip that block (its keys are not written).
  * Errors: LC_EINVAL (NULL pointer, info inconsistent), LC_EDEVICE. */
 lc_status lc_decompress(const void* d_blob, const lc_blob_info* info, void* d_out,
                         void* stream);
