@@ -226,9 +226,11 @@ __device__ __forceinline__ uint64_t row_scan64(uint64_t v)
     return v;
 }
 
-// Fit step limit per row: a row advances its candidate window by 16 keys or
-// closes a segment every step, so 2 * B + 64 steps always suffice; hitting
-// the limit would mean an internal error, flagged instead of looping on.
+// Fit step limit per row: an ordinary step advances the candidate window by
+// 16 keys or closes a segment, and a short-segment step closes at least one
+// segment or hands the row back to the ordinary step, so 4 * B + 64 steps
+// always suffice; hitting the limit would mean an internal error, flagged
+// instead of looping on.
 constexpr uint32_t kFlagInternal = 4u;
 
 // Four blocks per wave, one per row of 16 lanes (row r of workgroup w: block
@@ -294,12 +296,137 @@ __device__ __forceinline__ void fit_rows(const void* __restrict__ keys, const La
 
     uint32_t s = 0, nseg = 0, e0 = 1;
     uint64_t anchor = first, runP = 0, runH = ~0ull, maxA = 0, maxd = 0;
+    bool shortm = false;  // the row's last segment was short: try the short-segment step
+    const double inv3 = recip(3);
     for (uint32_t step = 0; __ballot(s < nb) != 0; step++) {
-        if (step >= 2 * B + 64) {
+        if (step >= 4 * B + 64) {
             if (lane == 0) atomicOr(flags, kFlagInternal);
             break;
         }
         const bool open = s < nb;
+        if (__ballot(open && !shortm) == 0) {
+            // Short-segment step (every open row of the wave asked for it):
+            // lane r takes key a = s + r as a possible anchor and evaluates
+            // candidates a + 1, a + 2, a + 3, which gives the greedy length
+            // of a segment starting at a (1, 2, 3, or 0 for four keys or
+            // more).  Walking the chain s -> s + len -> ... closes up to 16
+            // segments at once; a long one hands the row back to the
+            // ordinary step.  Bounds as in the ordinary step, with the
+            // divisions by d = 1, 2, 3 done as a copy, a shift and one
+            // division by 3.
+            const uint32_t a = s + r;
+            const bool has = open && a < nb;
+            const uint64_t Ka = has ? (uint64_t)K[a] : 0;
+            uint64_t Pc[3] = {0, 0, 0}, Hc[3] = {~0ull, ~0ull, ~0ull}, Dc[3] = {0, 0, 0};
+            bool okc[3];
+#pragma unroll
+            for (uint32_t k = 0; k < 3; k++) {
+                const uint32_t d = k + 1;
+                okc[k] = has && a + d < nb;
+                if (okc[k]) {
+                    const uint64_t D = (uint64_t)K[a + d] - Ka;
+                    Dc[k] = D;
+                    okc[k] = D < lim;
+                    if (okc[k]) {
+                        const uint64_t x = (D - eps) << F, y = ((D + eps + 1) << F) - 1;
+                        if (d == 1) {
+                            if (D >= eps) Pc[k] = x + 1;
+                            Hc[k] = y;
+                        } else if (d == 2) {
+                            if (D >= eps) Pc[k] = (x >> 1) + (x & 1) + 1;
+                            Hc[k] = y >> 1;
+                        } else {
+                            if (D >= eps) {
+                                uint32_t rem;
+                                const uint64_t q = div_small(x, 3, inv3, &rem);
+                                Pc[k] = q + (rem != 0) + 1;
+                            }
+                            Hc[k] = div_small(y, 3, inv3);
+                        }
+                    }
+                }
+            }
+            const uint64_t Q2 = Pc[0] > Pc[1] ? Pc[0] : Pc[1], G2 = Hc[0] < Hc[1] ? Hc[0] : Hc[1];
+            const uint64_t Q3 = Q2 > Pc[2] ? Q2 : Pc[2], G3 = G2 < Hc[2] ? G2 : Hc[2];
+            const bool j2 = okc[0];
+            const bool j3 = j2 && okc[1] && (Q2 == 0 || Q2 - 1 <= G2);
+            const bool j4 = j3 && okc[2] && (Q3 == 0 || Q3 - 1 <= G3);
+            const uint32_t len = !j2 ? 1u : !j3 ? 2u : !j4 ? 3u : 0u;
+            // walk the chain from anchor s (row-uniform cur)
+            uint32_t cur = 0, path = 0;
+            bool walking = open, hit_long = false;
+            for (uint32_t it = 0; it < 16; it++) {
+                const bool live = walking && cur < 16 && s + cur < nb;
+                if (__ballot(live) == 0) break;
+                const uint32_t lc = __shfl(len, row_lane0 + (cur & 15), 64);
+                if (live) {
+                    if (lc == 0) {
+                        walking = false;
+                        hit_long = true;
+                    } else {
+                        path |= 1u << cur;
+                        cur += lc;
+                    }
+                } else {
+                    walking = false;
+                }
+            }
+            const bool mine = open && ((path >> r) & 1u);
+            uint64_t A = 0;
+            if (mine && len >= 2) {
+                const uint64_t Pf = len == 2 ? Pc[0] : Q2, Hf = len == 2 ? Hc[0] : G2;
+                if (Pf != 0) {
+                    const uint64_t lo = Pf - 1;
+                    A = lo + (Hf - lo) / 2;
+                } else {
+                    // all lower ends negative: lo = -M, M = min floor((eps - D) 2^F / d)
+                    uint64_t M = (eps - Dc[0]) << F;
+                    if (len == 3) {
+                        const uint64_t m2 = ((eps - Dc[1]) << F) >> 1;
+                        M = m2 < M ? m2 : M;
+                    }
+                    A = Hf >= M ? (Hf - M) / 2 : 0;
+                }
+            }
+            if (mine) {
+                const uint32_t idx = nseg + __popc(path & ((1u << r) - 1u));
+                if (!SIZES) {
+                    ws.seg_start[rec + idx] = (uint16_t)a;
+                    ws.seg_delta[rec + idx] = Ka - first;
+                    ws.seg_A[rec + idx] = A;
+                    if (w != 0) {
+                        for (uint32_t k = 0; k < len; k++) {
+                            const uint32_t j = a + k;
+                            const uint64_t pred = Ka + ((A * (uint64_t)k) >> F);
+                            const uint64_t code = ((uint64_t)K[j] - pred + eps) & wmask;
+                            const uint32_t bitpos = j * w;
+                            const uint32_t wd = bitpos >> 5, sh = bitpos & 31;
+                            const uint64_t v = code << sh;
+                            atomicOr(&s_slab[wd], (uint32_t)v);
+                            if (sh + w > 32) atomicOr(&s_slab[wd + 1], (uint32_t)(v >> 32));
+                        }
+                    }
+                }
+            }
+            // row maxima of the closed segments' slopes and anchor deltas
+            uint64_t mA = mine ? A : 0, mD = mine ? Ka - first : 0;
+            mA = row_scan64<true>(mA);
+            mD = row_scan64<true>(mD);
+            mA = __shfl(mA, row_lane0 + 15, 64);
+            mD = __shfl(mD, row_lane0 + 15, 64);
+            if (open) {
+                maxA = mA > maxA ? mA : maxA;
+                maxd = mD > maxd ? mD : maxd;
+                nseg += __popc(path);
+                s += cur;
+                e0 = s + 1;
+                runP = 0;
+                runH = ~0ull;
+                if (s < nb) anchor = K[s];
+                if (hit_long) shortm = false;
+            }
+            continue;
+        }
         const uint32_t e = e0 + r;
         const bool valid = open && e < nb;
         uint64_t P = 0, H = ~0ull;
@@ -378,6 +505,7 @@ __device__ __forceinline__ void fit_rows(const void* __restrict__ keys, const La
             maxA = A > maxA ? A : maxA;
             maxd = anchor - first;
             nseg++;
+            shortm = e_end - s <= 3;
             s = e_end;
             e0 = s + 1;
             runP = 0;

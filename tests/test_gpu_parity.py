@@ -276,3 +276,32 @@ def test_sparse_blocks_read_from_global(lc, kb):
     batch = lc.batch_compress(d, [len(x) for x in lists], eps=3)
     assert np.array_equal(_host(lc.batch_decompress(batch), kb), cat)
     assert np.array_equal(batch.blob(1).data.cpu().numpy(), oracle.compress(keys, 3, 10))
+
+
+@pytest.mark.parametrize("frac_bits", [0, 20, 32])
+def test_short_and_long_segments_alternate(lc, frac_bits):
+    """Stretches of two- and three-key segments (the fit's short-segment
+    step) alternating with long arithmetic runs (its ordinary step), with
+    gaps that trigger the overflow cap inside the sparse stretches."""
+    rng = np.random.default_rng(70 + frac_bits)
+    parts, pos = [], np.uint64(5)
+    cap_gap = np.uint64(1) << np.uint64(64 - frac_bits) if frac_bits else np.uint64(0)  # D + eps + 1 >= 2^(64-F)
+    for k in range(60):
+        if k % 2 == 0:  # long arithmetic run
+            m, g = int(rng.integers(5, 400)), int(rng.integers(0, 50))
+            run = pos + np.uint64(g) * np.arange(m, dtype=np.uint64)
+        else:  # sparse: random wide gaps, sometimes past the cap
+            m = int(rng.integers(3, 300))
+            gaps = rng.integers(1, 1 << 30, m).astype(np.uint64)
+            if frac_bits and k % 6 == 1:
+                gaps[rng.integers(0, m)] = cap_gap
+            run = pos + np.cumsum(gaps, dtype=np.uint64)
+        parts.append(run)
+        pos = run[-1] + np.uint64(1)
+        if pos > np.uint64(1) << np.uint64(62):
+            break
+    keys = np.concatenate(parts)
+    assert np.all(np.diff(keys.astype(object)) >= 0)
+    for eps in (0, 3, 100):
+        for log2b in (6, 10):
+            check_all(lc, keys, eps, log2b, rng, nq=300, frac_bits=frac_bits)
