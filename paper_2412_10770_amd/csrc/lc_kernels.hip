@@ -232,6 +232,9 @@ __device__ __forceinline__ uint64_t row_scan64(uint64_t v)
 // always suffice; hitting the limit would mean an internal error, flagged
 // instead of looping on.
 constexpr uint32_t kFlagInternal = 4u;
+// Candidates per lane of the short-segment step: segments of up to this many
+// keys close there (divisions by 1, 2, 4 are shifts, by 3 one division).
+constexpr uint32_t kShortWindow = 4;
 
 // Four blocks per wave, one per row of 16 lanes (row r of workgroup w: block
 // 4 w + r).  LDS: the four residual slabs (u32[res_stride / 4 + 2] each);
@@ -297,7 +300,6 @@ __device__ __forceinline__ void fit_rows(const void* __restrict__ keys, const La
     uint32_t s = 0, nseg = 0, e0 = 1;
     uint64_t anchor = first, runP = 0, runH = ~0ull, maxA = 0, maxd = 0;
     bool shortm = false;  // the row's last segment was short: try the short-segment step
-    const double inv3 = recip(3);
     for (uint32_t step = 0; __ballot(s < nb) != 0; step++) {
         if (step >= 4 * B + 64) {
             if (lane == 0) atomicOr(flags, kFlagInternal);
@@ -307,21 +309,24 @@ __device__ __forceinline__ void fit_rows(const void* __restrict__ keys, const La
         if (__ballot(open && !shortm) == 0) {
             // Short-segment step (every open row of the wave asked for it):
             // lane r takes key a = s + r as a possible anchor and evaluates
-            // candidates a + 1, a + 2, a + 3, which gives the greedy length
-            // of a segment starting at a (1, 2, 3, or 0 for four keys or
-            // more).  Walking the chain s -> s + len -> ... closes up to 16
-            // segments at once; a long one hands the row back to the
-            // ordinary step.  Bounds as in the ordinary step, with the
-            // divisions by d = 1, 2, 3 done as a copy, a shift and one
-            // division by 3.
+            // candidates a + 1 .. a + kShortWindow, which gives the greedy
+            // length of a segment starting at a (1 .. kShortWindow keys, or 0
+            // for more).  Walking the chain s -> s + len -> ... closes up to
+            // 16 segments at once; a long one hands the row back to the
+            // ordinary step.  Bounds as in the ordinary step; divisions by a
+            // power of two are shifts.
             const uint32_t a = s + r;
             const bool has = open && a < nb;
             const uint64_t Ka = has ? (uint64_t)K[a] : 0;
-            uint64_t Pc[3] = {0, 0, 0}, Hc[3] = {~0ull, ~0ull, ~0ull}, Dc[3] = {0, 0, 0};
-            bool okc[3];
+            constexpr uint32_t W = kShortWindow;
+            uint64_t Pc[W], Hc[W], Dc[W];
+            bool okc[W];
 #pragma unroll
-            for (uint32_t k = 0; k < 3; k++) {
+            for (uint32_t k = 0; k < W; k++) {
                 const uint32_t d = k + 1;
+                Pc[k] = 0;
+                Hc[k] = ~0ull;
+                Dc[k] = 0;
                 okc[k] = has && a + d < nb;
                 if (okc[k]) {
                     const uint64_t D = (uint64_t)K[a + d] - Ka;
@@ -329,29 +334,40 @@ __device__ __forceinline__ void fit_rows(const void* __restrict__ keys, const La
                     okc[k] = D < lim;
                     if (okc[k]) {
                         const uint64_t x = (D - eps) << F, y = ((D + eps + 1) << F) - 1;
-                        if (d == 1) {
-                            if (D >= eps) Pc[k] = x + 1;
-                            Hc[k] = y;
-                        } else if (d == 2) {
-                            if (D >= eps) Pc[k] = (x >> 1) + (x & 1) + 1;
-                            Hc[k] = y >> 1;
+                        if ((d & (d - 1)) == 0) {
+                            const uint32_t sh = 31 - __clz(d);
+                            if (D >= eps) Pc[k] = (x >> sh) + ((x & (d - 1)) != 0) + 1;
+                            Hc[k] = y >> sh;
                         } else {
+                            const double inv = recip(d);
                             if (D >= eps) {
                                 uint32_t rem;
-                                const uint64_t q = div_small(x, 3, inv3, &rem);
+                                const uint64_t q = div_small(x, d, inv, &rem);
                                 Pc[k] = q + (rem != 0) + 1;
                             }
-                            Hc[k] = div_small(y, 3, inv3);
+                            Hc[k] = div_small(y, d, inv);
                         }
                     }
                 }
             }
-            const uint64_t Q2 = Pc[0] > Pc[1] ? Pc[0] : Pc[1], G2 = Hc[0] < Hc[1] ? Hc[0] : Hc[1];
-            const uint64_t Q3 = Q2 > Pc[2] ? Q2 : Pc[2], G3 = G2 < Hc[2] ? G2 : Hc[2];
-            const bool j2 = okc[0];
-            const bool j3 = j2 && okc[1] && (Q2 == 0 || Q2 - 1 <= G2);
-            const bool j4 = j3 && okc[2] && (Q3 == 0 || Q3 - 1 <= G3);
-            const uint32_t len = !j2 ? 1u : !j3 ? 2u : !j4 ? 3u : 0u;
+            // prefix intersections; len = keys of the greedy segment at a (0: more than W)
+            uint64_t Qp = Pc[0], Gp = Hc[0];
+            uint32_t len = okc[0] ? 0u : 1u;
+            uint64_t Pf = 0, Hf = ~0ull;
+            if (okc[0]) { Pf = Pc[0]; Hf = Hc[0]; }
+#pragma unroll
+            for (uint32_t k = 1; k < W; k++) {
+                const uint64_t Qn = Qp > Pc[k] ? Qp : Pc[k], Gn = Gp < Hc[k] ? Gp : Hc[k];
+                const bool join = okc[k] && (Qn == 0 || Qn - 1 <= Gn);
+                if (len == 0 && !join) {
+                    len = k + 1;  // candidates 1 .. k joined
+                } else if (len == 0) {
+                    Pf = Qn;
+                    Hf = Gn;
+                }
+                Qp = Qn;
+                Gp = Gn;
+            }
             // walk the chain from anchor s (row-uniform cur)
             uint32_t cur = 0, path = 0;
             bool walking = open, hit_long = false;
@@ -374,16 +390,20 @@ __device__ __forceinline__ void fit_rows(const void* __restrict__ keys, const La
             const bool mine = open && ((path >> r) & 1u);
             uint64_t A = 0;
             if (mine && len >= 2) {
-                const uint64_t Pf = len == 2 ? Pc[0] : Q2, Hf = len == 2 ? Hc[0] : G2;
                 if (Pf != 0) {
                     const uint64_t lo = Pf - 1;
                     A = lo + (Hf - lo) / 2;
                 } else {
                     // all lower ends negative: lo = -M, M = min floor((eps - D) 2^F / d)
-                    uint64_t M = (eps - Dc[0]) << F;
-                    if (len == 3) {
-                        const uint64_t m2 = ((eps - Dc[1]) << F) >> 1;
-                        M = m2 < M ? m2 : M;
+                    uint64_t M = ~0ull;
+#pragma unroll
+                    for (uint32_t k = 0; k + 1 < W; k++) {
+                        if (k + 1 < len) {
+                            const uint32_t d = k + 1;
+                            const uint64_t z = (eps - Dc[k]) << F;
+                            const uint64_t m = (d & (d - 1)) == 0 ? z >> (31 - __clz(d)) : div_small(z, d, recip(d));
+                            M = m < M ? m : M;
+                        }
                     }
                     A = Hf >= M ? (Hf - M) / 2 : 0;
                 }
@@ -505,7 +525,7 @@ __device__ __forceinline__ void fit_rows(const void* __restrict__ keys, const La
             maxA = A > maxA ? A : maxA;
             maxd = anchor - first;
             nseg++;
-            shortm = e_end - s <= 3;
+            shortm = e_end - s <= kShortWindow;
             s = e_end;
             e0 = s + 1;
             runP = 0;
