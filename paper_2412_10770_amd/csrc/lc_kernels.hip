@@ -725,11 +725,14 @@ __device__ __forceinline__ bool dir_ok(const uint4& dv, const Layout& L, uint64_
            seg_off <= bytes && area <= bytes - seg_off;
 }
 
-// Segment area of block b (one wave): the records in the workspace packed at
+constexpr uint32_t kEmitLanes = 16;
+
+// Segment area of block b (G lanes): the records in the workspace packed at
 // the block's widths into 16-byte chunks at the directory's offset.
+template <uint32_t G>
 __device__ __forceinline__ void emit_block(const Workspace& ws, const Layout& L, uint8_t* __restrict__ blob, uint64_t b)
 {
-    const uint32_t lane = lane_id();
+    const uint32_t lane = threadIdx.x % G;
     const uint4 dv = reinterpret_cast<const uint4*>(blob + L.off_dir)[b];
     const uint64_t seg_off = dv.x | ((uint64_t)dv.y << 32);
     const uint32_t n = dv.z;
@@ -739,20 +742,22 @@ __device__ __forceinline__ void emit_block(const Workspace& ws, const Layout& L,
     const uint32_t c_start = (uint32_t)(a16(2ull * n) / 16);
     const uint32_t c_anchor = (uint32_t)(a16((uint64_t)ab * n) / 16);
     const uint32_t c_slope = (uint32_t)(a16((uint64_t)sb * n) / 16);
-    for (uint32_t c = lane; c < c_start; c += 64) out[c] = pack_chunk(ws.seg_start + rec, n, c, 2);
+    for (uint32_t c = lane; c < c_start; c += G) out[c] = pack_chunk(ws.seg_start + rec, n, c, 2);
     out += c_start;
-    for (uint32_t c = lane; c < c_anchor; c += 64) out[c] = pack_chunk(ws.seg_delta + rec, n, c, ab);
+    for (uint32_t c = lane; c < c_anchor; c += G) out[c] = pack_chunk(ws.seg_delta + rec, n, c, ab);
     out += c_anchor;
-    for (uint32_t c = lane; c < c_slope; c += 64) out[c] = pack_chunk(ws.seg_A + rec, n, c, sb);
+    for (uint32_t c = lane; c < c_slope; c += G) out[c] = pack_chunk(ws.seg_A + rec, n, c, sb);
 }
 
-// Segment areas: one wave per block, four blocks per workgroup.
+// Segment areas: kEmitLanes lanes per block, 256 / kEmitLanes blocks per
+// workgroup (most blocks need three 16-byte chunks; a whole wave per block
+// left most lanes idle).
 __global__ __launch_bounds__(256) void seg_emit_kernel(Workspace ws, Layout L, uint8_t* __restrict__ blob,
                                                        uint64_t blk0)
 {
-    const uint64_t b = blk0 + (uint64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    const uint64_t b = blk0 + (uint64_t)blockIdx.x * (256 / kEmitLanes) + threadIdx.x / kEmitLanes;
     if (b >= L.nblocks) return;
-    emit_block(ws, L, blob, b);
+    emit_block<kEmitLanes>(ws, L, blob, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -1434,11 +1439,11 @@ __global__ __launch_bounds__(256) void batch_scan_kernel(const lc_batch_list* __
     }
 }
 
-// Segment areas of every block of the batch: one wave per block.
+// Segment areas of every block of the batch: kEmitLanes lanes per block.
 __global__ __launch_bounds__(256) void batch_emit_kernel(const lc_batch_list* __restrict__ lists, BatchArgs a,
                                                          uint8_t* __restrict__ blob, Workspace ws, uint64_t blk0)
 {
-    const uint64_t gb = blk0 + (uint64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    const uint64_t gb = blk0 + (uint64_t)blockIdx.x * (256 / kEmitLanes) + threadIdx.x / kEmitLanes;
     if (gb >= a.total_blocks) return;
     const uint32_t l = find_list<false>(lists, a.nlists, gb);
     const lc_batch_list li = lists[l];
@@ -1447,7 +1452,7 @@ __global__ __launch_bounds__(256) void batch_emit_kernel(const lc_batch_list* __
     if (!list_fits(li, a, L, li.eps, true) || b >= L.nblocks) return;  // flagged by the fit
     const uint4 dv = reinterpret_cast<const uint4*>(blob + li.blob_off + L.off_dir)[b];
     if (!dir_ok(dv, L, b, li.blob_cap)) return;  // flagged by the scan
-    emit_block(list_ws(ws, li.block_off, a.log2b, li.block_off), L, blob + li.blob_off, b);
+    emit_block<kEmitLanes>(list_ws(ws, li.block_off, a.log2b, li.block_off), L, blob + li.blob_off, b);
 }
 
 // Decode of every block of the batch, one wave per block, XCD-major as the
@@ -1564,11 +1569,12 @@ hipError_t launch_batch_fit(const void* d_keys, const lc_batch_list* d_lists, co
         hipLaunchKernelGGL(ks, dim3((uint32_t)g), dim3(256), 0, stream, d_lists, a, c, d_blob, ws, d_sizes, d_stats, i0);
     }
     if (!sizes_only) {
-        const uint64_t groups = (a.total_blocks + 3) / 4;
+        constexpr uint64_t per = 256 / kEmitLanes;
+        const uint64_t groups = (a.total_blocks + per - 1) / per;
         for (uint64_t g0 = 0; g0 < groups; g0 += kMaxGrid) {
             const uint64_t g = groups - g0 < kMaxGrid ? groups - g0 : kMaxGrid;
             hipLaunchKernelGGL(batch_emit_kernel, dim3((uint32_t)g), dim3(256), 0, stream, d_lists, a, d_blob, ws,
-                               g0 * 4);
+                               g0 * per);
         }
     }
     return hipGetLastError();
@@ -1645,10 +1651,11 @@ hipError_t launch_compress(const void* d_keys, const Layout& L, uint8_t* d_blob,
             const uint64_t g = nt - t0 < kMaxGrid ? nt - t0 : kMaxGrid;
             hipLaunchKernelGGL(dir_emit_kernel, dim3((uint32_t)g), dim3(256), 0, stream, ws, L, d_blob, t0);
         }
-        const uint64_t groups = (L.nblocks + 3) / 4;
-        for (uint64_t g0 = 0; g0 < groups; g0 += kMaxGrid) {
-            const uint64_t g = groups - g0 < kMaxGrid ? groups - g0 : kMaxGrid;
-            hipLaunchKernelGGL(seg_emit_kernel, dim3((uint32_t)g), dim3(256), 0, stream, ws, L, d_blob, g0 * 4);
+        constexpr uint64_t per = 256 / kEmitLanes;
+        const uint64_t egroups = (L.nblocks + per - 1) / per;
+        for (uint64_t g0 = 0; g0 < egroups; g0 += kMaxGrid) {
+            const uint64_t g = egroups - g0 < kMaxGrid ? egroups - g0 : kMaxGrid;
+            hipLaunchKernelGGL(seg_emit_kernel, dim3((uint32_t)g), dim3(256), 0, stream, ws, L, d_blob, g0 * per);
         }
     }
     return hipGetLastError();
