@@ -187,3 +187,39 @@ def test_posting_lists_reduced(lc, wl):
         e = CANDS[int(np.argmin(sizes))]
         assert batch.eps[l] == e, l
         assert np.array_equal(batch.blob(l).data.cpu().numpy(), oracle.compress(x, e, 10, 20)), l
+
+
+def test_tiny_lists_and_degenerate_batches(lc):
+    """20000 lists of 0..3 keys (most work items hold a single block), one
+    single-list batch, an all-empty batch, and u64 keys at the top of the
+    range: every blob equals the oracle's."""
+    rng = np.random.default_rng(31)
+    lens = rng.integers(0, 4, 20000)
+    top = np.uint64(2 ** 64 - 1)
+    lists = []
+    for i, m in enumerate(lens):
+        base = top - np.uint64(rng.integers(0, 1 << 20)) if i % 7 == 0 else np.uint64(rng.integers(0, 1 << 40))
+        x = np.sort(base - rng.integers(0, 1 << 10, m).astype(np.uint64)) if i % 7 == 0 else \
+            np.sort(base + rng.integers(0, 1 << 10, m).astype(np.uint64))
+        lists.append(x.astype(np.uint64))
+    keys, _ = _concat(lists, 8)
+    _say("tiny lists: 20000")
+    batch = lc.batch_compress(keys, lens, candidates=(0, 5, 1000))
+    assert torch.equal(lc.batch_decompress(batch), keys)
+    for l in rng.choice(len(lists), 300, replace=False):
+        sizes = [len(oracle.compress(lists[l], e, 10)) for e in (0, 5, 1000)]
+        e = (0, 5, 1000)[int(np.argmin(sizes))]
+        assert batch.eps[l] == e
+        assert np.array_equal(batch.blob(l).data.cpu().numpy(), oracle.compress(lists[l], e, 10)), l
+    # one list
+    one = np.cumsum(rng.integers(1, 100, 5000)).astype(np.uint64)
+    k1, _ = _concat([one], 8)
+    b1 = lc.batch_compress(k1, [len(one)], eps=31)
+    assert np.array_equal(b1.blob(0).data.cpu().numpy(), oracle.compress(one, 31, 10))
+    assert torch.equal(lc.batch_decompress(b1), k1)
+    # every list empty: header-only blobs, nothing to decode
+    k0 = torch.zeros(0, dtype=torch.int64, device=DEV)
+    b0 = lc.batch_compress(k0, [0, 0, 0], eps=7)
+    for l in range(3):
+        assert np.array_equal(b0.blob(l).data.cpu().numpy(), oracle.compress(np.zeros(0, np.uint64), 7, 10))
+    assert lc.batch_decompress(b0).numel() == 0
