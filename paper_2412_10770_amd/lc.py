@@ -506,3 +506,46 @@ def requests(ops, a, b=None, arrival_ns=None, d_dest=None) -> np.ndarray:
     if d_dest is not None:
         r["d_dest"] = np.asarray(d_dest, dtype=np.uint64)
     return r
+
+
+# ---------------------------------------------------------------------------
+# Batch autotuner
+# ---------------------------------------------------------------------------
+
+def autotune_batch(keys: torch.Tensor, lengths, eps_candidates=(7, 31, 127), block_candidates=(8, 9, 10, 11, 12),
+                   objective: str = "size", time_reps: int = 3, frac_bits: int = DEFAULT_FRAC_BITS, stream=None):
+    """Pick the batch's block size (and, per list, eps among eps_candidates)
+    by measurement.  For every log2 block size the whole batch is compressed
+    with the on-device eps autotune; its exact total bytes and its batch
+    decode time (HIP events, mean of time_reps runs) are recorded.
+    objective "size": fewest bytes (ties: faster decode); "speed": fastest
+    decode; "balanced": fewest bytes among the candidates whose decode is
+    within 10% of the fastest.  Returns (chosen Batch, report list)."""
+    if objective not in ("size", "speed", "balanced"):
+        raise ValueError("objective is 'size', 'speed' or 'balanced'")
+    report, batches = [], {}
+    out = torch.empty(keys.numel(), dtype=key_dtype(_key_bytes(keys)), device=keys.device)
+    for lb in block_candidates:
+        b = batch_compress(keys, lengths, candidates=eps_candidates, log2_block=lb, frac_bits=frac_bits,
+                           stream=stream)
+        batch_decompress(b, out=out, stream=stream)  # warm, and checks the flags
+        t = []
+        for _ in range(max(1, time_reps)):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            batch_decompress(b, out=out, stream=stream, check=False)
+            e1.record()
+            torch.cuda.synchronize()
+            t.append(e0.elapsed_time(e1))
+        report.append({"log2_block": lb, "bytes": b.nbytes, "decode_ms": float(sum(t) / len(t))})
+        batches[lb] = b
+    fastest = min(r["decode_ms"] for r in report)
+    if objective == "speed":
+        best = min(report, key=lambda r: (r["decode_ms"], r["bytes"]))
+    elif objective == "balanced":
+        best = min((r for r in report if r["decode_ms"] <= 1.1 * fastest), key=lambda r: (r["bytes"], r["decode_ms"]))
+    else:
+        best = min(report, key=lambda r: (r["bytes"], r["decode_ms"]))
+    for r in report:
+        r["chosen"] = r is best
+    return batches[best["log2_block"]], report

@@ -223,3 +223,26 @@ def test_tiny_lists_and_degenerate_batches(lc):
     for l in range(3):
         assert np.array_equal(b0.blob(l).data.cpu().numpy(), oracle.compress(np.zeros(0, np.uint64), 7, 10))
     assert lc.batch_decompress(b0).numel() == 0
+
+
+def test_autotune_block_size(lc, wl):
+    """The batch autotuner: every block size gives a batch that round-trips
+    and whose lists equal the oracle's blobs at that block size; the choice
+    is the argmin of the measured objective."""
+    keys, lengths = wl.posting_lists(64, device=DEV, hi=2e4)
+    _say(f"autotune block size: {keys.numel()} keys")
+    best, report = lc.autotune_batch(keys, lengths, block_candidates=(8, 10, 12), objective="size")
+    assert sum(r["chosen"] for r in report) == 1
+    chosen = next(r for r in report if r["chosen"])
+    assert chosen["bytes"] == min(r["bytes"] for r in report)
+    assert best.params.log2_block == chosen["log2_block"] and best.nbytes == chosen["bytes"]
+    assert torch.equal(lc.batch_decompress(best), keys)
+    host = keys.cpu().numpy().view(np.uint32)
+    offs = np.concatenate([[0], np.cumsum(lengths)[:-1]])
+    for l in (0, int(np.argmax(lengths))):
+        x = host[offs[l]:offs[l] + lengths[l]]
+        want = oracle.compress(x, int(best.eps[l]), chosen["log2_block"])
+        assert np.array_equal(best.blob(l).data.cpu().numpy(), want)
+    fast, rep2 = lc.autotune_batch(keys, lengths, block_candidates=(8, 12), objective="speed", time_reps=2)
+    c2 = next(r for r in rep2 if r["chosen"])
+    assert c2["decode_ms"] == min(r["decode_ms"] for r in rep2)
