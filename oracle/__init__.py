@@ -194,3 +194,44 @@ def access(keys, idx) -> np.ndarray:
 def lower_bound(keys, q) -> np.ndarray:
     k = _keys_array(keys)
     return np.searchsorted(k, np.asarray(q, dtype=k.dtype), side="left").astype(np.uint64)
+
+
+# --- query operators (Sec. III-A list AND / OR, Sec. III-C quantile and AQP) --
+
+def intersect(a, b) -> np.ndarray:
+    """AND of two sorted lists (Sec. III-A): the sorted set of keys in both."""
+    return np.intersect1d(_keys_array(a), _keys_array(b))
+
+
+def union(a, b) -> np.ndarray:
+    """OR of two sorted lists (Sec. III-A): the sorted set of keys in either."""
+    return np.union1d(_keys_array(a), _keys_array(b))
+
+
+def quantile(keys, k, q: int) -> np.ndarray:
+    """k-th q-quantile (Sec. III-C), 0-based: K[min(floor(N * k / q), N - 1)]
+    (Python integers for N * k)."""
+    kk = _keys_array(keys)
+    n = len(kk)
+    idx = [min((n * int(x)) // int(q), n - 1) for x in np.asarray(k).ravel()]
+    return kk[np.asarray(idx, dtype=np.int64)]
+
+
+def predict(keys, eps: int, log2_block: int = 10, frac_bits: int = 20) -> np.ndarray:
+    """The fitted eps-PLA without residuals (Def. 2; the AQP reading of
+    Sec. III-C): per block, segment t starting at s_t with anchor a_t and
+    slope A_t predicts f(i) = a_t + floor(A_t (i - s_t) / 2^F) for the keys
+    up to the next start; |K[i] - f(i)| <= eps.  Python integers; the
+    segments come from this oracle's own fit."""
+    kk = _keys_array(keys)
+    mask = (1 << (8 * kk.dtype.itemsize)) - 1
+    out = np.zeros_like(kk)
+    B = 1 << log2_block
+    for b0 in range(0, len(kk), B):
+        blk = kk[b0:b0 + B]
+        st, an, sl = fit_block(blk, eps, frac_bits)
+        ends = list(st[1:]) + [len(blk)]
+        for s, e, a, A in zip(st.tolist(), ends, an.tolist(), sl.tolist()):
+            for j in range(int(s), int(e)):
+                out[b0 + j] = (int(a) + ((int(A) * (j - int(s))) >> frac_bits)) & mask
+    return out
