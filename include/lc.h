@@ -149,6 +149,48 @@ lc_status lc_access(const void* d_blob, const lc_blob_info* info, const uint64_t
 lc_status lc_lower_bound(const void* d_blob, const lc_blob_info* info, const void* d_q,
                          uint64_t m, uint64_t* d_pos, void* stream);
 
+/* ---- Queries on the compressed form (Sec. III-A, III-C) --------------------
+ */
+
+/* The k-th q-quantile of the list (Sec. III-C: a quantile is one access of
+ * the learned encoding), 0-based: d_out[t] = K[min(floor(n * d_k[t] / q),
+ * n - 1)] for t < m (d_k: device u64[m]; d_out: key_bytes each).  approx
+ * != 0 returns the model's prediction f of that index instead (no residual
+ * read; within eps of the key).  n >= 1 and q >= 1, else LC_EINVAL. */
+lc_status lc_quantile(const void* d_blob, const lc_blob_info* info, const uint64_t* d_k, uint64_t q, uint64_t m,
+                      uint32_t approx, void* d_out, void* stream);
+
+/* Approximate query processing (Sec. III-C): keys [begin, end) decoded from
+ * the model alone, without reading the residuals -- d_out[i - begin] =
+ * f(i) = anchor + floor(A * (i - start) / 2^F) of i's segment, within eps
+ * of K[i] (Def. 2).  Arguments as lc_decompress_range. */
+lc_status lc_decompress_approx(const void* d_blob, const lc_blob_info* info, uint64_t begin, uint64_t end,
+                               void* d_out, void* stream);
+
+#define LC_SETOP_INTERSECT 1u /* AND: the sorted set of keys in both lists */
+#define LC_SETOP_UNION 2u     /* OR: the sorted set of keys in either list */
+
+/* Host, pure: output capacity (keys) and workspace bytes of lc_setop for two
+ * blobs of the same key width (AND: min(n_a, n_b); OR: n_a + n_b).
+ * Errors: LC_EINVAL (bad op, infos inconsistent, key widths differ). */
+lc_status lc_setop_bound(const lc_blob_info* a, const lc_blob_info* b, uint32_t op, uint64_t* out_max,
+                         uint64_t* ws_bytes);
+
+/* List AND / OR of two compressed lists (Sec. III-A), e.g. posting lists:
+ * d_out receives the result keys (sorted, each value once) and *d_count
+ * (device u64) their number.  AND decodes the smaller list and probes the
+ * larger one in its compressed form: each probe locates one block from the
+ * first keys, one segment from the block's anchors and the key inside that
+ * segment, so blocks and segments that cannot hold a probe are never read
+ * (the segment pruning that replaces skip pointers).  OR decodes both and
+ * places every distinct key at its rank.  d_ws: workspace of the size
+ * lc_setop_bound gives (16-byte aligned); d_out: out_cap keys, aligned to
+ * the key width.  Errors: LC_EINVAL, LC_ENOSPC (out_cap or ws_bytes too
+ * small), LC_EDEVICE. */
+lc_status lc_setop(uint32_t op, const void* d_blob_a, const lc_blob_info* a, const void* d_blob_b,
+                   const lc_blob_info* b, void* d_ws, uint64_t ws_bytes, void* d_out, uint64_t out_cap,
+                   uint64_t* d_count, void* stream);
+
 /* ---- Batches of lists ----------------------------------------------------
  * Many sorted lists (e.g. the posting lists of an inverted index, Sec. III-A)
  * compressed or decompressed together: one launch runs the fit over every

@@ -5,6 +5,8 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <utility>
+
 #include "lc.h"
 #include "lc_launch.h"
 
@@ -313,6 +315,113 @@ LC_API lc_status lc_lower_bound(const void* d_blob, const lc_blob_info* info, co
         return LC_EINVAL;
     hipError_t e = lc::launch_lower_bound(static_cast<const uint8_t*>(d_blob), L, d_q, m, d_pos,
                                           static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LC_OK : LC_EDEVICE;
+}
+
+LC_API lc_status lc_quantile(const void* d_blob, const lc_blob_info* info, const uint64_t* d_k, uint64_t q,
+                             uint64_t m, uint32_t approx, void* d_out, void* stream)
+{
+    lc::Layout L;
+    if (!d_blob || layout_of(info, &L) != LC_OK || L.n == 0 || q == 0) return LC_EINVAL;
+    if (m == 0) return LC_OK;
+    if (!d_k || !d_out || (reinterpret_cast<uintptr_t>(d_k) & 7) || (reinterpret_cast<uintptr_t>(d_out) & (L.kb - 1)))
+        return LC_EINVAL;
+    hipError_t e = lc::launch_quantile(static_cast<const uint8_t*>(d_blob), L, d_k, q, m, approx != 0, d_out,
+                                       static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LC_OK : LC_EDEVICE;
+}
+
+LC_API lc_status lc_decompress_approx(const void* d_blob, const lc_blob_info* info, uint64_t begin, uint64_t end,
+                                      void* d_out, void* stream)
+{
+    lc::Layout L;
+    if (!d_blob || layout_of(info, &L) != LC_OK) return LC_EINVAL;
+    if (begin > end || end > L.n) return LC_EINVAL;
+    if (begin == end) return LC_OK;
+    if (!d_out || (reinterpret_cast<uintptr_t>(d_out) & (L.kb - 1))) return LC_EINVAL;
+    hipError_t e = lc::launch_decode(static_cast<const uint8_t*>(d_blob), L, begin, end, d_out,
+                                     static_cast<hipStream_t>(stream), true);
+    return e == hipSuccess ? LC_OK : LC_EDEVICE;
+}
+
+namespace {
+
+struct SetPlan {
+    uint64_t a_keys, b_keys, fa, fb, PA, PB, cnt, tot, total;
+};
+
+// probe: the decoded side of an AND (the smaller list)
+SetPlan plan_setop(uint32_t op, uint64_t na, uint64_t nb, uint32_t kb)
+{
+    const uint64_t T = lc::kSetTileKeys;
+    const uint64_t ta = (na + T - 1) / T, tb = op == LC_SETOP_UNION ? (nb + T - 1) / T : 0;
+    const bool u = op == LC_SETOP_UNION;
+    SetPlan p;
+    p.a_keys = 0;
+    p.b_keys = p.a_keys + lc::align16(na * kb);
+    p.fa = p.b_keys + (u ? lc::align16(nb * kb) : 0);
+    p.fb = p.fa + lc::align16(na);
+    p.PA = p.fb + (u ? lc::align16(nb) : 0);
+    p.PB = p.PA + (u ? lc::align16((na + 1) * 8) : 0);
+    p.cnt = p.PB + (u ? lc::align16((nb + 1) * 8) : 0);
+    p.tot = p.cnt + lc::align16((ta + tb + 2) * 8);
+    p.total = p.tot + 16;
+    return p;
+}
+
+lc_status check_setop(const lc_blob_info* a, const lc_blob_info* b, uint32_t op, lc::Layout* La, lc::Layout* Lb)
+{
+    if (op != LC_SETOP_INTERSECT && op != LC_SETOP_UNION) return LC_EINVAL;
+    if (layout_of(a, La) != LC_OK || layout_of(b, Lb) != LC_OK || La->kb != Lb->kb) return LC_EINVAL;
+    return LC_OK;
+}
+
+}  // namespace
+
+LC_API lc_status lc_setop_bound(const lc_blob_info* a, const lc_blob_info* b, uint32_t op, uint64_t* out_max,
+                                uint64_t* ws_bytes)
+{
+    lc::Layout La, Lb;
+    lc_status st = check_setop(a, b, op, &La, &Lb);
+    if (st != LC_OK) return st;
+    const bool swap = op == LC_SETOP_INTERSECT && La.n > Lb.n;
+    const uint64_t na = swap ? Lb.n : La.n, nb = swap ? La.n : Lb.n;
+    if (out_max) *out_max = op == LC_SETOP_INTERSECT ? na : na + nb;
+    if (ws_bytes) *ws_bytes = plan_setop(op, na, nb, La.kb).total;
+    return LC_OK;
+}
+
+LC_API lc_status lc_setop(uint32_t op, const void* d_blob_a, const lc_blob_info* a, const void* d_blob_b,
+                          const lc_blob_info* b, void* d_ws, uint64_t ws_bytes, void* d_out, uint64_t out_cap,
+                          uint64_t* d_count, void* stream)
+{
+    lc::Layout La, Lb;
+    lc_status st = check_setop(a, b, op, &La, &Lb);
+    if (st != LC_OK) return st;
+    if (!d_blob_a || !d_blob_b || !d_ws || !d_count || (reinterpret_cast<uintptr_t>(d_ws) & 15) ||
+        (reinterpret_cast<uintptr_t>(d_count) & 7))
+        return LC_EINVAL;
+    // AND probes the larger list with the keys of the smaller one
+    const bool swap = op == LC_SETOP_INTERSECT && La.n > Lb.n;
+    const uint8_t* pa = static_cast<const uint8_t*>(swap ? d_blob_b : d_blob_a);
+    const uint8_t* pb = static_cast<const uint8_t*>(swap ? d_blob_a : d_blob_b);
+    if (swap) std::swap(La, Lb);
+    const uint64_t need = op == LC_SETOP_INTERSECT ? La.n : La.n + Lb.n;
+    if (out_cap < need) return LC_ENOSPC;
+    if (need && (!d_out || (reinterpret_cast<uintptr_t>(d_out) & (La.kb - 1)))) return LC_EINVAL;
+    const SetPlan p = plan_setop(op, La.n, Lb.n, La.kb);
+    if (ws_bytes < p.total) return LC_ENOSPC;
+    uint8_t* ws = static_cast<uint8_t*>(d_ws);
+    lc::SetWs w;
+    w.a_keys = ws + p.a_keys;
+    w.b_keys = ws + p.b_keys;
+    w.fa = ws + p.fa;
+    w.fb = ws + p.fb;
+    w.PA = reinterpret_cast<uint64_t*>(ws + p.PA);
+    w.PB = reinterpret_cast<uint64_t*>(ws + p.PB);
+    w.cnt = reinterpret_cast<uint64_t*>(ws + p.cnt);
+    w.tot = reinterpret_cast<uint64_t*>(ws + p.tot);
+    hipError_t e = lc::launch_setop(op, pa, La, pb, Lb, w, d_out, d_count, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? LC_OK : LC_EDEVICE;
 }
 

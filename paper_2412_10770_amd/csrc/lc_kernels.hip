@@ -960,7 +960,10 @@ __global__ __launch_bounds__(256) void touch_kernel(const uint8_t* __restrict__ 
 //     j0 + V * (l + 64 i), j0 chosen so that every group's output is
 //     16-byte aligned; each store instruction of the wave writes 1 KB of
 //     contiguous output (non-temporal: the output is not re-read here).
-template <int KB, bool RANGE>
+// APPROX: the model alone (approximate query processing, Sec. III-C): the
+// residual slab is not read and every key is its prediction f(i), within
+// eps of K[i].
+template <int KB, bool RANGE, bool APPROX = false>
 __device__ __forceinline__ void decode_block(const uint8_t* __restrict__ blob, const DecodeArgs& a, uint64_t b,
                                              uint32_t raw_cap, void* __restrict__ out)
 {
@@ -968,7 +971,7 @@ __device__ __forceinline__ void decode_block(const uint8_t* __restrict__ blob, c
     const uint32_t lane = threadIdx.x;
     const uint32_t nwords = (1u << L.log2b) >> 5;
     const uint32_t slab_words = (uint32_t)(L.res_stride / 4);
-    const uint32_t nch_slab = slab_words / 4;
+    const uint32_t nch_slab = APPROX ? 0u : slab_words / 4;
 
     extern __shared__ __align__(16) uint8_t smem[];
     uint8_t* s_raw = smem;                                                 // raw_cap
@@ -979,10 +982,13 @@ __device__ __forceinline__ void decode_block(const uint8_t* __restrict__ blob, c
 
     const uint32_t last_slab = nch_slab ? nch_slab - 1 : 0u;
     const uint4* g_slab = reinterpret_cast<const uint4*>(blob + L.off_res + b * L.res_stride);
-    const uint4 fs0 = g_slab[lane < last_slab ? lane : last_slab];
-    const uint4 fs1 = g_slab[lane + 64 < last_slab ? lane + 64 : last_slab];
-    const uint4 fs2 = g_slab[lane + 128 < last_slab ? lane + 128 : last_slab];
-    const uint4 fs3 = g_slab[lane + 192 < last_slab ? lane + 192 : last_slab];
+    uint4 fs0 = make_uint4(0, 0, 0, 0), fs1 = fs0, fs2 = fs0, fs3 = fs0;
+    if constexpr (!APPROX) {
+        fs0 = g_slab[lane < last_slab ? lane : last_slab];
+        fs1 = g_slab[lane + 64 < last_slab ? lane + 64 : last_slab];
+        fs2 = g_slab[lane + 128 < last_slab ? lane + 128 : last_slab];
+        fs3 = g_slab[lane + 192 < last_slab ? lane + 192 : last_slab];
+    }
 
     const uint4 dv = reinterpret_cast<const uint4*>(blob + L.off_dir)[b];
     const uint64_t seg_off = dv.x | ((uint64_t)dv.y << 32);
@@ -1031,9 +1037,9 @@ __device__ __forceinline__ void decode_block(const uint8_t* __restrict__ blob, c
 
     BlockCtx c;
     c.first = first;
-    c.eps = L.eps;
+    c.eps = APPROX ? 0 : L.eps;  // with w = 0 the code term vanishes: the key is f(i)
     c.F = L.F;
-    c.w = L.w;
+    c.w = APPROX ? 0 : L.w;
     c.ab = ab;
     c.sb = sb;
     c.s_slab = s_slab;
@@ -1080,13 +1086,37 @@ __device__ __forceinline__ void decode_block(const uint8_t* __restrict__ blob, c
 // One wave per block.  Workgroup w runs on XCD w % 8, so blocks are
 // assigned XCD-major: each XCD walks a contiguous run of blocks (and of
 // directory and segment bytes).
-template <int KB, bool RANGE>
+template <int KB, bool RANGE, bool APPROX = false>
 __global__ __launch_bounds__(64) void decode_kernel(const uint8_t* __restrict__ blob, DecodeArgs a,
                                                      void* __restrict__ out)
 {
     const uint64_t rel = (uint64_t)(blockIdx.x % 8) * a.per_xcd + blockIdx.x / 8;
     if (rel >= a.nblk) return;
-    decode_block<KB, RANGE>(blob, a, a.b_first + rel, a.raw_cap, out);
+    decode_block<KB, RANGE, APPROX>(blob, a, a.b_first + rel, a.raw_cap, out);
+}
+
+// Streams the directory entries and segment areas of blocks [b_lo, b_hi]
+// through the caches (the approximate decode reads no slab); the segment
+// byte range comes from the first and last directory entries, checked
+// against the layout.
+__global__ __launch_bounds__(256) void touch_blocks_kernel(const uint8_t* __restrict__ blob, Layout L, uint64_t b_lo,
+                                                           uint64_t b_hi)
+{
+    const uint4* dir = reinterpret_cast<const uint4*>(blob + L.off_dir);
+    const uint4 d0 = dir[b_lo], d1 = dir[b_hi];
+    uint64_t lo = d0.x | ((uint64_t)d0.y << 32);
+    uint64_t hi = (d1.x | ((uint64_t)d1.y << 32)) + a16(2ull * d1.z) + a16((uint64_t)((d1.w >> 16) & 0xFF) * d1.z) +
+                  a16((uint64_t)(d1.w >> 24) * d1.z);
+    if (!(lo >= L.off_seg && lo <= hi && hi <= L.blob_bytes)) lo = hi = L.off_seg;
+    const uint64_t dlo = (L.off_dir + 16 * b_lo) / 16, dn = b_hi + 1 - b_lo;
+    const uint64_t slo = lo / 16, sn = (hi - lo) / 16;
+    const uint4* p = reinterpret_cast<const uint4*>(blob);
+    uint32_t acc = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < dn + sn; i += (uint64_t)gridDim.x * 256) {
+        const uint4 v = p[i < dn ? dlo + i : slo + (i - dn)];
+        acc ^= v.x ^ v.y ^ v.z ^ v.w;
+    }
+    asm volatile("" ::"v"(acc));  // keeps the loads; no instruction is emitted
 }
 
 // ---------------------------------------------------------------------------
@@ -1124,7 +1154,7 @@ __device__ __forceinline__ uint64_t code_at(const uint8_t* blob, const Layout& L
 
 // K[i] for i < L.n: directory entry, the segment of position j among the
 // block's u16 starts, anchor, slope, one or two slab words.
-template <int KB>
+template <int KB, bool APPROX = false>
 __device__ __forceinline__ uint64_t access_one(const uint8_t* __restrict__ blob, const Layout& L, uint64_t i)
 {
     const uint64_t b = i >> L.log2b;
@@ -1136,7 +1166,9 @@ __device__ __forceinline__ uint64_t access_one(const uint8_t* __restrict__ blob,
     const uint8_t* sl = an + a16((uint64_t)v.ab * v.nseg);
     const uint64_t anchor = load_key<KB>(blob + L.off_first, b) + load_w(an, t, v.ab);
     const uint64_t A = load_w(sl, t, v.sb);
-    return anchor + ((A * (uint64_t)(j - st[t])) >> L.F) + code_at(blob, L, b, j) - L.eps;
+    const uint64_t pred = anchor + ((A * (uint64_t)(j - st[t])) >> L.F);
+    if constexpr (APPROX) return pred;  // f(i), within eps of K[i]
+    return pred + code_at(blob, L, b, j) - L.eps;
 }
 
 // First i with K[i] >= x (L.n if none): binary search over first_keys, then
@@ -1205,6 +1237,196 @@ __global__ __launch_bounds__(256) void lower_bound_kernel(const uint8_t* __restr
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < m; q += stride)
         pos[q] = lower_bound_one<KB>(blob, L, load_key<KB>(qs, q));
+}
+
+// ---------------------------------------------------------------------------
+// Quantiles and list AND / OR (Sec. III-C, III-A)
+// ---------------------------------------------------------------------------
+
+// out[i] = K[min(floor(n k_i / q), n - 1)]; APPROX: f of that index.
+template <int KB, bool APPROX>
+__global__ __launch_bounds__(256) void quantile_kernel(const uint8_t* __restrict__ blob, Layout L,
+                                                       const uint64_t* __restrict__ ks, uint64_t q, uint64_t m,
+                                                       void* __restrict__ out)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += stride) {
+        const unsigned __int128 prod = (unsigned __int128)L.n * ks[t];
+        const unsigned __int128 i = prod / q;
+        const uint64_t idx = i < (unsigned __int128)(L.n - 1) ? (uint64_t)i : L.n - 1;
+        store_key<KB>(out, t, access_one<KB, APPROX>(blob, L, idx));
+    }
+}
+
+constexpr uint32_t kSetTile = 1024;  // elements per tile of the set operations (one per thread)
+static_assert(kSetTile == kSetTileKeys, "host workspace plan uses the same tile");
+
+// x is a key of the compressed list (segment-pruned lower_bound, then one access)
+template <int KB>
+__device__ __forceinline__ bool contains_one(const uint8_t* __restrict__ blob, const Layout& L, uint64_t x)
+{
+    const uint64_t p = lower_bound_one<KB>(blob, L, x);
+    if (p >= L.n) return false;
+    uint64_t v = access_one<KB>(blob, L, p);
+    if constexpr (KB == 4) v &= 0xFFFFFFFFull;
+    return v == x;
+}
+
+// first index i of the decoded sorted array with a[i] >= x
+template <int KB>
+__device__ __forceinline__ uint64_t lb_sorted(const void* __restrict__ a, uint64_t n, uint64_t x)
+{
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (load_key<KB>(a, mid) < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void tile_count(uint32_t f, uint64_t* __restrict__ cnt, uint64_t tile)
+{
+    uint64_t tot;
+    block_excl_sum<kSetTile>(f, &tot);
+    if (threadIdx.x == 0) cnt[tile] = tot;
+}
+
+// AND, probing the compressed list B with the decoded keys of A: flag[i] =
+// A[i] is the first copy of its value and B holds it.  B is never decoded;
+// each probe reads one block's directory entry, the anchors of that block
+// and one segment -- the segment pruning of Sec. III-A.
+template <int KB>
+__global__ __launch_bounds__(kSetTile) void and_flags_kernel(const uint8_t* __restrict__ blob_b, Layout Lb,
+                                                             const void* __restrict__ a, uint64_t na,
+                                                             uint8_t* __restrict__ flags, uint64_t* __restrict__ cnt,
+                                                             uint64_t tile0)
+{
+    const uint64_t tile = tile0 + blockIdx.x;
+    const uint64_t i = tile * kSetTile + threadIdx.x;
+    uint32_t f = 0;
+    if (i < na) {
+        const uint64_t x = load_key<KB>(a, i);
+        f = (i == 0 || load_key<KB>(a, i - 1) != x) && contains_one<KB>(blob_b, Lb, x);
+        flags[i] = (uint8_t)f;
+    }
+    tile_count(f, cnt, tile);
+}
+
+// OR flags over the decoded lists: tiles [0, ta) cover A, the rest B.
+// fa[i] = A[i] is the first copy of its value; fb[j] = B[j] is the first
+// copy of its value and A does not hold it.
+template <int KB>
+__global__ __launch_bounds__(kSetTile) void or_flags_kernel(const void* __restrict__ a, uint64_t na,
+                                                            const void* __restrict__ b, uint64_t nb, uint64_t ta,
+                                                            uint8_t* __restrict__ fa, uint8_t* __restrict__ fb,
+                                                            uint64_t* __restrict__ cnt, uint64_t tile0)
+{
+    const uint64_t tile = tile0 + blockIdx.x;
+    uint32_t f = 0;
+    if (tile < ta) {
+        const uint64_t i = tile * kSetTile + threadIdx.x;
+        if (i < na) {
+            const uint64_t x = load_key<KB>(a, i);
+            f = i == 0 || load_key<KB>(a, i - 1) != x;
+            fa[i] = (uint8_t)f;
+        }
+    } else {
+        const uint64_t j = (tile - ta) * kSetTile + threadIdx.x;
+        if (j < nb) {
+            const uint64_t x = load_key<KB>(b, j);
+            const uint64_t p = lb_sorted<KB>(a, na, x);
+            f = (j == 0 || load_key<KB>(b, j - 1) != x) && !(p < na && load_key<KB>(a, p) == x);
+            fb[j] = (uint8_t)f;
+        }
+    }
+    tile_count(f, cnt, tile);
+}
+
+// One workgroup: exclusive scans of the tile counts of [0, ta) and of
+// [ta, ta + tb) in place; totals to tot[0], tot[1]; count = tot[0] + tot[1].
+__global__ __launch_bounds__(1024) void set_tiles_scan_kernel(uint64_t* __restrict__ cnt, uint64_t ta, uint64_t tb,
+                                                              uint64_t* __restrict__ tot, uint64_t* __restrict__ count)
+{
+    uint64_t sums[2] = {0, 0};
+    for (int part = 0; part < 2; part++) {
+        uint64_t* c = cnt + (part ? ta : 0);
+        const uint64_t nt = part ? tb : ta;
+        uint64_t carry = 0;
+        for (uint64_t t0 = 0; t0 < nt; t0 += 1024) {
+            const uint64_t t = t0 + threadIdx.x;
+            const uint64_t v = t < nt ? c[t] : 0;
+            uint64_t all;
+            const uint64_t ex = block_excl_sum<1024>(v, &all);
+            if (t < nt) c[t] = carry + ex;
+            carry += all;
+        }
+        sums[part] = carry;
+    }
+    if (threadIdx.x == 0) {
+        tot[0] = sums[0];
+        tot[1] = sums[1];
+        *count = sums[0] + sums[1];
+    }
+}
+
+// AND output: the flagged keys of A at their exclusive prefix positions.
+template <int KB>
+__global__ __launch_bounds__(kSetTile) void and_scatter_kernel(const void* __restrict__ a, uint64_t na,
+                                                               const uint8_t* __restrict__ flags,
+                                                               const uint64_t* __restrict__ off, void* __restrict__ out,
+                                                               uint64_t tile0)
+{
+    const uint64_t tile = tile0 + blockIdx.x;
+    const uint64_t i = tile * kSetTile + threadIdx.x;
+    const uint32_t f = i < na ? flags[i] : 0u;
+    uint64_t tot;
+    const uint64_t ex = block_excl_sum<kSetTile>(f, &tot);
+    if (f) store_key<KB>(out, off[tile] + ex, load_key<KB>(a, i));
+}
+
+// OR ranks: P[i] = flags before i (exclusive prefix), P[n] = total.
+// (launched over ceil((n + 1) / kSetTile) tiles, so that index n is covered)
+__global__ __launch_bounds__(kSetTile) void prefix_kernel(const uint8_t* __restrict__ flags, uint64_t n,
+                                                          const uint64_t* __restrict__ off,
+                                                          const uint64_t* __restrict__ total,
+                                                          uint64_t* __restrict__ P, uint64_t tile0)
+{
+    const uint64_t tile = tile0 + blockIdx.x;
+    const uint64_t i = tile * kSetTile + threadIdx.x;
+    const uint32_t f = i < n ? flags[i] : 0u;
+    uint64_t tot;
+    const uint64_t ex = block_excl_sum<kSetTile>(f, &tot);
+    if (i < n) P[i] = off[tile] + ex;
+    if (i == n) P[n] = *total;
+}
+
+// OR output: a kept key x of A goes to (distinct A before it) + (B-only keys
+// < x); a kept key of B to (distinct A < x) + (B-only keys before it): its
+// rank among the distinct keys of A u B.
+template <int KB>
+__global__ __launch_bounds__(kSetTile) void or_scatter_kernel(const void* __restrict__ a, uint64_t na,
+                                                              const void* __restrict__ b, uint64_t nb, uint64_t ta,
+                                                              const uint8_t* __restrict__ fa,
+                                                              const uint8_t* __restrict__ fb,
+                                                              const uint64_t* __restrict__ PA,
+                                                              const uint64_t* __restrict__ PB, void* __restrict__ out,
+                                                              uint64_t tile0)
+{
+    const uint64_t tile = tile0 + blockIdx.x;
+    if (tile < ta) {
+        const uint64_t i = tile * kSetTile + threadIdx.x;
+        if (i < na && fa[i]) {
+            const uint64_t x = load_key<KB>(a, i);
+            store_key<KB>(out, PA[i] + PB[lb_sorted<KB>(b, nb, x)], x);
+        }
+    } else {
+        const uint64_t j = (tile - ta) * kSetTile + threadIdx.x;
+        if (j < nb && fb[j]) {
+            const uint64_t x = load_key<KB>(b, j);
+            store_key<KB>(out, PB[j] + PA[lb_sorted<KB>(a, na, x)], x);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1662,22 +1884,26 @@ hipError_t launch_compress(const void* d_keys, const Layout& L, uint8_t* d_blob,
 }
 
 hipError_t launch_decode(const uint8_t* d_blob, const Layout& L, uint64_t begin, uint64_t end, void* d_out,
-                         hipStream_t stream)
+                         hipStream_t stream, bool approx)
 {
     if (begin >= end) return hipSuccess;
     const uint64_t b_lo = begin >> L.log2b, b_hi = (end - 1) >> L.log2b;
     const uint32_t raw_cap = decode_raw_cap(L.max_seg_bytes, kSegRawSmall);
     const size_t lds = decode_lds_bytes(L.log2b, L.res_stride, raw_cap);
-    const bool range = !(begin == 0 && end == L.n);
-    auto k = L.kb == 4 ? (range ? decode_kernel<4, true> : decode_kernel<4, false>)
-                       : (range ? decode_kernel<8, true> : decode_kernel<8, false>);
+    const bool range = approx || !(begin == 0 && end == L.n);
+    auto k = L.kb == 4 ? (approx ? decode_kernel<4, true, true> : range ? decode_kernel<4, true> : decode_kernel<4, false>)
+                       : (approx ? decode_kernel<8, true, true> : range ? decode_kernel<8, true> : decode_kernel<8, false>);
     hipError_t e = allow_lds((const void*)k, lds);
     if (e != hipSuccess) return e;
     // Stage the compressed bytes the decode will read in the on-die cache:
     // the whole tail of the blob for a full decode; the directory entries and
     // slabs of the blocks touched for a range (its segment areas are found
-    // only through the directory).
-    if (!range) {
+    // only through the directory); the directory entries and segment areas
+    // for the approximate decode, which reads no slab.
+    if (approx) {
+        if (b_hi + 1 - b_lo >= kTouchMinBytes / 1024)
+            hipLaunchKernelGGL(touch_blocks_kernel, dim3(kTouchGrid), dim3(256), 0, stream, d_blob, L, b_lo, b_hi);
+    } else if (!range) {
         hipLaunchKernelGGL(touch_kernel, dim3(kTouchGrid), dim3(256), 0, stream, d_blob, L.off_dir, L.blob_bytes);
     } else {
         const uint64_t d_lo = L.off_dir + 16 * b_lo, d_hi = L.off_dir + 16 * (b_hi + 1);
@@ -1701,6 +1927,73 @@ hipError_t launch_decode(const uint8_t* d_blob, const Layout& L, uint64_t begin,
         hipLaunchKernelGGL(k, dim3((uint32_t)(a.per_xcd * 8)), dim3(64), lds, stream, d_blob, a, d_out);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_quantile(const uint8_t* d_blob, const Layout& L, const uint64_t* d_k, uint64_t q, uint64_t m,
+                           bool approx, void* d_out, hipStream_t stream)
+{
+    if (m == 0) return hipSuccess;
+    auto k = L.kb == 4 ? (approx ? quantile_kernel<4, true> : quantile_kernel<4, false>)
+                       : (approx ? quantile_kernel<8, true> : quantile_kernel<8, false>);
+    hipLaunchKernelGGL(k, dim3(query_grid(m)), dim3(256), 0, stream, d_blob, L, d_k, q, m, d_out);
+    return hipGetLastError();
+}
+
+namespace {
+
+// kernel over `tiles` tiles of kSetTile threads, at most kMaxGrid per launch
+template <typename Fn>
+void over_tiles(uint64_t tiles, Fn launch)
+{
+    for (uint64_t t0 = 0; t0 < tiles; t0 += kMaxGrid) launch((uint32_t)(tiles - t0 < kMaxGrid ? tiles - t0 : kMaxGrid), t0);
+}
+
+template <int KB>
+hipError_t setop_impl(uint32_t op, const uint8_t* blob_a, const Layout& La, const uint8_t* blob_b, const Layout& Lb,
+                      const SetWs& w, void* out, uint64_t* count, hipStream_t st)
+{
+    hipError_t e = hipSuccess;
+    const uint64_t na = La.n, nb = Lb.n;
+    const uint64_t ta = (na + kSetTile - 1) / kSetTile, tb = (nb + kSetTile - 1) / kSetTile;
+    if (na && (e = launch_decode(blob_a, La, 0, na, w.a_keys, st)) != hipSuccess) return e;
+    if (op == LC_SETOP_INTERSECT) {
+        over_tiles(ta, [&](uint32_t g, uint64_t t0) {
+            hipLaunchKernelGGL(and_flags_kernel<KB>, dim3(g), dim3(kSetTile), 0, st, blob_b, Lb, w.a_keys, na, w.fa,
+                               w.cnt, t0);
+        });
+        hipLaunchKernelGGL(set_tiles_scan_kernel, dim3(1), dim3(1024), 0, st, w.cnt, ta, (uint64_t)0, w.tot, count);
+        over_tiles(ta, [&](uint32_t g, uint64_t t0) {
+            hipLaunchKernelGGL(and_scatter_kernel<KB>, dim3(g), dim3(kSetTile), 0, st, w.a_keys, na, w.fa, w.cnt, out,
+                               t0);
+        });
+        return hipGetLastError();
+    }
+    if (nb && (e = launch_decode(blob_b, Lb, 0, nb, w.b_keys, st)) != hipSuccess) return e;
+    over_tiles(ta + tb, [&](uint32_t g, uint64_t t0) {
+        hipLaunchKernelGGL(or_flags_kernel<KB>, dim3(g), dim3(kSetTile), 0, st, w.a_keys, na, w.b_keys, nb, ta, w.fa,
+                           w.fb, w.cnt, t0);
+    });
+    hipLaunchKernelGGL(set_tiles_scan_kernel, dim3(1), dim3(1024), 0, st, w.cnt, ta, tb, w.tot, count);
+    over_tiles(na / kSetTile + 1, [&](uint32_t g, uint64_t t0) {
+        hipLaunchKernelGGL(prefix_kernel, dim3(g), dim3(kSetTile), 0, st, w.fa, na, w.cnt, w.tot, w.PA, t0);
+    });
+    over_tiles(nb / kSetTile + 1, [&](uint32_t g, uint64_t t0) {
+        hipLaunchKernelGGL(prefix_kernel, dim3(g), dim3(kSetTile), 0, st, w.fb, nb, w.cnt + ta, w.tot + 1, w.PB, t0);
+    });
+    over_tiles(ta + tb, [&](uint32_t g, uint64_t t0) {
+        hipLaunchKernelGGL(or_scatter_kernel<KB>, dim3(g), dim3(kSetTile), 0, st, w.a_keys, na, w.b_keys, nb, ta, w.fa,
+                           w.fb, w.PA, w.PB, out, t0);
+    });
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_setop(uint32_t op, const uint8_t* blob_a, const Layout& La, const uint8_t* blob_b, const Layout& Lb,
+                        const SetWs& w, void* out, uint64_t* count, hipStream_t stream)
+{
+    return La.kb == 4 ? setop_impl<4>(op, blob_a, La, blob_b, Lb, w, out, count, stream)
+                      : setop_impl<8>(op, blob_a, La, blob_b, Lb, w, out, count, stream);
 }
 
 hipError_t launch_serve(const uint8_t* d_blob, const ServeArgs& args, const ServeRange* d_ranges,

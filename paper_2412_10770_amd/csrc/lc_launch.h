@@ -81,7 +81,22 @@ lc_status layout_from_info(const lc_blob_info* info, Layout* L);
 hipError_t launch_compress(const void* d_keys, const Layout& L, uint8_t* d_blob, const Workspace& ws,
                            uint64_t* d_blob_bytes, uint32_t* d_flags, hipStream_t stream);
 hipError_t launch_decode(const uint8_t* d_blob, const Layout& L, uint64_t begin, uint64_t end,
-                         void* d_out, hipStream_t stream);
+                         void* d_out, hipStream_t stream, bool approx = false);
+// Workspace of a list AND / OR (carved by the host).
+struct SetWs {
+    void* a_keys;        // decoded keys of A (the probe side for AND)
+    void* b_keys;        // decoded keys of B (OR only)
+    uint8_t *fa, *fb;    // per-key flags
+    uint64_t *PA, *PB;   // OR: exclusive prefix counts, n + 1 entries each
+    uint64_t* cnt;       // per-tile counts, then their exclusive scan
+    uint64_t* tot;       // two totals
+};
+constexpr uint64_t kSetTileKeys = 1024;  // keys per tile of the set operations
+
+hipError_t launch_quantile(const uint8_t* d_blob, const Layout& L, const uint64_t* d_k, uint64_t q, uint64_t m,
+                           bool approx, void* d_out, hipStream_t stream);
+hipError_t launch_setop(uint32_t op, const uint8_t* blob_a, const Layout& La, const uint8_t* blob_b, const Layout& Lb,
+                        const SetWs& w, void* out, uint64_t* count, hipStream_t stream);
 hipError_t launch_serve(const uint8_t* d_blob, const ServeArgs& s, const ServeRange* d_ranges, const ServePoint* d_points,
                         uint8_t* d_arena, hipStream_t stream);
 hipError_t launch_access(const uint8_t* d_blob, const Layout& L, const uint64_t* d_idx, uint64_t m,

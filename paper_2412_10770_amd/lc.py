@@ -30,13 +30,16 @@ LC_FLAG_UNSORTED = 1
 LC_FLAG_RANGE = 2
 LC_FLAG_INTERNAL = 4
 LC_FLAG_BADLIST = 8
+SETOP_INTERSECT = 1
+SETOP_UNION = 2
 BATCH_MAX_CANDIDATES = 8
 HEADER_BYTES = 128
 DEFAULT_LOG2_BLOCK = 10
 DEFAULT_FRAC_BITS = 20
 
 EXPORTED = ("lc_compress_bound", "lc_compress", "lc_info", "lc_decompress", "lc_decompress_range",
-            "lc_access", "lc_lower_bound", "lc_batch_plan", "lc_batch_compress", "lc_batch_sizes",
+            "lc_access", "lc_lower_bound", "lc_quantile", "lc_decompress_approx", "lc_setop_bound", "lc_setop",
+            "lc_batch_plan", "lc_batch_compress", "lc_batch_sizes",
             "lc_batch_pick_eps", "lc_batch_decompress", "lc_server_create", "lc_server_run",
             "lc_server_destroy", "lc_strerror")
 
@@ -100,6 +103,10 @@ def _load():
         "lc_decompress_range": [vp, I, u64, u64, vp, vp],
         "lc_access": [vp, I, vp, u64, vp, vp, vp],
         "lc_lower_bound": [vp, I, vp, u64, vp, vp],
+        "lc_quantile": [vp, I, vp, u64, u64, u32, vp, vp],
+        "lc_decompress_approx": [vp, I, u64, u64, vp, vp],
+        "lc_setop_bound": [I, I, u32, ctypes.POINTER(u64), ctypes.POINTER(u64)],
+        "lc_setop": [u32, vp, I, vp, I, vp, u64, vp, u64, vp, vp],
         "lc_batch_plan": [ctypes.POINTER(lc_batch_params), vp],
         "lc_batch_compress": [vp, u64, vp, ctypes.POINTER(lc_batch_params), vp, u64, vp, u64, vp, vp, vp],
         "lc_batch_sizes": [vp, u64, vp, ctypes.POINTER(lc_batch_params), vp, u32, vp, u64, vp, vp, vp],
@@ -305,6 +312,71 @@ def lower_bound(blob: Blob, q: torch.Tensor, out: torch.Tensor | None = None, st
                               ctypes.c_void_p(q.data_ptr()), q.numel(), ctypes.c_void_p(out.data_ptr()),
                               _stream(stream)), "lc_lower_bound")
     return out
+
+
+# ---------------------------------------------------------------------------
+# Queries on the compressed form: quantile, approximate decode, list AND / OR
+# ---------------------------------------------------------------------------
+
+def quantile(blob: Blob, k: torch.Tensor, q: int, approx: bool = False, out: torch.Tensor | None = None,
+             stream=None) -> torch.Tensor:
+    """k-th q-quantiles K[min(floor(n k / q), n - 1)] for every k (int64
+    tensor); approx: the model's prediction of that key (within eps)."""
+    _dev(k, "k")
+    if k.dtype not in (torch.int64, torch.uint64):
+        raise TypeError("k must be a 64-bit integer tensor")
+    if out is None:
+        out = torch.empty(k.numel(), dtype=key_dtype(blob.key_bytes), device=k.device)
+    _check(lib.lc_quantile(_ptr(blob.data), ctypes.byref(blob.info), _ptr(k), q, k.numel(), int(approx), _ptr(out),
+                           _stream(stream)), "lc_quantile")
+    return out
+
+
+def decompress_approx(blob: Blob, begin: int = 0, end: int | None = None, out: torch.Tensor | None = None,
+                      stream=None) -> torch.Tensor:
+    """Keys [begin, end) from the model alone (no residuals): each within eps."""
+    end = blob.n if end is None else end
+    if out is None:
+        out = torch.empty(max(0, end - begin), dtype=key_dtype(blob.key_bytes), device=blob.data.device)
+    _check(lib.lc_decompress_approx(_ptr(blob.data), ctypes.byref(blob.info), begin, end, _ptr(out),
+                                    _stream(stream)), "lc_decompress_approx")
+    return out
+
+
+def setop_bound(a: Blob, b: Blob, op: int):
+    """(out_max keys, workspace bytes) of lc_setop."""
+    out_max, ws = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(lib.lc_setop_bound(ctypes.byref(a.info), ctypes.byref(b.info), op, ctypes.byref(out_max),
+                              ctypes.byref(ws)), "lc_setop_bound")
+    return out_max.value, ws.value
+
+
+def setop_async(op: int, a: Blob, b: Blob, ws: torch.Tensor, out: torch.Tensor, count: torch.Tensor, stream=None):
+    """Enqueue lc_setop into caller-provided buffers (count: device int64[1])."""
+    _check(lib.lc_setop(op, _ptr(a.data), ctypes.byref(a.info), _ptr(b.data), ctypes.byref(b.info), _ptr(ws),
+                        ws.numel(), _ptr(out), out.numel(), _ptr(count), _stream(stream)), "lc_setop")
+
+
+def _setop(op: int, a: Blob, b: Blob, stream=None) -> torch.Tensor:
+    if a.key_bytes != b.key_bytes:
+        raise TypeError("both lists must have the same key width")
+    out_max, ws_bytes = setop_bound(a, b, op)
+    dev = a.data.device
+    ws = torch.empty(max(ws_bytes, 16), dtype=torch.uint8, device=dev)
+    out = torch.empty(max(out_max, 1), dtype=key_dtype(a.key_bytes), device=dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    setop_async(op, a, b, ws, out, count, stream)
+    return out[:int(count.item())]
+
+
+def intersect(a: Blob, b: Blob, stream=None) -> torch.Tensor:
+    """AND of two compressed lists (sorted, each key once)."""
+    return _setop(SETOP_INTERSECT, a, b, stream)
+
+
+def union(a: Blob, b: Blob, stream=None) -> torch.Tensor:
+    """OR of two compressed lists (sorted, each key once)."""
+    return _setop(SETOP_UNION, a, b, stream)
 
 
 # ---------------------------------------------------------------------------

@@ -166,3 +166,32 @@ def test_batch_bad_args(lc):
     assert lc.lib.lc_batch_decompress(fake, 1 << 30, fake, P(good), 4096, ctypes.c_void_p((1 << 20) + 2), 30, fake,
                                       None) == lc.LC_EINVAL
     assert lc.lib.lc_batch_decompress(fake, 1 << 30, None, P(good), 4096, fake, 30, fake, None) == lc.LC_EINVAL
+
+
+def test_setop_bound_and_bad_args(lc):
+    """lc_setop_bound is host code: AND capacity min(n_a, n_b), OR n_a + n_b;
+    key widths must match; bad arguments fail before any launch."""
+    a = lc.info(oracle.compress(np.arange(0, 30000, 3, dtype=np.uint64), 63, 10)[:128])
+    b = lc.info(oracle.compress(np.arange(0, 3000, 7, dtype=np.uint64), 15, 10)[:128])
+    c32 = lc.info(oracle.compress(np.arange(0, 500, dtype=np.uint32), 7, 10)[:128])
+    P = ctypes.byref
+    om, ws = ctypes.c_uint64(), ctypes.c_uint64()
+    assert lc.lib.lc_setop_bound(P(a), P(b), lc.SETOP_INTERSECT, P(om), P(ws)) == lc.LC_OK
+    assert om.value == min(a.n, b.n) and ws.value >= min(a.n, b.n) * 9
+    assert lc.lib.lc_setop_bound(P(a), P(b), lc.SETOP_UNION, P(om), P(ws)) == lc.LC_OK
+    assert om.value == a.n + b.n and ws.value >= (a.n + b.n) * 17
+    assert lc.lib.lc_setop_bound(P(a), P(c32), lc.SETOP_UNION, P(om), P(ws)) == lc.LC_EINVAL
+    assert lc.lib.lc_setop_bound(P(a), P(b), 3, P(om), P(ws)) == lc.LC_EINVAL
+    fake = ctypes.c_void_p(1 << 20)
+    # output too small / workspace too small / null count: refused before any launch
+    assert lc.lib.lc_setop(lc.SETOP_UNION, fake, P(a), fake, P(b), fake, 1 << 30, fake, a.n + b.n - 1, fake,
+                           None) == lc.LC_ENOSPC
+    assert lc.lib.lc_setop(lc.SETOP_UNION, fake, P(a), fake, P(b), fake, 16, fake, a.n + b.n, fake,
+                           None) == lc.LC_ENOSPC
+    assert lc.lib.lc_setop(lc.SETOP_INTERSECT, fake, P(a), fake, P(b), fake, 1 << 30, fake, 1 << 20, None,
+                           None) == lc.LC_EINVAL
+    # quantile: q = 0 and misaligned k; approximate decode: bad range
+    assert lc.lib.lc_quantile(fake, P(a), fake, 0, 5, 0, fake, None) == lc.LC_EINVAL
+    assert lc.lib.lc_quantile(fake, P(a), ctypes.c_void_p((1 << 20) + 4), 4, 5, 0, fake, None) == lc.LC_EINVAL
+    assert lc.lib.lc_decompress_approx(fake, P(a), 5, 4, fake, None) == lc.LC_EINVAL
+    assert lc.lib.lc_decompress_approx(fake, P(a), 0, a.n + 1, fake, None) == lc.LC_EINVAL
