@@ -279,6 +279,121 @@ def bench_lookups(dev, n: int = 200_000_000, eps: int = 63, n_access: int = 10_0
     }
 
 
+def bench_queries(dev, n: int = 100_000_000, eps: int = 63, n_quantile: int = 10_000_000, npairs: int = 48,
+                  reps: int = 5):
+    """Queries on the compressed form.  On the lognormal store (n keys, eps):
+    the approximate decode (model only, no residual slab) against the exact
+    decode, and n_quantile quantiles, exact and approximate.  On posting
+    lists (the batch workload's recipe): list AND of a short list (1e3..1e4
+    keys) with a long one (the longest lists) and list OR of the same pairs,
+    each one lc_setop call, against decoding both lists and intersecting /
+    merging the decoded keys with torch (searchsorted, masked_select,
+    cat + unique)."""
+    import numpy as np
+    import torch
+
+    from paper_2412_10770_amd import lc, workloads
+
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a, b = ev(), ev()
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.mean(ts))
+
+    keys = workloads.lognormal_distinct(n, device=dev)
+    blob = lc.compress(keys, eps)
+    out = torch.empty(n, dtype=torch.int64, device=dev)
+    lc.decompress(blob, out=out)
+    assert torch.equal(out, keys)
+    t_exact = timed(lambda: lc.decompress(blob, out=out))
+    t_apx = timed(lambda: lc.decompress_approx(blob, out=out))
+    err = int((out - keys).abs().max())
+    assert err <= eps
+    kq = workloads.uniform_indices(n_quantile, 1 << 20, seed=workloads.SEED_BASE + 106, device=dev)
+    qout = torch.empty(n_quantile, dtype=torch.int64, device=dev)
+    t_q = timed(lambda: lc.quantile(blob, kq, 1 << 20, out=qout))
+    t_qa = timed(lambda: lc.quantile(blob, kq, 1 << 20, approx=True, out=qout))
+    del keys, out, blob
+    torch.cuda.empty_cache()
+
+    pl, lengths = workloads.posting_lists(4096, device=dev)
+    offs = np.concatenate([[0], np.cumsum(lengths)[:-1]])
+    rng = np.random.default_rng(workloads.SEED_BASE + 107)
+    longs = np.argsort(lengths)[-npairs:]
+    shorts = rng.choice(np.flatnonzero((lengths >= 1000) & (lengths <= 10000)), npairs, replace=False)
+    pairs = []
+    for s_, l_ in zip(shorts, longs):
+        a = pl[offs[s_]:offs[s_] + lengths[s_]]
+        b = pl[offs[l_]:offs[l_] + lengths[l_]]
+        pairs.append((a, b, lc.compress(a, 31), lc.compress(b, 31)))
+    del pl
+    # buffers sized for the largest pair, allocated once
+    mx_and = max(lc.setop_bound(A, B, lc.SETOP_INTERSECT)[1] for _, _, A, B in pairs)
+    mx_or = max(lc.setop_bound(A, B, lc.SETOP_UNION) for _, _, A, B in pairs)
+    ws = torch.empty(max(mx_and, mx_or[1]), dtype=torch.uint8, device=dev)
+    sout = torch.empty(mx_or[0], dtype=torch.int32, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    da = torch.empty(max(int(x[0].numel()) for x in pairs), dtype=torch.int32, device=dev)
+    db = torch.empty(max(int(x[1].numel()) for x in pairs), dtype=torch.int32, device=dev)
+    u = lambda t: t.to(torch.int64) & 0xFFFFFFFF  # noqa: E731  (uint32 keys held as int32 bit patterns)
+    for a, b, A, B in pairs[:4]:  # the timed paths give the definitions' answers
+        assert torch.equal(u(lc.intersect(A, B)), u(a)[torch.isin(u(a), u(b))].unique())
+        assert torch.equal(u(lc.union(A, B)), torch.cat([u(a), u(b)]).unique())
+
+    def run_and():
+        for _, _, A, B in pairs:
+            lc.setop_async(lc.SETOP_INTERSECT, A, B, ws, sout, cnt)
+
+    def run_or():
+        for _, _, A, B in pairs:
+            lc.setop_async(lc.SETOP_UNION, A, B, ws, sout, cnt)
+
+    def base_and():
+        for _, _, A, B in pairs:
+            x, y = da[:A.n], db[:B.n]
+            lc.decompress(A, out=x)
+            lc.decompress(B, out=y)
+            x, y = u(x), u(y)
+            p = torch.searchsorted(y, x).clamp_(max=y.numel() - 1)
+            x.masked_select(y[p] == x)
+
+    def base_or():
+        for _, _, A, B in pairs:
+            x, y = da[:A.n], db[:B.n]
+            lc.decompress(A, out=x)
+            lc.decompress(B, out=y)
+            torch.cat([u(x), u(y)]).unique()
+
+    t_and, t_or = timed(run_and), timed(run_or)
+    t_band, t_bor = timed(base_and), timed(base_or)
+    short_keys = int(sum(A.n for _, _, A, _ in pairs))
+    long_keys = int(sum(B.n for _, _, _, B in pairs))
+    return {
+        "workload": f"approximate decode and quantiles on {n} lognormal uint64 keys (eps {eps}); list AND / OR "
+                    f"of {npairs} pairs of posting lists (a list of 1e3..1e4 keys with one of the {npairs} longest, "
+                    f"eps 31), one call per pair",
+        "decode_exact_GBps": round(n * 8 / t_exact / 1e6, 2),
+        "decode_approx_GBps": round(n * 8 / t_apx / 1e6, 2),
+        "approx_max_error": err,
+        "quantiles_per_s": round(n_quantile / t_q * 1e3, 1),
+        "approx_quantiles_per_s": round(n_quantile / t_qa * 1e3, 1),
+        "and_pairs_per_s": round(npairs / t_and * 1e3, 1),
+        "and_pairs_per_s_decode_both_torch": round(npairs / t_band * 1e3, 1),
+        "or_pairs_per_s": round(npairs / t_or * 1e3, 1),
+        "or_pairs_per_s_decode_both_torch": round(npairs / t_bor * 1e3, 1),
+        "and_probe_keys": short_keys, "and_searched_keys": long_keys,
+    }
+
+
 def bench_serve(dev, n: int = 1_000_000_000, qps_points=(1e3, 1e4, 1e5, 1e6, None), arena_bytes: int = 2 << 30,
                 max_batch: int = 1024, max_inflight: int = 4, eps_cands=(15, 63, 255, 1023)):
     """Request server over a compressed store of n uint64 keys (gaps
@@ -376,6 +491,8 @@ def main():
     ap.add_argument("--serve-only", action="store_true", help="only the request-server measurement")
     ap.add_argument("--serve-n", type=int, default=1_000_000_000)
     ap.add_argument("--no-lookups", action="store_true", help="skip the heterogeneous-runs lookup measurement")
+    ap.add_argument("--no-queries", action="store_true", help="skip the quantile / approximate / AND / OR measurement")
+    ap.add_argument("--queries-only", action="store_true", help="only the quantile / approximate / AND / OR measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path is "
@@ -391,6 +508,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.batch_only:
         print(json.dumps(bench_batch(dev, args.steps, args.warmup)), flush=True)
+        return
+    if args.queries_only:
+        print(json.dumps(bench_queries(dev)), flush=True)
         return
     if args.serve_only:
         print(json.dumps(bench_serve(dev, args.serve_n)), flush=True)
@@ -546,6 +666,9 @@ def main():
     }
     if not args.no_lookups:
         result["lookups"] = bench_lookups(dev)
+        torch.cuda.empty_cache()
+    if not args.no_queries:
+        result["queries"] = bench_queries(dev)
         torch.cuda.empty_cache()
     if not args.no_batch:
         del out, wss, blobs
