@@ -175,3 +175,51 @@ def test_serving_store_1e9(lc, wl):
         else:
             q = torch.tensor([int(a[i])], dtype=i64, device=DEV)
             assert int(seg[0]) == int(torch.searchsorted(keys, q, side="left")[0]), ("lower_bound", i)
+
+
+def test_grid_chunking_past_2_22_workgroups(lc, wl):
+    """1.1e9 uint32 keys in 64-key blocks: more than 2^22 fit workgroups
+    (four blocks each) and decode workgroups, so every launcher splits its
+    grid into several launches.  Round trip, directory / size closed forms,
+    blocks sampled on both sides of each split against the oracle, ranges
+    across the splits, access and lower_bound samples."""
+    n = 1_100_000_000
+    g = torch.Generator(device=DEV)
+    g.manual_seed(wl.SEED_BASE + 60)
+    keys = torch.cumsum(torch.randint(0, 4, (n,), device=DEV, generator=g, dtype=torch.int32), 0,
+                        dtype=torch.int64).to(torch.int32)  # gaps 0..3: < 2^32 in all
+    _say("grid chunking: 1.1e9 u32 keys, 64-key blocks")
+    blob = lc.compress(keys, 7, 6)
+    h = blob.info
+    assert h.nblocks > (1 << 22) * 4 and h.nblocks == (n + 63) // 64
+    out = lc.decompress(blob)
+    assert torch.equal(out, keys), "round trip (Def. 1)"
+    del out
+    data = blob.data.cpu().numpy()
+    dirs = data[h.off_dir:h.off_dir + 16 * h.nblocks].reshape(-1, 16)
+    seg_off = dirs[:, 0:8].copy().view(np.uint64).ravel().astype(np.int64)
+    nseg = dirs[:, 8:12].copy().view(np.uint32).ravel().astype(np.int64)
+    ab = dirs[:, 14].astype(np.int64)
+    sb = dirs[:, 15].astype(np.int64)
+    area = a16(2 * nseg) + a16(ab * nseg) + a16(sb * nseg)
+    assert np.array_equal(seg_off[1:], seg_off[:-1] + area[:-1]) and seg_off[0] == h.off_seg
+    assert h.blob_bytes == h.off_seg + int(area.sum()) == len(data)
+    split_fit, split_dec = (1 << 22) * 4, 1 << 22  # first block of the second launch of each
+    picks = {0, split_dec - 1, split_dec, split_dec + 1, 2 * split_dec, split_fit - 1, split_fit, split_fit + 3,
+             h.nblocks - 1}
+    for b in sorted(p for p in picks if p < h.nblocks):
+        kk = keys[b * 64:(b + 1) * 64].cpu().numpy().view(np.uint32)
+        one = oracle.compress(kk, 7, 6)
+        oh = oracle.header(one)
+        assert np.array_equal(one[oh["off_dir"] + 8:oh["off_dir"] + 16], dirs[b, 8:16]), b
+        assert np.array_equal(one[oh["off_res"]:oh["off_res"] + h.res_stride],
+                              data[h.off_res + b * h.res_stride:h.off_res + (b + 1) * h.res_stride]), b
+        assert np.array_equal(one[oh["off_seg"]:oh["blob_bytes"]], data[seg_off[b]:seg_off[b] + area[b]]), b
+    for a_, e_ in ((split_dec * 64 - 100, split_dec * 64 + 100), (split_fit * 64 - 5, split_fit * 64 + 77)):
+        assert torch.equal(lc.decompress_range(blob, a_, e_), keys[a_:e_]), (a_, e_)
+    idx = torch.randint(0, n, (100_000,), device=DEV, generator=g)
+    assert torch.equal(lc.access(blob, idx), keys[idx])
+    q = keys[idx[:10_000]] + 1  # uint32 bit patterns (wraps like the unsigned key)
+    u = lambda t: t.to(torch.int64) & 0xFFFFFFFF  # noqa: E731
+    want = torch.searchsorted(u(keys), u(q), side="left")
+    assert torch.equal(lc.lower_bound(blob, q), want)
