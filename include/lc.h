@@ -354,6 +354,40 @@ lc_status lc_server_run(lc_server* s, const lc_request* h_reqs, uint64_t n, lc_r
 /* Waits for the server's streams and frees what lc_server_create allocated. */
 lc_status lc_server_destroy(lc_server* s);
 
+/* ---- AND over many pairs of lists of one batch (Sec. III-A) -------------
+ * The list AND of lc_setop for every pair of a table, in five launches for
+ * all pairs: the probe list of each pair (the shorter one) is decoded into
+ * the workspace, every probe key is searched in the other list in its
+ * compressed form, and each pair's result (sorted, each key once) is packed
+ * at the start of its own output region. */
+
+/* One pair (40 bytes). */
+typedef struct lc_list_pair {
+    uint32_t a, b;          /* list indices into the batch table */
+    uint32_t probe, target; /* set by lc_batch_and_plan: probe = the shorter list */
+    uint64_t key_off;       /* set by the plan: output / workspace key offset (probe keys of earlier pairs) */
+    uint64_t block_off;     /* set by the plan: probe blocks of earlier pairs */
+    uint64_t n;             /* set by the plan: keys of the probe list (capacity of the pair's output) */
+} lc_list_pair;
+
+/* Host, pure: fills probe, target, key_off, block_off and n of h_pairs[0 ..
+ * npairs) from the host copy of the batch table (as lc_batch_plan left it)
+ * and returns the totals and the workspace size of lc_batch_and.  Errors:
+ * LC_EINVAL (a list index >= nlists, NULL, bad parameters). */
+lc_status lc_batch_and_plan(const lc_batch_params* p, const lc_batch_list* h_lists, lc_list_pair* h_pairs,
+                            uint32_t npairs, uint64_t* total_keys, uint64_t* total_blocks, uint64_t* ws_bytes);
+
+/* Runs the plan: d_pairs is the device copy of the planned table; pair i's
+ * result keys go to d_out + key_off (d_out: total_keys keys, aligned to the
+ * key width) and their number to d_counts[i] (device u64[npairs]).
+ * max_seg_bytes: as lc_batch_decompress.  A pair whose lists do not fit the
+ * buffers is skipped with count 0 and LC_FLAG_BADLIST in *d_stats.  Errors:
+ * LC_EINVAL, LC_ENOSPC (ws_bytes), LC_EDEVICE. */
+lc_status lc_batch_and(const void* d_blob, uint64_t blob_cap, const lc_batch_list* d_lists,
+                       const lc_batch_params* p, const lc_list_pair* d_pairs, uint32_t npairs, uint64_t total_keys,
+                       uint64_t total_blocks, uint32_t max_seg_bytes, void* d_ws, uint64_t ws_bytes, void* d_out,
+                       uint64_t* d_counts, uint32_t* d_stats, void* stream);
+
 /* Static description of a status code. */
 const char* lc_strerror(lc_status s);
 

@@ -524,6 +524,85 @@ LC_API lc_status lc_batch_decompress(const void* d_blob, uint64_t blob_cap, cons
     return e == hipSuccess ? LC_OK : LC_EDEVICE;
 }
 
+namespace {
+
+struct PairPlan {
+    uint64_t keys, flags, cnt, tot, P, total;
+};
+
+PairPlan plan_pairs(uint64_t total_keys, uint32_t kb)
+{
+    const uint64_t tiles = (total_keys + lc::kSetTileKeys - 1) / lc::kSetTileKeys;
+    PairPlan p;
+    p.keys = 0;
+    p.flags = lc::align16(total_keys * kb);
+    p.cnt = p.flags + lc::align16(total_keys);
+    p.tot = p.cnt + lc::align16((tiles + 2) * 8);
+    p.P = p.tot + 16;
+    p.total = p.P + lc::align16((total_keys + 1) * 8);
+    return p;
+}
+
+}  // namespace
+
+LC_API lc_status lc_batch_and_plan(const lc_batch_params* p, const lc_batch_list* h_lists, lc_list_pair* h_pairs,
+                                   uint32_t npairs, uint64_t* total_keys, uint64_t* total_blocks, uint64_t* ws_bytes)
+{
+    lc_status st = check_batch(p);
+    if (st != LC_OK) return st;
+    if (!h_lists || (npairs && !h_pairs)) return LC_EINVAL;
+    const uint64_t B = 1ull << p->log2_block;
+    uint64_t keys = 0, blocks = 0;
+    for (uint32_t i = 0; i < npairs; i++) {
+        lc_list_pair& pr = h_pairs[i];
+        if (pr.a >= p->nlists || pr.b >= p->nlists) return LC_EINVAL;
+        const bool a_probe = h_lists[pr.a].n <= h_lists[pr.b].n;
+        pr.probe = a_probe ? pr.a : pr.b;
+        pr.target = a_probe ? pr.b : pr.a;
+        pr.n = h_lists[pr.probe].n;
+        if (pr.n > kMaxKeys) return LC_EINVAL;
+        pr.key_off = keys;
+        pr.block_off = blocks;
+        keys += pr.n;
+        blocks += (pr.n + B - 1) / B;
+        if (keys >> 50) return LC_EINVAL;
+    }
+    if (total_keys) *total_keys = keys;
+    if (total_blocks) *total_blocks = blocks;
+    if (ws_bytes) *ws_bytes = plan_pairs(keys, p->key_bytes).total;
+    return LC_OK;
+}
+
+LC_API lc_status lc_batch_and(const void* d_blob, uint64_t blob_cap, const lc_batch_list* d_lists,
+                              const lc_batch_params* p, const lc_list_pair* d_pairs, uint32_t npairs,
+                              uint64_t total_keys, uint64_t total_blocks, uint32_t max_seg_bytes, void* d_ws,
+                              uint64_t ws_bytes, void* d_out, uint64_t* d_counts, uint32_t* d_stats, void* stream)
+{
+    lc_status st = check_batch(p);
+    if (st != LC_OK) return st;
+    if (npairs == 0) return LC_OK;
+    if (!d_blob || !d_lists || !d_pairs || !d_ws || !d_counts || !d_stats || misaligned(d_blob, 16) ||
+        misaligned(d_lists, 8) || misaligned(d_pairs, 8) || misaligned(d_ws, 16) || misaligned(d_counts, 8) ||
+        misaligned(d_stats, 4))
+        return LC_EINVAL;
+    if (total_keys > kMaxKeys || total_blocks > total_keys) return LC_EINVAL;
+    if (total_keys && (!d_out || misaligned(d_out, p->key_bytes))) return LC_EINVAL;
+    const PairPlan pl = plan_pairs(total_keys, p->key_bytes);
+    if (ws_bytes < pl.total) return LC_ENOSPC;
+    uint8_t* ws = static_cast<uint8_t*>(d_ws);
+    lc::PairWs w;
+    w.keys = ws + pl.keys;
+    w.flags = ws + pl.flags;
+    w.cnt = reinterpret_cast<uint64_t*>(ws + pl.cnt);
+    w.tot = reinterpret_cast<uint64_t*>(ws + pl.tot);
+    w.P = reinterpret_cast<uint64_t*>(ws + pl.P);
+    lc::BatchArgs a = batch_args(p, ~0ull, blob_cap);  // key offsets of the table are not used here
+    hipError_t e = lc::launch_batch_and(static_cast<const uint8_t*>(d_blob), d_lists, a, d_pairs, npairs, total_keys,
+                                        total_blocks, max_seg_bytes, w, d_out, d_counts, d_stats,
+                                        static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LC_OK : LC_EDEVICE;
+}
+
 LC_API const char* lc_strerror(lc_status s)
 {
     switch (s) {

@@ -1714,6 +1714,120 @@ __global__ __launch_bounds__(64) void batch_decode_kernel(const uint8_t* __restr
     decode_block<KB, true>(blob + li.blob_off, d, b, raw_cap, reinterpret_cast<uint8_t*>(out) + li.key_off * KB);
 }
 
+// ---- AND over pairs of lists of a batch ------------------------------------
+
+// The pair owning item x (a probe block or key): the last p with off(p) <= x.
+template <bool BY_BLOCK>
+__device__ __forceinline__ uint32_t find_pair(const lc_list_pair* __restrict__ pairs, uint32_t npairs, uint64_t x)
+{
+    uint32_t lo = 0, hi = npairs;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if ((BY_BLOCK ? pairs[mid].block_off : pairs[mid].key_off) <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Does the pair fit the buffers?  Both lists inside the batch, their slots
+// inside the blob buffer, the probe keys and blocks inside the plan's totals.
+__device__ __forceinline__ bool pair_fits(const lc_list_pair& pr, const lc_batch_list* __restrict__ lists,
+                                          const BatchArgs& a, uint64_t total_keys, uint64_t total_blocks,
+                                          lc_batch_list* lp, lc_batch_list* lt, Layout* Lp, Layout* Lt)
+{
+    if (pr.probe >= a.nlists || pr.target >= a.nlists) return false;
+    *lp = lists[pr.probe];
+    *lt = lists[pr.target];
+    *Lp = list_layout(a, lp->n, lp->eps);
+    *Lt = list_layout(a, lt->n, lt->eps);
+    return list_fits(*lp, a, *Lp, lp->eps, true) && list_fits(*lt, a, *Lt, lt->eps, true) && pr.n == lp->n &&
+           pr.key_off <= total_keys && pr.n <= total_keys - pr.key_off && pr.block_off <= total_blocks &&
+           Lp->nblocks <= total_blocks - pr.block_off;
+}
+
+// Probe lists of all pairs decoded into the workspace: one wave per block.
+template <int KB>
+__global__ __launch_bounds__(64) void pair_decode_kernel(const uint8_t* __restrict__ blob,
+                                                         const lc_batch_list* __restrict__ lists, BatchArgs a,
+                                                         const lc_list_pair* __restrict__ pairs, uint32_t npairs,
+                                                         uint64_t total_keys, uint64_t total_blocks, uint64_t blk0,
+                                                         uint64_t nblk, uint64_t per_xcd, uint32_t raw_cap,
+                                                         void* __restrict__ keys, uint32_t* __restrict__ stats)
+{
+    const uint64_t rel = (uint64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (rel >= nblk) return;
+    const uint64_t gb = blk0 + rel;
+    const lc_list_pair pr = pairs[find_pair<true>(pairs, npairs, gb)];
+    lc_batch_list lp, lt;
+    DecodeArgs d{};
+    Layout Lt;
+    if (!pair_fits(pr, lists, a, total_keys, total_blocks, &lp, &lt, &d.L, &Lt)) {
+        if (threadIdx.x == 0) atomicOr(stats, kFlagBadList);
+        return;
+    }
+    const uint64_t b = gb - pr.block_off;
+    if (b >= d.L.nblocks) return;  // blocks of an empty pair's neighbours
+    d.begin = 0;
+    d.end = lp.n;
+    d.raw_cap = raw_cap;
+    d.bytes = lp.blob_cap;
+    d.flags = stats;
+    decode_block<KB, true>(blob + lp.blob_off, d, b, raw_cap, reinterpret_cast<uint8_t*>(keys) + pr.key_off * KB);
+}
+
+// flag[i] = probe key i is the first copy of its value within its pair and
+// the pair's target list (compressed) holds it.
+template <int KB>
+__global__ __launch_bounds__(kSetTile) void pair_flags_kernel(const uint8_t* __restrict__ blob,
+                                                              const lc_batch_list* __restrict__ lists, BatchArgs a,
+                                                              const lc_list_pair* __restrict__ pairs, uint32_t npairs,
+                                                              uint64_t total_keys, uint64_t total_blocks,
+                                                              const void* __restrict__ keys,
+                                                              uint8_t* __restrict__ flags, uint64_t* __restrict__ cnt,
+                                                              uint64_t tile0)
+{
+    const uint64_t tile = tile0 + blockIdx.x;
+    const uint64_t i = tile * kSetTile + threadIdx.x;
+    uint32_t f = 0;
+    if (i < total_keys) {
+        const lc_list_pair pr = pairs[find_pair<false>(pairs, npairs, i)];
+        lc_batch_list lp, lt;
+        Layout Lp, Lt;
+        if (pair_fits(pr, lists, a, total_keys, total_blocks, &lp, &lt, &Lp, &Lt) && i - pr.key_off < pr.n) {
+            const uint64_t x = load_key<KB>(keys, i);
+            f = (i == pr.key_off || load_key<KB>(keys, i - 1) != x) && contains_one<KB>(blob + lt.blob_off, Lt, x);
+        }
+        flags[i] = (uint8_t)f;
+    }
+    tile_count(f, cnt, tile);
+}
+
+// Found keys packed at the start of their pair's region; counts per pair.
+template <int KB>
+__global__ __launch_bounds__(kSetTile) void pair_scatter_kernel(const lc_list_pair* __restrict__ pairs,
+                                                                uint32_t npairs, uint64_t total_keys,
+                                                                const void* __restrict__ keys,
+                                                                const uint8_t* __restrict__ flags,
+                                                                const uint64_t* __restrict__ P, void* __restrict__ out,
+                                                                uint64_t tile0)
+{
+    const uint64_t i = (tile0 + blockIdx.x) * kSetTile + threadIdx.x;
+    if (i >= total_keys || !flags[i]) return;
+    const lc_list_pair pr = pairs[find_pair<false>(pairs, npairs, i)];
+    store_key<KB>(out, pr.key_off + (P[i] - P[pr.key_off]), load_key<KB>(keys, i));
+}
+
+__global__ __launch_bounds__(256) void pair_counts_kernel(const lc_list_pair* __restrict__ pairs, uint32_t npairs,
+                                                          uint64_t total_keys, const uint64_t* __restrict__ P,
+                                                          uint64_t* __restrict__ counts)
+{
+    const uint32_t p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= npairs) return;
+    const lc_list_pair pr = pairs[p];
+    const bool ok = pr.key_off <= total_keys && pr.n <= total_keys - pr.key_off;
+    counts[p] = ok ? P[pr.key_off + pr.n] - P[pr.key_off] : 0;
+}
+
 // eps of list l := the candidate with the smallest size (ties: the smaller
 // eps, i.e. the earlier candidate).
 __global__ __launch_bounds__(256) void batch_pick_kernel(lc_batch_list* __restrict__ lists, uint32_t nlists,
@@ -1725,6 +1839,13 @@ __global__ __launch_bounds__(256) void batch_pick_kernel(lc_batch_list* __restri
     for (uint32_t c = 1; c < cands.n; c++)
         if (sizes[(uint64_t)c * nlists + l] < sizes[(uint64_t)best * nlists + l]) best = c;
     lists[l].eps = cands.eps[best];
+}
+
+// kernel over `tiles` tiles of kSetTile threads, at most kMaxGrid per launch
+template <typename Fn>
+void over_tiles(uint64_t tiles, Fn launch)
+{
+    for (uint64_t t0 = 0; t0 < tiles; t0 += kMaxGrid) launch((uint32_t)(tiles - t0 < kMaxGrid ? tiles - t0 : kMaxGrid), t0);
 }
 
 inline uint32_t query_grid(uint64_t m)
@@ -1849,6 +1970,47 @@ hipError_t launch_batch_decode(const uint8_t* d_blob, const lc_batch_list* d_lis
     return hipGetLastError();
 }
 
+hipError_t launch_batch_and(const uint8_t* d_blob, const lc_batch_list* d_lists, const BatchArgs& a,
+                            const lc_list_pair* d_pairs, uint32_t npairs, uint64_t total_keys, uint64_t total_blocks,
+                            uint32_t max_seg_bytes, const PairWs& w, void* d_out, uint64_t* d_counts,
+                            uint32_t* d_stats, hipStream_t stream)
+{
+    uint32_t wd = 0;
+    while ((1ull << wd) < 2ull * a.max_eps + 1) wd++;
+    const uint64_t res_stride = align16(((1ull << a.log2b) * wd + 7) / 8);
+    const uint32_t raw_cap = decode_raw_cap(max_seg_bytes, kSegRawSmall);
+    const size_t lds = decode_lds_bytes(a.log2b, res_stride, raw_cap);
+    auto kd = a.kb == 4 ? pair_decode_kernel<4> : pair_decode_kernel<8>;
+    hipError_t e = allow_lds((const void*)kd, lds);
+    if (e != hipSuccess) return e;
+    for (uint64_t b0 = 0; b0 < total_blocks; b0 += kMaxGrid) {
+        const uint64_t nblk = total_blocks - b0 < kMaxGrid ? total_blocks - b0 : kMaxGrid;
+        const uint64_t per_xcd = (nblk + 7) / 8;
+        hipLaunchKernelGGL(kd, dim3((uint32_t)(per_xcd * 8)), dim3(64), lds, stream, d_blob, d_lists, a, d_pairs,
+                           npairs, total_keys, total_blocks, b0, nblk, per_xcd, raw_cap, w.keys, d_stats);
+    }
+    const uint64_t tiles = (total_keys + kSetTile - 1) / kSetTile;
+    auto kf = a.kb == 4 ? pair_flags_kernel<4> : pair_flags_kernel<8>;
+    over_tiles(tiles, [&](uint32_t g, uint64_t t0) {
+        hipLaunchKernelGGL(kf, dim3(g), dim3(kSetTile), 0, stream, d_blob, d_lists, a, d_pairs, npairs, total_keys,
+                           total_blocks, w.keys, w.flags, w.cnt, t0);
+    });
+    hipLaunchKernelGGL(set_tiles_scan_kernel, dim3(1), dim3(1024), 0, stream, w.cnt, tiles, (uint64_t)0, w.tot,
+                       w.tot + 1);
+    over_tiles(total_keys / kSetTile + 1, [&](uint32_t g, uint64_t t0) {
+        hipLaunchKernelGGL(prefix_kernel, dim3(g), dim3(kSetTile), 0, stream, w.flags, total_keys, w.cnt, w.tot, w.P,
+                           t0);
+    });
+    auto ks = a.kb == 4 ? pair_scatter_kernel<4> : pair_scatter_kernel<8>;
+    over_tiles(tiles, [&](uint32_t g, uint64_t t0) {
+        hipLaunchKernelGGL(ks, dim3(g), dim3(kSetTile), 0, stream, d_pairs, npairs, total_keys, w.keys, w.flags, w.P,
+                           d_out, t0);
+    });
+    hipLaunchKernelGGL(pair_counts_kernel, dim3((npairs + 255) / 256), dim3(256), 0, stream, d_pairs, npairs,
+                       total_keys, w.P, d_counts);
+    return hipGetLastError();
+}
+
 hipError_t launch_compress(const void* d_keys, const Layout& L, uint8_t* d_blob, const Workspace& ws,
                            uint64_t* d_blob_bytes, uint32_t* d_flags, hipStream_t stream)
 {
@@ -1940,13 +2102,6 @@ hipError_t launch_quantile(const uint8_t* d_blob, const Layout& L, const uint64_
 }
 
 namespace {
-
-// kernel over `tiles` tiles of kSetTile threads, at most kMaxGrid per launch
-template <typename Fn>
-void over_tiles(uint64_t tiles, Fn launch)
-{
-    for (uint64_t t0 = 0; t0 < tiles; t0 += kMaxGrid) launch((uint32_t)(tiles - t0 < kMaxGrid ? tiles - t0 : kMaxGrid), t0);
-}
 
 template <int KB>
 hipError_t setop_impl(uint32_t op, const uint8_t* blob_a, const Layout& La, const uint8_t* blob_b, const Layout& Lb,

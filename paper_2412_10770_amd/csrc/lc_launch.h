@@ -97,6 +97,18 @@ hipError_t launch_quantile(const uint8_t* d_blob, const Layout& L, const uint64_
                            bool approx, void* d_out, hipStream_t stream);
 hipError_t launch_setop(uint32_t op, const uint8_t* blob_a, const Layout& La, const uint8_t* blob_b, const Layout& Lb,
                         const SetWs& w, void* out, uint64_t* count, hipStream_t stream);
+// Workspace of a batched AND (carved by the host).
+struct PairWs {
+    void* keys;      // decoded probe keys of every pair
+    uint8_t* flags;  // per probe key
+    uint64_t* cnt;   // per-tile counts, then their exclusive scan
+    uint64_t* tot;   // totals
+    uint64_t* P;     // exclusive prefix of the flags, total_keys + 1 entries
+};
+hipError_t launch_batch_and(const uint8_t* d_blob, const lc_batch_list* d_lists, const BatchArgs& a,
+                            const lc_list_pair* d_pairs, uint32_t npairs, uint64_t total_keys, uint64_t total_blocks,
+                            uint32_t max_seg_bytes, const PairWs& w, void* d_out, uint64_t* d_counts,
+                            uint32_t* d_stats, hipStream_t stream);
 hipError_t launch_serve(const uint8_t* d_blob, const ServeArgs& s, const ServeRange* d_ranges, const ServePoint* d_points,
                         uint8_t* d_arena, hipStream_t stream);
 hipError_t launch_access(const uint8_t* d_blob, const Layout& L, const uint64_t* d_idx, uint64_t m,

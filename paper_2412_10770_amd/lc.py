@@ -40,7 +40,7 @@ DEFAULT_FRAC_BITS = 20
 EXPORTED = ("lc_compress_bound", "lc_compress", "lc_info", "lc_decompress", "lc_decompress_range",
             "lc_access", "lc_lower_bound", "lc_quantile", "lc_decompress_approx", "lc_setop_bound", "lc_setop",
             "lc_batch_plan", "lc_batch_compress", "lc_batch_sizes",
-            "lc_batch_pick_eps", "lc_batch_decompress", "lc_server_create", "lc_server_run",
+            "lc_batch_pick_eps", "lc_batch_decompress", "lc_batch_and_plan", "lc_batch_and", "lc_server_create", "lc_server_run",
             "lc_server_destroy", "lc_strerror")
 
 
@@ -69,6 +69,10 @@ class lc_batch_params(ctypes.Structure):
 BATCH_LIST_DTYPE = np.dtype([("key_off", "<u8"), ("n", "<u8"), ("blob_off", "<u8"), ("blob_cap", "<u8"),
                              ("block_off", "<u8"), ("group_off", "<u8"), ("eps", "<u4"), ("reserved", "<u4", (3,))])
 assert BATCH_LIST_DTYPE.itemsize == 64
+# struct lc_list_pair
+PAIR_DTYPE = np.dtype([("a", "<u4"), ("b", "<u4"), ("probe", "<u4"), ("target", "<u4"), ("key_off", "<u8"),
+                       ("block_off", "<u8"), ("n", "<u8")])
+assert PAIR_DTYPE.itemsize == 40
 
 
 class lc_serve_config(ctypes.Structure):
@@ -112,6 +116,9 @@ def _load():
         "lc_batch_sizes": [vp, u64, vp, ctypes.POINTER(lc_batch_params), vp, u32, vp, u64, vp, vp, vp],
         "lc_batch_pick_eps": [vp, ctypes.POINTER(lc_batch_params), vp, vp, u32, vp],
         "lc_batch_decompress": [vp, u64, vp, ctypes.POINTER(lc_batch_params), u32, vp, u64, vp, vp],
+        "lc_batch_and_plan": [ctypes.POINTER(lc_batch_params), vp, vp, u32, ctypes.POINTER(u64), ctypes.POINTER(u64),
+                              ctypes.POINTER(u64)],
+        "lc_batch_and": [vp, u64, vp, ctypes.POINTER(lc_batch_params), vp, u32, u64, u64, u32, vp, u64, vp, vp, vp, vp],
         "lc_server_create": [vp, I, vp, u64, ctypes.POINTER(lc_serve_config), ctypes.POINTER(vp)],
         "lc_server_run": [vp, vp, u64, vp, ctypes.POINTER(lc_serve_stats)],
         "lc_server_destroy": [vp],
@@ -515,6 +522,43 @@ def batch_decompress(batch: Batch, out: torch.Tensor | None = None, stream=None,
     if check:
         _raise_flags(int(stats.item()), "lc_batch_decompress")
     return out
+
+
+def batch_and_plan(batch: Batch, pairs):
+    """lc_batch_and_plan for pairs (sequence of (a, b) list indices): the
+    planned pair table and (total_keys, total_blocks, ws_bytes)."""
+    pr = np.asarray(pairs, dtype=np.uint32).reshape(-1, 2)
+    t = np.zeros(len(pr), dtype=PAIR_DTYPE)
+    t["a"], t["b"] = pr[:, 0], pr[:, 1]
+    tk, tb, ws = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    _check(lib.lc_batch_and_plan(ctypes.byref(batch.params), batch.table.ctypes.data_as(ctypes.c_void_p),
+                                 t.ctypes.data_as(ctypes.c_void_p), len(t), ctypes.byref(tk), ctypes.byref(tb),
+                                 ctypes.byref(ws)), "lc_batch_and_plan")
+    return t, (tk.value, tb.value, ws.value)
+
+
+def batch_and_async(batch: Batch, d_pairs, npairs: int, totals, ws, out, counts, stats, stream=None):
+    """Enqueue lc_batch_and with a planned device pair table."""
+    tk, tb, _ = totals
+    _check(lib.lc_batch_and(_ptr(batch.data), batch.data.numel(), _ptr(batch.lists), ctypes.byref(batch.params),
+                            _ptr(d_pairs), npairs, tk, tb, batch.max_seg_bytes, _ptr(ws), ws.numel(), _ptr(out),
+                            _ptr(counts), _ptr(stats), _stream(stream)), "lc_batch_and")
+
+
+def batch_intersect(batch: Batch, pairs, stream=None):
+    """AND of every pair (a, b) of lists of the batch, in one pass: returns a
+    list of device tensors, the sorted keys in both lists of each pair."""
+    table, totals = batch_and_plan(batch, pairs)
+    dev = batch.data.device
+    d_pairs = torch.from_numpy(table.view(np.uint8).copy()).to(dev)
+    ws = torch.empty(max(totals[2], 16), dtype=torch.uint8, device=dev)
+    out = torch.empty(max(totals[0], 1), dtype=key_dtype(batch.key_bytes), device=dev)
+    counts = torch.zeros(len(table), dtype=torch.int64, device=dev)
+    stats = torch.zeros(1, dtype=torch.int32, device=dev)
+    batch_and_async(batch, d_pairs, len(table), totals, ws, out, counts, stats, stream)
+    _raise_flags(int(stats.item()), "lc_batch_and")
+    c = counts.cpu().numpy()
+    return [out[int(o):int(o) + int(k)] for o, k in zip(table["key_off"], c)]
 
 
 # ---------------------------------------------------------------------------

@@ -195,3 +195,26 @@ def test_setop_bound_and_bad_args(lc):
     assert lc.lib.lc_quantile(fake, P(a), ctypes.c_void_p((1 << 20) + 4), 4, 5, 0, fake, None) == lc.LC_EINVAL
     assert lc.lib.lc_decompress_approx(fake, P(a), 5, 4, fake, None) == lc.LC_EINVAL
     assert lc.lib.lc_decompress_approx(fake, P(a), 0, a.n + 1, fake, None) == lc.LC_EINVAL
+
+
+def test_batch_and_plan(lc):
+    """lc_batch_and_plan is host code: probe = the shorter list (a on ties),
+    key and block offsets are prefix sums of the probe lists."""
+    lengths = [0, 5, 1024, 1025, 100_000, 3]
+    p, t = lc.batch_plan(lengths, 7, 4)
+
+    class B:  # the two fields batch_and_plan reads
+        params, table = p, t
+    pairs = [(1, 2), (2, 1), (4, 3), (0, 4), (5, 5)]
+    table, (tk, tb, ws) = lc.batch_and_plan(B, pairs)
+    probe = [1, 1, 3, 0, 5]
+    assert list(table["probe"]) == probe
+    assert list(table["target"]) == [2, 2, 4, 4, 5]
+    n = [lengths[i] for i in probe]
+    assert list(table["n"]) == n
+    assert list(table["key_off"]) == list(np.concatenate([[0], np.cumsum(n)[:-1]]))
+    nb = [-(-x // 1024) for x in n]
+    assert list(table["block_off"]) == list(np.concatenate([[0], np.cumsum(nb)[:-1]]))
+    assert tk == sum(n) and tb == sum(nb) and ws >= tk * 13
+    with pytest.raises(lc.LcError):
+        lc.batch_and_plan(B, [(0, 6)])

@@ -246,3 +246,29 @@ def test_autotune_block_size(lc, wl):
     fast, rep2 = lc.autotune_batch(keys, lengths, block_candidates=(8, 12), objective="speed", time_reps=2)
     c2 = next(r for r in rep2 if r["chosen"])
     assert c2["decode_ms"] == min(r["decode_ms"] for r in rep2)
+
+
+@pytest.mark.parametrize("kb", [4, 8])
+def test_batch_and_pairs(lc, kb):
+    """AND of many pairs of lists of one batch in one pass: each pair's
+    result equals the set intersection of the two lists (either order,
+    shared keys, empty lists, a list with itself)."""
+    rng = np.random.default_rng(300 + kb)
+    dt = np.uint32 if kb == 4 else np.uint64
+    base = np.unique(rng.integers(0, 1 << 24, 40000)).astype(dt)
+    lists = [np.zeros(0, dt)]
+    for i in range(60):
+        m = int(rng.integers(1, 6000)) if i % 3 else int(rng.integers(6000, 30000))
+        pick = np.sort(rng.choice(base, min(m, len(base)), replace=False)) if i % 4 else \
+            np.unique(rng.integers(0, 1 << 24, m)).astype(dt)
+        lists.append(pick.astype(dt))
+    lists.append(np.sort(rng.integers(0, 300, 4000)).astype(dt))  # duplicates
+    keys, _ = _concat(lists, kb)
+    batch = lc.batch_compress(keys, [len(x) for x in lists], candidates=CANDS)
+    nl = len(lists)
+    pairs = [(int(rng.integers(0, nl)), int(rng.integers(0, nl))) for _ in range(500)]
+    pairs += [(0, 5), (5, 0), (7, 7), (nl - 1, nl - 1), (nl - 1, 3)]
+    _say(f"batch AND kb={kb}: {len(pairs)} pairs of {nl} lists")
+    res = lc.batch_intersect(batch, pairs)
+    for (a, b), r in zip(pairs, res):
+        assert np.array_equal(_host(r, kb), oracle.intersect(lists[a], lists[b])), (a, b)
