@@ -375,6 +375,35 @@ def bench_queries(dev, n: int = 100_000_000, eps: int = 63, n_quantile: int = 10
 
     t_and, t_or = timed(run_and), timed(run_or)
     t_band, t_bor = timed(base_and), timed(base_or)
+
+    # many pairs at once: AND of random pairs of lists of the whole batch
+    pl2, _ = workloads.posting_lists(4096, device=dev)
+    batch = lc.batch_compress(pl2, lengths, candidates=(7, 31, 127))
+    del pl2
+    npq = 4096
+    qpairs = rng.integers(0, len(lengths), (npq, 2))
+    table, totals = lc.batch_and_plan(batch, qpairs)
+    d_pairs = torch.from_numpy(table.view(np.uint8).copy()).to(dev)
+    bws = torch.empty(max(totals[2], 16), dtype=torch.uint8, device=dev)
+    bout = torch.empty(max(totals[0], 1), dtype=torch.int32, device=dev)
+    bcnt = torch.zeros(npq, dtype=torch.int64, device=dev)
+    bst = torch.zeros(1, dtype=torch.int32, device=dev)
+    t_batched = timed(lambda: lc.batch_and_async(batch, d_pairs, npq, totals, bws, bout, bcnt, bst))
+    assert int(bst.item()) == 0
+    blobs = [batch.blob(l) for l in range(len(lengths))]
+    for i in range(8):  # same answers one pair at a time
+        a, b = qpairs[i]
+        o = int(table["key_off"][i])
+        assert torch.equal(lc.intersect(blobs[a], blobs[b]), bout[o:o + int(bcnt[i])])
+    pws = torch.empty(max(lc.setop_bound(blobs[a], blobs[b], lc.SETOP_INTERSECT)[1] for a, b in qpairs),
+                      dtype=torch.uint8, device=dev)
+    pout = torch.empty(int(max(min(lengths[a], lengths[b]) for a, b in qpairs)) + 1, dtype=torch.int32, device=dev)
+
+    def per_pair():
+        for a, b in qpairs:
+            lc.setop_async(lc.SETOP_INTERSECT, blobs[a], blobs[b], pws, pout, cnt)
+
+    t_per_pair = timed(per_pair)
     short_keys = int(sum(A.n for _, _, A, _ in pairs))
     long_keys = int(sum(B.n for _, _, _, B in pairs))
     return {
@@ -391,6 +420,9 @@ def bench_queries(dev, n: int = 100_000_000, eps: int = 63, n_quantile: int = 10
         "or_pairs_per_s": round(npairs / t_or * 1e3, 1),
         "or_pairs_per_s_decode_both_torch": round(npairs / t_bor * 1e3, 1),
         "and_probe_keys": short_keys, "and_searched_keys": long_keys,
+        "batched_and": {"pairs": npq, "probe_keys": int(totals[0]), "ms": round(t_batched, 3),
+                        "pairs_per_s": round(npq / t_batched * 1e3, 1),
+                        "pairs_per_s_one_call_each": round(npq / t_per_pair * 1e3, 1)},
     }
 
 
