@@ -10,8 +10,9 @@ Two layers:
   ``decompress_range(b, e)`` is ``K[b:e]``, ``access(i)`` is ``K[i]``, and
   ``lower_bound(q)`` is the first index with ``K[i] >= q`` (the textbook
   lower bound, ``numpy.searchsorted(K, q, 'left')``);
-* the encoding (Def. 2, Eq. 1, Sec. II-A): ``compress`` fits the greedy
-  anchored fixed-point eps-PLA per block and writes blob v1; ``decode``
+* the encoding (Def. 2, Eq. 1, Sec. II-A): ``compress`` fits the anchored
+  fixed-point eps-PLA per block -- greedily, or with the fewest segments of
+  the same class (``fit="min"``) -- and writes blob v1; ``decode``
   is an independent blob decoder.  Both live in ``lcref.c`` (plain C,
   ``unsigned __int128`` cone arithmetic, bit-by-bit packing).
 """
@@ -57,8 +58,10 @@ def _bind(path: str):
                                   ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_void_p]
     L.lcref_fit_block.restype = ctypes.c_uint32
+    L.lcref_fit_block_min.argtypes = L.lcref_fit_block.argtypes
+    L.lcref_fit_block_min.restype = ctypes.c_uint32
     L.lcref_compress.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
-                                 ctypes.c_uint32, ctypes.c_uint32, u8p, ctypes.c_uint64,
+                                 ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, u8p, ctypes.c_uint64,
                                  ctypes.POINTER(ctypes.c_uint64)]
     L.lcref_compress.restype = ctypes.c_int
     L.lcref_decode.argtypes = [u8p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint64]
@@ -66,6 +69,12 @@ def _bind(path: str):
     L.lcref_header.argtypes = [u8p, ctypes.c_uint64, ctypes.c_void_p]
     L.lcref_header.restype = ctypes.c_int
     return L
+
+
+def _fit_code(fit: str) -> int:
+    if fit not in ("greedy", "min"):
+        raise ValueError(f"fit must be 'greedy' or 'min', not {fit!r}")
+    return 0 if fit == "greedy" else 1
 
 
 class OracleError(RuntimeError):
@@ -98,29 +107,33 @@ class Ref:
         """Residual width ceil(log2(2 eps + 1)) as the oracle computes it."""
         return int(self.L.lcref_width(eps))
 
-    def fit_block(self, keys, eps: int, frac_bits: int = 20):
-        """Greedy anchored fit of one block; returns (start, anchor, A) arrays."""
+    def fit_block(self, keys, eps: int, frac_bits: int = 20, fit: str = "greedy"):
+        """Anchored fit of one block; returns (start, anchor, A) arrays.
+        fit: "greedy" (each segment as long as it goes) or "min" (fewest
+        segments of the same anchored class)."""
         k = np.ascontiguousarray(_keys_array(keys), dtype=np.uint64)
         nb = len(k)
         st = np.zeros(max(nb, 1), np.uint32)
         an = np.zeros(max(nb, 1), np.uint64)
         sl = np.zeros(max(nb, 1), np.uint64)
-        m = self.L.lcref_fit_block(k.ctypes.data, nb, eps, frac_bits, st.ctypes.data,
-                                   an.ctypes.data, sl.ctypes.data)
+        fn = self.L.lcref_fit_block_min if _fit_code(fit) else self.L.lcref_fit_block
+        m = fn(k.ctypes.data, nb, eps, frac_bits, st.ctypes.data, an.ctypes.data, sl.ctypes.data)
         return st[:m].copy(), an[:m].copy(), sl[:m].copy()
 
-    def compress(self, keys, eps: int, log2_block: int = 10, frac_bits: int = 20) -> np.ndarray:
+    def compress(self, keys, eps: int, log2_block: int = 10, frac_bits: int = 20,
+                 fit: str = "greedy") -> np.ndarray:
         """Encode sorted keys into a blob v1 (uint8 array)."""
         k = _keys_array(keys)
         kb = k.dtype.itemsize
         need = ctypes.c_uint64(0)
         ptr = k.ctypes.data if len(k) else None
-        rc = self.L.lcref_compress(ptr, len(k), kb, log2_block, eps, frac_bits, None, 0,
+        fc = _fit_code(fit)
+        rc = self.L.lcref_compress(ptr, len(k), kb, log2_block, eps, frac_bits, fc, None, 0,
                                    ctypes.byref(need))
         if rc not in (REF_OK, REF_ENOSPC):
             raise OracleError(rc, "compress")
         out = np.zeros(need.value, np.uint8)
-        rc = self.L.lcref_compress(ptr, len(k), kb, log2_block, eps, frac_bits, _u8p(out),
+        rc = self.L.lcref_compress(ptr, len(k), kb, log2_block, eps, frac_bits, fc, _u8p(out),
                                    len(out), ctypes.byref(need))
         if rc != REF_OK:
             raise OracleError(rc, "compress")
@@ -161,12 +174,13 @@ def width(eps: int) -> int:
     return default().width(eps)
 
 
-def fit_block(keys, eps: int, frac_bits: int = 20):
-    return default().fit_block(keys, eps, frac_bits)
+def fit_block(keys, eps: int, frac_bits: int = 20, fit: str = "greedy"):
+    return default().fit_block(keys, eps, frac_bits, fit)
 
 
-def compress(keys, eps: int, log2_block: int = 10, frac_bits: int = 20) -> np.ndarray:
-    return default().compress(keys, eps, log2_block, frac_bits)
+def compress(keys, eps: int, log2_block: int = 10, frac_bits: int = 20,
+             fit: str = "greedy") -> np.ndarray:
+    return default().compress(keys, eps, log2_block, frac_bits, fit)
 
 
 def header(blob) -> dict:
@@ -217,7 +231,8 @@ def quantile(keys, k, q: int) -> np.ndarray:
     return kk[np.asarray(idx, dtype=np.int64)]
 
 
-def predict(keys, eps: int, log2_block: int = 10, frac_bits: int = 20) -> np.ndarray:
+def predict(keys, eps: int, log2_block: int = 10, frac_bits: int = 20,
+            fit: str = "greedy") -> np.ndarray:
     """The fitted eps-PLA without residuals (Def. 2; the AQP reading of
     Sec. III-C): per block, segment t starting at s_t with anchor a_t and
     slope A_t predicts f(i) = a_t + floor(A_t (i - s_t) / 2^F) for the keys
@@ -229,7 +244,7 @@ def predict(keys, eps: int, log2_block: int = 10, frac_bits: int = 20) -> np.nda
     B = 1 << log2_block
     for b0 in range(0, len(kk), B):
         blk = kk[b0:b0 + B]
-        st, an, sl = fit_block(blk, eps, frac_bits)
+        st, an, sl = fit_block(blk, eps, frac_bits, fit)
         ends = list(st[1:]) + [len(blk)]
         for s, e, a, A in zip(st.tolist(), ends, an.tolist(), sl.tolist()):
             for j in range(int(s), int(e)):

@@ -128,49 +128,115 @@ static uint64_t load_key(const void* keys, int kb, uint64_t i)
  * without clamping at zero -- clamped to A >= 0; a one-key segment has A = 0.
  * Writes nseg segments (start, anchor, A); returns nseg.
  */
+typedef __int128 i128;
+
+/* The cone of the segment anchored at s, grown over candidates s+1 .. limit-1:
+ * returns the end e (exclusive) of the longest feasible prefix (s < e <=
+ * limit) and leaves its interval of integer slopes in [*lo, *hi]
+ * (unbounded for a one-key segment). */
+static uint32_t cone(const uint64_t* k, uint32_t s, uint32_t limit, uint32_t eps, uint32_t F, i128* lo,
+                     i128* hi)
+{
+    const i128 scale = (i128)1 << F;
+    const i128 cap = (i128)1 << (64 - F);
+    const uint64_t anchor = k[s];
+    i128 l_run = -((i128)1 << 100), h_run = (i128)1 << 100;
+    uint32_t e = s + 1;
+    while (e < limit) {
+        i128 d = (i128)(e - s);
+        i128 D = (i128)k[e] - (i128)anchor;
+        if (D + eps + 1 >= cap)
+            break;
+        i128 num_lo = (D - eps) * scale;          /* may be negative */
+        i128 l = num_lo >= 0 ? (num_lo + d - 1) / d : -((-num_lo) / d); /* ceil */
+        i128 h = ((D + eps + 1) * scale - 1) / d; /* floor, never negative */
+        i128 nlo = l_run > l ? l_run : l;
+        i128 nhi = h_run < h ? h_run : h;
+        if (nlo > nhi)
+            break;
+        l_run = nlo;
+        h_run = nhi;
+        e++;
+    }
+    *lo = l_run;
+    *hi = h_run;
+    return e;
+}
+
+/* Stored slope of the segment [s, e) with slope interval [lo, hi]. */
+static uint64_t slope_of(uint32_t s, uint32_t e, i128 lo, i128 hi)
+{
+    if (e <= s + 1)
+        return 0;
+    i128 A = lo + (hi - lo) / 2; /* floor((lo + hi) / 2): hi - lo >= 0 */
+    return A < 0 ? 0 : (uint64_t)A;
+}
+
 uint32_t lcref_fit_block(const uint64_t* k, uint32_t nb, uint32_t eps, uint32_t F,
                          uint32_t* seg_start, uint64_t* seg_anchor, uint64_t* seg_A)
 {
-    typedef __int128 i128;
-    const i128 scale = (i128)1 << F;
-    const i128 cap = (i128)1 << (64 - F);
-    const i128 unbounded_lo = -((i128)1 << 100);
-    const i128 unbounded_hi = (i128)1 << 100;
     uint32_t nseg = 0;
     uint32_t s = 0;
     while (s < nb) {
-        uint64_t anchor = k[s];
-        i128 lo = unbounded_lo, hi = unbounded_hi;
-        uint32_t e = s + 1;
-        while (e < nb) {
-            i128 d = (i128)(e - s);
-            i128 D = (i128)k[e] - (i128)anchor;
-            if (D + eps + 1 >= cap)
-                break;
-            i128 num_lo = (D - eps) * scale;          /* may be negative */
-            i128 l = num_lo >= 0 ? (num_lo + d - 1) / d : -((-num_lo) / d); /* ceil */
-            i128 h = ((D + eps + 1) * scale - 1) / d; /* floor, never negative */
-            i128 nlo = lo > l ? lo : l;
-            i128 nhi = hi < h ? hi : h;
-            if (nlo > nhi)
-                break;
-            lo = nlo;
-            hi = nhi;
-            e++;
-        }
-        i128 A = 0;
-        if (e > s + 1) {
-            A = lo + (hi - lo) / 2; /* floor((lo + hi) / 2): hi - lo >= 0 */
-            if (A < 0)
-                A = 0;
-        }
+        i128 lo, hi;
+        uint32_t e = cone(k, s, nb, eps, F, &lo, &hi);
         seg_start[nseg] = s;
-        seg_anchor[nseg] = anchor;
-        seg_A[nseg] = (uint64_t)A;
+        seg_anchor[nseg] = k[s];
+        seg_A[nseg] = slope_of(s, e, lo, hi);
         nseg++;
         s = e;
     }
     return nseg;
+}
+
+/*
+ * Fewest segments within the same anchored class (the same segments the
+ * greedy fit may form, chosen to minimise their number; Def. 2 with the
+ * optimal-L goal of Sec. II-A restricted to anchored fixed-point segments).
+ * reach[s] is the end of the greedy segment anchored at s: the segment [s, e)
+ * is feasible exactly when e <= reach[s] (the cone only narrows as keys join).
+ * Going backwards from the end of the block, every boundary is the smallest
+ * s whose reach covers the boundary after it.  This gives a minimum number of
+ * segments, and of all minimum segmentations the one whose every boundary
+ * lies earliest: if c_0 < ... < c_m = nb is any feasible segmentation, then
+ * induction from the end shows the chosen b_j <= c_j, so the chosen chain
+ * reaches 0 within m steps.  Each segment's slope is then the midpoint rule
+ * of the greedy fit applied to the cone of exactly that segment.
+ */
+uint32_t lcref_fit_block_min(const uint64_t* k, uint32_t nb, uint32_t eps, uint32_t F,
+                             uint32_t* seg_start, uint64_t* seg_anchor, uint64_t* seg_A)
+{
+    if (nb == 0)
+        return 0;
+    uint32_t* reach = malloc(nb * sizeof(uint32_t));
+    uint32_t* bound = malloc((nb + 1) * sizeof(uint32_t));
+    if (!reach || !bound)
+        abort(); /* a test oracle: fail loudly rather than return a wrong fit */
+    for (uint32_t s = 0; s < nb; s++) {
+        i128 lo, hi;
+        reach[s] = cone(k, s, nb, eps, F, &lo, &hi);
+    }
+    /* boundaries from the end: bound[0] = nb, bound[1], ..., bound[m] = 0 */
+    uint32_t m = 0;
+    bound[0] = nb;
+    while (bound[m] > 0) {
+        uint32_t s = 0;
+        while (reach[s] < bound[m]) /* s = bound[m] - 1 always qualifies */
+            s++;
+        bound[++m] = s;
+    }
+    for (uint32_t t = 0; t < m; t++) {
+        uint32_t s = bound[m - t], e = bound[m - t - 1];
+        i128 lo, hi;
+        uint32_t got = cone(k, s, e, eps, F, &lo, &hi);
+        (void)got; /* == e: [s, e) is feasible because e <= reach[s] */
+        seg_start[t] = s;
+        seg_anchor[t] = k[s];
+        seg_A[t] = slope_of(s, e, lo, hi);
+    }
+    free(reach);
+    free(bound);
+    return m;
 }
 
 static void put_bits(uint8_t* slab, uint64_t bitpos, uint64_t code, int w)
@@ -227,11 +293,12 @@ static int layout_params(uint64_t n, int kb, int log2_block, uint32_t eps, uint3
  * REF_ENOSPC).
  */
 int lcref_compress(const void* keys, uint64_t n, int kb, int log2_block, uint32_t eps,
-                   uint32_t F, uint8_t* out, uint64_t cap, uint64_t* out_bytes)
+                   uint32_t F, int fit, uint8_t* out, uint64_t cap, uint64_t* out_bytes)
 {
     int rc = layout_params(n, kb, log2_block, eps, F);
     if (rc != REF_OK) return rc;
     if (n > 0 && keys == NULL) return REF_EINVAL;
+    if (fit != 0 && fit != 1) return REF_EINVAL; /* 0: greedy, 1: fewest segments */
 
     /* E0: the keys must be sorted (non-decreasing); duplicates are allowed. */
     for (uint64_t i = 1; i < n; i++)
@@ -262,8 +329,8 @@ int lcref_compress(const void* keys, uint64_t n, int kb, int log2_block, uint32_
         for (uint32_t j = 0; j < nb; j++)
             blockkeys[j] = load_key(keys, kb, base + j);
         /* segments of block b are stored from index base (at most nb of them) */
-        nseg[b] = lcref_fit_block(blockkeys, nb, eps, F, starts + base, anchors + base,
-                                  slopes + base);
+        nseg[b] = (fit ? lcref_fit_block_min : lcref_fit_block)(blockkeys, nb, eps, F, starts + base,
+                                                                anchors + base, slopes + base);
         nseg_total += nseg[b];
         if (nseg[b] > max_nseg) max_nseg = nseg[b];
     }

@@ -297,6 +297,82 @@ ALL_CHECKS = [check_width, check_golden, check_roundtrip, check_error_bound,
               check_cap_boundary, check_blob_size, check_byte_widths]
 
 
+# --- fewest-segment fit ---------------------------------------------------------
+
+def feasible_slopes(k, s, e, eps, F):
+    """All integer A (any sign) with |K[i] - (K[s] + floor(A (i - s) / 2^F))|
+    <= eps for s < i < e, by trying every A that could qualify: for d >= 1 a
+    slope with |A| > (span + eps + 1) 2^F predicts outside [K[s] - span - eps,
+    K[s] + span + eps] already at d = 1."""
+    span = int(k[e - 1]) - int(k[s])
+    amax = (span + eps + 1) << F
+    return [A for A in range(-amax, amax + 1)
+            if all(abs(int(k[i]) - (int(k[s]) + ((A * (i - s)) >> F))) <= eps for i in range(s + 1, e))]
+
+
+def brute_min_segmentations(k, eps, F):
+    """(fewest segments, componentwise-earliest boundaries of the minimum
+    segmentations) over every segmentation of k into feasible segments."""
+    n = len(k)
+    ok = {(s, e): bool(feasible_slopes(k, s, e, eps, F)) for s in range(n) for e in range(s + 1, n + 1)}
+    best, optimal = None, []
+    for mask in range(1 << max(n - 1, 0)):  # a cut after key i when bit i is set
+        cuts = [0] + [i + 1 for i in range(n - 1) if (mask >> i) & 1] + [n]
+        if all(ok[(a, b)] for a, b in zip(cuts, cuts[1:])):
+            m = len(cuts) - 1
+            if best is None or m < best:
+                best, optimal = m, [cuts]
+            elif m == best:
+                optimal.append(cuts)
+    return best, [min(c[j] for c in optimal) for j in range(best + 1)]
+
+
+def expected_slope(k, s, e, eps, F):
+    """The midpoint rule on the brute-force interval of feasible slopes."""
+    if e - s == 1:
+        return 0
+    sl = feasible_slopes(k, s, e, eps, F)
+    lo, hi = min(sl), max(sl)
+    assert sl == list(range(lo, hi + 1))  # the feasible slopes form an interval
+    return max(0, (lo + hi) // 2)
+
+
+def check_min_fit_bruteforce(ref, trials=800, seed=11):
+    """fit="min": the fewest segments, the earliest boundaries among the
+    minimum segmentations, and the midpoint slope of each segment, all by
+    brute force on tiny blocks; the trials must include blocks where the
+    greedy fit is not minimal."""
+    rng = np.random.default_rng(seed)
+    greedy_worse = 0
+    for trial in range(trials):
+        n = int(rng.integers(1, 9))
+        eps = int(rng.integers(0, 4))
+        F = int(rng.choice([0, 1, 3]))
+        hi = int(rng.choice([8, 24, 60]))
+        k = np.sort(rng.integers(0, hi, n)).astype(np.uint64)
+        st, an, sl = ref.fit_block(k, eps, F, "min")
+        best, earliest = brute_min_segmentations(k, eps, F)
+        assert len(st) == best, (trial, k.tolist(), eps, F)
+        assert st.tolist() == earliest[:-1], (trial, k.tolist(), eps, F)
+        ends = st.tolist()[1:] + [n]
+        for s, e, a, A in zip(st.tolist(), ends, an.tolist(), sl.tolist()):
+            assert a == int(k[s])
+            assert A == expected_slope(k, s, e, eps, F), (trial, k.tolist(), eps, F, s, e)
+        greedy_worse += len(ref.fit_block(k, eps, F)[0]) > best
+    assert greedy_worse > 0
+
+
+def check_min_fit_blobs(ref, seed=1, count=10):
+    """fit="min" blobs decode, and never hold more segments than greedy ones."""
+    for keys, eps, log2b in random_cases(seed, count):
+        keys = keys[:20000]
+        for F in (0, 20):
+            g = ref.compress(keys, eps, log2b, F)
+            m = ref.compress(keys, eps, log2b, F, fit="min")
+            assert ref.header(m)["nseg_total"] <= ref.header(g)["nseg_total"]
+            assert np.array_equal(ref.decode(m), keys)
+
+
 def run_quick(ref) -> str:
     """Run every check with small counts; return the name of the first that fails, or ''."""
     quick = [
@@ -304,6 +380,7 @@ def run_quick(ref) -> str:
         (check_error_bound, {"count": 12}), (check_arithmetic_progression, {}),
         (check_span_within_eps, {}), (check_bruteforce, {"trials": 200}),
         (check_cap_boundary, {}), (check_blob_size, {"count": 12}), (check_byte_widths, {}),
+        (check_min_fit_bruteforce, {"trials": 400}), (check_min_fit_blobs, {"count": 6}),
     ]
     for fn, kw in quick:
         try:

@@ -18,8 +18,14 @@ MUTANTS = [
     ("cap_off_by_one", "if (D + eps + 1 >= cap)", "if (D + eps >= cap)"),
     ("lower_end_tiebreak", "A = lo + (hi - lo) / 2;", "A = lo;"),
     ("upper_end_tiebreak", "A = lo + (hi - lo) / 2;", "A = hi;"),
-    ("clamped_midpoint", "if (A < 0)\n                A = 0;",
-     "if (A < 0)\n                A = 0;\n            if (lo < 0)\n                A = hi / 2;"),
+    ("clamped_midpoint", "    return A < 0 ? 0 : (uint64_t)A;",
+     "    if (lo < 0)\n        A = hi / 2;\n    return A < 0 ? 0 : (uint64_t)A;"),
+    ("min_slope_of_full_reach", "uint32_t got = cone(k, s, e, eps, F, &lo, &hi);",
+     "uint32_t got = cone(k, s, nb, eps, F, &lo, &hi);"),
+    ("min_chain_skips_first_anchor", "        uint32_t s = 0;\n        while (reach[s] < bound[m])",
+     "        uint32_t s = bound[m] > 1 ? 1 : 0;\n        while (reach[s] < bound[m])"),
+    ("min_reach_one_short", "        reach[s] = cone(k, s, nb, eps, F, &lo, &hi);",
+     "        reach[s] = cone(k, s, nb, eps, F, &lo, &hi);\n        if (reach[s] > s + 1 && reach[s] < nb) reach[s]--;"),
     ("residual_sign", "u128 code = key + eps - pred;", "u128 code = pred + eps - key;"),
     ("offset_dropped", "(u128)(j - starts[base + t])", "(u128)(j)"),
     ("decoder_search", "if (get_le(st + 2ull * u, 2) <= j)", "if (get_le(st + 2ull * u, 2) < j)"),
