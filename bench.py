@@ -507,6 +507,67 @@ def bench_serve(dev, n: int = 1_000_000_000, qps_points=(1e3, 1e4, 1e5, 1e6, Non
     }
 
 
+def bench_fits(dev, keys_lognormal=None, reps: int = 3):
+    """Greedy against fewest-segment fit: compress time (HIP events, mean of
+    `reps` after one warm-up), blob size and segment count, per workload and
+    eps.  Every fewest-segment blob is decoded and compared with its keys."""
+    import numpy as np
+    import torch
+
+    from paper_2412_10770_amd import lc, workloads
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    cases = [
+        ("lognormal_distinct_100M_u64", lambda: keys_lognormal if keys_lognormal is not None
+         else workloads.lognormal_distinct(100_000_000, device=dev), (15, 63, 255)),
+        ("uniform_gaps_100M_u32", lambda: workloads.uniform_gaps(100_000_000, device=dev), (7, 31, 127)),
+        ("lognormal_gaps_100M_u64", lambda: workloads.lognormal_gaps(100_000_000, device=dev), (63, 255, 1023)),
+        ("heterogeneous_runs_200M_u64", lambda: workloads.heterogeneous_runs(200_000_000, device=dev), (63,)),
+    ]
+    res = {}
+    for name, make, eps_list in cases:
+        keys = make()
+        torch.cuda.synchronize()
+        n, kb = keys.numel(), keys.element_size()
+        rows = {}
+        for eps in eps_list:
+            bmax, ws_bytes = lc.compress_bound(n, kb, eps)
+            blob = torch.empty(bmax, dtype=torch.uint8, device=dev)
+            ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+            nb = torch.zeros(1, dtype=torch.int64, device=dev)
+            fl = torch.zeros(1, dtype=torch.int32, device=dev)
+            row = {}
+            for fit in ("greedy", "min"):
+                lc.compress_async(keys, eps, blob, ws, nb, fl, fit=fit)
+                torch.cuda.synchronize()
+                marks = []
+                for _ in range(reps):
+                    e0, e1 = ev(), ev()
+                    e0.record()
+                    lc.compress_async(keys, eps, blob, ws, nb, fl, fit=fit)
+                    e1.record()
+                    marks.append((e0, e1))
+                torch.cuda.synchronize()
+                assert int(fl.item()) == 0, (name, eps, fit, int(fl.item()))
+                ms = float(np.mean([a.elapsed_time(b) for a, b in marks]))
+                b = lc.Blob.from_device(blob)
+                if fit == "min":
+                    assert torch.equal(lc.decompress(b), keys), (name, eps, "min-fit round trip")
+                row[fit] = {"compress_ms": round(ms, 3), "keys_per_s": round(n / ms * 1e3, 1),
+                            "bits_per_key": round(b.bits_per_key, 4), "nseg_total": b.info.nseg_total}
+            row["bytes_saved_pct"] = round(100 * (1 - row["min"]["bits_per_key"] / row["greedy"]["bits_per_key"]), 3)
+            row["segments_saved_pct"] = round(100 * (1 - row["min"]["nseg_total"] / row["greedy"]["nseg_total"]), 3)
+            rows[str(eps)] = row
+            log(f"fits {name} eps={eps}: {row}")
+            del blob, ws
+        res[name] = {"n": n, "key_bytes": kb, "per_eps": rows}
+        del keys
+        torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -525,6 +586,8 @@ def main():
     ap.add_argument("--no-lookups", action="store_true", help="skip the heterogeneous-runs lookup measurement")
     ap.add_argument("--no-queries", action="store_true", help="skip the quantile / approximate / AND / OR measurement")
     ap.add_argument("--queries-only", action="store_true", help="only the quantile / approximate / AND / OR measurement")
+    ap.add_argument("--no-fits", action="store_true", help="skip the greedy / fewest-segment fit comparison")
+    ap.add_argument("--fits-only", action="store_true", help="only the greedy / fewest-segment fit comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path is "
@@ -546,6 +609,9 @@ def main():
         return
     if args.serve_only:
         print(json.dumps(bench_serve(dev, args.serve_n)), flush=True)
+        return
+    if args.fits_only:
+        print(json.dumps(bench_fits(dev)), flush=True)
         return
     eps_list = [int(e) for e in args.eps.split(",")]
     t0 = time.perf_counter()
@@ -701,6 +767,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_queries:
         result["queries"] = bench_queries(dev)
+        torch.cuda.empty_cache()
+    if not args.no_fits:
+        result["fits"] = bench_fits(dev, keys)
         torch.cuda.empty_cache()
     if not args.no_batch:
         del out, wss, blobs

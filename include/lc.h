@@ -67,19 +67,32 @@ typedef int32_t lc_status;
 #define LC_MAX_EPS 0x7FFFFFFFu
 #define LC_HEADER_BYTES 128
 
+/* Segment choice of the fit (lc_params.fit).  Both fits form anchored
+ * segments (anchor = the segment's first key, integer slope A, the midpoint
+ * of the segment's feasible slopes) and write the same blob format.
+ *   LC_FIT_GREEDY  each segment grows while some slope keeps all its keys
+ *                  within eps (Def. 2, Eq. 1);
+ *   LC_FIT_MIN     the fewest segments of that same class per block (the
+ *                  optimal-size goal of Sec. II-A within anchored segments):
+ *                  among the minimum segmentations, the one whose every
+ *                  boundary lies earliest.  Fewer segments, slower fit. */
+#define LC_FIT_GREEDY 0
+#define LC_FIT_MIN 1
+
 /* Encoder parameters.
  *   key_bytes  4 or 8
  *   log2_block 6..12 (block size B = 2^log2_block keys; segments never cross
  *              a block)
  *   frac_bits  0..32, fractional bits F of the fixed-point slope A / 2^F
  *              (LC_DEFAULT_FRAC_BITS = 20)
+ *   fit        LC_FIT_GREEDY (0) or LC_FIT_MIN
  *   eps        0..LC_MAX_EPS, the error bound of Def. 2; residuals take
  *              w = ceil(log2(2 eps + 1)) bits each (Sec. II-A) */
 typedef struct lc_params {
     uint8_t key_bytes;
     uint8_t log2_block;
     uint8_t frac_bits;
-    uint8_t reserved; /* must be 0 */
+    uint8_t fit;
     uint32_t eps;
 } lc_params;
 
@@ -102,8 +115,9 @@ lc_status lc_compress_bound(uint64_t n, const lc_params* p, uint64_t* blob_max,
 
 /* Enc of Def. 1: compress n keys at d_keys (device, key_bytes each, sorted)
  * into d_blob (device, blob_cap bytes, 16-byte aligned).  The fit follows
- * Def. 2 / Eq. 1 per block: greedy anchored segments with an integer slope,
- * residuals bit-packed at ceil(log2(2 eps + 1)) bits (Sec. II-A).
+ * Def. 2 / Eq. 1 per block: anchored segments with an integer slope, chosen
+ * greedily or for the fewest segments (p->fit), residuals bit-packed at
+ * ceil(log2(2 eps + 1)) bits (Sec. II-A).
  * d_ws: device workspace of ws_bytes (16-byte aligned), contents scratch.
  * d_blob_bytes: device u64 receiving the blob size (may be NULL).
  * d_flags: device u32 flag word (required); LC_FLAG_UNSORTED is OR-ed in

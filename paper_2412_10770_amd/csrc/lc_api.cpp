@@ -31,7 +31,7 @@ lc_status check_params(const lc_params* p)
     if (!p) return LC_EINVAL;
     if (p->key_bytes != 4 && p->key_bytes != 8) return LC_EINVAL;
     if (p->log2_block < 6 || p->log2_block > 12) return LC_EINVAL;
-    if (p->frac_bits > 32 || p->reserved != 0) return LC_EINVAL;
+    if (p->frac_bits > 32 || p->fit > LC_FIT_MIN) return LC_EINVAL;
     if (p->eps > LC_MAX_EPS) return LC_EINVAL;
     return LC_OK;
 }
@@ -121,12 +121,11 @@ constexpr uint64_t kBlockInfoBytes = sizeof(lc::BlockInfo);
 
 lc_status check_batch(const lc_batch_params* p)
 {
-    if (!p || p->nlists == 0 || p->reserved2 != 0) return LC_EINVAL;
+    if (!p || p->nlists == 0 || p->reserved != 0 || p->reserved2 != 0) return LC_EINVAL;
     lc_params q{};
     q.key_bytes = p->key_bytes;
     q.log2_block = p->log2_block;
     q.frac_bits = p->frac_bits;
-    q.reserved = p->reserved;
     q.eps = p->max_eps;
     return check_params(&q);
 }
@@ -231,7 +230,7 @@ LC_API lc_status lc_compress(const void* d_keys, uint64_t n, const lc_params* p,
         W.seg_delta = reinterpret_cast<uint64_t*>(ws + w.delta);
         W.seg_A = reinterpret_cast<uint64_t*>(ws + w.slope);
     }
-    hipError_t e = lc::launch_compress(d_keys, L, static_cast<uint8_t*>(d_blob), W, d_blob_bytes, d_flags,
+    hipError_t e = lc::launch_compress(d_keys, L, p->fit, static_cast<uint8_t*>(d_blob), W, d_blob_bytes, d_flags,
                                        static_cast<hipStream_t>(stream));
     return e == hipSuccess ? LC_OK : LC_EDEVICE;
 }

@@ -30,6 +30,7 @@
 
 #include "lc_launch.h"
 #include "lc_search.h"
+#include "lc_arith.h"
 
 namespace lc {
 namespace {
@@ -212,6 +213,20 @@ __device__ __forceinline__ uint64_t div_small(uint64_t x, uint32_t d, double inv
     return ((uint64_t)qh << 32) | ql;
 }
 
+// The block's slope-bound numerators are all below 2^49 when
+// (span + eps + 1) 2^F < 2^49, span = last key - first key of the block.
+__device__ __forceinline__ bool fast_division_ok(uint64_t span, uint64_t eps, uint32_t F)
+{
+    const uint64_t lim = F < 49 ? (1ull << (49 - F)) : 0;
+    return eps + 1 < lim && span < lim - eps - 1;
+}
+
+// div_fast where the caller has established the 2^49 bound (a uniform flag), else div_small.
+__device__ __forceinline__ uint64_t div_pick(bool fast, uint64_t x, uint32_t d, double inv, uint32_t* rem = nullptr)
+{
+    return fast ? div_fast(x, d, inv, rem) : div_small(x, d, inv, rem);
+}
+
 // Inclusive max / min scan of u64 inside each row of 16 lanes (DPP row_shr).
 template <bool MAX>
 __device__ __forceinline__ uint64_t row_scan64(uint64_t v)
@@ -296,6 +311,8 @@ __device__ __forceinline__ void fit_rows(const void* __restrict__ keys, const La
     const uint64_t first = nb ? (uint64_t)K[0] : 0;
     const uint64_t rec = b << L.log2b;
     const uint32_t row_lane0 = row * 16;
+    // one-round divisions when all four blocks of the wave allow them (a wrapped span does not)
+    const bool fast = __ballot(!fast_division_ok(nb ? (uint64_t)K[nb - 1] - first : 0, eps, F)) == 0;
 
     uint32_t s = 0, nseg = 0, e0 = 1;
     uint64_t anchor = first, runP = 0, runH = ~0ull, maxA = 0, maxd = 0;
@@ -342,10 +359,10 @@ __device__ __forceinline__ void fit_rows(const void* __restrict__ keys, const La
                             const double inv = recip(d);
                             if (D >= eps) {
                                 uint32_t rem;
-                                const uint64_t q = div_small(x, d, inv, &rem);
+                                const uint64_t q = div_pick(fast, x, d, inv, &rem);
                                 Pc[k] = q + (rem != 0) + 1;
                             }
-                            Hc[k] = div_small(y, d, inv);
+                            Hc[k] = div_pick(fast, y, d, inv);
                         }
                     }
                 }
@@ -401,7 +418,7 @@ __device__ __forceinline__ void fit_rows(const void* __restrict__ keys, const La
                         if (k + 1 < len) {
                             const uint32_t d = k + 1;
                             const uint64_t z = (eps - Dc[k]) << F;
-                            const uint64_t m = (d & (d - 1)) == 0 ? z >> (31 - __clz(d)) : div_small(z, d, recip(d));
+                            const uint64_t m = (d & (d - 1)) == 0 ? z >> (31 - __clz(d)) : div_pick(fast, z, d, recip(d));
                             M = m < M ? m : M;
                         }
                     }
@@ -459,10 +476,10 @@ __device__ __forceinline__ void fit_rows(const void* __restrict__ keys, const La
                 const double inv = recip(d);
                 if (D >= eps) {
                     uint32_t rem;
-                    const uint64_t q = div_small((D - eps) << F, d, inv, &rem);
+                    const uint64_t q = div_pick(fast, (D - eps) << F, d, inv, &rem);
                     P = q + (rem != 0) + 1;  // 1 + ceil((D - eps) 2^F / d)
                 }
-                H = div_small(((D + eps + 1) << F) - 1, d, inv);
+                H = div_pick(fast, ((D + eps + 1) << F) - 1, d, inv);
             }
         }
         P = row_scan64<true>(P);
@@ -496,7 +513,7 @@ __device__ __forceinline__ void fit_rows(const void* __restrict__ keys, const La
                     for (uint32_t j = s + 1 + r; j < e_end; j += 16) {
                         const uint32_t d = j - s;
                         const uint64_t D = (uint64_t)K[j] - anchor;
-                        const uint64_t m = div_small((eps - D) << F, d, recip(d));
+                        const uint64_t m = div_pick(fast, (eps - D) << F, d, recip(d));
                         M = m < M ? m : M;
                     }
                     for (int o = 8; o > 0; o >>= 1) {
@@ -562,6 +579,343 @@ __global__ __launch_bounds__(64) void fit_pack_kernel(const void* __restrict__ k
                                                        uint32_t* __restrict__ flags, uint64_t blk0)
 {
     fit_rows<KB, false>(keys, L, blob, ws, flags, blk0 + (uint64_t)blockIdx.x * 4);
+}
+
+// ---------------------------------------------------------------------------
+// Fewest-segment fit within the anchored class, one block per wave (a
+// workgroup of 64 lanes).  Same segments, slopes and codes as the greedy fit
+// would store for the chosen boundaries; only the boundaries differ, so the
+// blob format and every decoder are unchanged.
+//
+// reach[s] is where the greedy segment anchored at s ends: [s, e) is a
+// feasible segment exactly when e <= reach[s].  Going backwards from the end
+// of the block, each boundary is the smallest s whose reach covers the
+// boundary after it; that chain has the fewest segments, and among minimum
+// segmentations every one of its boundaries lies earliest.  With
+// PM(s) = max(reach[0..s]) non-decreasing, "smallest s with reach[s] >= b"
+// is "smallest s with PM(s) >= b", a search in a sorted array.
+//
+// Phase 1a: anchor 0's reach by the whole wave, 64 candidates per step (DPP
+// scans of the slope bounds, as the greedy fit's ordinary step); a block
+// that one segment covers is done.  Phase 1b: lane t walks the cones of
+// anchors t, t + 64, ... one candidate per step; an anchor whose reach is
+// the end of the block covers every boundary, so anchors past the first such
+// one are skipped.  Phase 2: PM in place, then the chain: per boundary, one
+// 64-way pass over chunk ends and one inside the chunk found.  Phase 3: each
+// segment's slope interval, midpoint slope (as in the greedy fit), record and
+// residual codes; segments of up to kMinSerialLen keys one per lane, longer
+// ones by the whole wave.
+// When (span of the block + eps + 1) 2^F < 2^49 every numerator of the
+// block's slope bounds fits a one-round FP64 division (block-uniform branch).
+// LDS: misc u32[4] | keys KT[B] | slab u32[res_stride / 4 + 4] | PM u16[B] |
+// boundaries u16[B + 1].
+constexpr uint32_t kMinLanes = 64;
+constexpr uint32_t kMinSerialLen = 48;
+
+__device__ __forceinline__ uint64_t wave_max64(uint64_t v) { return __shfl(wave_scan64<true>(v), 63, 64); }
+__device__ __forceinline__ uint64_t wave_min64(uint64_t v) { return __shfl(wave_scan64<false>(v), 63, 64); }
+
+struct ConeArgs {
+    uint64_t eps;
+    uint32_t F;
+    bool fast;  // every numerator below 2^49
+};
+
+__device__ __forceinline__ uint64_t div_cone(const ConeArgs& c, uint64_t x, uint32_t d, double inv,
+                                             uint32_t* rem = nullptr)
+{
+    return div_pick(c.fast, x, d, inv, rem);
+}
+
+// Slope bounds of key e for the segment anchored at s (D = K[e] - K[s] below
+// the cap, d = e - s): P = 1 + ceil((D - eps) 2^F / d) if D >= eps, else 0;
+// H = floor(((D + eps + 1) 2^F - 1) / d).
+__device__ __forceinline__ void cone_bounds(const ConeArgs& c, uint64_t D, uint32_t d, uint64_t& P, uint64_t& H)
+{
+    const double inv = recip(d);
+    P = 0;
+    if (D >= c.eps) {
+        uint32_t rem;
+        const uint64_t q = div_cone(c, (D - c.eps) << c.F, d, inv, &rem);
+        P = q + (rem != 0) + 1;
+    }
+    H = div_cone(c, ((D + c.eps + 1) << c.F) - 1, d, inv);
+}
+
+// Stored slope from the interval (P, H) of a segment of two or more keys;
+// when every lower end is negative (P = 0), lo = -M with M the minimum of
+// floor((eps - D) 2^F / d) over the segment's keys.
+__device__ __forceinline__ uint64_t mid_slope(uint64_t P, uint64_t H, uint64_t M)
+{
+    if (P != 0) {
+        const uint64_t lo = P - 1;
+        return lo + (H - lo) / 2;
+    }
+    return H >= M ? (H - M) / 2 : 0;  // floor((H - M) / 2), clamped at 0
+}
+
+template <int KB>
+__global__ __launch_bounds__(kMinLanes) void fit_min_kernel(const void* __restrict__ keys, Layout L,
+                                                             uint8_t* __restrict__ blob, Workspace ws,
+                                                             uint32_t* __restrict__ flags, uint64_t blk0)
+{
+    using KT = typename std::conditional<KB == 4, uint32_t, uint64_t>::type;
+    extern __shared__ __align__(16) uint8_t smem[];
+    const uint32_t B = 1u << L.log2b;
+    const uint32_t lane = threadIdx.x;
+    const uint64_t b = blk0 + blockIdx.x;  // the launcher keeps b < nblocks
+    const uint64_t base = b << L.log2b;
+    const uint32_t nb = (L.n - base) < B ? (uint32_t)(L.n - base) : B;  // >= 1
+    const KT* Kg = reinterpret_cast<const KT*>(keys) + base;
+
+    uint32_t* s_full = reinterpret_cast<uint32_t*>(smem);  // first anchor known to reach nb
+    KT* sk = reinterpret_cast<KT*>(smem + 16);
+    uint32_t* s_slab = reinterpret_cast<uint32_t*>(smem + 16 + KB * B);
+    const uint32_t slab_words = (uint32_t)(L.res_stride / 4);
+    uint16_t* pm = reinterpret_cast<uint16_t*>(smem + 16 + KB * B + L.res_stride + 16);
+    uint16_t* bnd = pm + ((2 * B + 15) & ~15u) / 2;
+
+    bool unsorted = false;
+    for (uint32_t j = lane; j < nb; j += kMinLanes) {
+        const KT k = Kg[j];
+        const KT prev = j ? Kg[j - 1] : (b ? Kg[-1] : KT(0));
+        unsorted |= k < prev;
+        sk[j] = k;
+        pm[j] = 0;
+    }
+    for (uint32_t i = lane; i < slab_words + 4; i += kMinLanes) s_slab[i] = 0;
+    if (lane == 0) *s_full = nb;
+    if (__ballot(unsorted) != 0 && lane == 0) atomicOr(flags, kFlagUnsorted);
+    __syncthreads();
+
+    const uint64_t eps = L.eps;
+    const uint32_t F = L.F, w = L.w;
+    const uint64_t wmask = (1ull << w) - 1;
+    const uint64_t lim = F == 0 ? (~0ull - eps) : ((1ull << (64 - F)) - eps - 1);
+    const uint64_t first = (uint64_t)sk[0];
+    ConeArgs ca;
+    ca.eps = eps;
+    ca.F = F;
+    ca.fast = fast_division_ok((uint64_t)sk[nb - 1] - first, eps, F);  // a wrapped span takes div_small
+
+    // Phase 1a: anchor 0 by the whole wave.
+    uint32_t r0 = nb;
+    {
+        uint64_t runP = 0, runH = ~0ull;
+        for (uint32_t e0 = 1; e0 < nb; e0 += kMinLanes) {
+            const uint32_t e = e0 + lane;
+            const bool valid = e < nb;
+            uint64_t P = 0, H = ~0ull;
+            bool capped = false;
+            if (valid) {
+                const uint64_t D = (uint64_t)sk[e] - first;
+                capped = D >= lim;
+                if (!capped) cone_bounds(ca, D, e, P, H);
+            }
+            P = wave_scan64<true>(P);
+            H = wave_scan64<false>(H);
+            P = P > runP ? P : runP;
+            H = H < runH ? H : runH;
+            const uint64_t fm = __ballot(valid && (capped || (P != 0 && P - 1 > H)));
+            if (fm != 0) {
+                r0 = e0 + (uint32_t)__builtin_ctzll(fm);
+                break;
+            }
+            runP = __shfl(P, 63, 64);
+            runH = __shfl(H, 63, 64);
+        }
+    }
+    if (lane == 0) {
+        pm[0] = (uint16_t)r0;
+        if (r0 == nb) *s_full = 0;
+    }
+    __syncthreads();
+
+    // Phase 1b: the other anchors, one walk per lane, up to the first that reaches nb.
+    if (r0 < nb) {
+        const uint32_t per_lane = (nb + kMinLanes - 1) / kMinLanes;
+        const uint32_t step_cap = per_lane * (nb + 1) + 64;
+        uint32_t s = lane ? lane : kMinLanes, e = s + 1, steps = 0;
+        uint64_t Ka = s < nb ? (uint64_t)sk[s] : 0, P = 0, H = ~0ull;
+        while (s < nb) {
+            if (++steps > step_cap) {
+                atomicOr(flags, kFlagInternal);
+                break;
+            }
+            bool stop = e >= nb;
+            if (!stop) {
+                const uint64_t D = (uint64_t)sk[e] - Ka;
+                stop = D >= lim;
+                if (!stop) {
+                    uint64_t p, h;
+                    cone_bounds(ca, D, e - s, p, h);
+                    const uint64_t Pn = p > P ? p : P, Hn = h < H ? h : H;
+                    stop = Pn != 0 && Pn - 1 > Hn;
+                    if (!stop) {
+                        P = Pn;
+                        H = Hn;
+                        e++;
+                    }
+                }
+            }
+            if (stop) {
+                pm[s] = (uint16_t)e;
+                if (e == nb) atomicMin(s_full, s);
+                s += kMinLanes;
+                if (s >= nb || s > __hip_atomic_load(s_full, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+                    break;
+                Ka = sk[s];
+                e = s + 1;
+                P = 0;
+                H = ~0ull;
+            }
+        }
+    }
+    __syncthreads();
+
+    // Phase 2a: PM = running max of reach, in place; lane t owns entries
+    // [t c, t c + c).  Values are at most nb <= 4096.
+    {
+        const uint32_t c = (nb + kMinLanes - 1) / kMinLanes;
+        const uint32_t j0 = lane * c < nb ? lane * c : nb, j1 = j0 + c < nb ? j0 + c : nb;
+        uint32_t run = 0;
+        for (uint32_t j = j0; j < j1; j++) run = pm[j] > run ? pm[j] : run;
+        const uint32_t incl = (uint32_t)wave_scan64<true>(run);
+        uint32_t acc = (uint32_t)__shfl_up((int)incl, 1, 64);
+        if (lane == 0) acc = 0;
+        for (uint32_t j = j0; j < j1; j++) {
+            acc = pm[j] > acc ? pm[j] : acc;
+            pm[j] = (uint16_t)acc;
+        }
+    }
+    __syncthreads();
+
+    // Phase 2b: the chain of boundaries, nb = bnd[0] > bnd[1] > ... > bnd[m] = 0.
+    uint32_t m = 0;
+    {
+        const uint32_t stride = (nb + 63) / 64;
+        uint32_t cur = nb;
+        if (lane == 0) bnd[0] = (uint16_t)nb;
+        while (cur > 0 && m < nb) {
+            const uint32_t p1 = (lane + 1) * stride - 1 < nb ? (lane + 1) * stride - 1 : nb - 1;
+            const uint64_t b1 = __ballot(pm[p1] >= cur);
+            if (b1 == 0) break;  // cannot happen: pm[nb - 1] = nb
+            const uint32_t f = (uint32_t)__builtin_ctzll(b1);  // the chunk holding the answer
+            const uint32_t p2 = f * stride + lane;
+            const uint64_t b2 = __ballot(lane < stride && p2 < nb && pm[p2] >= cur);
+            if (b2 == 0) break;  // cannot happen: the chunk's last entry qualifies
+            const uint32_t nxt = f * stride + (uint32_t)__builtin_ctzll(b2);
+            if (nxt >= cur) break;  // cannot happen: PM(cur - 1) >= cur
+            cur = nxt;
+            m++;
+            if (lane == 0) bnd[m] = (uint16_t)cur;
+        }
+        if (cur != 0) {
+            m = 0;  // no blob: flagged
+            if (lane == 0) atomicOr(flags, kFlagInternal);
+        }
+    }
+    __syncthreads();
+
+    // Phase 3: slopes, records and codes of the m segments (segment t is
+    // [bnd[m - t], bnd[m - t - 1])).
+    const uint64_t rec = b << L.log2b;
+    uint64_t maxA = 0;
+    auto emit = [&](uint32_t t, uint32_t s, uint64_t anchor, uint64_t A) {
+        ws.seg_start[rec + t] = (uint16_t)s;
+        ws.seg_delta[rec + t] = anchor - first;
+        ws.seg_A[rec + t] = A;
+    };
+    auto put_code = [&](uint32_t j, uint32_t s, uint64_t anchor, uint64_t A) {
+        const uint64_t pred = anchor + ((A * (uint64_t)(j - s)) >> F);
+        const uint64_t code = ((uint64_t)sk[j] - pred + eps) & wmask;
+        const uint32_t bitpos = j * w;
+        const uint32_t wd = bitpos >> 5, sh = bitpos & 31;
+        const uint64_t v = code << sh;
+        atomicOr(&s_slab[wd], (uint32_t)v);
+        if (sh + w > 32) atomicOr(&s_slab[wd + 1], (uint32_t)(v >> 32));
+    };
+    for (uint32_t t0 = 0; t0 < m; t0 += kMinLanes) {
+        const uint32_t t = t0 + lane;
+        bool is_long = false;
+        if (t < m) {
+            const uint32_t s = bnd[m - t], e = bnd[m - t - 1];
+            is_long = e - s > kMinSerialLen;
+            if (!is_long) {
+                const uint64_t anchor = sk[s];
+                uint64_t P = 0, H = ~0ull, A = 0;
+                for (uint32_t j = s + 1; j < e; j++) {
+                    uint64_t p, h;
+                    cone_bounds(ca, (uint64_t)sk[j] - anchor, j - s, p, h);
+                    P = p > P ? p : P;
+                    H = h < H ? h : H;
+                }
+                if (e > s + 1) {
+                    uint64_t M = ~0ull;
+                    if (P == 0)
+                        for (uint32_t j = s + 1; j < e; j++) {
+                            const uint32_t d = j - s;
+                            const uint64_t mm = div_cone(ca, (eps - ((uint64_t)sk[j] - anchor)) << F, d, recip(d));
+                            M = mm < M ? mm : M;
+                        }
+                    A = mid_slope(P, H, M);
+                }
+                emit(t, s, anchor, A);
+                maxA = A > maxA ? A : maxA;
+                if (w != 0)
+                    for (uint32_t j = s; j < e; j++) put_code(j, s, anchor, A);
+            }
+        }
+        for (uint64_t lm = __ballot(is_long); lm != 0; lm &= lm - 1) {
+            const uint32_t tl = t0 + (uint32_t)__builtin_ctzll(lm);
+            const uint32_t s = bnd[m - tl], e = bnd[m - tl - 1];
+            const uint64_t anchor = sk[s];
+            uint64_t P = 0, H = ~0ull;
+            for (uint32_t j = s + 1 + lane; j - lane < e; j += kMinLanes) {
+                if (j < e) {
+                    uint64_t p, h;
+                    cone_bounds(ca, (uint64_t)sk[j] - anchor, j - s, p, h);
+                    P = p > P ? p : P;
+                    H = h < H ? h : H;
+                }
+            }
+            P = wave_max64(P);
+            H = wave_min64(H);
+            uint64_t M = ~0ull;
+            if (P == 0) {
+                for (uint32_t j = s + 1 + lane; j < e; j += kMinLanes) {
+                    const uint32_t d = j - s;
+                    const uint64_t mm = div_cone(ca, (eps - ((uint64_t)sk[j] - anchor)) << F, d, recip(d));
+                    M = mm < M ? mm : M;
+                }
+                M = wave_min64(M);
+            }
+            const uint64_t A = mid_slope(P, H, M);
+            if (lane == 0) emit(tl, s, anchor, A);
+            maxA = A > maxA ? A : maxA;
+            if (w != 0)
+                for (uint32_t j = s + lane; j < e; j += kMinLanes) put_code(j, s, anchor, A);
+        }
+    }
+    maxA = wave_max64(maxA);
+    __syncthreads();
+
+    uint4* dst = reinterpret_cast<uint4*>(blob + L.off_res + b * L.res_stride);
+    const uint4* src4 = reinterpret_cast<const uint4*>(s_slab);
+    for (uint32_t c = lane; c < slab_words / 4; c += kMinLanes) dst[c] = src4[c];
+    if (lane == 0) {
+        store_key<KB>(blob + L.off_first, b, first);
+        const uint64_t maxd = m ? (uint64_t)sk[bnd[1]] - first : 0;  // the last anchor is the largest
+        const uint32_t ab = byte_width(maxd), sb = byte_width(maxA);
+        BlockInfo bi;
+        bi.nseg = m;
+        bi.seg_bytes = (uint32_t)(a16(2ull * m) + a16((uint64_t)ab * m) + a16((uint64_t)sb * m));
+        bi.nkeys = nb;
+        bi.ab = (uint8_t)ab;
+        bi.sb = (uint8_t)sb;
+        bi.pad = 0;
+        ws.blk[b] = bi;
+    }
 }
 
 // Sums over tiles of kTileBlocks blocks.
@@ -2011,10 +2365,21 @@ hipError_t launch_batch_and(const uint8_t* d_blob, const lc_batch_list* d_lists,
     return hipGetLastError();
 }
 
-hipError_t launch_compress(const void* d_keys, const Layout& L, uint8_t* d_blob, const Workspace& ws,
+hipError_t launch_compress(const void* d_keys, const Layout& L, uint32_t fit, uint8_t* d_blob, const Workspace& ws,
                            uint64_t* d_blob_bytes, uint32_t* d_flags, hipStream_t stream)
 {
-    if (L.nblocks) {
+    if (L.nblocks && fit == LC_FIT_MIN) {
+        const uint64_t B = 1ull << L.log2b;
+        const size_t lds = 16 + L.kb * B + L.res_stride + 16 + align16(2 * B) + align16(2 * (B + 1));
+        auto k = L.kb == 4 ? fit_min_kernel<4> : fit_min_kernel<8>;
+        const hipError_t e = allow_lds((const void*)k, lds);
+        if (e != hipSuccess) return e;
+        for (uint64_t b0 = 0; b0 < L.nblocks; b0 += kMaxGrid) {
+            const uint64_t nw = L.nblocks - b0 < kMaxGrid ? L.nblocks - b0 : kMaxGrid;
+            hipLaunchKernelGGL(k, dim3((uint32_t)nw), dim3(kMinLanes), lds, stream, d_keys, L, d_blob, ws, d_flags,
+                               b0);
+        }
+    } else if (L.nblocks) {
         const size_t lds = 4 * (L.res_stride + 16);
         auto k = L.kb == 4 ? fit_pack_kernel<4> : fit_pack_kernel<8>;
         const uint64_t groups = (L.nblocks + 3) / 4;
@@ -2022,6 +2387,8 @@ hipError_t launch_compress(const void* d_keys, const Layout& L, uint8_t* d_blob,
             const uint64_t ng = groups - g0 < kMaxGrid ? groups - g0 : kMaxGrid;
             hipLaunchKernelGGL(k, dim3((uint32_t)ng), dim3(64), lds, stream, d_keys, L, d_blob, ws, d_flags, g0 * 4);
         }
+    }
+    if (L.nblocks) {
         const uint64_t nt = ntiles_of(L.nblocks);
         for (uint64_t t0 = 0; t0 < nt; t0 += kMaxGrid) {
             const uint64_t g = nt - t0 < kMaxGrid ? nt - t0 : kMaxGrid;

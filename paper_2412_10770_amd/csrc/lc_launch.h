@@ -78,7 +78,7 @@ struct ServeArgs {
 lc_status layout_from_info(const lc_blob_info* info, Layout* L);
 
 // Kernel launchers; each returns the hipError_t of its last launch.
-hipError_t launch_compress(const void* d_keys, const Layout& L, uint8_t* d_blob, const Workspace& ws,
+hipError_t launch_compress(const void* d_keys, const Layout& L, uint32_t fit, uint8_t* d_blob, const Workspace& ws,
                            uint64_t* d_blob_bytes, uint32_t* d_flags, hipStream_t stream);
 hipError_t launch_decode(const uint8_t* d_blob, const Layout& L, uint64_t begin, uint64_t end,
                          void* d_out, hipStream_t stream, bool approx = false);

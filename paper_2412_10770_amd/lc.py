@@ -46,7 +46,7 @@ EXPORTED = ("lc_compress_bound", "lc_compress", "lc_info", "lc_decompress", "lc_
 
 class lc_params(ctypes.Structure):
     _fields_ = [("key_bytes", ctypes.c_uint8), ("log2_block", ctypes.c_uint8),
-                ("frac_bits", ctypes.c_uint8), ("reserved", ctypes.c_uint8), ("eps", ctypes.c_uint32)]
+                ("frac_bits", ctypes.c_uint8), ("fit", ctypes.c_uint8), ("eps", ctypes.c_uint32)]
 
 
 class lc_blob_info(ctypes.Structure):
@@ -173,9 +173,20 @@ def key_dtype(key_bytes: int) -> torch.dtype:
     return torch.int32 if key_bytes == 4 else torch.int64
 
 
+FITS = {"greedy": 0, "min": 1}   # LC_FIT_GREEDY, LC_FIT_MIN
+
+
+def _fit(fit) -> int:
+    if fit in FITS:
+        return FITS[fit]
+    if fit in FITS.values():
+        return int(fit)
+    raise ValueError(f"fit must be one of {sorted(FITS)}, not {fit!r}")
+
+
 def params(key_bytes: int, eps: int, log2_block: int = DEFAULT_LOG2_BLOCK,
-           frac_bits: int = DEFAULT_FRAC_BITS) -> lc_params:
-    return lc_params(key_bytes, log2_block, frac_bits, 0, eps)
+           frac_bits: int = DEFAULT_FRAC_BITS, fit="greedy") -> lc_params:
+    return lc_params(key_bytes, log2_block, frac_bits, _fit(fit), eps)
 
 
 def compress_bound(n: int, key_bytes: int, eps: int, log2_block: int = DEFAULT_LOG2_BLOCK,
@@ -234,11 +245,12 @@ class Blob:
 
 def compress_async(keys: torch.Tensor, eps: int, blob: torch.Tensor, workspace: torch.Tensor,
                    blob_bytes: torch.Tensor, flags: torch.Tensor, log2_block: int = DEFAULT_LOG2_BLOCK,
-                   frac_bits: int = DEFAULT_FRAC_BITS, stream=None):
-    """Enqueue lc_compress into caller-provided buffers; no synchronisation."""
+                   frac_bits: int = DEFAULT_FRAC_BITS, stream=None, fit="greedy"):
+    """Enqueue lc_compress into caller-provided buffers; no synchronisation.
+    fit: "greedy" or "min" (fewest segments, same blob format)."""
     _dev(keys, "keys")
     kb = _key_bytes(keys)
-    p = params(kb, eps, log2_block, frac_bits)
+    p = params(kb, eps, log2_block, frac_bits, fit)
     _check(lib.lc_compress(ctypes.c_void_p(keys.data_ptr()), keys.numel(), ctypes.byref(p),
                            ctypes.c_void_p(blob.data_ptr()), blob.numel(),
                            ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
@@ -247,8 +259,9 @@ def compress_async(keys: torch.Tensor, eps: int, blob: torch.Tensor, workspace: 
 
 
 def compress(keys: torch.Tensor, eps: int, log2_block: int = DEFAULT_LOG2_BLOCK,
-             frac_bits: int = DEFAULT_FRAC_BITS, stream=None) -> Blob:
-    """Enc of Def. 1 on the GPU; synchronises to learn the blob size."""
+             frac_bits: int = DEFAULT_FRAC_BITS, stream=None, fit="greedy") -> Blob:
+    """Enc of Def. 1 on the GPU; synchronises to learn the blob size.
+    fit: "greedy" or "min" (fewest segments, same blob format)."""
     _dev(keys, "keys")
     kb = _key_bytes(keys)
     blob_max, ws_bytes = compress_bound(keys.numel(), kb, eps, log2_block, frac_bits)
@@ -257,7 +270,7 @@ def compress(keys: torch.Tensor, eps: int, log2_block: int = DEFAULT_LOG2_BLOCK,
     ws = torch.empty(max(ws_bytes, 16), dtype=torch.uint8, device=dev)
     nbytes = torch.zeros(1, dtype=torch.int64, device=dev)
     flags = torch.zeros(1, dtype=torch.int32, device=dev)
-    compress_async(keys, eps, blob, ws, nbytes, flags, log2_block, frac_bits, stream)
+    compress_async(keys, eps, blob, ws, nbytes, flags, log2_block, frac_bits, stream, fit)
     fl = int(flags.item())
     if fl & LC_FLAG_UNSORTED:
         raise LcError(LC_EINVAL, "lc_compress: keys are not sorted (LC_FLAG_UNSORTED)")

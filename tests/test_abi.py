@@ -58,6 +58,15 @@ def test_compress_bound(lc):
         assert lc.lib.lc_compress_bound(10, ctypes.byref(p), ctypes.byref(a), ctypes.byref(b)) == lc.LC_EINVAL
     p = lc.params(8, 63)
     assert lc.lib.lc_compress_bound(2 ** 41, ctypes.byref(p), None, None) == lc.LC_EINVAL
+    # the fit field: greedy (0) and fewest segments (1) share sizes; anything else is rejected
+    a, b = ctypes.c_uint64(), ctypes.c_uint64()
+    assert lc.lib.lc_compress_bound(5000, ctypes.byref(lc.params(8, 63, fit="min")), ctypes.byref(a), ctypes.byref(b)) == 0
+    assert (a.value, b.value) == lc.compress_bound(5000, 8, 63)
+    for fit in (2, 255):
+        p = lc.lc_params(8, 10, 20, fit, 63)
+        assert lc.lib.lc_compress_bound(10, ctypes.byref(p), None, None) == lc.LC_EINVAL
+    with pytest.raises(ValueError):
+        lc.params(8, 63, fit="optimal")
 
 
 def test_info_parses_oracle_headers(lc):

@@ -32,11 +32,11 @@ def a16(x):
     return (x + 15) // 16 * 16
 
 
-def check_fullsize(lc, keys: torch.Tensor, eps: int, n_access: int, n_lb: int, seed: int):
+def check_fullsize(lc, keys: torch.Tensor, eps: int, n_access: int, n_lb: int, seed: int, fit: str = "greedy"):
     n = keys.numel()
     kb = keys.element_size()
-    _say(f"full-size case n={n} kb={kb} eps={eps}")
-    blob = lc.compress(keys, eps)  # log2_block 10, F 20: the benchmark's configuration
+    _say(f"full-size case n={n} kb={kb} eps={eps} fit={fit}")
+    blob = lc.compress(keys, eps, fit=fit)  # log2_block 10, F 20: the benchmark's configuration
     h = blob.info
     B = 1 << h.log2_block
     assert h.n == n and h.nblocks == (n + B - 1) // B
@@ -65,7 +65,7 @@ def check_fullsize(lc, keys: torch.Tensor, eps: int, n_access: int, n_lb: int, s
     picks |= {0, h.nblocks - 1, int(np.argmax(nseg)), int(np.argmax(area))}
     for b in sorted(picks):
         kk = host[b * B:(b + 1) * B]
-        one = oracle.compress(kk, eps, h.log2_block)
+        one = oracle.compress(kk, eps, h.log2_block, fit=fit)
         oh = oracle.header(one)
         od = one[oh["off_dir"]:oh["off_dir"] + 16]
         assert np.array_equal(od[8:16], dirs[b, 8:16]), b
@@ -107,6 +107,22 @@ def test_lognormal_100m(lc, wl):
     keys = wl.lognormal_distinct(100_000_000, device=DEV)
     for eps in (15, 63, 255):
         check_fullsize(lc, keys, eps, n_access=1_000_000, n_lb=1_000_000, seed=eps)
+
+
+def test_lognormal_100m_min_fit(lc, wl):
+    """The fewest-segment fit on the same 100M keys: never more segments than
+    the greedy fit, same checks."""
+    keys = wl.lognormal_distinct(100_000_000, device=DEV)
+    for eps in (63, 255):
+        g = lc.compress(keys, eps).info.nseg_total
+        m = check_fullsize(lc, keys, eps, n_access=1_000_000, n_lb=1_000_000, seed=100 + eps, fit="min")
+        assert m.info.nseg_total <= g
+
+
+def test_heterogeneous_runs_200m_min_fit(lc, wl):
+    """Dense runs: every anchor's cone stays open across much of its block."""
+    keys = wl.heterogeneous_runs(200_000_000, device=DEV)
+    check_fullsize(lc, keys, 63, n_access=1_000_000, n_lb=1_000_000, seed=4, fit="min")
 
 
 def test_heterogeneous_runs_200m(lc, wl):

@@ -44,13 +44,14 @@ def _host(t: torch.Tensor, kb: int) -> np.ndarray:
     return t.cpu().numpy().view(np.uint32 if kb == 4 else np.uint64)
 
 
-def check_all(lc, keys: np.ndarray, eps: int, log2b: int, rng, nq: int = 2000, frac_bits: int = 20):
+def check_all(lc, keys: np.ndarray, eps: int, log2b: int, rng, nq: int = 2000, frac_bits: int = 20,
+              fit: str = "greedy"):
     kb = keys.dtype.itemsize
     n = len(keys)
-    _say(f"case n={n} kb={kb} eps={eps} log2b={log2b} F={frac_bits}")
-    want = oracle.compress(keys, eps, log2b, frac_bits)
+    _say(f"case n={n} kb={kb} eps={eps} log2b={log2b} F={frac_bits} fit={fit}")
+    want = oracle.compress(keys, eps, log2b, frac_bits, fit=fit)
     d = _to_dev(keys)
-    blob = lc.compress(d, eps, log2b, frac_bits)
+    blob = lc.compress(d, eps, log2b, frac_bits, fit=fit)
     got = blob.data.cpu().numpy()
     if not np.array_equal(got, want):
         h = oracle.header(want)
@@ -305,3 +306,107 @@ def test_short_and_long_segments_alternate(lc, frac_bits):
     for eps in (0, 3, 100):
         for log2b in (6, 10):
             check_all(lc, keys, eps, log2b, rng, nq=300, frac_bits=frac_bits)
+
+
+# --- fewest-segment fit (fit="min"): same blob format, other boundaries --------
+
+def test_min_fit_random_small_cases(lc):
+    rng = np.random.default_rng(41)
+    for keys, eps, log2b in P.random_cases(seed=41, count=40):
+        check_all(lc, keys, eps, log2b, rng, nq=300, fit="min")
+
+
+@pytest.mark.parametrize("frac_bits", [0, 8, 32])
+def test_min_fit_other_frac_bits(lc, frac_bits):
+    rng = np.random.default_rng(50 + frac_bits)
+    for keys, eps, log2b in P.random_cases(seed=50 + frac_bits, count=8):
+        check_all(lc, keys, eps, log2b, rng, nq=200, frac_bits=frac_bits, fit="min")
+
+
+def test_min_fit_edge_lists(lc, wl):
+    rng = np.random.default_rng(13)
+    for name, keys in wl.edge_lists():
+        for eps in (0, 63, 2 ** 31 - 1):
+            for log2b in (6, 12):
+                check_all(lc, keys, eps, log2b, rng, nq=100, fit="min")
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 1025, 4096 * 3 + 5])
+def test_min_fit_block_edges(lc, n):
+    rng = np.random.default_rng(100 + n)
+    keys = np.cumsum(rng.integers(1, 65, n)).astype(np.uint64)
+    for log2b in (6, 10, 12):
+        check_all(lc, keys, 31, log2b, rng, nq=200, fit="min")
+
+
+def test_min_fit_long_segments_and_singletons(lc):
+    """One segment per block (an anchor reaching the block's end early, so
+    later anchors are skipped), every key its own segment, equal keys."""
+    rng = np.random.default_rng(6)
+    ap = (np.uint64(3) + np.uint64(17) * np.arange(50_000, dtype=np.uint64))
+    check_all(lc, ap, 0, 12, rng, nq=200, fit="min")
+    cap = np.cumsum(np.full(9000, 1 << 45, dtype=np.uint64))
+    check_all(lc, cap, 3, 12, rng, nq=200, fit="min")
+    check_all(lc, np.full(10_000, 123, np.uint32), 5, 10, rng, nq=200, fit="min")
+    # dense block: every anchor's cone stays open for hundreds of keys
+    dense = np.cumsum(rng.integers(0, 3, 3 * 4096 + 17)).astype(np.uint32)
+    check_all(lc, dense, 255, 12, rng, nq=200, fit="min")
+
+
+@pytest.mark.parametrize("frac_bits", [0, 20, 32])
+def test_min_fit_short_and_long_segments_alternate(lc, frac_bits):
+    rng = np.random.default_rng(90 + frac_bits)
+    parts, pos = [], np.uint64(5)
+    cap_gap = np.uint64(1) << np.uint64(64 - frac_bits) if frac_bits else np.uint64(0)
+    for k in range(40):
+        if k % 2 == 0:
+            m, g = int(rng.integers(5, 400)), int(rng.integers(0, 50))
+            run = pos + np.uint64(g) * np.arange(m, dtype=np.uint64)
+        else:
+            m = int(rng.integers(3, 300))
+            gaps = rng.integers(1, 1 << 30, m).astype(np.uint64)
+            if frac_bits and k % 6 == 1:
+                gaps[rng.integers(0, m)] = cap_gap
+            run = pos + np.cumsum(gaps, dtype=np.uint64)
+        parts.append(run)
+        pos = run[-1] + np.uint64(1)
+        if pos > np.uint64(1) << np.uint64(62):
+            break
+    keys = np.concatenate(parts)
+    for eps in (0, 3, 100):
+        for log2b in (6, 10):
+            check_all(lc, keys, eps, log2b, rng, nq=200, frac_bits=frac_bits, fit="min")
+
+
+def test_min_fit_width_combinations(lc):
+    rng = np.random.default_rng(19)
+    for keys, eps, F in _width_combo_lists()[::4]:
+        check_all(lc, keys, eps, 6, rng, nq=32, frac_bits=F, fit="min")
+
+
+def test_min_fit_configs_reduced(lc, wl):
+    """The benchmark recipes at sizes the oracle's fewest-segment fit
+    finishes in seconds."""
+    rng = np.random.default_rng(3)
+    keys = wl.as_numpy(wl.uniform_gaps(1_000_000, device="cpu"))
+    check_all(lc, keys, 31, 10, rng, nq=20_000, fit="min")
+    keys = wl.as_numpy(wl.lognormal_distinct(1_000_000, device="cpu"))
+    for eps in (15, 255):
+        check_all(lc, keys, eps, 10, rng, nq=20_000, fit="min")
+    keys = wl.as_numpy(wl.heterogeneous_runs(300_000, device="cpu", run_lo=1e3, run_hi=1e5))
+    check_all(lc, keys, 63, 10, rng, nq=20_000, fit="min")
+    keys = wl.as_numpy(wl.lognormal_gaps(1_000_000, device="cpu"))
+    check_all(lc, keys, 255, 10, rng, nq=20_000, fit="min")
+
+
+def test_min_fit_determinism_and_unsorted(lc):
+    rng = np.random.default_rng(2)
+    keys = np.cumsum(rng.integers(0, 1000, 300_000)).astype(np.uint64)
+    d = _to_dev(keys)
+    assert torch.equal(lc.compress(d, 63, fit="min").data, lc.compress(d, 63, fit="min").data)
+    g, m = lc.compress(d, 63), lc.compress(d, 63, fit="min")
+    assert m.info.nseg_total <= g.info.nseg_total
+    bad = keys[:5000].copy()
+    bad[2500] = bad[2499] - np.uint64(1)
+    with pytest.raises(lc.LcError):
+        lc.compress(_to_dev(bad), 15, fit="min")

@@ -1,7 +1,8 @@
 """Host-testable pieces of the native code, compiled with g++ (address and
 undefined-behaviour sanitizers on) and run on the CPU: the request server's
-output arena (csrc/lc_arena.h) against random alloc/free sequences, and the
-point queries' searches (csrc/lc_search.h) against linear scans."""
+output arena (csrc/lc_arena.h) against random alloc/free sequences, the
+point queries' searches (csrc/lc_search.h) against linear scans, and the fit
+kernels' one-round division (csrc/lc_arith.h) against integer division."""
 import os
 import shutil
 import subprocess
@@ -29,3 +30,8 @@ def test_arena(tmp_path):
 @pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
 def test_searches(tmp_path):
     _run(tmp_path, "search_test", "search ok")
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_one_round_division(tmp_path):
+    _run(tmp_path, "div_test", "div ok")
