@@ -28,6 +28,10 @@ METRIC = "decoded GB/s + lookups/s vs plain per-list kernel; comp. ratio; p99 la
 HBM_PEAK_GBPS = 8000.0
 CALIB_COPY_BYTES = 256 << 20  # plain device copy of known size, read by counter runs to scale them
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "decode_traffic.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "compress_valu.json")
+# VALU peak in lane-operations: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a wave64
+# instruction is 64 lane-operations issued over 4 cycles on a 16-lane SIMD)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 KERNEL_SRC = os.path.join(ROOT, "paper_2412_10770_amd", "csrc", "lc_kernels.hip")
 
 
@@ -41,6 +45,18 @@ def recorded_traffic():
     when the kernels changed since they were taken."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_src_sha256_16") != kernel_src_hash():
+        return None
+    return rec
+
+
+def recorded_valu():
+    """VALU instructions per lc_compress call (all its kernels) from the
+    committed counter run, or None when the kernels changed since."""
+    try:
+        rec = json.load(open(VALU_FILE))
     except (OSError, ValueError):
         return None
     if rec.get("kernel_src_sha256_16") != kernel_src_hash():
@@ -726,6 +742,26 @@ def main():
     traffic = None
     if rec is not None and rec.get("n") == n and rec.get("eps") == eps_list:
         traffic = rec["bytes_per_decompress"]
+    # encode against both rooflines: HBM (keys read + blob written) and VALU
+    # (issued lane-operations of the compress kernels, from the counter record)
+    enc_ms = {e: float(np.mean([r[e][0].elapsed_time(r[e][1]) for r in recs])) for e in eps_list}
+    enc_hbm = float(np.mean([(n * 8 + infos[e].nbytes) / (enc_ms[e] / 1e3) / 1e9 for e in eps_list]))
+    vrec = recorded_valu()
+    enc_alu = None
+    if vrec is not None and vrec.get("n") == n and vrec.get("eps") == eps_list:
+        enc_alu = float(np.mean([vrec["valu_insts_per_call"][str(e)] * 64 / (enc_ms[e] / 1e3) / 1e12
+                                 for e in eps_list]))
+    roofline_encode = {
+        "bound": "alu", "kernel": "lc_compress (fit_pack_kernel<8> + tile_reduce + tile_scan + dir_emit + seg_emit)",
+        "achieved": None if enc_alu is None else round(enc_alu, 2), "peak": round(VALU_PEAK_TOPS, 2),
+        "unit": "T VALU lane-ops/s", "frac": None if enc_alu is None else round(enc_alu / VALU_PEAK_TOPS, 4),
+        "traffic": None,
+        "hbm": {"achieved": round(enc_hbm, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(enc_hbm / HBM_PEAK_GBPS, 4), "bytes": "8 n keys read + blob written"},
+        "avg_call_ms": round(float(np.mean(list(enc_ms.values()))), 4),
+        "valu_source": "profiles/compress_valu.json (rocprofv3 --pmc SQ_INSTS_VALU)" if enc_alu is not None
+                       else "counter record absent or taken on other kernels",
+    }
     rng_ms = float(np.mean([r["q"][0].elapsed_time(r["q"][1]) for r in recs]))
     acc_ms = float(np.mean([r["q"][1].elapsed_time(r["q"][2]) for r in recs]))
     lb_ms = float(np.mean([r["q"][2].elapsed_time(r["q"][3]) for r in recs]))
@@ -756,6 +792,7 @@ def main():
             "kernel": "lc_decompress (touch_kernel + decode_kernel<8,false>)",
             "bytes_per_launch": int(np.mean(dec_alg_bytes)), "avg_launch_ms": round(dec_avg_ms, 4),
         },
+        "roofline_encode": roofline_encode,
         "per_eps": per_eps,
         "decompress_range_GBps": round((r_end - r_begin) * 8 / rng_ms / 1e6, 2),
         "access_lookups_per_s": round(args.access / acc_ms * 1e3, 1),
