@@ -752,7 +752,7 @@ def main():
         enc_alu = float(np.mean([vrec["valu_insts_per_call"][str(e)] * 64 / (enc_ms[e] / 1e3) / 1e12
                                  for e in eps_list]))
     roofline_encode = {
-        "bound": "alu", "kernel": "lc_compress (fit_pack_kernel<8> + tile_reduce + tile_scan + dir_emit + seg_emit)",
+        "bound": "alu", "kernel": "lc_compress (fit_lanes_kernel<8> + code_pack_kernel<8> + tile_reduce + tile_scan + dir_emit + seg_emit)",
         "achieved": None if enc_alu is None else round(enc_alu, 2), "peak": round(VALU_PEAK_TOPS, 2),
         "unit": "T VALU lane-ops/s", "frac": None if enc_alu is None else round(enc_alu / VALU_PEAK_TOPS, 4),
         "traffic": None,

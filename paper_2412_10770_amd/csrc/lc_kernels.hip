@@ -221,6 +221,12 @@ __device__ __forceinline__ bool fast_division_ok(uint64_t span, uint64_t eps, ui
     return eps + 1 < lim && span < lim - eps - 1;
 }
 
+// v as a double, exactly, for v < 2^52: the mantissa of 2^52 + v holds v.
+__device__ __forceinline__ double exact_f64(uint64_t v)
+{
+    return __longlong_as_double((long long)(0x4330000000000000ull | v)) - 4503599627370496.0;
+}
+
 // div_fast where the caller has established the 2^49 bound (a uniform flag), else div_small.
 __device__ __forceinline__ uint64_t div_pick(bool fast, uint64_t x, uint32_t d, double inv, uint32_t* rem = nullptr)
 {
@@ -1161,6 +1167,373 @@ __device__ __forceinline__ uint32_t wave_incl_sum32(uint32_t v)
         if (lane >= (uint32_t)o) v += t;
     }
     return v;
+}
+
+// ---------------------------------------------------------------------------
+// Greedy fit with one block per lane (64 blocks per wave), for lists of at
+// least kLanesMinBlocks blocks.  The greedy walk consumes exactly one key per
+// step -- a key either joins the open segment or closes it and becomes the
+// next anchor -- so all 64 walks advance in lockstep over keys 0, 1, 2, ...
+// of their blocks: no cross-lane scans, one candidate per lane per step.
+// Keys arrive in chunks of kLaneChunk keys per block, loaded coalesced into
+// registers one chunk ahead and written to LDS (a row per block, padded
+// against bank conflicts).  Slopes follow the same rules as fit_rows; the
+// residual codes, which need each segment's final slope, are packed by
+// code_pack_kernel from the segment records.
+constexpr uint32_t kLaneChunk = 16;
+constexpr uint64_t kLanesMinBlocks = 16384;
+
+template <int KB>
+__global__ __launch_bounds__(64) void fit_lanes_kernel(const void* __restrict__ keys, Layout L,
+                                                        uint8_t* __restrict__ blob, Workspace ws,
+                                                        uint32_t* __restrict__ flags, uint64_t blk0)
+{
+    using KT = typename std::conditional<KB == 4, uint32_t, uint64_t>::type;
+    constexpr uint32_t kPitch = kLaneChunk + 1;                 // keys per LDS row
+    constexpr uint32_t kParts = kLaneChunk * KB / 16;           // 16-byte loads per block and chunk
+    constexpr uint32_t kLoads = 64 * kParts / 64;               // loads per lane and chunk
+    constexpr uint32_t kPer = 16 / KB;                          // keys per load
+    __shared__ KT s_keys[2][64 * kPitch];
+
+    const uint32_t lane = threadIdx.x;
+    const uint32_t B = 1u << L.log2b;
+    const uint64_t b0 = blk0 + (uint64_t)blockIdx.x * 64;       // first block of the wave
+    const uint64_t b = b0 + lane;
+    const bool has = b < L.nblocks;
+    const uint32_t nb = has ? ((L.n - (b << L.log2b)) < B ? (uint32_t)(L.n - (b << L.log2b)) : B) : 0u;
+    const KT* Kb = reinterpret_cast<const KT*>(keys) + (has ? (b << L.log2b) : 0);
+
+    const uint64_t eps = L.eps;
+    const uint32_t F = L.F;
+    const uint64_t lim = F == 0 ? (~0ull - eps) : ((1ull << (64 - F)) - eps - 1);
+    const uint64_t first = nb ? (uint64_t)Kb[0] : 0;
+    // one-round divisions when every block of the wave allows them (a wrapped span does not)
+    const bool fast = __ballot(!fast_division_ok(nb ? (uint64_t)Kb[nb - 1] - first : 0, eps, F)) == 0;
+
+    // chunk c of every block of the wave -> registers (16-byte loads; a part
+    // holding keys past its block's end is loaded key by key, or not at all)
+    uint4 pre[kLoads];
+    // Only the wave holding the list's last block can meet a missing block or
+    // a part past a block's end; every other wave loads unconditionally, so
+    // no load waits at a branch join and all kLoads stay in flight.
+    const bool tail_wave = b0 + 64 >= L.nblocks;
+    auto load_chunk = [&](uint32_t c) {
+        if (!tail_wave) {
+#pragma unroll
+            for (uint32_t i = 0; i < kLoads; i++) {
+                const uint32_t f = i * 64 + lane, q = f / kParts, p = f % kParts;
+                pre[i] = *reinterpret_cast<const uint4*>(reinterpret_cast<const KT*>(keys) +
+                                                         ((b0 + q) << L.log2b) + c * kLaneChunk + p * kPer);
+            }
+            return;
+        }
+#pragma unroll
+        for (uint32_t i = 0; i < kLoads; i++) {
+            const uint32_t f = i * 64 + lane, q = f / kParts, p = f % kParts;
+            const uint64_t bq = b0 + q;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (bq < L.nblocks) {
+                const uint64_t kq0 = bq << L.log2b;
+                const uint64_t nq = (L.n - kq0) < B ? (L.n - kq0) : B;
+                const uint32_t j0 = c * kLaneChunk + p * kPer;
+                const KT* src = reinterpret_cast<const KT*>(keys) + kq0 + j0;
+                if (j0 + kPer <= nq) {
+                    v = *reinterpret_cast<const uint4*>(src);
+                } else if (j0 < nq) {
+                    KT tmp[kPer] = {};
+                    for (uint32_t u = 0; u < kPer && j0 + u < nq; u++) tmp[u] = src[u];
+                    __builtin_memcpy(&v, tmp, 16);
+                }
+            }
+            pre[i] = v;
+        }
+    };
+    auto store_chunk = [&](uint32_t buf) {
+#pragma unroll
+        for (uint32_t i = 0; i < kLoads; i++) {
+            const uint32_t f = i * 64 + lane, q = f / kParts, p = f % kParts;
+            KT v[kPer];
+            __builtin_memcpy(v, &pre[i], 16);
+#pragma unroll
+            for (uint32_t u = 0; u < kPer; u++) s_keys[buf][q * kPitch + p * kPer + u] = v[u];
+        }
+    };
+
+    uint32_t s = 0, nseg = 0;
+    uint64_t Ka = first, P = 0, H = ~0ull, maxA = 0, maxd = 0;
+    double inv = 1.0;  // recip(d) for the next key, d = its distance from the anchor
+    constexpr double kTwo52 = 4503599627370496.0, kBig = 1.8e19;  // kBig: no upper end yet (> 2^64)
+    double Pf = 0.0, Hf = kBig;  // the fast path's P and H
+    const double epsf = (double)eps, scf = (double)(1ull << F);
+    uint64_t prev = (has && b > 0) ? (uint64_t)Kb[-1] : 0;
+    bool unsorted = false;
+    const uint64_t rec = b << L.log2b;
+
+    // closes segment [s, e) with slope interval (Pc, Hc) (P encoding: 1 + the
+    // largest non-negative lower end, 0 while there is none); the keys are
+    // re-read from global memory only when every lower end is negative
+    auto close = [&](uint32_t e, uint64_t Pc, uint64_t Hc) {
+        uint64_t A = 0;
+        if (e > s + 1) {
+            if (Pc != 0) {
+                const uint64_t lo = Pc - 1;
+                A = lo + (Hc - lo) / 2;
+            } else {
+                uint64_t M = ~0ull;
+                for (uint32_t j = s + 1; j < e; j++) {
+                    const uint32_t d = j - s;
+                    const uint64_t m = div_pick(fast, (eps - ((uint64_t)Kb[j] - Ka)) << F, d, recip(d));
+                    M = m < M ? m : M;
+                }
+                A = Hc >= M ? (Hc - M) / 2 : 0;
+            }
+        }
+        ws.seg_start[rec + nseg] = (uint16_t)s;
+        ws.seg_delta[rec + nseg] = Ka - first;
+        ws.seg_A[rec + nseg] = A;
+        nseg++;
+        maxA = A > maxA ? A : maxA;
+        maxd = Ka - first;  // anchors grow with the segment index
+    };
+
+    const uint32_t nchunks = B / kLaneChunk;
+    load_chunk(0);
+    store_chunk(0);
+    __syncthreads();
+    for (uint32_t c = 0; c < nchunks; c++) {
+        if (c + 1 < nchunks) load_chunk(c + 1);
+        // the lane's kLaneChunk keys of this chunk, all read before the walk
+        // (no LDS latency inside the dependent step chain)
+        const KT* row = &s_keys[c & 1][lane * kPitch];
+        uint64_t kc[kLaneChunk];
+#pragma unroll
+        for (uint32_t t = 0; t < kLaneChunk; t++) kc[t] = row[t];
+        if (fast) {
+            // Every quantity of a step is an integer below 2^49 here (block span
+            // + eps + 1 < 2^(49 - F)), exact in FP64: the bounds are FP64
+            // integers, each quotient is rounded by one FMA in the mantissa of
+            // 2^52 and corrected from its exact FMA remainder, and the cap
+            // cannot be reached.
+#pragma unroll
+            for (uint32_t t = 0; t < kLaneChunk; t++) {
+                const uint32_t e = c * kLaneChunk + t;
+                const uint64_t key = kc[t];
+                if (e < nb) {
+                    unsorted |= key < prev;
+                    prev = key;
+                    if (e > 0) {
+                        const uint32_t d = e - s;
+                        const double inv_next = recip(d + 1);  // the next step's, off the critical path
+                        const double df = (double)d;
+                        const double Df = exact_f64(key - Ka);
+                        double Pn = Pf;
+                        if (Df >= epsf) {
+                            const double x = (Df - epsf) * scf;
+                            double q = __builtin_fma(x, inv, kTwo52) - kTwo52;
+                            double r = __builtin_fma(-q, df, x);
+                            q = r < 0.0 ? q - 1.0 : (r >= df ? q + 1.0 : q);
+                            r = r < 0.0 ? r + df : (r >= df ? r - df : r);
+                            const double pp = q + (r != 0.0 ? 2.0 : 1.0);  // 1 + ceil(x / d)
+                            Pn = pp > Pf ? pp : Pf;
+                        }
+                        const double y = (Df + epsf + 1.0) * scf - 1.0;
+                        double q = __builtin_fma(y, inv, kTwo52) - kTwo52;
+                        const double r = __builtin_fma(-q, df, y);
+                        q = r < 0.0 ? q - 1.0 : (r >= df ? q + 1.0 : q);  // floor(y / d)
+                        const double Hn = q < Hf ? q : Hf;
+                        if (Pn != 0.0 && Pn - 1.0 > Hn) {
+                            close(e, (uint64_t)Pf, (uint64_t)Hf);
+                            s = e;
+                            Ka = key;
+                            Pf = 0.0;
+                            Hf = kBig;
+                            inv = 1.0;  // d = 1 at the next key
+                        } else {
+                            Pf = Pn;
+                            Hf = Hn;
+                            inv = inv_next;
+                        }
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (uint32_t t = 0; t < kLaneChunk; t++) {
+                const uint32_t e = c * kLaneChunk + t;
+                const uint64_t key = kc[t];
+                if (e < nb) {
+                    unsorted |= key < prev;
+                    prev = key;
+                    if (e > 0) {
+                        const uint32_t d = e - s;
+                        const double inv_next = recip(d + 1);
+                        const uint64_t D = key - Ka;
+                        bool fail = D >= lim;
+                        uint64_t Pn = P, Hn = H;
+                        if (!fail) {
+                            if (D >= eps) {
+                                uint32_t rem;
+                                const uint64_t q = div_small((D - eps) << F, d, inv, &rem);
+                                const uint64_t pp = q + (rem != 0) + 1;  // 1 + ceil((D - eps) 2^F / d)
+                                Pn = pp > P ? pp : P;
+                            }
+                            const uint64_t h = div_small(((D + eps + 1) << F) - 1, d, inv);
+                            Hn = h < H ? h : H;
+                            fail = Pn != 0 && Pn - 1 > Hn;
+                        }
+                        if (fail) {
+                            close(e, P, H);
+                            s = e;
+                            Ka = key;
+                            P = 0;
+                            H = ~0ull;
+                            inv = 1.0;
+                        } else {
+                            P = Pn;
+                            H = Hn;
+                            inv = inv_next;
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (c + 1 < nchunks) store_chunk((c + 1) & 1);
+        __syncthreads();
+    }
+    if (nb) {
+        if (fast)
+            close(nb, (uint64_t)Pf, Hf >= kBig ? ~0ull : (uint64_t)Hf);
+        else
+            close(nb, P, H);
+    }
+    if (__ballot(unsorted) != 0 && lane == 0) atomicOr(flags, kFlagUnsorted);
+    if (nb) {
+        store_key<KB>(blob + L.off_first, b, first);
+        const uint32_t ab = byte_width(maxd), sb = byte_width(maxA);
+        BlockInfo bi;
+        bi.nseg = nseg;
+        bi.seg_bytes = (uint32_t)(a16(2ull * nseg) + a16((uint64_t)ab * nseg) + a16((uint64_t)sb * nseg));
+        bi.nkeys = nb;
+        bi.ab = (uint8_t)ab;
+        bi.sb = (uint8_t)sb;
+        bi.pad = 0;
+        ws.blk[b] = bi;
+    }
+}
+
+// Residual codes of one block from its segment records (one wave per block):
+// the records' starts -> LDS bitmap with per-word prefix counts, so key j's
+// segment is the number of starts <= j, minus one; code = K[j] - pred + eps
+// packed LSB-first into the LDS slab, then copied to the blob.  Records of
+// blocks with at most kCodeSegCap segments are staged in LDS; larger ones
+// are read from the workspace.  Keys are loaded 16 per lane ahead of use.
+// LDS: bitmap u32[B / 32] | prefix u32[B / 32] | slab u32[res_stride / 4 + 4] |
+// deltas u64[cap] | slopes u64[cap] | starts u16[cap].
+constexpr uint32_t kCodeSegCap = 256;
+
+inline size_t code_pack_lds(uint32_t log2b, uint64_t res_stride)
+{
+    return 8 * ((1ull << log2b) >> 5) + res_stride + 16 + 18 * kCodeSegCap;
+}
+
+template <int KB>
+__global__ __launch_bounds__(64) void code_pack_kernel(const void* __restrict__ keys, Layout L,
+                                                        uint8_t* __restrict__ blob, Workspace ws, uint64_t blk0)
+{
+    using KT = typename std::conditional<KB == 4, uint32_t, uint64_t>::type;
+    extern __shared__ __align__(16) uint8_t smem[];
+    const uint32_t lane = threadIdx.x;
+    const uint32_t B = 1u << L.log2b, nwords = B >> 5;
+    const uint64_t b = blk0 + blockIdx.x;  // the launcher keeps b < nblocks
+    const BlockInfo bi = ws.blk[b];
+    const uint32_t nb = bi.nkeys <= B ? bi.nkeys : B, nseg = bi.nseg <= B ? bi.nseg : B;
+    const uint32_t slab_words = (uint32_t)(L.res_stride / 4);
+    uint32_t* s_bm = reinterpret_cast<uint32_t*>(smem);
+    uint32_t* s_pre = s_bm + nwords;
+    uint32_t* s_slab = s_pre + nwords;
+    uint64_t* s_delta = reinterpret_cast<uint64_t*>(s_slab + slab_words + 4);  // 16-byte aligned
+    uint64_t* s_A = s_delta + kCodeSegCap;
+    uint16_t* s_st = reinterpret_cast<uint16_t*>(s_A + kCodeSegCap);
+    const KT* K = reinterpret_cast<const KT*>(keys) + (b << L.log2b);
+    const uint64_t rec = b << L.log2b;
+    const bool staged = nseg <= kCodeSegCap;
+
+    for (uint32_t w = lane; w < nwords; w += 64) s_bm[w] = 0;
+    for (uint32_t w = lane; w < slab_words + 4; w += 64) s_slab[w] = 0;
+    __syncthreads();
+    const uint32_t smask = B - 1;
+    for (uint32_t t = lane; t < nseg; t += 64) {
+        const uint32_t st = ws.seg_start[rec + t] & smask;
+        atomicOr(&s_bm[st >> 5], 1u << (st & 31));
+        if (staged) {
+            s_st[t] = (uint16_t)st;
+            s_delta[t] = ws.seg_delta[rec + t];
+            s_A[t] = ws.seg_A[rec + t];
+        }
+    }
+    __syncthreads();
+    uint32_t carry = 0;
+    for (uint32_t w0 = 0; w0 < nwords; w0 += 64) {
+        const uint32_t w = w0 + lane;
+        const uint32_t cnt = w < nwords ? __popc(s_bm[w]) : 0u;
+        const uint32_t incl = wave_incl_sum32(cnt);
+        if (w < nwords) s_pre[w] = carry + incl - cnt;
+        carry += __shfl(incl, 63, 64);
+    }
+    __syncthreads();
+
+    const uint64_t first = (uint64_t)K[0], eps = L.eps;
+    const uint32_t F = L.F, w = L.w;
+    const uint64_t wmask = (1ull << w) - 1;
+    const uint32_t tmax = nseg ? nseg - 1 : 0;
+    // one loop per record source, so each read has one address space (a
+    // pointer chosen at run time would become a flat load, which waits for
+    // every outstanding key load)
+    auto pack = [&](auto rd) {
+        for (uint32_t j0 = 0; j0 < nb; j0 += 16 * 64) {
+            uint64_t kv[16];
+#pragma unroll
+            for (uint32_t i = 0; i < 16; i++) {  // unconditional (clamped) loads: all 16 in flight
+                const uint32_t j = j0 + i * 64 + lane;
+                kv[i] = (uint64_t)K[j < nb ? j : nb - 1];
+            }
+#pragma unroll
+            for (uint32_t i = 0; i < 16; i++) {
+                const uint32_t j = j0 + i * 64 + lane;
+                if (j >= nb) continue;
+                const uint32_t wd = j >> 5, bit = j & 31;
+                const uint32_t r = s_pre[wd] + __popc(s_bm[wd] & ((2u << bit) - 1u));
+                const uint32_t t = r ? (r - 1 < tmax ? r - 1 : tmax) : 0u;  // key 0 always starts segment 0
+                uint32_t s;
+                uint64_t delta, A;
+                rd(t, s, delta, A);
+                const uint64_t pred = first + delta + ((A * (uint64_t)(j - s)) >> F);
+                const uint64_t code = (kv[i] - pred + eps) & wmask;
+                const uint32_t bitpos = j * w;
+                const uint32_t wo = bitpos >> 5, sh = bitpos & 31;
+                const uint64_t v = code << sh;
+                atomicOr(&s_slab[wo], (uint32_t)v);
+                if (sh + w > 32) atomicOr(&s_slab[wo + 1], (uint32_t)(v >> 32));
+            }
+        }
+    };
+    if (w != 0 && staged)
+        pack([&](uint32_t t, uint32_t& s, uint64_t& delta, uint64_t& A) {
+            s = s_st[t];
+            delta = s_delta[t];
+            A = s_A[t];
+        });
+    else if (w != 0)
+        pack([&](uint32_t t, uint32_t& s, uint64_t& delta, uint64_t& A) {
+            s = ws.seg_start[rec + t];
+            delta = ws.seg_delta[rec + t];
+            A = ws.seg_A[rec + t];
+        });
+    __syncthreads();
+    uint4* dst = reinterpret_cast<uint4*>(blob + L.off_res + b * L.res_stride);
+    const uint4* src4 = reinterpret_cast<const uint4*>(s_slab);
+    for (uint32_t c = lane; c < slab_words / 4; c += 64) dst[c] = src4[c];
 }
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -2378,6 +2751,19 @@ hipError_t launch_compress(const void* d_keys, const Layout& L, uint32_t fit, ui
             const uint64_t nw = L.nblocks - b0 < kMaxGrid ? L.nblocks - b0 : kMaxGrid;
             hipLaunchKernelGGL(k, dim3((uint32_t)nw), dim3(kMinLanes), lds, stream, d_keys, L, d_blob, ws, d_flags,
                                b0);
+        }
+    } else if (L.nblocks >= kLanesMinBlocks) {
+        auto kf = L.kb == 4 ? fit_lanes_kernel<4> : fit_lanes_kernel<8>;
+        const uint64_t waves = (L.nblocks + 63) / 64;
+        for (uint64_t g0 = 0; g0 < waves; g0 += kMaxGrid) {
+            const uint64_t ng = waves - g0 < kMaxGrid ? waves - g0 : kMaxGrid;
+            hipLaunchKernelGGL(kf, dim3((uint32_t)ng), dim3(64), 0, stream, d_keys, L, d_blob, ws, d_flags, g0 * 64);
+        }
+        const size_t lds = code_pack_lds(L.log2b, L.res_stride);
+        auto kc = L.kb == 4 ? code_pack_kernel<4> : code_pack_kernel<8>;
+        for (uint64_t b0 = 0; b0 < L.nblocks; b0 += kMaxGrid) {
+            const uint64_t nw = L.nblocks - b0 < kMaxGrid ? L.nblocks - b0 : kMaxGrid;
+            hipLaunchKernelGGL(kc, dim3((uint32_t)nw), dim3(64), lds, stream, d_keys, L, d_blob, ws, b0);
         }
     } else if (L.nblocks) {
         const size_t lds = 4 * (L.res_stride + 16);

@@ -410,3 +410,92 @@ def test_min_fit_determinism_and_unsorted(lc):
     bad[2500] = bad[2499] - np.uint64(1)
     with pytest.raises(lc.LcError):
         lc.compress(_to_dev(bad), 15, fit="min")
+
+
+# --- greedy fit with one block per lane: lists of at least 16384 blocks -------
+
+LANES_MIN_BLOCKS = 16384  # lc_compress switches to the lane-per-block fit from here
+
+
+def _big_keys(rng, n, kb, kind):
+    """n sorted keys whose span fits the key width: small gaps, duplicates,
+    wide gaps, or small gaps with rare jumps; shifted to the top of the range
+    a third of the time."""
+    wide = 12 if kb == 4 else 20
+    if kind == "uniform":
+        g = rng.integers(0, 100, n)
+    elif kind == "dups":
+        g = rng.integers(0, 2, n)
+    elif kind == "wide":
+        g = rng.integers(0, 1 << wide, n)
+    else:
+        g = rng.integers(0, 5, n)
+        jumps = rng.random(n) < 0.01
+        g[jumps] = rng.integers(1000, 1 << (wide + 6), int(jumps.sum()))
+    k = np.cumsum(g.astype(np.uint64))
+    hi = (1 << (8 * kb)) - 1
+    assert int(k[-1]) <= hi
+    base = hi - int(k[-1]) if rng.random() < 1 / 3 else 0
+    return (k + np.uint64(base)).astype(np.uint32 if kb == 4 else np.uint64)
+
+
+@pytest.mark.parametrize("kb", [4, 8])
+def test_lanes_fit_random_lists(lc, kb):
+    """16385 blocks of 64 keys (a partial last block, a block count that is
+    not a multiple of 64) in four key shapes, eps / F pairs from exact to wide."""
+    rng = np.random.default_rng(200 + kb)
+    n = 64 * LANES_MIN_BLOCKS + 37
+    for kind in ("uniform", "dups", "wide", "bursty"):
+        keys = _big_keys(rng, n, kb, kind)
+        for eps, F in ((0, 20), (3, 0), (63, 20), (4095, 32)):
+            check_all(lc, keys, eps, 6, rng, nq=300, frac_bits=F)
+
+
+@pytest.mark.parametrize("frac_bits", [0, 20, 32])
+def test_lanes_fit_cap_gaps_and_runs(lc, frac_bits):
+    """Arithmetic runs and sparse stretches with gaps at the overflow cap,
+    repeated past 16384 blocks of 64 keys."""
+    rng = np.random.default_rng(300 + frac_bits)
+    parts, pos, total = [], np.uint64(5), 0
+    cap_gap = np.uint64(1) << np.uint64(64 - frac_bits) if frac_bits else np.uint64(1) << np.uint64(40)
+    k = 0
+    while total < 64 * LANES_MIN_BLOCKS + 100:
+        if k % 2 == 0:
+            m, g = int(rng.integers(5, 2000)), int(rng.integers(0, 50))
+            run = pos + np.uint64(g) * np.arange(m, dtype=np.uint64)
+        else:
+            m = int(rng.integers(3, 300))
+            gaps = rng.integers(1, 1 << 20, m).astype(np.uint64)
+            if k % 6 == 1 and pos < (np.uint64(1) << np.uint64(62)) - cap_gap:
+                gaps[rng.integers(0, m)] = cap_gap
+            run = pos + np.cumsum(gaps, dtype=np.uint64)
+        parts.append(run)
+        pos = run[-1] + np.uint64(1)
+        total += m
+        k += 1
+        if pos > np.uint64(1) << np.uint64(62):
+            pos = np.uint64(1) << np.uint64(62)
+    keys = np.sort(np.concatenate(parts))[:64 * LANES_MIN_BLOCKS + 100]
+    for eps in (0, 3, 100):
+        check_all(lc, keys, eps, 6, rng, nq=300, frac_bits=frac_bits)
+
+
+def test_lanes_fit_blocks_of_1024(lc, wl):
+    """The benchmark's block size: 16.8M lognormal keys (16384 blocks plus a
+    partial one), eps 63 and 255."""
+    rng = np.random.default_rng(7)
+    keys = wl.as_numpy(wl.lognormal_distinct(1024 * LANES_MIN_BLOCKS + 500, device="cpu"))
+    for eps in (63, 255):
+        check_all(lc, keys, eps, 10, rng, nq=20_000)
+
+
+def test_lanes_fit_unsorted_and_determinism(lc):
+    rng = np.random.default_rng(8)
+    keys = np.cumsum(rng.integers(0, 100, 64 * LANES_MIN_BLOCKS + 64)).astype(np.uint64)
+    d = _to_dev(keys)
+    assert torch.equal(lc.compress(d, 15, 6).data, lc.compress(d, 15, 6).data)
+    for pos in (64 * 5000, 64 * 5000 + 17, len(keys) - 1):  # at a block boundary, inside, last key
+        bad = keys.copy()
+        bad[pos] = bad[pos - 1] - np.uint64(1)
+        with pytest.raises(lc.LcError):
+            lc.compress(_to_dev(bad), 15, 6)
