@@ -227,6 +227,32 @@ __device__ __forceinline__ double exact_f64(uint64_t v)
     return __longlong_as_double((long long)(0x4330000000000000ull | v)) - 4503599627370496.0;
 }
 
+// Slope bounds of one key in exact FP64 integer arithmetic, for blocks whose
+// span keeps every numerator below 2^49 (fast_division_ok): Df = D, df = d,
+// inv = recip(d) (or 1 for d = 1).  pp = 1 + ceil((D - eps) 2^F / d) when
+// D >= eps, else 0 (the P encoding); h = floor(((D + eps + 1) 2^F - 1) / d).
+// Each quotient is rounded by one FMA into the mantissa of 2^52, which puts
+// it at the floor or one above; its exact FMA remainder corrects it.
+__device__ __forceinline__ void bounds_f64(double Df, double epsf, double scf, double df, double inv, double& pp,
+                                           double& h)
+{
+    constexpr double kTwo52 = 4503599627370496.0;
+    pp = 0.0;
+    if (Df >= epsf) {
+        const double x = (Df - epsf) * scf;
+        double q = __builtin_fma(x, inv, kTwo52) - kTwo52;
+        double r = __builtin_fma(-q, df, x);
+        const bool neg = r < 0.0;
+        q = neg ? q - 1.0 : q;
+        r = neg ? r + df : r;
+        pp = q + (r != 0.0 ? 2.0 : 1.0);
+    }
+    const double y = (Df + epsf + 1.0) * scf - 1.0;
+    const double q = __builtin_fma(y, inv, kTwo52) - kTwo52;
+    const double r = __builtin_fma(-q, df, y);
+    h = r < 0.0 ? q - 1.0 : q;
+}
+
 // div_fast where the caller has established the 2^49 bound (a uniform flag), else div_small.
 __device__ __forceinline__ uint64_t div_pick(bool fast, uint64_t x, uint32_t d, double inv, uint32_t* rem = nullptr)
 {
@@ -743,6 +769,9 @@ __global__ __launch_bounds__(kMinLanes) void fit_min_kernel(const void* __restri
         const uint32_t step_cap = per_lane * (nb + 1) + 64;
         uint32_t s = lane ? lane : kMinLanes, e = s + 1, steps = 0;
         uint64_t Ka = s < nb ? (uint64_t)sk[s] : 0, P = 0, H = ~0ull;
+        constexpr double kBig = 1.8e19;  // no upper end yet: above every real bound (< 2^49)
+        const double epsf = (double)eps, scf = (double)(1ull << F);
+        double Pf = 0.0, Hf = kBig, inv = 1.0;  // the exact FP64 walk (ca.fast); inv = recip(e - s)
         while (s < nb) {
             if (++steps > step_cap) {
                 atomicOr(flags, kFlagInternal);
@@ -750,17 +779,31 @@ __global__ __launch_bounds__(kMinLanes) void fit_min_kernel(const void* __restri
             }
             bool stop = e >= nb;
             if (!stop) {
-                const uint64_t D = (uint64_t)sk[e] - Ka;
-                stop = D >= lim;
-                if (!stop) {
-                    uint64_t p, h;
-                    cone_bounds(ca, D, e - s, p, h);
-                    const uint64_t Pn = p > P ? p : P, Hn = h < H ? h : H;
-                    stop = Pn != 0 && Pn - 1 > Hn;
+                if (ca.fast) {  // block-uniform; no cap in such blocks
+                    const double inv_next = recip(e - s + 1);
+                    double pp, h;
+                    bounds_f64(exact_f64((uint64_t)sk[e] - Ka), epsf, scf, (double)(e - s), inv, pp, h);
+                    const double Pn = pp > Pf ? pp : Pf, Hn = h < Hf ? h : Hf;
+                    stop = Pn != 0.0 && Pn - 1.0 > Hn;
                     if (!stop) {
-                        P = Pn;
-                        H = Hn;
+                        Pf = Pn;
+                        Hf = Hn;
+                        inv = inv_next;
                         e++;
+                    }
+                } else {
+                    const uint64_t D = (uint64_t)sk[e] - Ka;
+                    stop = D >= lim;
+                    if (!stop) {
+                        uint64_t p, h;
+                        cone_bounds(ca, D, e - s, p, h);
+                        const uint64_t Pn = p > P ? p : P, Hn = h < H ? h : H;
+                        stop = Pn != 0 && Pn - 1 > Hn;
+                        if (!stop) {
+                            P = Pn;
+                            H = Hn;
+                            e++;
+                        }
                     }
                 }
             }
@@ -774,6 +817,9 @@ __global__ __launch_bounds__(kMinLanes) void fit_min_kernel(const void* __restri
                 e = s + 1;
                 P = 0;
                 H = ~0ull;
+                Pf = 0.0;
+                Hf = kBig;
+                inv = 1.0;
             }
         }
     }
@@ -1262,7 +1308,7 @@ __global__ __launch_bounds__(64) void fit_lanes_kernel(const void* __restrict__ 
     uint32_t s = 0, nseg = 0;
     uint64_t Ka = first, P = 0, H = ~0ull, maxA = 0, maxd = 0;
     double inv = 1.0;  // recip(d) for the next key, d = its distance from the anchor
-    constexpr double kTwo52 = 4503599627370496.0, kBig = 1.8e19;  // kBig: no upper end yet (> 2^64)
+    constexpr double kBig = 1.8e19;  // no upper end yet: above every real bound (< 2^49)
     double Pf = 0.0, Hf = kBig;  // the fast path's P and H
     const double epsf = (double)eps, scf = (double)(1ull << F);
     uint64_t prev = (has && b > 0) ? (uint64_t)Kb[-1] : 0;
@@ -1324,23 +1370,9 @@ __global__ __launch_bounds__(64) void fit_lanes_kernel(const void* __restrict__ 
                     if (e > 0) {
                         const uint32_t d = e - s;
                         const double inv_next = recip(d + 1);  // the next step's, off the critical path
-                        const double df = (double)d;
-                        const double Df = exact_f64(key - Ka);
-                        double Pn = Pf;
-                        if (Df >= epsf) {
-                            const double x = (Df - epsf) * scf;
-                            double q = __builtin_fma(x, inv, kTwo52) - kTwo52;
-                            double r = __builtin_fma(-q, df, x);
-                            q = r < 0.0 ? q - 1.0 : (r >= df ? q + 1.0 : q);
-                            r = r < 0.0 ? r + df : (r >= df ? r - df : r);
-                            const double pp = q + (r != 0.0 ? 2.0 : 1.0);  // 1 + ceil(x / d)
-                            Pn = pp > Pf ? pp : Pf;
-                        }
-                        const double y = (Df + epsf + 1.0) * scf - 1.0;
-                        double q = __builtin_fma(y, inv, kTwo52) - kTwo52;
-                        const double r = __builtin_fma(-q, df, y);
-                        q = r < 0.0 ? q - 1.0 : (r >= df ? q + 1.0 : q);  // floor(y / d)
-                        const double Hn = q < Hf ? q : Hf;
+                        double pp, h;
+                        bounds_f64(exact_f64(key - Ka), epsf, scf, (double)d, inv, pp, h);
+                        const double Pn = pp > Pf ? pp : Pf, Hn = h < Hf ? h : Hf;
                         if (Pn != 0.0 && Pn - 1.0 > Hn) {
                             close(e, (uint64_t)Pf, (uint64_t)Hf);
                             s = e;
