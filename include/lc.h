@@ -7,8 +7,11 @@
  * piecewise linear model plus bit-packed residuals (Def. 2, Eq. 1, Sec. II-A)
  * and answers queries on the compressed form.  Every entry point works on
  * device memory and only enqueues work on the given stream; nothing here
- * allocates device memory, synchronises, or keeps state between calls (the
- * library is reentrant).  The caller owns every buffer.
+ * allocates device memory or synchronises (the request server below is the
+ * one exception to both, and says so), and the only state kept between
+ * calls is a per-device record of kernels whose LDS limit was already
+ * raised (guarded by a mutex; the library is reentrant).  The caller owns
+ * every buffer.
  *
  * Conventions shared by all entry points:
  *   - keys are unsigned integers of key_bytes = 4 or 8 bytes, little-endian,
