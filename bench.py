@@ -232,6 +232,9 @@ def bench_batch(dev, steps: int, warmup: int, nlists: int = 4096, cands=(7, 31, 
     _, tune = lc.autotune_batch(keys, lengths, cands, block_candidates=(8, 9, 10, 11, 12), objective="size")
     block_tune = [{"log2_block": r["log2_block"], "bits_per_key": round(8.0 * r["bytes"] / n, 4),
                    "decode_GBps": round(key_bytes / r["decode_ms"] / 1e6, 2), "chosen": r["chosen"]} for r in tune]
+    picked = next(r for r in tune if r["chosen"])
+    tiling_tune = {"log2_block": picked["log2_block"], "tiling": picked.get("tiling"),
+                   "compress_ms": {k: round(v, 3) for k, v in picked.get("compress_ms_by_tiling", {}).items()}}
     return {
         "workload": f"{nlists} sorted uint32 lists, lengths ~ L^-1.1 on [100, 1e6] ({n} keys), geometric gaps "
                     f"with per-list mean log-uniform in [2, 2000]; eps per list argmin-size over {list(cands)}",
@@ -247,6 +250,7 @@ def bench_batch(dev, steps: int, warmup: int, nlists: int = 4096, cands=(7, 31, 
         "step_ms": {k: v["ms"] for k, v in res.items()},
         "phases_ms": {k: {kk: vv for kk, vv in v.items() if kk != "ms"} for k, v in res.items() if "eager" in k},
         "block_size_autotune": block_tune,
+        "tiling_autotune": tiling_tune,
         "note": "batched step = autotune (size pass over the candidates + pick) + compress + decompress; "
                 "per-list step = compress + decompress only (eps given), identical blobs; the step runs at "
                 "1024-key blocks, block_size_autotune reports the tuner's sweep (objective: fewest bytes)",

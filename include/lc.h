@@ -238,9 +238,21 @@ typedef struct lc_batch_list {
     uint32_t reserved[3];
 } lc_batch_list;
 
+/* Wave tiling of a batch's greedy fit (lc_batch_params.tiling).  Both give
+ * byte-identical blobs; they differ in speed only.
+ *   LC_TILING_AUTO   lanes from 16384 blocks in the batch on, rows below
+ *   LC_TILING_ROWS   four blocks per wave, 16 lanes evaluating 16 candidate
+ *                    keys of one block per step
+ *   LC_TILING_LANES  64 blocks per wave, one lane walking each block key by
+ *                    key (the residual codes packed by a second pass) */
+#define LC_TILING_AUTO 0
+#define LC_TILING_ROWS 1
+#define LC_TILING_LANES 2
+
 /* Parameters shared by the lists of a batch. */
 typedef struct lc_batch_params {
-    uint8_t key_bytes, log2_block, frac_bits, reserved; /* as lc_params */
+    uint8_t key_bytes, log2_block, frac_bits; /* as lc_params (the greedy fit) */
+    uint8_t tiling;        /* LC_TILING_* */
     uint32_t nlists;       /* >= 1 */
     uint32_t max_eps;      /* the largest eps any list may take; sizes the slots */
     uint32_t reserved2;

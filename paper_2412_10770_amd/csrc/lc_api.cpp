@@ -121,7 +121,7 @@ constexpr uint64_t kBlockInfoBytes = sizeof(lc::BlockInfo);
 
 lc_status check_batch(const lc_batch_params* p)
 {
-    if (!p || p->nlists == 0 || p->reserved != 0 || p->reserved2 != 0) return LC_EINVAL;
+    if (!p || p->nlists == 0 || p->tiling > LC_TILING_LANES || p->reserved2 != 0) return LC_EINVAL;
     lc_params q{};
     q.key_bytes = p->key_bytes;
     q.log2_block = p->log2_block;
@@ -157,6 +157,7 @@ lc::BatchArgs batch_args(const lc_batch_params* p, uint64_t nkeys, uint64_t blob
     a.F = p->frac_bits;
     a.nlists = p->nlists;
     a.max_eps = p->max_eps;
+    a.tiling = p->tiling;
     a.total_blocks = p->total_blocks;
     a.total_groups = p->total_groups;
     a.nkeys = nkeys;

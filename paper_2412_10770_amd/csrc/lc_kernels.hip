@@ -1229,67 +1229,69 @@ __device__ __forceinline__ uint32_t wave_incl_sum32(uint32_t v)
 constexpr uint32_t kLaneChunk = 16;
 constexpr uint64_t kLanesMinBlocks = 16384;
 
-template <int KB>
-__global__ __launch_bounds__(64) void fit_lanes_kernel(const void* __restrict__ keys, Layout L,
-                                                        uint8_t* __restrict__ blob, Workspace ws,
-                                                        uint32_t* __restrict__ flags, uint64_t blk0)
+// One lane's block for lanes_fit.
+struct LaneBlock {
+    const void* keys;       // the block's first key
+    uint32_t nb;            // keys in the block; 0: the lane has no block
+    bool has_prev;          // a key of the same list precedes the block (order check)
+    uint64_t eps;           // the block's error bound
+    uint16_t* st;           // the block's segment records (RECORDS only)
+    uint64_t* dl;
+    uint64_t* sa;
+    BlockInfo* info;        // where the block's info goes (when nb > 0)
+    uint8_t* first_dst;     // the block's first_keys slot (RECORDS only)
+};
+
+// The walk of lanes_fit.  Keys arrive in chunks of kLaneChunk keys per
+// block, loaded coalesced into registers one chunk ahead and staged through
+// a padded LDS tile; each lane reads its chunk into registers before walking
+// it.  Loads are unconditional unless some lane of the wave has no block or
+// a block reaching past keys_end (then a part past its block's end is loaded
+// key by key or not at all): a branch around a load would make the compiler
+// wait for every load at the join.  Reading past a block's end but before
+// keys_end only reads keys the walk ignores.
+template <int KB, bool RECORDS>
+__device__ __forceinline__ void lanes_fit(const LaneBlock& in, uint32_t log2b, uint32_t F, const void* keys_end,
+                                          uint32_t* __restrict__ flags)
 {
     using KT = typename std::conditional<KB == 4, uint32_t, uint64_t>::type;
-    constexpr uint32_t kPitch = kLaneChunk + 1;                 // keys per LDS row
-    constexpr uint32_t kParts = kLaneChunk * KB / 16;           // 16-byte loads per block and chunk
-    constexpr uint32_t kLoads = 64 * kParts / 64;               // loads per lane and chunk
-    constexpr uint32_t kPer = 16 / KB;                          // keys per load
+    constexpr uint32_t kPitch = kLaneChunk + 1;        // keys per LDS row
+    constexpr uint32_t kParts = kLaneChunk * KB / 16;  // 16-byte loads per block and chunk
+    constexpr uint32_t kLoads = kParts;                // loads per lane and chunk (64 blocks per wave)
+    constexpr uint32_t kPer = 16 / KB;                 // keys per load
     __shared__ KT s_keys[2][64 * kPitch];
 
     const uint32_t lane = threadIdx.x;
-    const uint32_t B = 1u << L.log2b;
-    const uint64_t b0 = blk0 + (uint64_t)blockIdx.x * 64;       // first block of the wave
-    const uint64_t b = b0 + lane;
-    const bool has = b < L.nblocks;
-    const uint32_t nb = has ? ((L.n - (b << L.log2b)) < B ? (uint32_t)(L.n - (b << L.log2b)) : B) : 0u;
-    const KT* Kb = reinterpret_cast<const KT*>(keys) + (has ? (b << L.log2b) : 0);
-
-    const uint64_t eps = L.eps;
-    const uint32_t F = L.F;
+    const uint32_t B = 1u << log2b;
+    const uint32_t nb = in.nb;
+    const KT* Kb = reinterpret_cast<const KT*>(in.keys);
+    const KT* kend = reinterpret_cast<const KT*>(keys_end);
+    const uint64_t eps = in.eps;
     const uint64_t lim = F == 0 ? (~0ull - eps) : ((1ull << (64 - F)) - eps - 1);
     const uint64_t first = nb ? (uint64_t)Kb[0] : 0;
     // one-round divisions when every block of the wave allows them (a wrapped span does not)
     const bool fast = __ballot(!fast_division_ok(nb ? (uint64_t)Kb[nb - 1] - first : 0, eps, F)) == 0;
+    const bool careful = __ballot(nb == 0 || Kb + B > kend) != 0;  // wave-uniform
 
-    // chunk c of every block of the wave -> registers (16-byte loads; a part
-    // holding keys past its block's end is loaded key by key, or not at all)
     uint4 pre[kLoads];
-    // Only the wave holding the list's last block can meet a missing block or
-    // a part past a block's end; every other wave loads unconditionally, so
-    // no load waits at a branch join and all kLoads stay in flight.
-    const bool tail_wave = b0 + 64 >= L.nblocks;
     auto load_chunk = [&](uint32_t c) {
-        if (!tail_wave) {
-#pragma unroll
-            for (uint32_t i = 0; i < kLoads; i++) {
-                const uint32_t f = i * 64 + lane, q = f / kParts, p = f % kParts;
-                pre[i] = *reinterpret_cast<const uint4*>(reinterpret_cast<const KT*>(keys) +
-                                                         ((b0 + q) << L.log2b) + c * kLaneChunk + p * kPer);
-            }
-            return;
-        }
 #pragma unroll
         for (uint32_t i = 0; i < kLoads; i++) {
             const uint32_t f = i * 64 + lane, q = f / kParts, p = f % kParts;
-            const uint64_t bq = b0 + q;
+            const KT* bq = reinterpret_cast<const KT*>(__shfl((unsigned long long)Kb, q, 64));
+            const uint32_t j0 = c * kLaneChunk + p * kPer;
+            if (!careful) {
+                pre[i] = *reinterpret_cast<const uint4*>(bq + j0);
+                continue;
+            }
+            const uint32_t nq = (uint32_t)__shfl((int)nb, q, 64);
             uint4 v = make_uint4(0, 0, 0, 0);
-            if (bq < L.nblocks) {
-                const uint64_t kq0 = bq << L.log2b;
-                const uint64_t nq = (L.n - kq0) < B ? (L.n - kq0) : B;
-                const uint32_t j0 = c * kLaneChunk + p * kPer;
-                const KT* src = reinterpret_cast<const KT*>(keys) + kq0 + j0;
-                if (j0 + kPer <= nq) {
-                    v = *reinterpret_cast<const uint4*>(src);
-                } else if (j0 < nq) {
-                    KT tmp[kPer] = {};
-                    for (uint32_t u = 0; u < kPer && j0 + u < nq; u++) tmp[u] = src[u];
-                    __builtin_memcpy(&v, tmp, 16);
-                }
+            if (j0 + kPer <= nq && bq + j0 + kPer <= kend) {
+                v = *reinterpret_cast<const uint4*>(bq + j0);
+            } else if (j0 < nq) {
+                KT tmp[kPer] = {};
+                for (uint32_t u = 0; u < kPer && j0 + u < nq; u++) tmp[u] = bq[j0 + u];
+                __builtin_memcpy(&v, tmp, 16);
             }
             pre[i] = v;
         }
@@ -1311,9 +1313,8 @@ __global__ __launch_bounds__(64) void fit_lanes_kernel(const void* __restrict__ 
     constexpr double kBig = 1.8e19;  // no upper end yet: above every real bound (< 2^49)
     double Pf = 0.0, Hf = kBig;  // the fast path's P and H
     const double epsf = (double)eps, scf = (double)(1ull << F);
-    uint64_t prev = (has && b > 0) ? (uint64_t)Kb[-1] : 0;
+    uint64_t prev = (nb && in.has_prev) ? (uint64_t)Kb[-1] : 0;
     bool unsorted = false;
-    const uint64_t rec = b << L.log2b;
 
     // closes segment [s, e) with slope interval (Pc, Hc) (P encoding: 1 + the
     // largest non-negative lower end, 0 while there is none); the keys are
@@ -1334,9 +1335,11 @@ __global__ __launch_bounds__(64) void fit_lanes_kernel(const void* __restrict__ 
                 A = Hc >= M ? (Hc - M) / 2 : 0;
             }
         }
-        ws.seg_start[rec + nseg] = (uint16_t)s;
-        ws.seg_delta[rec + nseg] = Ka - first;
-        ws.seg_A[rec + nseg] = A;
+        if (RECORDS) {
+            in.st[nseg] = (uint16_t)s;
+            in.dl[nseg] = Ka - first;
+            in.sa[nseg] = A;
+        }
         nseg++;
         maxA = A > maxA ? A : maxA;
         maxd = Ka - first;  // anchors grow with the segment index
@@ -1356,9 +1359,7 @@ __global__ __launch_bounds__(64) void fit_lanes_kernel(const void* __restrict__ 
         for (uint32_t t = 0; t < kLaneChunk; t++) kc[t] = row[t];
         if (fast) {
             // Every quantity of a step is an integer below 2^49 here (block span
-            // + eps + 1 < 2^(49 - F)), exact in FP64: the bounds are FP64
-            // integers, each quotient is rounded by one FMA in the mantissa of
-            // 2^52 and corrected from its exact FMA remainder, and the cap
+            // + eps + 1 < 2^(49 - F)), exact in FP64 (bounds_f64), and the cap
             // cannot be reached.
 #pragma unroll
             for (uint32_t t = 0; t < kLaneChunk; t++) {
@@ -1441,7 +1442,12 @@ __global__ __launch_bounds__(64) void fit_lanes_kernel(const void* __restrict__ 
     }
     if (__ballot(unsorted) != 0 && lane == 0) atomicOr(flags, kFlagUnsorted);
     if (nb) {
-        store_key<KB>(blob + L.off_first, b, first);
+        if (RECORDS) {
+            if (KB == 4)
+                *reinterpret_cast<uint32_t*>(in.first_dst) = (uint32_t)first;
+            else
+                *reinterpret_cast<uint64_t*>(in.first_dst) = first;
+        }
         const uint32_t ab = byte_width(maxd), sb = byte_width(maxA);
         BlockInfo bi;
         bi.nseg = nseg;
@@ -1450,8 +1456,38 @@ __global__ __launch_bounds__(64) void fit_lanes_kernel(const void* __restrict__ 
         bi.ab = (uint8_t)ab;
         bi.sb = (uint8_t)sb;
         bi.pad = 0;
-        ws.blk[b] = bi;
+        *in.info = bi;
     }
+}
+
+// Greedy fit with one block per lane (64 blocks per wave), for lists of at
+// least kLanesMinBlocks blocks.  The greedy walk consumes exactly one key per
+// step -- a key either joins the open segment or closes it and becomes the
+// next anchor -- so all 64 walks advance in lockstep over keys 0, 1, 2, ...
+// of their blocks: no cross-lane scans, one candidate per lane per step.
+// Slopes follow the same rules as fit_rows; the residual codes, which need
+// each segment's final slope, are packed by code_pack_kernel from the
+// segment records.
+template <int KB>
+__global__ __launch_bounds__(64) void fit_lanes_kernel(const void* __restrict__ keys, Layout L,
+                                                        uint8_t* __restrict__ blob, Workspace ws,
+                                                        uint32_t* __restrict__ flags, uint64_t blk0)
+{
+    const uint64_t b = blk0 + (uint64_t)blockIdx.x * 64 + threadIdx.x;
+    const bool has = b < L.nblocks;
+    const uint32_t B = 1u << L.log2b;
+    LaneBlock in;
+    in.nb = has ? ((L.n - (b << L.log2b)) < B ? (uint32_t)(L.n - (b << L.log2b)) : B) : 0u;
+    in.keys = reinterpret_cast<const uint8_t*>(keys) + (has ? (b << L.log2b) : 0) * KB;
+    in.has_prev = b > 0;
+    in.eps = L.eps;
+    const uint64_t rec = has ? (b << L.log2b) : 0;
+    in.st = ws.seg_start + rec;
+    in.dl = ws.seg_delta + rec;
+    in.sa = ws.seg_A + rec;
+    in.info = ws.blk + (has ? b : 0);
+    in.first_dst = blob + L.off_first + (has ? b : 0) * KB;
+    lanes_fit<KB, true>(in, L.log2b, L.F, reinterpret_cast<const uint8_t*>(keys) + L.n * KB, flags);
 }
 
 // Residual codes of one block from its segment records (one wave per block):
@@ -1470,53 +1506,53 @@ inline size_t code_pack_lds(uint32_t log2b, uint64_t res_stride)
 }
 
 template <int KB>
-__global__ __launch_bounds__(64) void code_pack_kernel(const void* __restrict__ keys, Layout L,
-                                                        uint8_t* __restrict__ blob, Workspace ws, uint64_t blk0)
+__device__ __forceinline__ void code_pack_block(const void* __restrict__ keys, const BlockInfo& bi,
+                                                const uint16_t* __restrict__ rst, const uint64_t* __restrict__ rdl,
+                                                const uint64_t* __restrict__ rsa, uint32_t log2b,
+                                                uint64_t res_stride, uint32_t w, uint64_t eps, uint32_t F,
+                                                uint8_t* __restrict__ slab_dst)
 {
     using KT = typename std::conditional<KB == 4, uint32_t, uint64_t>::type;
     extern __shared__ __align__(16) uint8_t smem[];
     const uint32_t lane = threadIdx.x;
-    const uint32_t B = 1u << L.log2b, nwords = B >> 5;
-    const uint64_t b = blk0 + blockIdx.x;  // the launcher keeps b < nblocks
-    const BlockInfo bi = ws.blk[b];
+    const uint32_t B = 1u << log2b, nwords = B >> 5;
     const uint32_t nb = bi.nkeys <= B ? bi.nkeys : B, nseg = bi.nseg <= B ? bi.nseg : B;
-    const uint32_t slab_words = (uint32_t)(L.res_stride / 4);
+    const uint32_t slab_words = (uint32_t)(res_stride / 4);
     uint32_t* s_bm = reinterpret_cast<uint32_t*>(smem);
     uint32_t* s_pre = s_bm + nwords;
     uint32_t* s_slab = s_pre + nwords;
     uint64_t* s_delta = reinterpret_cast<uint64_t*>(s_slab + slab_words + 4);  // 16-byte aligned
     uint64_t* s_A = s_delta + kCodeSegCap;
     uint16_t* s_st = reinterpret_cast<uint16_t*>(s_A + kCodeSegCap);
-    const KT* K = reinterpret_cast<const KT*>(keys) + (b << L.log2b);
-    const uint64_t rec = b << L.log2b;
+    const KT* K = reinterpret_cast<const KT*>(keys);
     const bool staged = nseg <= kCodeSegCap;
+    if (nb == 0) return;
 
-    for (uint32_t w = lane; w < nwords; w += 64) s_bm[w] = 0;
-    for (uint32_t w = lane; w < slab_words + 4; w += 64) s_slab[w] = 0;
+    for (uint32_t x = lane; x < nwords; x += 64) s_bm[x] = 0;
+    for (uint32_t x = lane; x < slab_words + 4; x += 64) s_slab[x] = 0;
     __syncthreads();
     const uint32_t smask = B - 1;
     for (uint32_t t = lane; t < nseg; t += 64) {
-        const uint32_t st = ws.seg_start[rec + t] & smask;
+        const uint32_t st = rst[t] & smask;
         atomicOr(&s_bm[st >> 5], 1u << (st & 31));
         if (staged) {
             s_st[t] = (uint16_t)st;
-            s_delta[t] = ws.seg_delta[rec + t];
-            s_A[t] = ws.seg_A[rec + t];
+            s_delta[t] = rdl[t];
+            s_A[t] = rsa[t];
         }
     }
     __syncthreads();
     uint32_t carry = 0;
     for (uint32_t w0 = 0; w0 < nwords; w0 += 64) {
-        const uint32_t w = w0 + lane;
-        const uint32_t cnt = w < nwords ? __popc(s_bm[w]) : 0u;
+        const uint32_t x = w0 + lane;
+        const uint32_t cnt = x < nwords ? __popc(s_bm[x]) : 0u;
         const uint32_t incl = wave_incl_sum32(cnt);
-        if (w < nwords) s_pre[w] = carry + incl - cnt;
+        if (x < nwords) s_pre[x] = carry + incl - cnt;
         carry += __shfl(incl, 63, 64);
     }
     __syncthreads();
 
-    const uint64_t first = (uint64_t)K[0], eps = L.eps;
-    const uint32_t F = L.F, w = L.w;
+    const uint64_t first = (uint64_t)K[0];
     const uint64_t wmask = (1ull << w) - 1;
     const uint32_t tmax = nseg ? nseg - 1 : 0;
     // one loop per record source, so each read has one address space (a
@@ -1558,14 +1594,25 @@ __global__ __launch_bounds__(64) void code_pack_kernel(const void* __restrict__ 
         });
     else if (w != 0)
         pack([&](uint32_t t, uint32_t& s, uint64_t& delta, uint64_t& A) {
-            s = ws.seg_start[rec + t];
-            delta = ws.seg_delta[rec + t];
-            A = ws.seg_A[rec + t];
+            s = rst[t];
+            delta = rdl[t];
+            A = rsa[t];
         });
     __syncthreads();
-    uint4* dst = reinterpret_cast<uint4*>(blob + L.off_res + b * L.res_stride);
+    uint4* dst = reinterpret_cast<uint4*>(slab_dst);
     const uint4* src4 = reinterpret_cast<const uint4*>(s_slab);
     for (uint32_t c = lane; c < slab_words / 4; c += 64) dst[c] = src4[c];
+}
+
+template <int KB>
+__global__ __launch_bounds__(64) void code_pack_kernel(const void* __restrict__ keys, Layout L,
+                                                        uint8_t* __restrict__ blob, Workspace ws, uint64_t blk0)
+{
+    const uint64_t b = blk0 + blockIdx.x;  // the launcher keeps b < nblocks
+    const uint64_t rec = b << L.log2b;
+    code_pack_block<KB>(reinterpret_cast<const uint8_t*>(keys) + rec * KB, ws.blk[b], ws.seg_start + rec,
+                        ws.seg_delta + rec, ws.seg_A + rec, L.log2b, L.res_stride, L.w, L.eps, L.F,
+                        blob + L.off_res + b * L.res_stride);
 }
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -2335,6 +2382,80 @@ __global__ __launch_bounds__(64) void batch_fit_kernel(const void* __restrict__ 
     fit_rows<KB, SIZES>(k, L, SIZES ? nullptr : blob + li.blob_off, w, stats, local * 4);
 }
 
+// Lane-per-block fit over the blocks of a batch (lanes_fit): item = a
+// 64-block group of the batch, or (candidate, group) for the size pass
+// (SIZES: block infos only).  Each lane finds its block's list by binary
+// search over the block offsets and checks it like batch_fit_kernel.
+template <int KB, bool SIZES>
+__global__ __launch_bounds__(64) void batch_lanes_kernel(const void* __restrict__ keys,
+                                                         const lc_batch_list* __restrict__ lists, BatchArgs a,
+                                                         Cands cands, uint8_t* __restrict__ blob, Workspace ws,
+                                                         uint32_t* __restrict__ stats, uint64_t item0)
+{
+    const uint64_t item = item0 + blockIdx.x;
+    const uint64_t groups = (a.total_blocks + 63) / 64;
+    const uint64_t cand = SIZES ? item / groups : 0;
+    const uint64_t gb = (SIZES ? item % groups : item) * 64 + threadIdx.x;
+    const uint32_t B = 1u << a.log2b;
+    LaneBlock in;
+    in.keys = keys;
+    in.nb = 0;
+    in.has_prev = false;
+    in.eps = 0;
+    in.st = nullptr;
+    in.dl = nullptr;
+    in.sa = nullptr;
+    in.info = nullptr;
+    in.first_dst = nullptr;
+    bool bad = false;
+    if (gb < a.total_blocks) {
+        const uint32_t l = find_list<false>(lists, a.nlists, gb);
+        const lc_batch_list li = lists[l];
+        const uint32_t eps = SIZES ? cands.eps[cand] : li.eps;
+        const Layout L = list_layout(a, li.n, eps);
+        const uint64_t lb = gb - li.block_off;
+        if (!list_fits(li, a, L, eps, !SIZES) || lb >= L.nblocks) {
+            bad = true;
+        } else {
+            const Workspace w = list_ws(ws, li.block_off, a.log2b, cand * a.total_blocks + li.block_off);
+            const uint64_t rec = lb << a.log2b;
+            in.nb = (li.n - rec) < B ? (uint32_t)(li.n - rec) : B;
+            in.keys = reinterpret_cast<const uint8_t*>(keys) + (li.key_off + rec) * KB;
+            in.has_prev = lb > 0;
+            in.eps = eps;
+            if (!SIZES) {
+                in.st = w.seg_start + rec;
+                in.dl = w.seg_delta + rec;
+                in.sa = w.seg_A + rec;
+                in.first_dst = blob + li.blob_off + L.off_first + lb * KB;
+            }
+            in.info = w.blk + lb;
+        }
+    }
+    if (__ballot(bad) != 0 && threadIdx.x == 0) atomicOr(stats, kFlagBadList);
+    lanes_fit<KB, !SIZES>(in, a.log2b, a.F, reinterpret_cast<const uint8_t*>(keys) + a.nkeys * KB, stats);
+}
+
+// Residual codes of every block of a batch after batch_lanes_kernel, one
+// wave per block (code_pack_block on the list's slot).
+template <int KB>
+__global__ __launch_bounds__(64) void batch_code_pack_kernel(const void* __restrict__ keys,
+                                                             const lc_batch_list* __restrict__ lists, BatchArgs a,
+                                                             uint8_t* __restrict__ blob, Workspace ws, uint64_t b0)
+{
+    const uint64_t gb = b0 + blockIdx.x;  // the launcher keeps gb < total_blocks
+    const uint32_t l = find_list<false>(lists, a.nlists, gb);
+    const lc_batch_list li = lists[l];
+    const Layout L = list_layout(a, li.n, li.eps);
+    const uint64_t lb = gb - li.block_off;
+    if (!list_fits(li, a, L, li.eps, true) || lb >= L.nblocks) return;  // flagged by the fit
+    const Workspace w = list_ws(ws, li.block_off, a.log2b, li.block_off);
+    const uint64_t rec = lb << a.log2b;
+    code_pack_block<KB>(reinterpret_cast<const uint8_t*>(keys) + (li.key_off + rec) * KB, w.blk[lb],
+                        w.seg_start + rec, w.seg_delta + rec, w.seg_A + rec, a.log2b, L.res_stride, L.w, li.eps,
+                        a.F, blob + li.blob_off + L.off_res + lb * L.res_stride);
+}
+
 template <int NT>
 __device__ __forceinline__ uint64_t block_max(uint64_t v)
 {
@@ -2656,13 +2777,34 @@ hipError_t launch_batch_fit(const void* d_keys, const lc_batch_list* d_lists, co
     uint32_t w = 0;
     while ((1ull << w) < 2ull * eps_max + 1) w++;
     const uint64_t res_stride = align16(((1ull << a.log2b) * w + 7) / 8);
-    const size_t lds = 4 * (res_stride + 16);
-    const uint64_t items = a.total_groups * ncand;
-    auto k = a.kb == 4 ? (sizes_only ? batch_fit_kernel<4, true> : batch_fit_kernel<4, false>)
-                       : (sizes_only ? batch_fit_kernel<8, true> : batch_fit_kernel<8, false>);
-    for (uint64_t i0 = 0; i0 < items; i0 += kMaxGrid) {
-        const uint64_t g = items - i0 < kMaxGrid ? items - i0 : kMaxGrid;
-        hipLaunchKernelGGL(k, dim3((uint32_t)g), dim3(64), lds, stream, d_keys, d_lists, a, c, d_blob, ws, d_stats, i0);
+    const bool lanes = a.tiling == LC_TILING_LANES || (a.tiling == LC_TILING_AUTO && a.total_blocks >= kLanesMinBlocks);
+    if (lanes) {
+        const uint64_t items = (a.total_blocks + 63) / 64 * ncand;
+        auto k = a.kb == 4 ? (sizes_only ? batch_lanes_kernel<4, true> : batch_lanes_kernel<4, false>)
+                           : (sizes_only ? batch_lanes_kernel<8, true> : batch_lanes_kernel<8, false>);
+        for (uint64_t i0 = 0; i0 < items; i0 += kMaxGrid) {
+            const uint64_t g = items - i0 < kMaxGrid ? items - i0 : kMaxGrid;
+            hipLaunchKernelGGL(k, dim3((uint32_t)g), dim3(64), 0, stream, d_keys, d_lists, a, c, d_blob, ws, d_stats,
+                               i0);
+        }
+        if (!sizes_only) {
+            auto kc = a.kb == 4 ? batch_code_pack_kernel<4> : batch_code_pack_kernel<8>;
+            const size_t clds = code_pack_lds(a.log2b, res_stride);
+            for (uint64_t b0 = 0; b0 < a.total_blocks; b0 += kMaxGrid) {
+                const uint64_t nw = a.total_blocks - b0 < kMaxGrid ? a.total_blocks - b0 : kMaxGrid;
+                hipLaunchKernelGGL(kc, dim3((uint32_t)nw), dim3(64), clds, stream, d_keys, d_lists, a, d_blob, ws, b0);
+            }
+        }
+    } else {
+        const size_t lds = 4 * (res_stride + 16);
+        const uint64_t items = a.total_groups * ncand;
+        auto k = a.kb == 4 ? (sizes_only ? batch_fit_kernel<4, true> : batch_fit_kernel<4, false>)
+                           : (sizes_only ? batch_fit_kernel<8, true> : batch_fit_kernel<8, false>);
+        for (uint64_t i0 = 0; i0 < items; i0 += kMaxGrid) {
+            const uint64_t g = items - i0 < kMaxGrid ? items - i0 : kMaxGrid;
+            hipLaunchKernelGGL(k, dim3((uint32_t)g), dim3(64), lds, stream, d_keys, d_lists, a, c, d_blob, ws, d_stats,
+                               i0);
+        }
     }
     const uint64_t scans = (uint64_t)a.nlists * ncand;
     auto ks = sizes_only ? batch_scan_kernel<true> : batch_scan_kernel<false>;

@@ -60,7 +60,7 @@ class lc_blob_info(ctypes.Structure):
 
 class lc_batch_params(ctypes.Structure):
     _fields_ = [("key_bytes", ctypes.c_uint8), ("log2_block", ctypes.c_uint8), ("frac_bits", ctypes.c_uint8),
-                ("reserved", ctypes.c_uint8), ("nlists", ctypes.c_uint32), ("max_eps", ctypes.c_uint32),
+                ("tiling", ctypes.c_uint8), ("nlists", ctypes.c_uint32), ("max_eps", ctypes.c_uint32),
                 ("reserved2", ctypes.c_uint32)] + \
                [(f, ctypes.c_uint64) for f in ("total_blocks", "total_groups", "blob_bytes", "ws_bytes")]
 
@@ -407,11 +407,23 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+TILINGS = {"auto": 0, "rows": 1, "lanes": 2}  # LC_TILING_*
+
+
+def _tiling(tiling) -> int:
+    if tiling in TILINGS:
+        return TILINGS[tiling]
+    if tiling in TILINGS.values():
+        return int(tiling)
+    raise ValueError(f"tiling must be one of {sorted(TILINGS)}, not {tiling!r}")
+
+
 def batch_plan(lengths, eps, key_bytes: int, max_eps: int | None = None, log2_block: int = DEFAULT_LOG2_BLOCK,
-               frac_bits: int = DEFAULT_FRAC_BITS, key_offsets=None):
+               frac_bits: int = DEFAULT_FRAC_BITS, key_offsets=None, tiling="auto"):
     """lc_batch_plan: (lc_batch_params, host table) for lists of the given
     lengths, stored one after another in the key array unless key_offsets is
-    given.  eps: one value or one per list; max_eps sizes the blob slots."""
+    given.  eps: one value or one per list; max_eps sizes the blob slots;
+    tiling: the fit's wave tiling ("auto", "rows" or "lanes"; same blobs)."""
     lengths = np.asarray(lengths, dtype=np.uint64).ravel()
     nl = lengths.size
     table = np.zeros(nl, dtype=BATCH_LIST_DTYPE)
@@ -422,7 +434,7 @@ def batch_plan(lengths, eps, key_bytes: int, max_eps: int | None = None, log2_bl
     table["eps"] = np.broadcast_to(np.asarray(eps, dtype=np.uint32), (nl,))
     if max_eps is None:
         max_eps = int(table["eps"].max()) if nl else 0
-    p = lc_batch_params(key_bytes, log2_block, frac_bits, 0, nl, max_eps, 0, 0, 0, 0, 0)
+    p = lc_batch_params(key_bytes, log2_block, frac_bits, _tiling(tiling), nl, max_eps, 0, 0, 0, 0, 0)
     _check(lib.lc_batch_plan(ctypes.byref(p), table.ctypes.data_as(ctypes.c_void_p)), "lc_batch_plan")
     return p, table
 
@@ -494,17 +506,18 @@ def _raise_flags(fl: int, what: str):
 
 
 def batch_compress(keys: torch.Tensor, lengths, eps=None, candidates=None, log2_block: int = DEFAULT_LOG2_BLOCK,
-                   frac_bits: int = DEFAULT_FRAC_BITS, stream=None, check: bool = True) -> Batch:
+                   frac_bits: int = DEFAULT_FRAC_BITS, stream=None, check: bool = True, tiling="auto") -> Batch:
     """Compress the lists stored one after another in keys.  Either eps (one
     value or one per list) or candidates (the autotuner picks each list's eps
-    among them by exact blob size, ties to the smaller)."""
+    among them by exact blob size, ties to the smaller).  tiling: the fit's
+    wave tiling (same blobs either way)."""
     _dev(keys, "keys")
     kb = _key_bytes(keys)
     if (eps is None) == (candidates is None):
         raise ValueError("give exactly one of eps and candidates")
     cands = sorted(set(int(c) for c in candidates)) if candidates is not None else None
     p, table = batch_plan(lengths, cands[0] if cands else eps, kb, max(cands) if cands else None, log2_block,
-                          frac_bits)
+                          frac_bits, tiling=tiling)
     dev = keys.device
     nl = p.nlists
     lists = torch.from_numpy(table.view(np.uint8).copy()).to(dev)
@@ -641,15 +654,59 @@ def requests(ops, a, b=None, arrival_ns=None, d_dest=None) -> np.ndarray:
 # Batch autotuner
 # ---------------------------------------------------------------------------
 
+def time_batch_fit(keys: torch.Tensor, lengths, eps_candidates=(7, 31, 127), log2_block: int = DEFAULT_LOG2_BLOCK,
+                   tilings=("rows", "lanes"), reps: int = 3, frac_bits: int = DEFAULT_FRAC_BITS):
+    """Mean time (ms, HIP events, after one warm-up) of the batch's whole
+    compress -- size pass over eps_candidates, on-device pick, compress --
+    for each wave tiling of the fit.  The blobs are identical; only the time
+    differs.  Returns {tiling: ms}."""
+    kb = _key_bytes(keys)
+    cands = sorted(set(int(c) for c in eps_candidates))
+    out = {}
+    for tl in tilings:
+        p, table = batch_plan(lengths, cands[0], kb, max(cands), log2_block, frac_bits, tiling=tl)
+        dev = keys.device
+        lists = torch.from_numpy(table.view(np.uint8).copy()).to(dev)
+        ws = torch.empty(max(p.ws_bytes, 16), dtype=torch.uint8, device=dev)
+        blob = torch.empty(max(p.blob_bytes, 16), dtype=torch.uint8, device=dev)
+        csizes = torch.empty(len(cands) * p.nlists, dtype=torch.int64, device=dev)
+        sizes = torch.empty(p.nlists, dtype=torch.int64, device=dev)
+        stats = torch.zeros(2, dtype=torch.int32, device=dev)
+
+        def run():
+            batch_sizes_async(keys, lists, p, cands, ws, csizes, stats)
+            batch_pick_eps_async(lists, p, csizes, cands)
+            batch_compress_async(keys, lists, p, blob, ws, sizes, stats)
+
+        run()
+        torch.cuda.synchronize()
+        _raise_flags(int(stats[0].item()), "lc_batch_compress")
+        marks = []
+        for _ in range(max(1, reps)):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            run()
+            e1.record()
+            marks.append((e0, e1))
+        torch.cuda.synchronize()
+        out[tl] = float(sum(a.elapsed_time(b) for a, b in marks) / len(marks))
+        del ws, blob
+    return out
+
+
 def autotune_batch(keys: torch.Tensor, lengths, eps_candidates=(7, 31, 127), block_candidates=(8, 9, 10, 11, 12),
-                   objective: str = "size", time_reps: int = 3, frac_bits: int = DEFAULT_FRAC_BITS, stream=None):
+                   objective: str = "size", time_reps: int = 3, frac_bits: int = DEFAULT_FRAC_BITS, stream=None,
+                   tilings=("rows", "lanes")):
     """Pick the batch's block size (and, per list, eps among eps_candidates)
     by measurement.  For every log2 block size the whole batch is compressed
     with the on-device eps autotune; its exact total bytes and its batch
     decode time (HIP events, mean of time_reps runs) are recorded.
     objective "size": fewest bytes (ties: faster decode); "speed": fastest
     decode; "balanced": fewest bytes among the candidates whose decode is
-    within 10% of the fastest.  Returns (chosen Batch, report list)."""
+    within 10% of the fastest.  Then, for the chosen block size, the fit's
+    wave tiling is picked by timing the whole compress under each of tilings
+    (same bytes, so only speed decides).  Returns (chosen Batch, report
+    list); the chosen entry records the tiling times and the tiling picked."""
     if objective not in ("size", "speed", "balanced"):
         raise ValueError("objective is 'size', 'speed' or 'balanced'")
     report, batches = [], {}
@@ -677,4 +734,8 @@ def autotune_batch(keys: torch.Tensor, lengths, eps_candidates=(7, 31, 127), blo
         best = min(report, key=lambda r: (r["bytes"], r["decode_ms"]))
     for r in report:
         r["chosen"] = r is best
+    if tilings:
+        t = time_batch_fit(keys, lengths, eps_candidates, best["log2_block"], tilings, time_reps, frac_bits)
+        best["compress_ms_by_tiling"] = t
+        best["tiling"] = min(t, key=t.get)
     return batches[best["log2_block"]], report

@@ -147,7 +147,8 @@ def test_batch_bad_args(lc):
                 lc.lc_batch_params(4, 5, 20, 0, 2, 31, 0, 0, 0, 0, 0),
                 lc.lc_batch_params(4, 10, 33, 0, 2, 31, 0, 0, 0, 0, 0),
                 lc.lc_batch_params(4, 10, 20, 0, 0, 31, 0, 0, 0, 0, 0),
-                lc.lc_batch_params(4, 10, 20, 0, 2, 2 ** 31, 0, 0, 0, 0, 0)):
+                lc.lc_batch_params(4, 10, 20, 0, 2, 2 ** 31, 0, 0, 0, 0, 0),
+                lc.lc_batch_params(4, 10, 20, 3, 2, 31, 0, 0, 0, 0, 0)):  # no such tiling
         assert lc.lib.lc_batch_plan(P(bad), tp) == lc.LC_EINVAL
     assert lc.lib.lc_batch_plan(P(good), None) == lc.LC_EINVAL
     assert lc.lib.lc_batch_plan(P(good), tp) == lc.LC_OK

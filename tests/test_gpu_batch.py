@@ -82,14 +82,19 @@ def _check_batch(lc, batch, lists, eps, log2b, frac_bits, kb):
     assert np.array_equal(_host(out, kb), cat)
 
 
+TILINGS = ("rows", "lanes")  # the two wave tilings of the batch fit: identical blobs
+
+
+@pytest.mark.parametrize("tiling", TILINGS)
 @pytest.mark.parametrize("kb,log2b,frac_bits", [(4, 10, 20), (8, 10, 20), (4, 6, 20), (8, 12, 32), (8, 8, 0)])
-def test_fixed_eps_per_list(lc, kb, log2b, frac_bits):
+def test_fixed_eps_per_list(lc, kb, log2b, frac_bits, tiling):
     rng = np.random.default_rng(100 + kb + log2b)
     lists = _mixed_lists(rng, kb, 40)
     eps = rng.choice([0, 1, 7, 31, 63, 127, 1000, 65535], len(lists)).astype(np.uint32)
-    _say(f"batch fixed eps kb={kb} log2b={log2b} F={frac_bits} lists={len(lists)}")
+    _say(f"batch fixed eps kb={kb} log2b={log2b} F={frac_bits} lists={len(lists)} tiling={tiling}")
     keys, _ = _concat(lists, kb)
-    batch = lc.batch_compress(keys, [len(x) for x in lists], eps=eps, log2_block=log2b, frac_bits=frac_bits)
+    batch = lc.batch_compress(keys, [len(x) for x in lists], eps=eps, log2_block=log2b, frac_bits=frac_bits,
+                              tiling=tiling)
     assert np.array_equal(batch.eps, eps)
     _check_batch(lc, batch, lists, eps, log2b, frac_bits, kb)
     # a list's blob is an ordinary blob: the single-list queries work on it
@@ -99,15 +104,16 @@ def test_fixed_eps_per_list(lc, kb, log2b, frac_bits):
     assert np.array_equal(_host(lc.access(b, idx), kb), lists[l][idx.cpu().numpy()])
 
 
+@pytest.mark.parametrize("tiling", TILINGS)
 @pytest.mark.parametrize("kb", [4, 8])
-def test_autotune_picks_the_oracle_argmin(lc, kb):
+def test_autotune_picks_the_oracle_argmin(lc, kb, tiling):
     rng = np.random.default_rng(200 + kb)
     lists = _mixed_lists(rng, kb, 30)
-    _say(f"batch autotune kb={kb} lists={len(lists)}")
+    _say(f"batch autotune kb={kb} lists={len(lists)} tiling={tiling}")
     keys, _ = _concat(lists, kb)
     lengths = [len(x) for x in lists]
     # the size pass itself
-    p, table = lc.batch_plan(lengths, CANDS[0], kb, max(CANDS))
+    p, table = lc.batch_plan(lengths, CANDS[0], kb, max(CANDS), tiling=tiling)
     d_lists = torch.from_numpy(table.view(np.uint8).copy()).to(DEV)
     ws = torch.empty(p.ws_bytes, dtype=torch.uint8, device=DEV)
     sizes = torch.empty(len(CANDS) * len(lists), dtype=torch.int64, device=DEV)
@@ -118,12 +124,13 @@ def test_autotune_picks_the_oracle_argmin(lc, kb):
     want_sizes = np.array([[len(oracle.compress(x, e, 10, 20)) for x in lists] for e in CANDS])
     assert np.array_equal(got_sizes, want_sizes)
     best = np.array([CANDS[int(np.argmin(want_sizes[:, l]))] for l in range(len(lists))], dtype=np.uint32)
-    batch = lc.batch_compress(keys, lengths, candidates=CANDS)
+    batch = lc.batch_compress(keys, lengths, candidates=CANDS, tiling=tiling)
     assert np.array_equal(batch.eps, best)
     _check_batch(lc, batch, lists, best, 10, 20, kb)
 
 
-def test_bad_list_is_flagged_and_skipped(lc):
+@pytest.mark.parametrize("tiling", TILINGS)
+def test_bad_list_is_flagged_and_skipped(lc, tiling):
     rng = np.random.default_rng(7)
     lists = _mixed_lists(rng, 4, 12)
     keys, _ = _concat(lists, 4)
@@ -132,7 +139,7 @@ def test_bad_list_is_flagged_and_skipped(lc):
     bad = 9
     offs_bad = offs.copy()
     offs_bad[bad] = keys.numel() - lengths[bad] + 1  # one key past the end
-    p, table = lc.batch_plan(lengths, 31, 4, key_offsets=offs_bad)
+    p, table = lc.batch_plan(lengths, 31, 4, key_offsets=offs_bad, tiling=tiling)
     d_lists = torch.from_numpy(table.view(np.uint8).copy()).to(DEV)
     ws = torch.empty(p.ws_bytes, dtype=torch.uint8, device=DEV)
     blob = torch.zeros(p.blob_bytes, dtype=torch.uint8, device=DEV)
@@ -161,21 +168,23 @@ def test_bad_list_is_flagged_and_skipped(lc):
             assert np.array_equal(h[int(offs[l]):int(offs[l]) + len(x)], x), l
 
 
-def test_unsorted_list_is_flagged(lc):
+@pytest.mark.parametrize("tiling", TILINGS)
+def test_unsorted_list_is_flagged(lc, tiling):
     rng = np.random.default_rng(8)
     lists = _mixed_lists(rng, 8, 12)
     lists[10] = lists[10].copy()  # 5000 keys
     lists[10][100], lists[10][101] = lists[10][101] + 1, lists[10][100]
     keys, _ = _concat(lists, 8)
     with pytest.raises(lc.LcError, match="not sorted"):
-        lc.batch_compress(keys, [len(x) for x in lists], eps=15)
+        lc.batch_compress(keys, [len(x) for x in lists], eps=15, tiling=tiling)
 
 
-def test_posting_lists_reduced(lc, wl):
+@pytest.mark.parametrize("tiling", TILINGS)
+def test_posting_lists_reduced(lc, wl, tiling):
     """The batch workload's recipe at 256 lists of 100 .. 10^5 keys, autotuned."""
     keys, lengths = wl.posting_lists(256, device=DEV, hi=1e5)
-    _say(f"posting lists reduced: {len(lengths)} lists, {keys.numel()} keys")
-    batch = lc.batch_compress(keys, lengths, candidates=CANDS)
+    _say(f"posting lists reduced: {len(lengths)} lists, {keys.numel()} keys, tiling={tiling}")
+    batch = lc.batch_compress(keys, lengths, candidates=CANDS, tiling=tiling)
     out = lc.batch_decompress(batch)
     assert torch.equal(out, keys)
     host = _host(keys, 4)
@@ -189,7 +198,8 @@ def test_posting_lists_reduced(lc, wl):
         assert np.array_equal(batch.blob(l).data.cpu().numpy(), oracle.compress(x, e, 10, 20)), l
 
 
-def test_tiny_lists_and_degenerate_batches(lc):
+@pytest.mark.parametrize("tiling", TILINGS)
+def test_tiny_lists_and_degenerate_batches(lc, tiling):
     """20000 lists of 0..3 keys (most work items hold a single block), one
     single-list batch, an all-empty batch, and u64 keys at the top of the
     range: every blob equals the oracle's."""
@@ -204,7 +214,7 @@ def test_tiny_lists_and_degenerate_batches(lc):
         lists.append(x.astype(np.uint64))
     keys, _ = _concat(lists, 8)
     _say("tiny lists: 20000")
-    batch = lc.batch_compress(keys, lens, candidates=(0, 5, 1000))
+    batch = lc.batch_compress(keys, lens, candidates=(0, 5, 1000), tiling=tiling)
     assert torch.equal(lc.batch_decompress(batch), keys)
     for l in rng.choice(len(lists), 300, replace=False):
         sizes = [len(oracle.compress(lists[l], e, 10)) for e in (0, 5, 1000)]
@@ -214,12 +224,12 @@ def test_tiny_lists_and_degenerate_batches(lc):
     # one list
     one = np.cumsum(rng.integers(1, 100, 5000)).astype(np.uint64)
     k1, _ = _concat([one], 8)
-    b1 = lc.batch_compress(k1, [len(one)], eps=31)
+    b1 = lc.batch_compress(k1, [len(one)], eps=31, tiling=tiling)
     assert np.array_equal(b1.blob(0).data.cpu().numpy(), oracle.compress(one, 31, 10))
     assert torch.equal(lc.batch_decompress(b1), k1)
     # every list empty: header-only blobs, nothing to decode
     k0 = torch.zeros(0, dtype=torch.int64, device=DEV)
-    b0 = lc.batch_compress(k0, [0, 0, 0], eps=7)
+    b0 = lc.batch_compress(k0, [0, 0, 0], eps=7, tiling=tiling)
     for l in range(3):
         assert np.array_equal(b0.blob(l).data.cpu().numpy(), oracle.compress(np.zeros(0, np.uint64), 7, 10))
     assert lc.batch_decompress(b0).numel() == 0
