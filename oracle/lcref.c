@@ -33,6 +33,10 @@
  *     with a cap that keeps A (i - s) below 2^64; the stored A is the midpoint
  *     of the final feasible interval of integer slopes (its lower end not
  *     clamped at zero), then clamped to A >= 0; A = 0 for a one-key segment;
+ *   - the fewest-segment fit (fit = 1) keeps that class of segments and that
+ *     slope rule and chooses the boundaries: a minimum number of segments per
+ *     block, and of the minimum segmentations the one whose every boundary
+ *     lies earliest (lcref_fit_block_min);
  *   - a residual is stored offset by eps: code = Delta + eps in [0, 2 eps];
  *   - indices are 0-based.
  *
