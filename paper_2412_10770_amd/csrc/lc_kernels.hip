@@ -1249,7 +1249,9 @@ struct LaneBlock {
 // a block reaching past keys_end (then a part past its block's end is loaded
 // key by key or not at all): a branch around a load would make the compiler
 // wait for every load at the join.  Reading past a block's end but before
-// keys_end only reads keys the walk ignores.
+// keys_end only reads keys the walk ignores.  A block may start at any
+// key-width-aligned address (a batch's lists start anywhere); the 16-byte
+// global loads need only dword alignment on this hardware.
 template <int KB, bool RECORDS>
 __device__ __forceinline__ void lanes_fit(const LaneBlock& in, uint32_t log2b, uint32_t F, const void* keys_end,
                                           uint32_t* __restrict__ flags)
