@@ -1231,7 +1231,7 @@ constexpr uint64_t kLanesMinBlocks = 16384;
 
 // One lane's block for lanes_fit.
 struct LaneBlock {
-    const void* keys;       // the block's first key
+    uint64_t koff;          // index of the block's first key in the key array
     uint32_t nb;            // keys in the block; 0: the lane has no block
     bool has_prev;          // a key of the same list precedes the block (order check)
     uint64_t eps;           // the block's error bound
@@ -1251,10 +1251,14 @@ struct LaneBlock {
 // wait for every load at the join.  Reading past a block's end but before
 // keys_end only reads keys the walk ignores.  A block may start at any
 // key-width-aligned address (a batch's lists start anywhere); the 16-byte
-// global loads need only dword alignment on this hardware.
+// global loads need only dword alignment on this hardware.  Every key address
+// is the kernel's key pointer plus an offset (never a pointer rebuilt from an
+// integer), so the loads stay global loads: a flat load would also count
+// against the LDS wait counter and stall every LDS read behind the chunk
+// loads in flight.
 template <int KB, bool RECORDS>
-__device__ __forceinline__ void lanes_fit(const LaneBlock& in, uint32_t log2b, uint32_t F, const void* keys_end,
-                                          uint32_t* __restrict__ flags)
+__device__ __forceinline__ void lanes_fit(const LaneBlock& in, const void* __restrict__ keys, uint64_t nkeys,
+                                          uint32_t log2b, uint32_t F, uint32_t* __restrict__ flags)
 {
     using KT = typename std::conditional<KB == 4, uint32_t, uint64_t>::type;
     constexpr uint32_t kPitch = kLaneChunk + 1;        // keys per LDS row
@@ -1266,29 +1270,43 @@ __device__ __forceinline__ void lanes_fit(const LaneBlock& in, uint32_t log2b, u
     const uint32_t lane = threadIdx.x;
     const uint32_t B = 1u << log2b;
     const uint32_t nb = in.nb;
-    const KT* Kb = reinterpret_cast<const KT*>(in.keys);
-    const KT* kend = reinterpret_cast<const KT*>(keys_end);
+    const KT* K0 = reinterpret_cast<const KT*>(keys);
+    const KT* Kb = K0 + in.koff;
+    const uint64_t kend = nkeys;  // key index bound of every load
     const uint64_t eps = in.eps;
     const uint64_t lim = F == 0 ? (~0ull - eps) : ((1ull << (64 - F)) - eps - 1);
     const uint64_t first = nb ? (uint64_t)Kb[0] : 0;
     // one-round divisions when every block of the wave allows them (a wrapped span does not)
     const bool fast = __ballot(!fast_division_ok(nb ? (uint64_t)Kb[nb - 1] - first : 0, eps, F)) == 0;
-    const bool careful = __ballot(nb == 0 || Kb + B > kend) != 0;  // wave-uniform
+    const bool careful = __ballot(nb == 0 || in.koff + B > kend) != 0;  // wave-uniform
 
+    // the blocks this lane loads parts of, and their key counts (fixed for the walk)
+    uint64_t qoff[kLoads];
+    uint32_t qn[kLoads];
+#pragma unroll
+    for (uint32_t i = 0; i < kLoads; i++) {
+        const uint32_t q = (i * 64 + lane) / kParts;
+        qoff[i] = (uint64_t)__shfl((unsigned long long)in.koff, q, 64);
+        qn[i] = (uint32_t)__shfl((int)nb, q, 64);
+    }
     uint4 pre[kLoads];
     auto load_chunk = [&](uint32_t c) {
+        if (!careful) {  // one branch per chunk around a straight run of loads, all in flight together
+#pragma unroll
+            for (uint32_t i = 0; i < kLoads; i++) {
+                const uint32_t p = (i * 64 + lane) % kParts;
+                pre[i] = *reinterpret_cast<const uint4*>(K0 + qoff[i] + c * kLaneChunk + p * kPer);
+            }
+            return;
+        }
 #pragma unroll
         for (uint32_t i = 0; i < kLoads; i++) {
-            const uint32_t f = i * 64 + lane, q = f / kParts, p = f % kParts;
-            const KT* bq = reinterpret_cast<const KT*>(__shfl((unsigned long long)Kb, q, 64));
+            const uint32_t p = (i * 64 + lane) % kParts;
+            const KT* bq = K0 + qoff[i];
             const uint32_t j0 = c * kLaneChunk + p * kPer;
-            if (!careful) {
-                pre[i] = *reinterpret_cast<const uint4*>(bq + j0);
-                continue;
-            }
-            const uint32_t nq = (uint32_t)__shfl((int)nb, q, 64);
+            const uint32_t nq = qn[i];
             uint4 v = make_uint4(0, 0, 0, 0);
-            if (j0 + kPer <= nq && bq + j0 + kPer <= kend) {
+            if (j0 + kPer <= nq && qoff[i] + j0 + kPer <= kend) {
                 v = *reinterpret_cast<const uint4*>(bq + j0);
             } else if (j0 < nq) {
                 KT tmp[kPer] = {};
@@ -1480,7 +1498,7 @@ __global__ __launch_bounds__(64) void fit_lanes_kernel(const void* __restrict__ 
     const uint32_t B = 1u << L.log2b;
     LaneBlock in;
     in.nb = has ? ((L.n - (b << L.log2b)) < B ? (uint32_t)(L.n - (b << L.log2b)) : B) : 0u;
-    in.keys = reinterpret_cast<const uint8_t*>(keys) + (has ? (b << L.log2b) : 0) * KB;
+    in.koff = has ? (b << L.log2b) : 0;
     in.has_prev = b > 0;
     in.eps = L.eps;
     const uint64_t rec = has ? (b << L.log2b) : 0;
@@ -1489,7 +1507,7 @@ __global__ __launch_bounds__(64) void fit_lanes_kernel(const void* __restrict__ 
     in.sa = ws.seg_A + rec;
     in.info = ws.blk + (has ? b : 0);
     in.first_dst = blob + L.off_first + (has ? b : 0) * KB;
-    lanes_fit<KB, true>(in, L.log2b, L.F, reinterpret_cast<const uint8_t*>(keys) + L.n * KB, flags);
+    lanes_fit<KB, true>(in, keys, L.n, L.log2b, L.F, flags);
 }
 
 // Residual codes of one block from its segment records (one wave per block):
@@ -2400,7 +2418,7 @@ __global__ __launch_bounds__(64) void batch_lanes_kernel(const void* __restrict_
     const uint64_t gb = (SIZES ? item % groups : item) * 64 + threadIdx.x;
     const uint32_t B = 1u << a.log2b;
     LaneBlock in;
-    in.keys = keys;
+    in.koff = 0;
     in.nb = 0;
     in.has_prev = false;
     in.eps = 0;
@@ -2422,7 +2440,7 @@ __global__ __launch_bounds__(64) void batch_lanes_kernel(const void* __restrict_
             const Workspace w = list_ws(ws, li.block_off, a.log2b, cand * a.total_blocks + li.block_off);
             const uint64_t rec = lb << a.log2b;
             in.nb = (li.n - rec) < B ? (uint32_t)(li.n - rec) : B;
-            in.keys = reinterpret_cast<const uint8_t*>(keys) + (li.key_off + rec) * KB;
+            in.koff = li.key_off + rec;
             in.has_prev = lb > 0;
             in.eps = eps;
             if (!SIZES) {
@@ -2435,7 +2453,7 @@ __global__ __launch_bounds__(64) void batch_lanes_kernel(const void* __restrict_
         }
     }
     if (__ballot(bad) != 0 && threadIdx.x == 0) atomicOr(stats, kFlagBadList);
-    lanes_fit<KB, !SIZES>(in, a.log2b, a.F, reinterpret_cast<const uint8_t*>(keys) + a.nkeys * KB, stats);
+    lanes_fit<KB, !SIZES>(in, keys, a.nkeys, a.log2b, a.F, stats);
 }
 
 // Residual codes of every block of a batch after batch_lanes_kernel, one
