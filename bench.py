@@ -289,7 +289,24 @@ def bench_lookups(dev, n: int = 200_000_000, eps: int = 63, n_access: int = 10_0
         ta.append(e0.elapsed_time(e1))
         tl.append(e1.elapsed_time(e2))
     assert int(flags.item()) == 0
+    # the same lookups on the uncompressed keys (torch gather / searchsorted), for context
+    ua, ul = [], []
+    for _ in range(reps):
+        e0, e1, e2 = ev(), ev(), ev()
+        e0.record()
+        torch.index_select(keys, 0, idx, out=acc)
+        e1.record()
+        torch.searchsorted(keys, q, side="left", out=pos)
+        e2.record()
+        torch.cuda.synchronize()
+        ua.append(e0.elapsed_time(e1))
+        ul.append(e1.elapsed_time(e2))
     return {
+        "uncompressed_torch": {
+            "access_lookups_per_s": round(n_access / float(np.mean(ua)) * 1e3, 1),
+            "lower_bound_lookups_per_s": round(n_lb / float(np.mean(ul)) * 1e3, 1),
+            "bytes": n * 8,
+        },
         "workload": f"{n} uint64 keys, alternating dense (gaps U[1,4]) and Zipf(1.2) runs of 1e4..1e6 keys; "
                     f"eps {eps}; {n_access} access(i), i uniform; {n_lb} lower_bound(q), q uniform over the key range",
         "bits_per_key": round(blob.bits_per_key, 4),
