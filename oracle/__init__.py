@@ -12,7 +12,8 @@ Two layers:
   lower bound, ``numpy.searchsorted(K, q, 'left')``);
 * the encoding (Def. 2, Eq. 1, Sec. II-A): ``compress`` fits the anchored
   fixed-point eps-PLA per block -- greedily, or with the fewest segments of
-  the same class (``fit="min"``) -- and writes blob v1; ``decode``
+  the same class (``fit="min"``) -- or the optimal fit over lines with a free
+  fixed-point intercept (``fit="opt"``), and writes blob v1; ``decode``
   is an independent blob decoder.  Both live in ``lcref.c`` (plain C,
   ``unsigned __int128`` cone arithmetic, bit-by-bit packing).
 """
@@ -36,7 +37,7 @@ REF_EUNSORTED = -5
 
 HEADER_FIELDS = ("key_bytes", "log2_block", "frac_bits", "width", "eps", "max_nseg", "max_seg_bytes", "n",
                  "nblocks", "nseg_total", "off_first", "off_dir", "off_res", "res_stride",
-                 "off_seg", "blob_bytes")
+                 "off_seg", "blob_bytes", "flags")
 
 
 def build(force: bool = True, src: str = _SRC, out: str = _LIB) -> str:
@@ -60,6 +61,8 @@ def _bind(path: str):
     L.lcref_fit_block.restype = ctypes.c_uint32
     L.lcref_fit_block_min.argtypes = L.lcref_fit_block.argtypes
     L.lcref_fit_block_min.restype = ctypes.c_uint32
+    L.lcref_fit_block_opt.argtypes = L.lcref_fit_block.argtypes + [ctypes.c_void_p]
+    L.lcref_fit_block_opt.restype = ctypes.c_uint32
     L.lcref_compress.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
                                  ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, u8p, ctypes.c_uint64,
                                  ctypes.POINTER(ctypes.c_uint64)]
@@ -71,10 +74,13 @@ def _bind(path: str):
     return L
 
 
+FITS = ("greedy", "min", "opt")
+
+
 def _fit_code(fit: str) -> int:
-    if fit not in ("greedy", "min"):
-        raise ValueError(f"fit must be 'greedy' or 'min', not {fit!r}")
-    return 0 if fit == "greedy" else 1
+    if fit not in FITS:
+        raise ValueError(f"fit must be one of {FITS}, not {fit!r}")
+    return FITS.index(fit)
 
 
 class OracleError(RuntimeError):
@@ -108,15 +114,23 @@ class Ref:
         return int(self.L.lcref_width(eps))
 
     def fit_block(self, keys, eps: int, frac_bits: int = 20, fit: str = "greedy"):
-        """Anchored fit of one block; returns (start, anchor, A) arrays.
-        fit: "greedy" (each segment as long as it goes) or "min" (fewest
-        segments of the same anchored class)."""
+        """Fit of one block.  fit: "greedy" (each anchored segment as long as
+        it goes) or "min" (fewest segments of the same anchored class) return
+        (start, anchor, A) arrays; "opt" (free fixed-point intercept C,
+        fewest segments) returns (start, floor(C / 2^F) mod 2^64, A,
+        C mod 2^F)."""
         k = np.ascontiguousarray(_keys_array(keys), dtype=np.uint64)
         nb = len(k)
         st = np.zeros(max(nb, 1), np.uint32)
         an = np.zeros(max(nb, 1), np.uint64)
         sl = np.zeros(max(nb, 1), np.uint64)
-        fn = self.L.lcref_fit_block_min if _fit_code(fit) else self.L.lcref_fit_block
+        fc = _fit_code(fit)
+        if fc == 2:
+            fr = np.zeros(max(nb, 1), np.uint64)
+            m = self.L.lcref_fit_block_opt(k.ctypes.data, nb, eps, frac_bits, st.ctypes.data, an.ctypes.data,
+                                           sl.ctypes.data, fr.ctypes.data)
+            return st[:m].copy(), an[:m].copy(), sl[:m].copy(), fr[:m].copy()
+        fn = self.L.lcref_fit_block_min if fc else self.L.lcref_fit_block
         m = fn(k.ctypes.data, nb, eps, frac_bits, st.ctypes.data, an.ctypes.data, sl.ctypes.data)
         return st[:m].copy(), an[:m].copy(), sl[:m].copy()
 
@@ -141,7 +155,7 @@ class Ref:
 
     def header(self, blob) -> dict:
         b = np.ascontiguousarray(blob, dtype=np.uint8)
-        f = np.zeros(16, np.uint64)
+        f = np.zeros(len(HEADER_FIELDS), np.uint64)
         rc = self.L.lcref_header(_u8p(b), len(b), f.ctypes.data)
         if rc != REF_OK:
             raise OracleError(rc, "header")
@@ -234,19 +248,22 @@ def quantile(keys, k, q: int) -> np.ndarray:
 def predict(keys, eps: int, log2_block: int = 10, frac_bits: int = 20,
             fit: str = "greedy") -> np.ndarray:
     """The fitted eps-PLA without residuals (Def. 2; the AQP reading of
-    Sec. III-C): per block, segment t starting at s_t with anchor a_t and
-    slope A_t predicts f(i) = a_t + floor(A_t (i - s_t) / 2^F) for the keys
-    up to the next start; |K[i] - f(i)| <= eps.  Python integers; the
-    segments come from this oracle's own fit."""
+    Sec. III-C): per block, segment t starting at s_t with anchor a_t, slope
+    A_t and intercept fraction c_t (0 but for fit="opt") predicts
+    f(i) = a_t + floor((A_t (i - s_t) + c_t) / 2^F) for the keys up to the
+    next start; |K[i] - f(i)| <= eps.  Python integers, reduced modulo
+    2^(8 key_bytes); the segments come from this oracle's own fit."""
     kk = _keys_array(keys)
     mask = (1 << (8 * kk.dtype.itemsize)) - 1
     out = np.zeros_like(kk)
     B = 1 << log2_block
     for b0 in range(0, len(kk), B):
         blk = kk[b0:b0 + B]
-        st, an, sl = fit_block(blk, eps, frac_bits, fit)
+        seg = fit_block(blk, eps, frac_bits, fit)
+        st, an, sl = seg[:3]
+        fr = seg[3].tolist() if fit == "opt" else [0] * len(st)
         ends = list(st[1:]) + [len(blk)]
-        for s, e, a, A in zip(st.tolist(), ends, an.tolist(), sl.tolist()):
+        for s, e, a, A, c in zip(st.tolist(), ends, an.tolist(), sl.tolist(), fr):
             for j in range(int(s), int(e)):
-                out[b0 + j] = (int(a) + ((int(A) * (j - int(s))) >> frac_bits)) & mask
+                out[b0 + j] = (int(a) + ((int(A) * (j - int(s)) + int(c)) >> frac_bits)) & mask
     return out

@@ -37,6 +37,12 @@
  *     slope rule and chooses the boundaries: a minimum number of segments per
  *     block, and of the minimum segmentations the one whose every boundary
  *     lies earliest (lcref_fit_block_min);
+ *   - the optimal fit (fit = 2) widens the class to lines with a free
+ *     fixed-point intercept, floor(f(i)) = floor((C + A (i - s)) / 2^F) with
+ *     integers A >= 0 and C >= first_key 2^F (the line class of the optimal
+ *     eps-PLA of Sec. II-A written in fixed point); a segment grows greedily
+ *     while some (A, C) keeps every key within eps, which in this class gives
+ *     the fewest segments (lcref_fit_block_opt);
  *   - a residual is stored offset by eps: code = Delta + eps in [0, 2 eps];
  *   - indices are 0-based.
  *
@@ -50,7 +56,8 @@
  *      0 u32 magic 0x3142434C ("LCB1")   4 u16 version (1)
  *      6 u8  key_bytes (4|8)             7 u8  log2_block (6..12)
  *      8 u8  frac_bits F (0..32)         9 u8  width w
- *     10 u16 0                          12 u32 eps
+ *     10 u8  flags (bit 0: intercept fractions; no other bit is set)
+ *     11 u8  0                          12 u32 eps
  *     16 u64 n                          24 u64 nblocks = ceil(n / B)
  *     32 u64 nseg_total                 40 u32 max_nseg (largest per block)
  *     44 u32 max_seg_bytes (largest segment area of a block)
@@ -71,8 +78,17 @@
  *                           anchor_delta[nseg] (K[s]-first_key[b]),
  *                                 anchor_bytes each         padded to 16
  *                           A[nseg], slope_bytes each      padded to 16
+ *                           with flag bit 0 only (optimal fit):
+ *                           frac[nseg], frac_bytes each    padded to 16
+ *                           (frac_bytes = 0 if F = 0, 1 if F <= 8, 2 if
+ *                           F <= 16, else 4: the array is absent at F = 0)
  *                         anchor_bytes / slope_bytes = the smallest of
  *                         1, 2, 4, 8 bytes holding the block's largest value.
+ *   decoding key j of block b in segment t (d = j - start[t]):
+ *     K = first_key[b] + anchor_delta[t] + floor((A[t] d + frac[t]) / 2^F)
+ *         + code_j - eps  (mod 2^(8 key_bytes)), frac = 0 without the flag;
+ *   with fractions, anchor_delta is floor(C / 2^F) - first_key[b] taken
+ *   modulo 2^64 and frac = C mod 2^F.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -89,8 +105,12 @@ typedef unsigned __int128 u128;
 #define REF_MAGIC 0x3142434Cu
 #define REF_VERSION 1u
 #define REF_HEADER 128u
+#define REF_FLAG_FRAC 1u
 
 static uint64_t align16(uint64_t x) { return (x + 15u) / 16u * 16u; }
+
+/* Bytes of one intercept fraction C mod 2^F: enough for F bits. */
+static int frac_bytes(uint32_t F) { return F == 0 ? 0 : F <= 8 ? 1 : F <= 16 ? 2 : 4; }
 
 /* Residual width: the smallest w with 2^w >= 2 eps + 1 (Sec. II-A). */
 int lcref_width(uint32_t eps)
@@ -243,6 +263,95 @@ uint32_t lcref_fit_block_min(const uint64_t* k, uint32_t nb, uint32_t eps, uint3
     return m;
 }
 
+/* floor(a / b) and ceil(a / b) for b > 0 (C division truncates toward 0). */
+static i128 floor_div(i128 a, i128 b)
+{
+    i128 q = a / b;
+    if (a % b != 0 && a < 0)
+        q--;
+    return q;
+}
+
+static i128 ceil_div(i128 a, i128 b) { return -floor_div(-a, b); }
+
+/*
+ * Optimal fit (fit = 2): the class of fixed-point lines with a free intercept
+ * (Def. 2 / Eq. 1 with any beta; the optimal eps-PLA of Sec. II-A, in fixed
+ * point): floor(f(i)) = floor((C + A d) / 2^F), d = i - s, integers A >= 0
+ * and C.  Key i of the segment is within eps exactly when
+ *     Lo_i <= C + A d_i <= Up_i,
+ *     Lo_i = (K[i] - eps) 2^F,   Up_i = (K[i] + eps + 1) 2^F - 1.
+ * The blob keeps floor(C / 2^F) - first_key as the anchor delta, so C must
+ * also be at least first_key 2^F: Lo_s is raised to max(K[s] - eps,
+ * first_key) 2^F.  For an integer A, the feasible C are the integers of
+ * [max_i (Lo_i - A d_i), min_i (Up_i - A d_i)]; that interval is non-empty
+ * exactly when every pair i < j has Lo_j - Up_i <= A (j - i) <= Up_j - Lo_i.
+ * So the feasible slopes are the integers of
+ *     lo = max(0, max_{i<j} ceil((Lo_j - Up_i) / (j - i))),
+ *     hi = min_{i<j} floor((Up_j - Lo_i) / (j - i)),
+ * and a key e joins the segment when [lo, hi] stays non-empty with the pairs
+ * (i, e) added and K[e] - K[s] + 2 eps + 1 < 2^(64 - F) (the cap, which keeps
+ * A d + (C mod 2^F) below 2^64 for every key of the segment).
+ * A sub-segment of a feasible segment is feasible (the same line, its
+ * intercept moved to the new start, which stays >= first_key 2^F since
+ * A >= 0), so growing each segment as far as it goes gives the fewest
+ * segments of the class.  Stored: A = floor((lo + hi) / 2) (0 for a one-key
+ * segment), C = floor((g + h) / 2) of that A's intercept interval [g, h],
+ * anchor = floor(C / 2^F) modulo 2^64 and frac = C mod 2^F.
+ */
+uint32_t lcref_fit_block_opt(const uint64_t* k, uint32_t nb, uint32_t eps, uint32_t F,
+                             uint32_t* seg_start, uint64_t* seg_anchor, uint64_t* seg_A, uint64_t* seg_frac)
+{
+    if (nb == 0)
+        return 0;
+    const i128 scale = (i128)1 << F;
+    const i128 cap = (i128)1 << (64 - F);
+    const i128 first = (i128)k[0];
+    const i128 E = (i128)eps;
+    uint32_t nseg = 0;
+    uint32_t s = 0;
+    while (s < nb) {
+        /* Lo of key i in the segment starting at s (the start raised), and Up */
+#define LO(i) ((i) == s ? ((i128)k[s] - E > first ? (i128)k[s] - E : first) * scale : ((i128)k[i] - E) * scale)
+#define UP(i) (((i128)k[i] + E + 1) * scale - 1)
+        i128 lo = 0, hi = (i128)1 << 120;
+        uint32_t e = s + 1;
+        while (e < nb) {
+            if ((i128)k[e] - (i128)k[s] + 2 * E + 1 >= cap)
+                break;
+            i128 nlo = lo, nhi = hi;
+            for (uint32_t i = s; i < e; i++) {
+                i128 l = ceil_div(LO(e) - UP(i), (i128)(e - i));
+                i128 h = floor_div(UP(e) - LO(i), (i128)(e - i));
+                if (l > nlo) nlo = l;
+                if (h < nhi) nhi = h;
+            }
+            if (nlo > nhi)
+                break;
+            lo = nlo;
+            hi = nhi;
+            e++;
+        }
+        i128 A = e > s + 1 ? lo + (hi - lo) / 2 : 0;
+        i128 g = LO(s), h = UP(s);
+        for (uint32_t i = s + 1; i < e; i++) {
+            i128 gi = LO(i) - A * (i128)(i - s), hi_ = UP(i) - A * (i128)(i - s);
+            if (gi > g) g = gi;
+            if (hi_ < h) h = hi_;
+        }
+#undef LO
+#undef UP
+        i128 C = g + (h - g) / 2; /* g <= h: A is feasible; C >= first 2^F >= 0 */
+        seg_start[nseg] = s;
+        seg_anchor[nseg] = (uint64_t)(C >> F);
+        seg_A[nseg] = (uint64_t)A;
+        seg_frac[nseg] = (uint64_t)(C & (scale - 1));
+        nseg++;
+        s = e;
+    }
+    return nseg;
+}
+
 static void put_bits(uint8_t* slab, uint64_t bitpos, uint64_t code, int w)
 {
     for (int t = 0; t < w; t++) {
@@ -302,7 +411,8 @@ int lcref_compress(const void* keys, uint64_t n, int kb, int log2_block, uint32_
     int rc = layout_params(n, kb, log2_block, eps, F);
     if (rc != REF_OK) return rc;
     if (n > 0 && keys == NULL) return REF_EINVAL;
-    if (fit != 0 && fit != 1) return REF_EINVAL; /* 0: greedy, 1: fewest segments */
+    if (fit < 0 || fit > 2) return REF_EINVAL; /* 0: greedy, 1: fewest anchored, 2: optimal */
+    const int fb = fit == 2 ? frac_bytes(F) : 0; /* fraction bytes per segment */
 
     /* E0: the keys must be sorted (non-decreasing); duplicates are allowed. */
     for (uint64_t i = 1; i < n; i++)
@@ -319,9 +429,10 @@ int lcref_compress(const void* keys, uint64_t n, int kb, int log2_block, uint32_
     uint32_t* starts = malloc((n ? n : 1) * sizeof(uint32_t));
     uint64_t* anchors = malloc((n ? n : 1) * sizeof(uint64_t));
     uint64_t* slopes = malloc((n ? n : 1) * sizeof(uint64_t));
+    uint64_t* fracs = calloc(n ? n : 1, sizeof(uint64_t));
     uint64_t* blockkeys = malloc(B * sizeof(uint64_t));
-    if (!nseg || !starts || !anchors || !slopes || !blockkeys) {
-        free(nseg); free(starts); free(anchors); free(slopes); free(blockkeys);
+    if (!nseg || !starts || !anchors || !slopes || !fracs || !blockkeys) {
+        free(nseg); free(starts); free(anchors); free(slopes); free(fracs); free(blockkeys);
         return REF_ENOSPC;
     }
     uint64_t nseg_total = 0;
@@ -333,8 +444,12 @@ int lcref_compress(const void* keys, uint64_t n, int kb, int log2_block, uint32_
         for (uint32_t j = 0; j < nb; j++)
             blockkeys[j] = load_key(keys, kb, base + j);
         /* segments of block b are stored from index base (at most nb of them) */
-        nseg[b] = (fit ? lcref_fit_block_min : lcref_fit_block)(blockkeys, nb, eps, F, starts + base,
-                                                                anchors + base, slopes + base);
+        if (fit == 2)
+            nseg[b] = lcref_fit_block_opt(blockkeys, nb, eps, F, starts + base, anchors + base, slopes + base,
+                                          fracs + base);
+        else
+            nseg[b] = (fit ? lcref_fit_block_min : lcref_fit_block)(blockkeys, nb, eps, F, starts + base,
+                                                                    anchors + base, slopes + base);
         nseg_total += nseg[b];
         if (nseg[b] > max_nseg) max_nseg = nseg[b];
     }
@@ -347,7 +462,7 @@ int lcref_compress(const void* keys, uint64_t n, int kb, int log2_block, uint32_
     uint64_t total = off_seg;
     for (uint64_t b = 0; b < nblocks; b++) {
         uint64_t base = b * B;
-        uint64_t first = anchors[base];
+        uint64_t first = load_key(keys, kb, base);
         uint64_t maxd = 0, maxa = 0;
         for (uint32_t t = 0; t < nseg[b]; t++) {
             uint64_t dlt = anchors[base + t] - first;
@@ -356,13 +471,13 @@ int lcref_compress(const void* keys, uint64_t n, int kb, int log2_block, uint32_
         }
         uint64_t m = nseg[b];
         uint64_t area = align16(2 * m) + align16((uint64_t)byte_width(maxd) * m) +
-                        align16((uint64_t)byte_width(maxa) * m);
+                        align16((uint64_t)byte_width(maxa) * m) + align16((uint64_t)fb * m);
         total += area;
         if (area > max_area) max_area = area;
     }
     *out_bytes = total;
     if (cap < total || out == NULL) {
-        free(nseg); free(starts); free(anchors); free(slopes); free(blockkeys);
+        free(nseg); free(starts); free(anchors); free(slopes); free(fracs); free(blockkeys);
         return REF_ENOSPC;
     }
     memset(out, 0, total);
@@ -374,6 +489,7 @@ int lcref_compress(const void* keys, uint64_t n, int kb, int log2_block, uint32_
     out[7] = (uint8_t)log2_block;
     out[8] = (uint8_t)F;
     out[9] = (uint8_t)w;
+    out[10] = fit == 2 ? (uint8_t)REF_FLAG_FRAC : 0;
     put_le(out + 12, eps, 4);
     put_le(out + 16, n, 8);
     put_le(out + 24, nblocks, 8);
@@ -418,9 +534,11 @@ int lcref_compress(const void* keys, uint64_t n, int kb, int log2_block, uint32_
             while (t + 1 < m && starts[base + t + 1] <= j)
                 t++;
             u128 pred = (u128)anchors[base + t] +
-                        (((u128)slopes[base + t] * (u128)(j - starts[base + t])) >> F);
+                        (((u128)slopes[base + t] * (u128)(j - starts[base + t]) + fracs[base + t]) >> F);
             u128 key = load_key(keys, kb, base + j);
-            u128 code = key + eps - pred; /* exact: pred - eps <= key <= pred + eps */
+            /* pred - eps <= key <= pred + eps, pred taken modulo 2^64 (an
+             * intercept of the optimal fit may pass 2^64): exact modulo 2^64 */
+            u128 code = (uint64_t)(key + eps - pred);
             put_bits(slab, (uint64_t)j * (uint64_t)w, (uint64_t)code, w);
         }
 
@@ -433,16 +551,20 @@ int lcref_compress(const void* keys, uint64_t n, int kb, int log2_block, uint32_
         sa += align16((uint64_t)ab * m);
         for (uint32_t u = 0; u < m; u++)
             put_le(sa + (uint64_t)sb * u, slopes[base + u], sb);
-        seg_off += align16(2ull * m) + align16((uint64_t)ab * m) + align16((uint64_t)sb * m);
+        sa += align16((uint64_t)sb * m);
+        for (uint32_t u = 0; u < m && fb; u++)
+            put_le(sa + (uint64_t)fb * u, fracs[base + u], fb);
+        seg_off += align16(2ull * m) + align16((uint64_t)ab * m) + align16((uint64_t)sb * m) +
+                   align16((uint64_t)fb * m);
     }
 
-    free(nseg); free(starts); free(anchors); free(slopes); free(blockkeys);
+    free(nseg); free(starts); free(anchors); free(slopes); free(fracs); free(blockkeys);
     return REF_OK;
 }
 
 /* Header fields, parsed and checked against the layout rules. */
 typedef struct {
-    uint32_t kb, log2_block, F, w, eps, max_nseg, max_seg_bytes;
+    uint32_t kb, log2_block, F, w, eps, max_nseg, max_seg_bytes, flags;
     uint64_t n, nblocks, nseg_total, off_first, off_dir, off_res, res_stride, off_seg, bytes;
 } ref_header;
 
@@ -454,6 +576,8 @@ static int parse_header(const uint8_t* blob, uint64_t avail, ref_header* h)
     h->log2_block = blob[7];
     h->F = blob[8];
     h->w = blob[9];
+    h->flags = blob[10];
+    if ((h->flags & ~REF_FLAG_FRAC) != 0 || blob[11] != 0) return REF_EFORMAT;
     h->eps = (uint32_t)get_le(blob + 12, 4);
     h->n = get_le(blob + 16, 8);
     h->nblocks = get_le(blob + 24, 8);
@@ -499,12 +623,15 @@ int lcref_decode(const uint8_t* blob, uint64_t avail, void* out, uint64_t out_ca
         if (nb != expect_nb || m == 0 || m > nb) return REF_EFORMAT;
         if (!(ab == 1 || ab == 2 || ab == 4 || ab == 8)) return REF_EFORMAT;
         if (!(sb == 1 || sb == 2 || sb == 4 || sb == 8)) return REF_EFORMAT;
-        uint64_t area = align16(2ull * m) + align16((uint64_t)ab * m) + align16((uint64_t)sb * m);
+        const int fb = (h.flags & REF_FLAG_FRAC) ? frac_bytes(h.F) : 0;
+        uint64_t area = align16(2ull * m) + align16((uint64_t)ab * m) + align16((uint64_t)sb * m) +
+                        align16((uint64_t)fb * m);
         if (seg_off < h.off_seg || seg_off + area > h.bytes) return REF_EFORMAT;
         if (m > h.max_nseg || area > h.max_seg_bytes) return REF_EFORMAT;
         const uint8_t* st = blob + seg_off;
         const uint8_t* an = st + align16(2ull * m);
         const uint8_t* sl = an + align16((uint64_t)ab * m);
+        const uint8_t* fr = sl + align16((uint64_t)sb * m);
         const uint8_t* slab = blob + h.off_res + b * h.res_stride;
         uint64_t first = get_le(blob + h.off_first + b * h.kb, (int)h.kb);
         for (uint32_t j = 0; j < nb; j++) {
@@ -516,7 +643,8 @@ int lcref_decode(const uint8_t* blob, uint64_t avail, void* out, uint64_t out_ca
             uint64_t s = get_le(st + 2ull * t, 2);
             u128 anchor = (u128)first + get_le(an + (uint64_t)ab * t, ab);
             u128 A = get_le(sl + (uint64_t)sb * t, sb);
-            u128 pred = anchor + ((A * (u128)(j - s)) >> h.F);
+            u128 frac = fb ? get_le(fr + (uint64_t)fb * t, fb) : 0;
+            u128 pred = anchor + ((A * (u128)(j - s) + frac) >> h.F);
             u128 code = get_bits(slab, (uint64_t)j * h.w, (int)h.w);
             u128 key = pred + code - h.eps;
             uint64_t i = b * B + j;
@@ -529,15 +657,15 @@ int lcref_decode(const uint8_t* blob, uint64_t avail, void* out, uint64_t out_ca
     return REF_OK;
 }
 
-/* Header fields for tests: writes 16 u64 values in the order of ref_header. */
+/* Header fields for tests: writes 17 u64 values in the order of ref_header. */
 int lcref_header(const uint8_t* blob, uint64_t avail, uint64_t* fields)
 {
     ref_header h;
     int rc = parse_header(blob, avail, &h);
     if (rc != REF_OK) return rc;
-    uint64_t v[16] = {h.kb, h.log2_block, h.F, h.w, h.eps, h.max_nseg, h.max_seg_bytes, h.n,
+    uint64_t v[17] = {h.kb, h.log2_block, h.F, h.w, h.eps, h.max_nseg, h.max_seg_bytes, h.n,
                       h.nblocks, h.nseg_total, h.off_first, h.off_dir, h.off_res,
-                      h.res_stride, h.off_seg, h.bytes};
+                      h.res_stride, h.off_seg, h.bytes, h.flags};
     memcpy(fields, v, sizeof v);
     return REF_OK;
 }

@@ -16,7 +16,12 @@ AssertionError when the build disagrees with:
   any slope, the stored slope is the midpoint of the enumerated feasible set,
   and the greedy count is at least the minimum over all anchored
   segmentations (equal when that minimum is 1);
-* hand-derived worked examples under tests/golden/.
+* hand-derived worked examples under tests/golden/;
+* the optimal fit (free fixed-point intercept): brute force over every
+  integer (A, C) on tiny blocks for the greedy boundaries, the fewest
+  segments over all segmentations, and the midpoint slope and intercept; a
+  line with a fractional intercept is one segment at eps 0; the cap and the
+  modulo-2^64 intercept at the top of the key range.
 
 The same checks run against deliberately mutated builds of the oracle to
 show that a plausible mistake in it fails at least one of them.
@@ -373,6 +378,139 @@ def check_min_fit_blobs(ref, seed=1, count=10):
             assert np.array_equal(ref.decode(m), keys)
 
 
+# --- optimal fit: free fixed-point intercept ---------------------------------------
+
+def opt_lines(k, s, e, eps, F, first):
+    """Boolean grid over (A, C) of the lines floor((C + A d) / 2^F) that keep
+    keys s .. e-1 within eps, with A >= 0 and C >= first 2^F, tried by
+    evaluating the floor for every key (numpy int64; tiny keys and F only).
+    Returns (A values, C values, mask)."""
+    ks = [int(x) for x in k]
+    span = ks[e - 1] - ks[s]
+    A = np.arange(0, ((span + 2 * eps + 1) << F) + 1, dtype=np.int64)
+    # key s alone: K[s] - eps <= floor(C / 2^F) <= K[s] + eps
+    c_lo = max((ks[s] - eps) << F, first << F)
+    C = np.arange(c_lo, ((ks[s] + eps + 1) << F), dtype=np.int64)
+    ok = np.ones((len(A), len(C)), bool)
+    for i in range(s, e):
+        pred = (C[None, :] + A[:, None] * (i - s)) >> F
+        ok &= np.abs(ks[i] - pred) <= eps
+    return A, C, ok
+
+
+def opt_feasible(k, s, e, eps, F, first):
+    if ((int(k[e - 1]) - int(k[s]) + 2 * eps + 1) >> (64 - F)) != 0:  # the cap
+        return False
+    return bool(opt_lines(k, s, e, eps, F, first)[2].any())
+
+
+def check_opt_fit_bruteforce(ref, trials=300, seed=12):
+    """fit="opt" on tiny blocks against the grid: each segment is the longest
+    feasible one from its start, their number is the minimum over every
+    segmentation, and the stored A and C are the midpoints of the feasible
+    slopes and of that slope's feasible intercepts.  The trials must include
+    blocks where the anchored minimum needs more segments."""
+    rng = np.random.default_rng(seed)
+    beats_anchored = 0
+    for trial in range(trials):
+        n = int(rng.integers(1, 8))
+        eps = int(rng.integers(0, 3))
+        F = int(rng.choice([0, 1, 2]))
+        hi = int(rng.choice([6, 20, 40]))
+        k = np.sort(rng.integers(0, hi, n)).astype(np.uint64)
+        first = int(k[0])
+        st, an, sl, fr = ref.fit_block(k, eps, F, "opt")
+        ok = {(a, b): opt_feasible(k, a, b, eps, F, first) for a in range(n) for b in range(a + 1, n + 1)}
+        ends = st.tolist()[1:] + [n]
+        for s_, e_ in zip(st.tolist(), ends):
+            assert ok[(s_, e_)], (trial, k.tolist(), eps, F, s_, e_)
+            assert e_ == n or not ok[(s_, e_ + 1)], (trial, k.tolist(), eps, F, s_, e_)
+        # fewest segments over every segmentation (dynamic programming)
+        best = [0] + [n + 1] * n
+        for b in range(1, n + 1):
+            best[b] = min(best[a] + 1 for a in range(b) if ok[(a, b)])
+        assert len(st) == best[n], (trial, k.tolist(), eps, F)
+        for s_, e_, a, A_, c in zip(st.tolist(), ends, an.tolist(), sl.tolist(), fr.tolist()):
+            As, Cs, m = opt_lines(k, s_, e_, eps, F, first)
+            feas_A = As[m.any(axis=1)].tolist()
+            assert feas_A == list(range(feas_A[0], feas_A[-1] + 1))  # an interval
+            want_A = 0 if e_ - s_ == 1 else (feas_A[0] + feas_A[-1]) // 2
+            assert A_ == want_A, (trial, k.tolist(), eps, F, s_, e_)
+            feas_C = Cs[m[want_A - int(As[0])]].tolist()
+            assert feas_C == list(range(feas_C[0], feas_C[-1] + 1))
+            want_C = (feas_C[0] + feas_C[-1]) // 2
+            assert (int(a) << F) + int(c) == want_C and int(c) < (1 << F), (trial, k.tolist(), eps, F, s_)
+        beats_anchored += len(ref.fit_block(k, eps, F, "min")[0]) > len(st)
+    assert beats_anchored > 0
+
+
+def check_opt_fit_closed_forms(ref):
+    """A fixed-point line with a fractional intercept is one segment at eps 0
+    (the anchored fits need more), rebuilt exactly; the cap
+    K[e] - K[s] + 2 eps + 1 < 2^(64 - F) at its boundary; intercepts past
+    2^64 near the top of the key range decode modulo 2^64."""
+    for F, A0, C0 in ((8, 700, 5 * 256 + 200), (20, 3 << 19, 77), (0, 3, 11)):
+        k = np.array([(C0 + A0 * i) >> F for i in range(512)], np.uint64)
+        st, an, sl, fr = ref.fit_block(k, 0, F, "opt")
+        assert len(st) == 1
+        pred = [((int(an[0]) << F) + int(fr[0]) + int(sl[0]) * i) >> F for i in range(512)]
+        assert pred == k.tolist()
+        if F == 8:
+            assert len(ref.fit_block(k, 0, F, "min")[0]) > 1
+        blob = ref.compress(k, 0, 9, F, fit="opt")
+        assert np.array_equal(ref.decode(blob), k)
+    for F in (20, 32):
+        cap = 1 << (64 - F)
+        for eps in (0, 5):
+            joined = np.array([0, cap - 2 - 2 * eps], np.uint64)  # K[1] - K[0] + 2 eps + 1 = cap - 1
+            split = np.array([0, cap - 1 - 2 * eps], np.uint64)   # ... = cap
+            assert len(ref.fit_block(joined, eps, F, "opt")[0]) == 1
+            assert len(ref.fit_block(split, eps, F, "opt")[0]) == 2
+            for kk in (joined, split):
+                assert np.array_equal(ref.decode(ref.compress(kk, eps, 6, F, fit="opt")), kk)
+    top = (1 << 64) - 1
+    for eps in (3, 100):
+        k = np.array(sorted({0, 9, top - 300, top - 40, top - 3, top - 1, top}), np.uint64)
+        for F in (0, 20):
+            blob = ref.compress(k, eps, 6, F, fit="opt")
+            assert np.array_equal(ref.decode(blob), k)
+            h = ref.header(blob)
+            assert h["flags"] == 1 and h["nseg_total"] <= len(ref.fit_block(k, eps, F, "min")[0])
+
+
+def check_opt_fit_blobs(ref, seed=5, count=8):
+    """fit="opt" blobs decode (4- and 8-byte keys, F from 0 to 32), keep
+    every prediction within eps, never hold more segments than the anchored
+    minimum, and have the size the layout statement gives: the fraction
+    array takes 0, 1, 2 or 4 bytes per segment for F = 0, <= 8, <= 16, more."""
+    for keys, eps, log2b in random_cases(seed, count):
+        keys = keys[:6000]
+        for F in (0, 5, 12, 20, 32):
+            m = ref.compress(keys, eps, log2b, F, fit="min")
+            o = ref.compress(keys, eps, log2b, F, fit="opt")
+            ho = ref.header(o)
+            assert ho["flags"] == 1 and ref.header(m)["flags"] == 0
+            assert ho["nseg_total"] <= ref.header(m)["nseg_total"]
+            assert np.array_equal(ref.decode(o), keys)
+            fb = 0 if F == 0 else 1 if F <= 8 else 2 if F <= 16 else 4
+            B = 1 << log2b
+            size = ho["off_seg"]
+            for b0 in range(0, len(keys), B):
+                st, an, sl, fr = ref.fit_block(keys[b0:b0 + B], eps, F, "opt")
+                nseg = len(st)
+                first = int(keys[b0])
+                dmax = max(((int(a) - first) % (1 << 64)) for a in an)
+                size += (align16(2 * nseg) + align16(widths_of(dmax) * nseg) +
+                         align16(widths_of(int(sl.max())) * nseg) + align16(fb * nseg))
+                ends = st.tolist()[1:] + [min(B, len(keys) - b0)]
+                for s_, e_, a, A_, c in zip(st.tolist(), ends, an.tolist(), sl.tolist(), fr.tolist()):
+                    for j in range(s_, e_):
+                        f = (int(a) + ((int(A_) * (j - s_) + int(c)) >> F)) % (1 << 64)
+                        d = (int(keys[b0 + j]) - f + (1 << 63)) % (1 << 64) - (1 << 63)
+                        assert abs(d) <= eps
+            assert size == ho["blob_bytes"] == len(o)
+
+
 def run_quick(ref) -> str:
     """Run every check with small counts; return the name of the first that fails, or ''."""
     quick = [
@@ -381,6 +519,8 @@ def run_quick(ref) -> str:
         (check_span_within_eps, {}), (check_bruteforce, {"trials": 200}),
         (check_cap_boundary, {}), (check_blob_size, {"count": 12}), (check_byte_widths, {}),
         (check_min_fit_bruteforce, {"trials": 400}), (check_min_fit_blobs, {"count": 6}),
+        (check_opt_fit_closed_forms, {}), (check_opt_fit_bruteforce, {"trials": 150}),
+        (check_opt_fit_blobs, {"count": 8}),
     ]
     for fn, kw in quick:
         try:

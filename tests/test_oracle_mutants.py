@@ -26,7 +26,7 @@ MUTANTS = [
      "        uint32_t s = bound[m] > 1 ? 1 : 0;\n        while (reach[s] < bound[m])"),
     ("min_reach_one_short", "        reach[s] = cone(k, s, nb, eps, F, &lo, &hi);",
      "        reach[s] = cone(k, s, nb, eps, F, &lo, &hi);\n        if (reach[s] > s + 1 && reach[s] < nb) reach[s]--;"),
-    ("residual_sign", "u128 code = key + eps - pred;", "u128 code = pred + eps - key;"),
+    ("residual_sign", "u128 code = (uint64_t)(key + eps - pred);", "u128 code = (uint64_t)(pred + eps - key);"),
     ("offset_dropped", "(u128)(j - starts[base + t])", "(u128)(j)"),
     ("decoder_search", "if (get_le(st + 2ull * u, 2) <= j)", "if (get_le(st + 2ull * u, 2) < j)"),
     ("bit_order", "slab[p / 8] |= (uint8_t)(1u << (p % 8));", "slab[p / 8] |= (uint8_t)(1u << (7 - p % 8));"),
@@ -38,6 +38,19 @@ MUTANTS = [
     ("stride_unaligned", "const uint64_t res_stride = align16((B * (uint64_t)w + 7) / 8);",
      "const uint64_t res_stride = (B * (uint64_t)w + 7) / 8;"),
     ("dir_count", "put_le(d + 12, nb - 1, 2);", "put_le(d + 12, nb, 2);"),
+    ("opt_start_not_raised", "#define LO(i) ((i) == s ? ((i128)k[s] - E > first ? (i128)k[s] - E : first) * scale",
+     "#define LO(i) ((i) == s ? ((i128)k[s] - E) * scale"),
+    ("opt_ceil_as_floor", "i128 l = ceil_div(LO(e) - UP(i), (i128)(e - i));",
+     "i128 l = floor_div(LO(e) - UP(i), (i128)(e - i));"),
+    ("opt_pairs_with_start_only", "            for (uint32_t i = s; i < e; i++) {\n                i128 l = ceil_div",
+     "            for (uint32_t i = s; i < s + 1; i++) {\n                i128 l = ceil_div"),
+    ("opt_cap_eps_once", "if ((i128)k[e] - (i128)k[s] + 2 * E + 1 >= cap)", "if ((i128)k[e] - (i128)k[s] + E + 1 >= cap)"),
+    ("opt_intercept_low_end", "i128 C = g + (h - g) / 2;", "i128 C = g;"),
+    ("opt_slope_low_end", "i128 A = e > s + 1 ? lo + (hi - lo) / 2 : 0;", "i128 A = e > s + 1 ? lo : 0;"),
+    ("opt_fraction_dropped", "(((u128)slopes[base + t] * (u128)(j - starts[base + t]) + fracs[base + t]) >> F)",
+     "(((u128)slopes[base + t] * (u128)(j - starts[base + t])) >> F)"),
+    ("opt_fraction_width", "static int frac_bytes(uint32_t F) { return F == 0 ? 0 : F <= 8 ? 1 : F <= 16 ? 2 : 4; }",
+     "static int frac_bytes(uint32_t F) { return F == 0 ? 0 : F <= 8 ? 1 : 4; }"),
 ]
 
 RUNNER = (
