@@ -25,20 +25,24 @@
  * Blob v1 (the compressed form, little-endian, every region 16-byte aligned,
  * every pad byte zero):
  *   header (128 B): magic "LCB1", version 1, key_bytes, log2_block, frac_bits
- *     F, residual width w, eps, n, nblocks, nseg_total, max_nseg,
- *     max_seg_bytes, the byte offsets of the four regions below, res_stride,
- *     blob_bytes;
+ *     F, residual width w, flags (byte 10; bit 0 = LC_BLOB_FLAG_FRAC), eps,
+ *     n, nblocks, nseg_total, max_nseg, max_seg_bytes, the byte offsets of
+ *     the four regions below, res_stride, blob_bytes;
  *   first_keys[nblocks]   the first key of every block of B = 2^log2_block keys;
  *   dir[nblocks]          16 B each: segment-area offset, segment count,
  *                         key count - 1, anchor and slope byte widths;
  *   residual slabs        block b at off_res + b*res_stride, code j of the
  *                         block in bits [j*w, j*w + w) of an LSB-first stream;
  *   segment areas         per block: u16 start[], anchor - first_key[] and
- *                         slope A[] (1, 2, 4 or 8 bytes each).
+ *                         slope A[] (1, 2, 4 or 8 bytes each), and with
+ *                         LC_BLOB_FLAG_FRAC the intercept fractions frac[]
+ *                         (LC_FRAC_BYTES(F) bytes each; none at F = 0).
  * Key i = b*B + j decodes as
- *   anchor[t] + floor(A[t] * (j - start[t]) / 2^F) + code_j - eps  (mod 2^64)
- * with t the last segment of block b starting at or before j, i.e. the
- * paper's K[i] = floor(f(i)) + Delta[i] with an anchored fixed-point f.
+ *   anchor[t] + floor((A[t] * (j - start[t]) + frac[t]) / 2^F) + code_j - eps
+ * (mod 2^64; frac = 0 without the flag) with t the last segment of block b
+ * starting at or before j, i.e. the paper's K[i] = floor(f(i)) + Delta[i]
+ * with a fixed-point f.  Without the flag the anchor is the segment's first
+ * key; with it, anchor + frac / 2^F is the line's intercept at the start.
  */
 #ifndef LC_H
 #define LC_H
@@ -70,17 +74,31 @@ typedef int32_t lc_status;
 #define LC_MAX_EPS 0x7FFFFFFFu
 #define LC_HEADER_BYTES 128
 
-/* Segment choice of the fit (lc_params.fit).  Both fits form anchored
+/* Segment choice of the fit (lc_params.fit).  The first two form anchored
  * segments (anchor = the segment's first key, integer slope A, the midpoint
- * of the segment's feasible slopes) and write the same blob format.
+ * of the segment's feasible slopes):
  *   LC_FIT_GREEDY  each segment grows while some slope keeps all its keys
  *                  within eps (Def. 2, Eq. 1);
  *   LC_FIT_MIN     the fewest segments of that same class per block (the
  *                  optimal-size goal of Sec. II-A within anchored segments):
  *                  among the minimum segmentations, the one whose every
- *                  boundary lies earliest.  Fewer segments, slower fit. */
+ *                  boundary lies earliest.  Fewer segments, slower fit.
+ *   LC_FIT_OPT     the optimal eps-PLA of Sec. II-A in fixed point: lines
+ *                  floor((C + A d) / 2^F) with a free integer intercept C
+ *                  >= first_key * 2^F and integer A >= 0; each segment grows
+ *                  while some (A, C) keeps its keys within eps, which in this
+ *                  class gives the fewest segments.  Stored: A = midpoint of
+ *                  the feasible slopes, C = midpoint of that A's feasible
+ *                  intercepts.  Sets LC_BLOB_FLAG_FRAC; at F = 0 the blob
+ *                  carries no fraction array.  One wave per block. */
 #define LC_FIT_GREEDY 0
 #define LC_FIT_MIN 1
+#define LC_FIT_OPT 2
+
+/* Header flag (lc_blob_info.flags): segments carry intercept fractions. */
+#define LC_BLOB_FLAG_FRAC 1u
+/* Bytes of one intercept fraction for F fractional bits. */
+#define LC_FRAC_BYTES(F) ((F) == 0 ? 0u : (F) <= 8 ? 1u : (F) <= 16 ? 2u : 4u)
 
 /* Encoder parameters.
  *   key_bytes  4 or 8
@@ -88,7 +106,7 @@ typedef int32_t lc_status;
  *              a block)
  *   frac_bits  0..32, fractional bits F of the fixed-point slope A / 2^F
  *              (LC_DEFAULT_FRAC_BITS = 20)
- *   fit        LC_FIT_GREEDY (0) or LC_FIT_MIN
+ *   fit        LC_FIT_GREEDY (0), LC_FIT_MIN or LC_FIT_OPT
  *   eps        0..LC_MAX_EPS, the error bound of Def. 2; residuals take
  *              w = ceil(log2(2 eps + 1)) bits each (Sec. II-A) */
 typedef struct lc_params {
@@ -104,7 +122,7 @@ typedef struct lc_blob_info {
     uint32_t key_bytes, log2_block, frac_bits, width, eps;
     uint32_t max_nseg;      /* most segments in one block */
     uint32_t max_seg_bytes; /* largest segment area of one block (sizes decode's LDS) */
-    uint32_t reserved;
+    uint32_t flags;         /* header byte 10: LC_BLOB_FLAG_FRAC or 0 */
     uint64_t n, nblocks, nseg_total;
     uint64_t off_first, off_dir, off_res, res_stride, off_seg, blob_bytes;
 } lc_blob_info;
@@ -118,8 +136,9 @@ lc_status lc_compress_bound(uint64_t n, const lc_params* p, uint64_t* blob_max,
 
 /* Enc of Def. 1: compress n keys at d_keys (device, key_bytes each, sorted)
  * into d_blob (device, blob_cap bytes, 16-byte aligned).  The fit follows
- * Def. 2 / Eq. 1 per block: anchored segments with an integer slope, chosen
- * greedily or for the fewest segments (p->fit), residuals bit-packed at
+ * Def. 2 / Eq. 1 per block: segments with an integer slope, anchored and
+ * chosen greedily or for the fewest segments, or with a free fixed-point
+ * intercept (p->fit), residuals bit-packed at
  * ceil(log2(2 eps + 1)) bits (Sec. II-A).
  * d_ws: device workspace of ws_bytes (16-byte aligned), contents scratch.
  * d_blob_bytes: device u64 receiving the blob size (may be NULL).

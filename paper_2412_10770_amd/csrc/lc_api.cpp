@@ -31,7 +31,7 @@ lc_status check_params(const lc_params* p)
     if (!p) return LC_EINVAL;
     if (p->key_bytes != 4 && p->key_bytes != 8) return LC_EINVAL;
     if (p->log2_block < 6 || p->log2_block > 12) return LC_EINVAL;
-    if (p->frac_bits > 32 || p->fit > LC_FIT_MIN) return LC_EINVAL;
+    if (p->frac_bits > 32 || p->fit > LC_FIT_OPT) return LC_EINVAL;
     if (p->eps > LC_MAX_EPS) return LC_EINVAL;
     return LC_OK;
 }
@@ -54,11 +54,13 @@ lc::Layout fixed_layout(uint64_t n, const lc_params* p)
     L.off_res = L.off_dir + 16 * L.nblocks;
     L.off_seg = L.off_res + L.nblocks * L.res_stride;
     L.max_nseg = 0;
+    L.flags = p->fit == LC_FIT_OPT ? lc::kFlagFrac : 0u;
+    L.fb = L.flags ? lc::frac_bytes(L.F) : 0u;
     return L;
 }
 
 struct WsPlan {
-    uint64_t blk, tiles, start, delta, slope, total;
+    uint64_t blk, tiles, start, delta, slope, frac, total;
 };
 
 WsPlan plan_workspace(const lc::Layout& L)
@@ -70,7 +72,8 @@ WsPlan plan_workspace(const lc::Layout& L)
     w.start = w.tiles + lc::align16(lc::ntiles_of(L.nblocks) * sizeof(lc::TileSum));
     w.delta = w.start + lc::align16(recs * 2);
     w.slope = w.delta + recs * 8;
-    w.total = w.slope + recs * 8;
+    w.frac = w.slope + recs * 8;
+    w.total = w.frac + (L.flags ? recs * 4 : 0);
     if (w.total == 0) w.total = 16;
     return w;
 }
@@ -78,7 +81,7 @@ WsPlan plan_workspace(const lc::Layout& L)
 uint64_t worst_blob(const lc::Layout& L)
 {
     const uint64_t B = 1ull << L.log2b;
-    const uint64_t seg_area = lc::align16(2 * B) + 2 * lc::align16(8 * B);
+    const uint64_t seg_area = lc::align16(2 * B) + 2 * lc::align16(8 * B) + lc::align16(L.fb * B);
     return L.off_seg + L.nblocks * seg_area;
 }
 
@@ -98,6 +101,8 @@ lc_status layout_of(const lc_blob_info* info, lc::Layout* L)
     p.log2_block = (uint8_t)info->log2_block;
     p.frac_bits = (uint8_t)info->frac_bits;
     p.eps = info->eps;
+    if (info->flags & ~lc::kFlagFrac) return LC_EINVAL;
+    p.fit = info->flags ? LC_FIT_OPT : LC_FIT_GREEDY;  // the layout depends on it only through the fractions
     if (info->key_bytes > 8 || info->log2_block > 12 || info->frac_bits > 32) return LC_EINVAL;
     if (check_params(&p) != LC_OK || info->n > kMaxKeys) return LC_EINVAL;
     *L = fixed_layout(info->n, &p);
@@ -108,7 +113,8 @@ lc_status layout_of(const lc_blob_info* info, lc::Layout* L)
     const uint64_t B = 1ull << info->log2_block;
     if (info->n && (info->max_nseg == 0 || info->max_nseg > B)) return LC_EINVAL;
     if (info->blob_bytes < L->off_seg) return LC_EINVAL;
-    if (info->n && (info->max_seg_bytes < 48 || info->max_seg_bytes > lc::align16(2 * B) + 2 * lc::align16(8 * B) ||
+    if (info->n && (info->max_seg_bytes < 48 ||
+                    info->max_seg_bytes > lc::align16(2 * B) + 2 * lc::align16(8 * B) + lc::align16(L->fb * B) ||
                     info->max_seg_bytes % 16))
         return LC_EINVAL;
     L->max_nseg = info->max_nseg;
@@ -230,6 +236,7 @@ LC_API lc_status lc_compress(const void* d_keys, uint64_t n, const lc_params* p,
         W.seg_start = reinterpret_cast<uint16_t*>(ws + w.start);
         W.seg_delta = reinterpret_cast<uint64_t*>(ws + w.delta);
         W.seg_A = reinterpret_cast<uint64_t*>(ws + w.slope);
+        W.seg_frac = L.flags ? reinterpret_cast<uint32_t*>(ws + w.frac) : nullptr;
     }
     hipError_t e = lc::launch_compress(d_keys, L, p->fit, static_cast<uint8_t*>(d_blob), W, d_blob_bytes, d_flags,
                                        static_cast<hipStream_t>(stream));
@@ -247,6 +254,8 @@ LC_API lc_status lc_info(const void* h_header, uint64_t header_bytes, lc_blob_in
     I.log2_block = h[7];
     I.frac_bits = h[8];
     I.width = h[9];
+    I.flags = h[10];
+    if (h[11] != 0) return LC_EFORMAT;
     I.eps = (uint32_t)rd(h + 12, 4);
     I.n = rd(h + 16, 8);
     I.nblocks = rd(h + 24, 8);

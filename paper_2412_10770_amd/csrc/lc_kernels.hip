@@ -970,6 +970,214 @@ __global__ __launch_bounds__(kMinLanes) void fit_min_kernel(const void* __restri
     }
 }
 
+// ---------------------------------------------------------------------------
+// Optimal fit (LC_FIT_OPT): fixed-point lines with a free intercept, the
+// class of the optimal eps-PLA of Sec. II-A.  Segment [s, e) holds a line
+// floor((C + A d) / 2^F) with integers A >= 0 and C >= first * 2^F exactly
+// when every pair i < j of its keys has
+//   ceil((Lo_j - Up_i) / (j - i)) <= A <= floor((Up_j - Lo_i) / (j - i)),
+//   Lo_i = (K[i] - eps) 2^F (Lo_s raised to max(K[s] - eps, first) 2^F),
+//   Up_i = (K[i] + eps + 1) 2^F - 1,
+// and K[e-1] - K[s] + 2 eps + 1 < 2^(64 - F) (the cap: A d + (C mod 2^F)
+// stays below 2^64).  Key e adds the pairs (i, e).  The largest new lower
+// bound is the steepest line from (e, Lo_e) back to a point (i, Up_i); it
+// touches the lower convex hull of those points (all of them lie on or above
+// it), and the smallest new upper bound touches the upper hull of the points
+// (i, Lo_i) -- O'Rourke's observation.  So each key scans the vertices of two
+// hulls of (i, K[i]) (the upper one with the raised start), one vertex per
+// lane and a wave max / min, instead of every earlier key.  The hulls are
+// kept in LDS as index stacks; their updates are wave-uniform, with exact
+// 128-bit cross products.  A sub-segment of a feasible segment is feasible
+// (the intercept moved to a later start only grows, as A >= 0), so growing
+// each segment as far as it goes gives the fewest segments.  Stored: A =
+// floor((lo + hi) / 2) of the final slope interval (0 for one key), C = the
+// midpoint of that A's feasible intercepts, anchor delta = floor(C / 2^F) -
+// first (mod 2^64), fraction = C mod 2^F.  One wave per block, sequential
+// over the block's keys.
+// LDS: keys KT[B] | slab u32[res_stride / 4 + 4] | lower hull u16[B] | upper hull u16[B].
+template <int KB>
+__global__ __launch_bounds__(64) void fit_opt_kernel(const void* __restrict__ keys, Layout L,
+                                                     uint8_t* __restrict__ blob, Workspace ws,
+                                                     uint32_t* __restrict__ flags, uint64_t blk0)
+{
+    using KT = typename std::conditional<KB == 4, uint32_t, uint64_t>::type;
+    using u128 = unsigned __int128;
+    using i128 = __int128;
+    extern __shared__ __align__(16) uint8_t smem[];
+    const uint32_t B = 1u << L.log2b;
+    const uint32_t lane = threadIdx.x;
+    const uint64_t b = blk0 + blockIdx.x;  // the launcher keeps b < nblocks
+    const uint64_t base = b << L.log2b;
+    const uint32_t nb = (L.n - base) < B ? (uint32_t)(L.n - base) : B;  // >= 1
+    const KT* Kg = reinterpret_cast<const KT*>(keys) + base;
+
+    KT* sk = reinterpret_cast<KT*>(smem);
+    uint32_t* s_slab = reinterpret_cast<uint32_t*>(smem + KB * B);
+    const uint32_t slab_words = (uint32_t)(L.res_stride / 4);
+    uint16_t* hU = reinterpret_cast<uint16_t*>(smem + KB * B + L.res_stride + 16);  // lower hull
+    uint16_t* hL = hU + B;                                                          // upper hull
+
+    bool unsorted = false;
+    for (uint32_t j = lane; j < nb; j += 64) {
+        const KT k = Kg[j];
+        const KT prev = j ? Kg[j - 1] : (b ? Kg[-1] : KT(0));
+        unsorted |= k < prev;
+        sk[j] = k;
+    }
+    for (uint32_t i = lane; i < slab_words + 4; i += 64) s_slab[i] = 0;
+    if (__ballot(unsorted) != 0 && lane == 0) atomicOr(flags, kFlagUnsorted);
+    __syncthreads();
+
+    const uint64_t eps = L.eps, two_e1 = 2 * eps + 1;
+    const uint32_t F = L.F, w = L.w;
+    const uint64_t wmask = (1ull << w) - 1;
+    const uint64_t fmask = (1ull << F) - 1;
+    // key e joins only while K[e] - K[s] < lim, i.e. K[e] - K[s] + 2 eps + 1 < 2^(64 - F)
+    const uint64_t lim = F == 0 ? ~0ull - 2 * eps : (1ull << (64 - F)) - two_e1;
+    const uint64_t first = (uint64_t)sk[0];
+    const uint64_t span = (uint64_t)sk[nb - 1] - first;
+    // every numerator below is at most (span + 2 eps + 1) 2^F
+    const bool fast = span < (1ull << 50) && fast_division_ok(span, 2 * eps, F);
+
+    uint32_t nseg = 0;
+    uint64_t maxA = 0, maxd = 0;
+    uint32_t s = 0;
+    while (s < nb) {
+        const uint64_t Ks = (uint64_t)sk[s];
+        // the raised start: Lo_s = (K[s] - eps + r) 2^F with r = max(0, first - (K[s] - eps))
+        const uint64_t r = Ks - first >= eps ? 0 : eps - (Ks - first);
+        // y of hull point i relative to K[s] (the raise only on the upper hull's start)
+        auto yU = [&](uint32_t i) -> uint64_t { return (uint64_t)sk[i] - Ks; };
+        auto yL = [&](uint32_t i) -> uint64_t { return i == s ? r : (uint64_t)sk[i] - Ks; };
+        uint32_t nU = 1, nL = 1;
+        if (lane == 0) {
+            hU[0] = (uint16_t)s;
+            hL[0] = (uint16_t)s;
+        }
+        __syncthreads();
+        uint64_t lo = 0, hi = ~0ull;
+        uint32_t e = s + 1;
+        for (; e < nb; e++) {
+            const uint64_t Ke = (uint64_t)sk[e];
+            if (Ke - Ks >= lim) break;
+            uint64_t cl = 0, ch = ~0ull;
+            for (uint32_t v = lane; v < nU; v += 64) {
+                // ceil(((K[e] - K[i] - 2 eps - 1) 2^F + 1) / m), positive only when K[e] - K[i] > 2 eps
+                const uint32_t i = hU[v];
+                const uint64_t Di = Ke - (uint64_t)sk[i];
+                if (Di >= two_e1) {
+                    const uint32_t m = e - i;
+                    const uint64_t q = div_pick(fast, (Di - two_e1) << F, m, recip(m)) + 1;
+                    cl = q > cl ? q : cl;
+                }
+            }
+            for (uint32_t v = lane; v < nL; v += 64) {
+                // floor(((K[e] + eps + 1 - Lo_j / 2^F) 2^F - 1) / m)
+                const uint32_t j = hL[v];
+                const uint32_t m = e - j;
+                const uint64_t Y = (Ke - (uint64_t)sk[j]) + two_e1 - (j == s ? r : 0);
+                const uint64_t q = div_pick(fast, (Y << F) - 1, m, recip(m));
+                ch = q < ch ? q : ch;
+            }
+            cl = wave_max64(cl);
+            ch = wave_min64(ch);
+            const uint64_t nlo = cl > lo ? cl : lo, nhi = ch < hi ? ch : hi;
+            if (nlo > nhi) break;
+            lo = nlo;
+            hi = nhi;
+            // push e on both hulls; a vertex h1 after h2 stays when it lies
+            // strictly below (lower hull) / above (upper hull) the line h2 -> e:
+            //   (y1 - y2)(e - h2) vs (ye - y2)(h1 - h2), rearranged so every
+            //   term is non-negative: y1 (e - h2) + y2 (h1 - h2) vs ye (h1 - h2) + y2 (e - h2)
+            const uint64_t ye_u = Ke - Ks, ye_l = Ke - Ks;
+            while (nU >= 2) {
+                const uint32_t h1 = hU[nU - 1], h2 = hU[nU - 2];
+                const u128 lhs = (u128)yU(h1) * (e - h2) + (u128)yU(h2) * (h1 - h2);
+                const u128 rhs = (u128)ye_u * (h1 - h2) + (u128)yU(h2) * (e - h2);
+                if (lhs < rhs) break;
+                nU--;
+            }
+            while (nL >= 2) {
+                const uint32_t h1 = hL[nL - 1], h2 = hL[nL - 2];
+                const u128 lhs = (u128)yL(h1) * (e - h2) + (u128)yL(h2) * (h1 - h2);
+                const u128 rhs = (u128)ye_l * (h1 - h2) + (u128)yL(h2) * (e - h2);
+                if (lhs > rhs) break;
+                nL--;
+            }
+            __syncthreads();  // every lane has read the hulls before lane 0 writes
+            if (lane == 0) {
+                hU[nU] = (uint16_t)e;
+                hL[nL] = (uint16_t)e;
+            }
+            nU++;
+            nL++;
+            __syncthreads();
+        }
+        // slope, then the intercept interval [g, h] of that slope, relative to
+        // Lo_s = (K[s] - eps + r) 2^F: g' = max(0, max_j (y_j - r) 2^F - A d_j),
+        // h' = min_j (y_j + 2 eps + 1 - r) 2^F - 1 - A d_j  (>= g' >= 0)
+        const uint64_t A = e > s + 1 ? lo + (hi - lo) / 2 : 0;
+        uint64_t gp = 0, hp = ~0ull;
+        for (uint32_t j = s + lane; j < e; j += 64) {
+            const uint64_t y = (uint64_t)sk[j] - Ks;
+            const i128 Ad = (i128)((u128)A * (j - s));
+            const i128 scale = (i128)1 << F;  // multiply: y - r may be negative
+            const i128 g = j == s ? (i128)0 : ((i128)y - (i128)r) * scale - Ad;
+            const i128 h = ((i128)y + (i128)two_e1 - (i128)r) * scale - 1 - Ad;
+            const uint64_t gu = g > 0 ? (uint64_t)g : 0;
+            const uint64_t hu = h > 0 ? (uint64_t)h : 0;
+            gp = gu > gp ? gu : gp;
+            hp = hu < hp ? hu : hp;
+        }
+        gp = wave_max64(gp);
+        hp = wave_min64(hp);
+        const uint64_t Cp = gp + (hp - gp) / 2;
+        const uint64_t c_hi = (Ks - eps + r) + (Cp >> F);  // floor(C / 2^F), modulo 2^64
+        const uint64_t frac = Cp & fmask;
+        const uint64_t delta = c_hi - first;
+        if (lane == 0) {
+            ws.seg_start[base + nseg] = (uint16_t)s;
+            ws.seg_delta[base + nseg] = delta;
+            ws.seg_A[base + nseg] = A;
+            ws.seg_frac[base + nseg] = (uint32_t)frac;
+        }
+        if (w != 0) {
+            for (uint32_t j = s + lane; j < e; j += 64) {
+                const uint64_t pred = c_hi + ((A * (uint64_t)(j - s) + frac) >> F);
+                const uint64_t code = ((uint64_t)sk[j] - pred + eps) & wmask;
+                const uint32_t bitpos = j * w;
+                const uint32_t wd = bitpos >> 5, sh = bitpos & 31;
+                const uint64_t v = code << sh;
+                atomicOr(&s_slab[wd], (uint32_t)v);
+                if (sh + w > 32) atomicOr(&s_slab[wd + 1], (uint32_t)(v >> 32));
+            }
+        }
+        maxA = A > maxA ? A : maxA;
+        maxd = delta > maxd ? delta : maxd;
+        nseg++;
+        s = e;
+        __syncthreads();  // the hull stacks are reset for the next segment
+    }
+    __syncthreads();
+
+    uint4* dst = reinterpret_cast<uint4*>(blob + L.off_res + b * L.res_stride);
+    const uint4* src4 = reinterpret_cast<const uint4*>(s_slab);
+    for (uint32_t c = lane; c < slab_words / 4; c += 64) dst[c] = src4[c];
+    if (lane == 0) {
+        store_key<KB>(blob + L.off_first, b, first);
+        const uint32_t ab = byte_width(maxd), sb = byte_width(maxA);
+        BlockInfo bi;
+        bi.nseg = nseg;
+        bi.seg_bytes = (uint32_t)(a16(2ull * nseg) + a16((uint64_t)ab * nseg) + a16((uint64_t)sb * nseg) +
+                                  a16((uint64_t)L.fb * nseg));
+        bi.nkeys = nb;
+        bi.ab = (uint8_t)ab;
+        bi.sb = (uint8_t)sb;
+        bi.pad = 0;
+        ws.blk[b] = bi;
+    }
+}
+
 // Sums over tiles of kTileBlocks blocks.
 __global__ __launch_bounds__(256) void tile_reduce_kernel(Workspace ws, uint64_t nblocks, uint64_t tile0)
 {
@@ -1016,7 +1224,7 @@ __device__ __forceinline__ void write_header(uint8_t* __restrict__ blob, const L
     for (int k = 0; k < 32; k++) h[k] = 0;
     h[0] = kMagic;
     h[1] = kVersion | (L.kb << 16) | (L.log2b << 24);
-    h[2] = L.F | (L.w << 8);
+    h[2] = L.F | (L.w << 8) | (L.flags << 16);
     h[3] = L.eps;
     h[4] = (uint32_t)L.n;            h[5] = (uint32_t)(L.n >> 32);
     h[6] = (uint32_t)L.nblocks;      h[7] = (uint32_t)(L.nblocks >> 32);
@@ -1126,7 +1334,8 @@ __device__ __forceinline__ bool dir_ok(const uint4& dv, const Layout& L, uint64_
     const uint32_t nseg = dv.z, nkeys = (dv.w & 0xFFFF) + 1;
     const uint32_t ab = (dv.w >> 16) & 0xFF, sb = dv.w >> 24;
     const bool widths = ab && sb && ab <= 8 && sb <= 8 && !(ab & (ab - 1)) && !(sb & (sb - 1));
-    const uint64_t area = a16(2ull * nseg) + a16((uint64_t)ab * nseg) + a16((uint64_t)sb * nseg);
+    const uint64_t area =
+        a16(2ull * nseg) + a16((uint64_t)ab * nseg) + a16((uint64_t)sb * nseg) + a16((uint64_t)L.fb * nseg);
     return nkeys == want && nseg >= 1 && nseg <= nkeys && widths && (seg_off & 15) == 0 && seg_off >= L.off_seg &&
            seg_off <= bytes && area <= bytes - seg_off;
 }
@@ -1153,6 +1362,11 @@ __device__ __forceinline__ void emit_block(const Workspace& ws, const Layout& L,
     for (uint32_t c = lane; c < c_anchor; c += G) out[c] = pack_chunk(ws.seg_delta + rec, n, c, ab);
     out += c_anchor;
     for (uint32_t c = lane; c < c_slope; c += G) out[c] = pack_chunk(ws.seg_A + rec, n, c, sb);
+    if (L.fb) {  // intercept fractions of the optimal fit
+        out += c_slope;
+        const uint32_t c_frac = (uint32_t)(a16((uint64_t)L.fb * n) / 16);
+        for (uint32_t c = lane; c < c_frac; c += G) out[c] = pack_chunk(ws.seg_frac + rec, n, c, L.fb);
+    }
 }
 
 // Segment areas: kEmitLanes lanes per block, 256 / kEmitLanes blocks per
@@ -1640,7 +1854,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // Per-block decode context.
 struct BlockCtx {
     uint64_t first, eps, obase;
-    uint32_t F, w, ab, sb, jlo, jhi;
+    uint32_t F, w, ab, sb, fb, jlo, jhi;
     uint32_t tmax;  // last segment index of the block
     const uint32_t* s_slab;
     const uint32_t* s_bm;
@@ -1666,11 +1880,13 @@ __device__ __forceinline__ uint64_t slope_term(uint64_t A, uint32_t d, uint32_t 
 }
 
 // Decodes keys [jlo, jhi) of one block whose model arrays (u16 start[],
-// anchor-first_key[] of AB bytes, A[] of SB bytes) are read through
-// `start`, `an`, `sl` -- LDS copies for staged blocks, the blob otherwise.
-// AB / SB are the block's byte widths (0: read at the runtime widths).
-template <int KB, bool RANGE, bool CLAMP, uint32_t AB, uint32_t SB, typename P16, typename P8>
-__device__ __forceinline__ void decode_keys(const BlockCtx& c, P16 start, P8 an, P8 sl, void* __restrict__ out)
+// anchor-first_key[] of AB bytes, A[] of SB bytes, and with FRAC the
+// intercept fractions of c.fb bytes) are read through `start`, `an`, `sl`,
+// `fr` -- LDS copies for staged blocks, the blob otherwise.  AB / SB are the
+// block's byte widths (0: read at the runtime widths).
+template <int KB, bool RANGE, bool CLAMP, uint32_t AB, uint32_t SB, bool FRAC, typename P16, typename P8>
+__device__ __forceinline__ void decode_keys(const BlockCtx& c, P16 start, P8 an, P8 sl, P8 fr,
+                                            void* __restrict__ out)
 {
     constexpr uint32_t V = 16 / KB;
     const uint32_t lane = lane_id();
@@ -1689,7 +1905,11 @@ __device__ __forceinline__ void decode_keys(const BlockCtx& c, P16 start, P8 an,
         // arrays when those live in global memory
         if constexpr (CLAMP) t = t < c.tmax ? t : c.tmax;
         const uint32_t d = j - start[t];
-        const uint64_t pred = c.first + anchor_of(t) + slope_term<SB == 0 ? 8 : SB>(slope_of(t), d, c.F);
+        uint64_t pred;
+        if constexpr (FRAC)  // A d + frac < 2^64 (the optimal fit's cap)
+            pred = c.first + anchor_of(t) + ((slope_of(t) * d + load_w(fr, t, c.fb)) >> c.F);
+        else
+            pred = c.first + anchor_of(t) + slope_term<SB == 0 ? 8 : SB>(slope_of(t), d, c.F);
         const uint32_t bitpos = j * c.w;
         const uint32_t wd = bitpos >> 5, sh = bitpos & 31;
         const uint64_t win = (uint64_t)c.s_slab[wd] | ((uint64_t)c.s_slab[wd + 1] << 32);
@@ -1739,19 +1959,23 @@ __device__ __forceinline__ void decode_keys(const BlockCtx& c, P16 start, P8 an,
 // per-key loop has no width branches.
 template <int KB, bool RANGE, bool CLAMP>
 __device__ __forceinline__ void decode_staged(const BlockCtx& c, const uint8_t* s_raw, uint32_t off_an,
-                                              uint32_t off_sl, void* __restrict__ out)
+                                              uint32_t off_sl, uint32_t off_fr, void* __restrict__ out)
 {
     const uint16_t* st = reinterpret_cast<const uint16_t*>(s_raw);
     const uint8_t* an = s_raw + off_an;
     const uint8_t* sl = s_raw + off_sl;
+    if (c.fb) {  // blobs of the optimal fit: runtime widths
+        decode_keys<KB, RANGE, CLAMP, 0, 0, true>(c, st, an, sl, s_raw + off_fr, out);
+        return;
+    }
 #define LC_DECODE_CASE(A_, S_) \
-    case (A_) * 16 + (S_): decode_keys<KB, RANGE, CLAMP, A_, S_>(c, st, an, sl, out); return;
+    case (A_) * 16 + (S_): decode_keys<KB, RANGE, CLAMP, A_, S_, false>(c, st, an, sl, sl, out); return;
     switch (c.ab * 16 + c.sb) {
         LC_DECODE_CASE(1, 1) LC_DECODE_CASE(1, 2) LC_DECODE_CASE(1, 4) LC_DECODE_CASE(1, 8)
         LC_DECODE_CASE(2, 1) LC_DECODE_CASE(2, 2) LC_DECODE_CASE(2, 4) LC_DECODE_CASE(2, 8)
         LC_DECODE_CASE(4, 1) LC_DECODE_CASE(4, 2) LC_DECODE_CASE(4, 4) LC_DECODE_CASE(4, 8)
         LC_DECODE_CASE(8, 1) LC_DECODE_CASE(8, 2) LC_DECODE_CASE(8, 4) LC_DECODE_CASE(8, 8)
-        default: decode_keys<KB, RANGE, CLAMP, 0, 0>(c, st, an, sl, out); return;
+        default: decode_keys<KB, RANGE, CLAMP, 0, 0, false>(c, st, an, sl, sl, out); return;
     }
 #undef LC_DECODE_CASE
 }
@@ -1824,7 +2048,8 @@ __device__ __forceinline__ void decode_block(const uint8_t* __restrict__ blob, c
     const uint64_t first = load_key<KB>(blob + L.off_first, b);
     const uint32_t off_an = (uint32_t)a16(2ull * nseg);
     const uint32_t off_sl = off_an + (uint32_t)a16((uint64_t)ab * nseg);
-    const uint32_t seg_bytes = off_sl + (uint32_t)a16((uint64_t)sb * nseg);
+    const uint32_t off_fr = off_sl + (uint32_t)a16((uint64_t)sb * nseg);
+    const uint32_t seg_bytes = off_fr + (uint32_t)a16((uint64_t)L.fb * nseg);
     if (!dir_ok(dv, L, b, a.bytes)) {  // corrupt blob: skip the block
         if (a.flags && lane == 0) atomicOr(a.flags, kFlagBadList);
         return;
@@ -1868,6 +2093,7 @@ __device__ __forceinline__ void decode_block(const uint8_t* __restrict__ blob, c
     c.w = APPROX ? 0 : L.w;
     c.ab = ab;
     c.sb = sb;
+    c.fb = L.fb;
     c.s_slab = s_slab;
     c.s_bm = s_bm;
     c.s_pre = s_pre;
@@ -1902,11 +2128,11 @@ __device__ __forceinline__ void decode_block(const uint8_t* __restrict__ blob, c
     };
     if (!staged) {  // model arrays read from the blob (cached), keys decoded as for staged blocks
         build_bitmap(reinterpret_cast<const uint16_t*>(g_seg));
-        decode_staged<KB, RANGE, true>(c, g_seg, off_an, off_sl, out);
+        decode_staged<KB, RANGE, true>(c, g_seg, off_an, off_sl, off_fr, out);
         return;
     }
     build_bitmap(reinterpret_cast<const uint16_t*>(s_raw));
-    decode_staged<KB, RANGE, false>(c, s_raw, off_an, off_sl, out);
+    decode_staged<KB, RANGE, false>(c, s_raw, off_an, off_sl, off_fr, out);
 }
 
 // One wave per block.  Workgroup w runs on XCD w % 8, so blocks are
@@ -1932,7 +2158,7 @@ __global__ __launch_bounds__(256) void touch_blocks_kernel(const uint8_t* __rest
     const uint4 d0 = dir[b_lo], d1 = dir[b_hi];
     uint64_t lo = d0.x | ((uint64_t)d0.y << 32);
     uint64_t hi = (d1.x | ((uint64_t)d1.y << 32)) + a16(2ull * d1.z) + a16((uint64_t)((d1.w >> 16) & 0xFF) * d1.z) +
-                  a16((uint64_t)(d1.w >> 24) * d1.z);
+                  a16((uint64_t)(d1.w >> 24) * d1.z) + a16((uint64_t)L.fb * d1.z);
     if (!(lo >= L.off_seg && lo <= hi && hi <= L.blob_bytes)) lo = hi = L.off_seg;
     const uint64_t dlo = (L.off_dir + 16 * b_lo) / 16, dn = b_hi + 1 - b_lo;
     const uint64_t slo = lo / 16, sn = (hi - lo) / 16;
@@ -1992,14 +2218,18 @@ __device__ __forceinline__ uint64_t access_one(const uint8_t* __restrict__ blob,
     const uint8_t* sl = an + a16((uint64_t)v.ab * v.nseg);
     const uint64_t anchor = load_key<KB>(blob + L.off_first, b) + load_w(an, t, v.ab);
     const uint64_t A = load_w(sl, t, v.sb);
-    const uint64_t pred = anchor + ((A * (uint64_t)(j - st[t])) >> L.F);
+    // the intercept fraction (optimal fit; A d + frac < 2^64 by its cap)
+    const uint64_t frac = L.fb ? load_w(sl + a16((uint64_t)v.sb * v.nseg), t, L.fb) : 0;
+    const uint64_t pred = anchor + ((A * (uint64_t)(j - st[t]) + frac) >> L.F);
     if constexpr (APPROX) return pred;  // f(i), within eps of K[i]
     return pred + code_at(blob, L, b, j) - L.eps;
 }
 
 // First i with K[i] >= x (L.n if none): binary search over first_keys, then
 // over the block's segment anchors (segment pruning), then over the decoded
-// keys of one segment.
+// keys of one segment.  An anchor is its segment's first key, except in
+// blobs of the optimal fit (kFlagFrac), whose anchors are intercepts within
+// eps of it: there the segment search decodes each probed first key.
 template <int KB>
 __device__ __forceinline__ uint64_t lower_bound_one(const uint8_t* __restrict__ blob, const Layout& L, uint64_t x)
 {
@@ -2014,21 +2244,33 @@ __device__ __forceinline__ uint64_t lower_bound_one(const uint8_t* __restrict__ 
     const uint8_t* an = blob + v.seg_off + a16(2ull * v.nseg);
     const uint8_t* sl = an + a16((uint64_t)v.ab * v.nseg);
     const uint64_t first = load_key<KB>(fk, b);
-    // last segment whose anchor (its first key) is < x (binary search: on
-    // heavy-tailed key distributions the anchors of sparse blocks are too
-    // uneven for a proportional guess to pay off)
+    const bool free_icpt = (L.flags & kFlagFrac) != 0;
+    // first key of segment u: its anchor, or with free intercepts anchor +
+    // code - eps (the fraction adds floor(frac / 2^F) = 0 at d = 0)
+    auto seg_first = [&](uint32_t u) -> uint64_t {
+        uint64_t k = first + load_w(an, u, v.ab);
+        if (free_icpt) {
+            k += code_at(blob, L, b, st[u]) - L.eps;
+            if constexpr (KB == 4) k &= 0xFFFFFFFFull;
+        }
+        return k;
+    };
+    // last segment whose first key is < x (binary search: on heavy-tailed
+    // key distributions the anchors of sparse blocks are too uneven for a
+    // proportional guess to pay off)
     uint32_t t = 0;
     for (uint32_t step = pow2_floor(v.nseg); step; step >>= 1)
-        if (t + step < v.nseg && first + load_w(an, t + step, v.ab) < x) t += step;
+        if (t + step < v.nseg && seg_first(t + step) < x) t += step;
     const uint32_t s = st[t];
     const uint32_t e = t + 1 < v.nseg ? st[t + 1] : v.nkeys;
     const uint64_t anchor = first + load_w(an, t, v.ab);
     const uint64_t A = load_w(sl, t, v.sb);
+    const uint64_t frac = L.fb ? load_w(sl + a16((uint64_t)v.sb * v.nseg), t, L.fb) : 0;
     // keys s+1 .. e-1 of the segment: first one >= x, else e
     uint32_t lo = s + 1, hi = e;
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
-        uint64_t k = anchor + ((A * (uint64_t)(mid - s)) >> L.F) + code_at(blob, L, b, mid) - L.eps;
+        uint64_t k = anchor + ((A * (uint64_t)(mid - s) + frac) >> L.F) + code_at(blob, L, b, mid) - L.eps;
         if constexpr (KB == 4) k &= 0xFFFFFFFFull;
         if (k >= x) hi = mid;
         else lo = mid + 1;
@@ -2326,6 +2568,8 @@ __device__ __forceinline__ Layout list_layout(const BatchArgs& a, uint64_t n, ui
     L.max_nseg = 0;
     L.max_seg_bytes = 0;
     L.blob_bytes = 0;
+    L.flags = 0;  // batches use the greedy fit: no intercept fractions
+    L.fb = 0;
     return L;
 }
 
@@ -2935,7 +3179,17 @@ hipError_t launch_batch_and(const uint8_t* d_blob, const lc_batch_list* d_lists,
 hipError_t launch_compress(const void* d_keys, const Layout& L, uint32_t fit, uint8_t* d_blob, const Workspace& ws,
                            uint64_t* d_blob_bytes, uint32_t* d_flags, hipStream_t stream)
 {
-    if (L.nblocks && fit == LC_FIT_MIN) {
+    if (L.nblocks && fit == LC_FIT_OPT) {
+        const uint64_t B = 1ull << L.log2b;
+        const size_t lds = L.kb * B + L.res_stride + 16 + 4 * B;
+        auto k = L.kb == 4 ? fit_opt_kernel<4> : fit_opt_kernel<8>;
+        const hipError_t e = allow_lds((const void*)k, lds);
+        if (e != hipSuccess) return e;
+        for (uint64_t b0 = 0; b0 < L.nblocks; b0 += kMaxGrid) {
+            const uint64_t nw = L.nblocks - b0 < kMaxGrid ? L.nblocks - b0 : kMaxGrid;
+            hipLaunchKernelGGL(k, dim3((uint32_t)nw), dim3(64), lds, stream, d_keys, L, d_blob, ws, d_flags, b0);
+        }
+    } else if (L.nblocks && fit == LC_FIT_MIN) {
         const uint64_t B = 1ull << L.log2b;
         const size_t lds = 16 + L.kb * B + L.res_stride + 16 + align16(2 * B) + align16(2 * (B + 1));
         auto k = L.kb == 4 ? fit_min_kernel<4> : fit_min_kernel<8>;

@@ -14,7 +14,17 @@ struct Layout {
     uint64_t n, nblocks;
     uint64_t off_first, off_dir, off_res, res_stride, off_seg, blob_bytes;
     uint32_t kb, log2b, F, w, eps, max_nseg, max_seg_bytes;
+    uint32_t flags;  // header flags: kFlagFrac for the free-intercept (optimal) fit
+    uint32_t fb;     // intercept-fraction bytes per segment (0 without kFlagFrac or at F = 0)
 };
+
+// Header flag of blobs whose segments carry a free fixed-point intercept
+// (the optimal fit): the anchor delta is floor(C / 2^F) - first key (mod
+// 2^64) and a fraction array C mod 2^F follows the slopes.
+constexpr uint32_t kFlagFrac = 1;
+
+// Bytes of one intercept fraction (F bits).
+inline __host__ __device__ uint32_t frac_bytes(uint32_t F) { return F == 0 ? 0u : F <= 8 ? 1u : F <= 16 ? 2u : 4u; }
 
 // Per-block result of the fit kernel, read by the scan and emit kernels.
 struct BlockInfo {
@@ -38,6 +48,7 @@ struct Workspace {
     uint16_t* seg_start;  // [nblocks * B]: segment starts, block-major
     uint64_t* seg_delta;  // [nblocks * B]: anchor - first key of the block
     uint64_t* seg_A;      // [nblocks * B]: fixed-point slopes
+    uint32_t* seg_frac;   // [nblocks * B]: intercept fractions (optimal fit only, else null)
 };
 
 constexpr uint32_t kTileBlocks = 256;

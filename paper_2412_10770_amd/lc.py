@@ -52,7 +52,7 @@ class lc_params(ctypes.Structure):
 class lc_blob_info(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint32) for f in
                 ("key_bytes", "log2_block", "frac_bits", "width", "eps", "max_nseg", "max_seg_bytes",
-                 "reserved")] + \
+                 "flags")] + \
                [(f, ctypes.c_uint64) for f in
                 ("n", "nblocks", "nseg_total", "off_first", "off_dir", "off_res", "res_stride",
                  "off_seg", "blob_bytes")]
@@ -173,7 +173,7 @@ def key_dtype(key_bytes: int) -> torch.dtype:
     return torch.int32 if key_bytes == 4 else torch.int64
 
 
-FITS = {"greedy": 0, "min": 1}   # LC_FIT_GREEDY, LC_FIT_MIN
+FITS = {"greedy": 0, "min": 1, "opt": 2}   # LC_FIT_GREEDY, LC_FIT_MIN, LC_FIT_OPT
 
 
 def _fit(fit) -> int:
@@ -190,10 +190,11 @@ def params(key_bytes: int, eps: int, log2_block: int = DEFAULT_LOG2_BLOCK,
 
 
 def compress_bound(n: int, key_bytes: int, eps: int, log2_block: int = DEFAULT_LOG2_BLOCK,
-                   frac_bits: int = DEFAULT_FRAC_BITS):
-    """(blob_max, ws_bytes): worst-case blob size and workspace size."""
+                   frac_bits: int = DEFAULT_FRAC_BITS, fit="greedy"):
+    """(blob_max, ws_bytes): worst-case blob size and workspace size (the
+    optimal fit needs room for its intercept fractions)."""
     blob_max, ws = ctypes.c_uint64(), ctypes.c_uint64()
-    p = params(key_bytes, eps, log2_block, frac_bits)
+    p = params(key_bytes, eps, log2_block, frac_bits, fit)
     _check(lib.lc_compress_bound(n, ctypes.byref(p), ctypes.byref(blob_max), ctypes.byref(ws)),
            "lc_compress_bound")
     return blob_max.value, ws.value
@@ -247,7 +248,9 @@ def compress_async(keys: torch.Tensor, eps: int, blob: torch.Tensor, workspace: 
                    blob_bytes: torch.Tensor, flags: torch.Tensor, log2_block: int = DEFAULT_LOG2_BLOCK,
                    frac_bits: int = DEFAULT_FRAC_BITS, stream=None, fit="greedy"):
     """Enqueue lc_compress into caller-provided buffers; no synchronisation.
-    fit: "greedy" or "min" (fewest segments, same blob format)."""
+    fit: "greedy", "min" (fewest anchored segments) or "opt" (free
+    fixed-point intercept, fewest segments of that class; the blob carries
+    the intercept fractions)."""
     _dev(keys, "keys")
     kb = _key_bytes(keys)
     p = params(kb, eps, log2_block, frac_bits, fit)
@@ -261,10 +264,10 @@ def compress_async(keys: torch.Tensor, eps: int, blob: torch.Tensor, workspace: 
 def compress(keys: torch.Tensor, eps: int, log2_block: int = DEFAULT_LOG2_BLOCK,
              frac_bits: int = DEFAULT_FRAC_BITS, stream=None, fit="greedy") -> Blob:
     """Enc of Def. 1 on the GPU; synchronises to learn the blob size.
-    fit: "greedy" or "min" (fewest segments, same blob format)."""
+    fit: "greedy", "min" or "opt" (as compress_async)."""
     _dev(keys, "keys")
     kb = _key_bytes(keys)
-    blob_max, ws_bytes = compress_bound(keys.numel(), kb, eps, log2_block, frac_bits)
+    blob_max, ws_bytes = compress_bound(keys.numel(), kb, eps, log2_block, frac_bits, fit)
     dev = keys.device
     blob = torch.empty(blob_max, dtype=torch.uint8, device=dev)
     ws = torch.empty(max(ws_bytes, 16), dtype=torch.uint8, device=dev)

@@ -58,31 +58,42 @@ def test_compress_bound(lc):
         assert lc.lib.lc_compress_bound(10, ctypes.byref(p), ctypes.byref(a), ctypes.byref(b)) == lc.LC_EINVAL
     p = lc.params(8, 63)
     assert lc.lib.lc_compress_bound(2 ** 41, ctypes.byref(p), None, None) == lc.LC_EINVAL
-    # the fit field: greedy (0) and fewest segments (1) share sizes; anything else is rejected
+    # the fit field: greedy (0) and fewest segments (1) share sizes; the
+    # optimal fit (2) adds the intercept fractions (LC_FRAC_BYTES(F) per
+    # segment, and 4 bytes per key slot of workspace); anything else is rejected
     a, b = ctypes.c_uint64(), ctypes.c_uint64()
     assert lc.lib.lc_compress_bound(5000, ctypes.byref(lc.params(8, 63, fit="min")), ctypes.byref(a), ctypes.byref(b)) == 0
     assert (a.value, b.value) == lc.compress_bound(5000, 8, 63)
-    for fit in (2, 255):
+    g_blob, g_ws = lc.compress_bound(5000, 8, 63)
+    nblocks = -(-5000 // 1024)
+    for F, fb in ((0, 0), (8, 1), (16, 2), (20, 4), (32, 4)):
+        o_blob, o_ws = lc.compress_bound(5000, 8, 63, 10, F, fit="opt")
+        assert o_blob == lc.compress_bound(5000, 8, 63, 10, F)[0] + nblocks * fb * 1024
+        assert o_ws == g_ws + 4 * nblocks * 1024
+    for fit in (3, 255):
         p = lc.lc_params(8, 10, 20, fit, 63)
         assert lc.lib.lc_compress_bound(10, ctypes.byref(p), None, None) == lc.LC_EINVAL
     with pytest.raises(ValueError):
         lc.params(8, 63, fit="optimal")
+    assert lc.FITS["opt"] == 2
 
 
 def test_info_parses_oracle_headers(lc):
     rng = np.random.default_rng(3)
     for kb, eps, log2b, n in ((4, 63, 10, 5000), (8, 0, 6, 1), (8, 4095, 12, 9000), (4, 7, 8, 0)):
         keys = np.cumsum(rng.integers(0, 50, n)).astype(np.uint32 if kb == 4 else np.uint64)
-        blob = oracle.compress(keys, eps, log2b)
-        inf = lc.info(blob[:128])
-        h = oracle.header(blob)
-        for f in oracle.HEADER_FIELDS:
-            assert getattr(inf, f if f != "width" else "width") == h[f], f
+        for fit, F in (("greedy", 20), ("opt", 20), ("opt", 0), ("opt", 12)):
+            blob = oracle.compress(keys, eps, log2b, F, fit=fit)
+            inf = lc.info(blob[:128])
+            h = oracle.header(blob)
+            assert h["flags"] == (fit == "opt")
+            for f in oracle.HEADER_FIELDS:
+                assert getattr(inf, f) == h[f], (fit, F, f)
 
 
 def test_info_rejects_bad_headers(lc):
     blob = oracle.compress(np.arange(0, 3000, 2, dtype=np.uint64), 15, 9)
-    for off, val in ((0, 0), (4, 9), (6, 3), (7, 5), (9, 1), (24, 7), (56, 1)):
+    for off, val in ((0, 0), (4, 9), (6, 3), (7, 5), (9, 1), (10, 2), (11, 1), (24, 7), (56, 1)):
         bad = blob[:128].copy()
         bad[off] = val
         with pytest.raises(lc.LcError) as e:

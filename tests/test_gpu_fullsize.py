@@ -32,11 +32,12 @@ def a16(x):
     return (x + 15) // 16 * 16
 
 
-def check_fullsize(lc, keys: torch.Tensor, eps: int, n_access: int, n_lb: int, seed: int, fit: str = "greedy"):
+def check_fullsize(lc, keys: torch.Tensor, eps: int, n_access: int, n_lb: int, seed: int, fit: str = "greedy",
+                   frac_bits: int = 20):
     n = keys.numel()
     kb = keys.element_size()
-    _say(f"full-size case n={n} kb={kb} eps={eps} fit={fit}")
-    blob = lc.compress(keys, eps, fit=fit)  # log2_block 10, F 20: the benchmark's configuration
+    _say(f"full-size case n={n} kb={kb} eps={eps} fit={fit} F={frac_bits}")
+    blob = lc.compress(keys, eps, 10, frac_bits, fit=fit)  # log2_block 10 (F 20): the benchmark's configuration
     h = blob.info
     B = 1 << h.log2_block
     assert h.n == n and h.nblocks == (n + B - 1) // B
@@ -52,7 +53,8 @@ def check_fullsize(lc, keys: torch.Tensor, eps: int, n_access: int, n_lb: int, s
     nk = dirs[:, 12:14].copy().view(np.uint16).ravel().astype(np.int64) + 1
     ab = dirs[:, 14].astype(np.int64)
     sb = dirs[:, 15].astype(np.int64)
-    area = a16(2 * nseg) + a16(ab * nseg) + a16(sb * nseg)
+    fb = 0 if not h.flags or frac_bits == 0 else 1 if frac_bits <= 8 else 2 if frac_bits <= 16 else 4
+    area = a16(2 * nseg) + a16(ab * nseg) + a16(sb * nseg) + a16(fb * nseg)
     assert np.array_equal(seg_off, h.off_seg + np.concatenate([[0], np.cumsum(area)[:-1]]))
     assert h.blob_bytes == h.off_seg + int(area.sum()) == len(data)
     assert h.nseg_total == int(nseg.sum()) and h.max_nseg == int(nseg.max())
@@ -65,7 +67,7 @@ def check_fullsize(lc, keys: torch.Tensor, eps: int, n_access: int, n_lb: int, s
     picks |= {0, h.nblocks - 1, int(np.argmax(nseg)), int(np.argmax(area))}
     for b in sorted(picks):
         kk = host[b * B:(b + 1) * B]
-        one = oracle.compress(kk, eps, h.log2_block, fit=fit)
+        one = oracle.compress(kk, eps, h.log2_block, frac_bits, fit=fit)
         oh = oracle.header(one)
         od = one[oh["off_dir"]:oh["off_dir"] + 16]
         assert np.array_equal(od[8:16], dirs[b, 8:16]), b
@@ -117,6 +119,25 @@ def test_lognormal_100m_min_fit(lc, wl):
         g = lc.compress(keys, eps).info.nseg_total
         m = check_fullsize(lc, keys, eps, n_access=1_000_000, n_lb=1_000_000, seed=100 + eps, fit="min")
         assert m.info.nseg_total <= g
+
+
+def test_lognormal_100m_opt_fit(lc, wl):
+    """The optimal fit (free fixed-point intercepts) on the same 100M keys, at
+    F = 20 (4-byte fractions) and F = 0 (none): never more segments than the
+    fewest-segment anchored fit at F = 20, same checks."""
+    keys = wl.lognormal_distinct(100_000_000, device=DEV)
+    m = lc.compress(keys, 63, fit="min").info.nseg_total
+    for F in (20, 0):
+        o = check_fullsize(lc, keys, 63, n_access=1_000_000, n_lb=1_000_000, seed=300 + F, fit="opt", frac_bits=F)
+        assert o.info.flags == 1
+        if F == 20:
+            assert o.info.nseg_total <= m
+
+
+def test_heterogeneous_runs_200m_opt_fit(lc, wl):
+    """Dense runs: segments span whole blocks, so the hulls grow long."""
+    keys = wl.heterogeneous_runs(200_000_000, device=DEV)
+    check_fullsize(lc, keys, 63, n_access=1_000_000, n_lb=1_000_000, seed=5, fit="opt", frac_bits=0)
 
 
 def test_heterogeneous_runs_200m_min_fit(lc, wl):

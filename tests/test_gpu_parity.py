@@ -412,6 +412,121 @@ def test_min_fit_determinism_and_unsorted(lc):
         lc.compress(_to_dev(bad), 15, fit="min")
 
 
+# --- optimal fit (fit="opt"): free fixed-point intercept, fraction array ------
+
+def test_opt_fit_random_small_cases(lc):
+    rng = np.random.default_rng(61)
+    for keys, eps, log2b in P.random_cases(seed=61, count=40):
+        check_all(lc, keys, eps, log2b, rng, nq=300, fit="opt")
+
+
+@pytest.mark.parametrize("frac_bits", [0, 5, 12, 32])
+def test_opt_fit_other_frac_bits(lc, frac_bits):
+    """F = 0 (no fraction array), 1-, 2- and 4-byte fractions."""
+    rng = np.random.default_rng(70 + frac_bits)
+    for keys, eps, log2b in P.random_cases(seed=70 + frac_bits, count=10):
+        check_all(lc, keys, eps, log2b, rng, nq=200, frac_bits=frac_bits, fit="opt")
+
+
+def test_opt_fit_edge_lists(lc, wl):
+    rng = np.random.default_rng(14)
+    for name, keys in wl.edge_lists():
+        for eps in (0, 63, 2 ** 31 - 1):
+            for log2b in (6, 12):
+                check_all(lc, keys, eps, log2b, rng, nq=100, fit="opt")
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 1025, 4096 * 3 + 5])
+def test_opt_fit_block_edges(lc, n):
+    rng = np.random.default_rng(200 + n)
+    keys = np.cumsum(rng.integers(1, 65, n)).astype(np.uint64)
+    for log2b in (6, 10, 12):
+        check_all(lc, keys, 31, log2b, rng, nq=200, fit="opt")
+
+
+def test_opt_fit_lines_caps_and_top_of_range(lc):
+    """A fixed-point line with a fractional intercept (one segment per block
+    at eps 0), one long segment per block with large hulls, two-key segments
+    at the cap, equal keys, and keys at the top of the 64-bit range, where
+    intercepts pass 2^64 and are stored modulo 2^64."""
+    rng = np.random.default_rng(7)
+    line = np.array([(1000 * 256 + 77 + 700 * i) >> 8 for i in range(40_000)], np.uint64)
+    blob = check_all(lc, line, 0, 10, rng, nq=200, frac_bits=8, fit="opt")
+    assert blob.info.nseg_total == -(-len(line) // 1024)
+    dense = np.cumsum(rng.integers(0, 3, 3 * 4096 + 17)).astype(np.uint32)
+    check_all(lc, dense, 255, 12, rng, nq=200, fit="opt")
+    cap = np.cumsum(np.full(9000, 1 << 45, dtype=np.uint64))
+    check_all(lc, cap, 3, 12, rng, nq=200, fit="opt")
+    check_all(lc, np.full(10_000, 123, np.uint32), 5, 10, rng, nq=200, fit="opt")
+    top = np.uint64((1 << 64) - 1)
+    high = top - np.cumsum(rng.integers(0, 1 << 20, 5000).astype(np.uint64))[::-1]
+    for eps in (3, 1000):
+        for F in (0, 20):
+            check_all(lc, high, eps, 8, rng, nq=200, frac_bits=F, fit="opt")
+    low_high = np.concatenate([np.arange(0, 100, 3, dtype=np.uint64), high[-40:]])
+    check_all(lc, low_high, 7, 6, rng, nq=100, fit="opt")
+
+
+@pytest.mark.parametrize("frac_bits", [0, 20, 32])
+def test_opt_fit_short_and_long_segments_alternate(lc, frac_bits):
+    rng = np.random.default_rng(95 + frac_bits)
+    parts, pos = [], np.uint64(5)
+    cap_gap = np.uint64(1) << np.uint64(64 - frac_bits) if frac_bits else np.uint64(0)
+    for k in range(40):
+        if k % 2 == 0:
+            m, g = int(rng.integers(5, 400)), int(rng.integers(0, 50))
+            run = pos + np.uint64(g) * np.arange(m, dtype=np.uint64)
+        else:
+            m = int(rng.integers(3, 300))
+            gaps = rng.integers(1, 1 << 30, m).astype(np.uint64)
+            if frac_bits and k % 6 == 1:
+                gaps[rng.integers(0, m)] = cap_gap
+            run = pos + np.cumsum(gaps, dtype=np.uint64)
+        parts.append(run)
+        pos = run[-1] + np.uint64(1)
+        if pos > np.uint64(1) << np.uint64(62):
+            break
+    keys = np.concatenate(parts)
+    for eps in (0, 3, 100):
+        for log2b in (6, 10):
+            check_all(lc, keys, eps, log2b, rng, nq=200, frac_bits=frac_bits, fit="opt")
+
+
+def test_opt_fit_width_combinations(lc):
+    rng = np.random.default_rng(20)
+    for keys, eps, F in _width_combo_lists()[1::4]:
+        check_all(lc, keys, eps, 6, rng, nq=32, frac_bits=F, fit="opt")
+
+
+def test_opt_fit_configs_reduced(lc, wl):
+    """The benchmark recipes at sizes the oracle's optimal fit finishes in
+    seconds, at F = 20 and F = 0."""
+    rng = np.random.default_rng(4)
+    keys = wl.as_numpy(wl.uniform_gaps(1_000_000, device="cpu"))
+    for F in (0, 20):
+        check_all(lc, keys, 31, 10, rng, nq=20_000, frac_bits=F, fit="opt")
+    keys = wl.as_numpy(wl.lognormal_distinct(1_000_000, device="cpu"))
+    for eps in (15, 255):
+        check_all(lc, keys, eps, 10, rng, nq=20_000, fit="opt")
+    keys = wl.as_numpy(wl.heterogeneous_runs(300_000, device="cpu", run_lo=1e3, run_hi=1e5))
+    check_all(lc, keys, 63, 10, rng, nq=20_000, frac_bits=0, fit="opt")
+    keys = wl.as_numpy(wl.lognormal_gaps(1_000_000, device="cpu"))
+    check_all(lc, keys, 255, 10, rng, nq=20_000, fit="opt")
+
+
+def test_opt_fit_determinism_and_unsorted(lc):
+    rng = np.random.default_rng(3)
+    keys = np.cumsum(rng.integers(0, 1000, 300_000)).astype(np.uint64)
+    d = _to_dev(keys)
+    assert torch.equal(lc.compress(d, 63, fit="opt").data, lc.compress(d, 63, fit="opt").data)
+    m, o = lc.compress(d, 63, fit="min"), lc.compress(d, 63, fit="opt")
+    assert o.info.nseg_total <= m.info.nseg_total and o.info.flags == 1 and m.info.flags == 0
+    bad = keys[:5000].copy()
+    bad[2500] = bad[2499] - np.uint64(1)
+    with pytest.raises(lc.LcError):
+        lc.compress(_to_dev(bad), 15, fit="opt")
+
+
 # --- greedy fit with one block per lane: lists of at least 16384 blocks -------
 
 LANES_MIN_BLOCKS = 16384  # lc_compress switches to the lane-per-block fit from here

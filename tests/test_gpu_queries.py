@@ -123,3 +123,34 @@ def test_union_large(lc):
     A, B = lc.compress(_dev(a), 63), lc.compress(_dev(b), 255)
     assert np.array_equal(_host(lc.union(A, B), 8), oracle.union(a, b))
     assert np.array_equal(_host(lc.intersect(A, B), 8), oracle.intersect(a, b))
+
+
+@pytest.mark.parametrize("F", [0, 20])
+def test_queries_on_optimal_fit_blobs(lc, F):
+    """Quantiles, the model-only decode and list AND / OR on blobs of the
+    optimal fit (free intercepts, fraction arrays): the same answers as on
+    any blob, and the model-only decode equals the oracle's prediction."""
+    rng = np.random.default_rng(30 + F)
+    for keys, eps, log2b in P.random_cases(30 + F, 10):
+        keys = keys[:4000]
+        kb = keys.dtype.itemsize
+        n = len(keys)
+        _say(f"opt-fit queries n={n} kb={kb} eps={eps} log2b={log2b} F={F}")
+        blob = lc.compress(_dev(keys), eps, log2b, F, fit="opt")
+        f = oracle.predict(keys, eps, log2b, F, fit="opt")
+        assert np.array_equal(_host(lc.decompress_approx(blob), kb), f)
+        if n:
+            q = 7
+            k = torch.arange(q + 1, dtype=torch.int64, device="cuda:0")
+            got = _host(lc.quantile(blob, k, q), kb)
+            assert np.array_equal(got, oracle.quantile(keys, k.cpu().numpy(), q))
+    a = np.unique(rng.integers(0, 1 << 36, 60_000)).astype(np.uint64)
+    b = np.unique(np.concatenate([rng.choice(a, 20_000, replace=False),
+                                  rng.integers(0, 1 << 36, 40_000).astype(np.uint64)]))
+    A = lc.compress(_dev(a), 63, 10, F, fit="opt")
+    B = lc.compress(_dev(b), 7, 10, F, fit="opt")
+    G = lc.compress(_dev(b), 7)
+    assert np.array_equal(_host(lc.intersect(A, B), 8), oracle.intersect(a, b))
+    assert np.array_equal(_host(lc.intersect(B, A), 8), oracle.intersect(a, b))
+    assert np.array_equal(_host(lc.intersect(A, G), 8), oracle.intersect(a, b))
+    assert np.array_equal(_host(lc.union(A, B), 8), oracle.union(a, b))
