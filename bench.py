@@ -64,6 +64,12 @@ def recorded_valu():
     return rec
 
 
+# Fractional bits F of the fixed-point slopes in every measured blob
+# (--frac-bits).  0, integer slopes, gives smaller blobs and equal or faster
+# decode than 20 on every workload measured here; bench_fits reports both.
+FRAC_BITS = 0
+
+
 def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -74,7 +80,7 @@ def cpu_baseline(host_keys, eps: int, budget_s: float = 12.0):
     import oracle
 
     n_probe = min(len(host_keys), 1 << 20)
-    blob = oracle.compress(host_keys[:n_probe], eps, 10)
+    blob = oracle.compress(host_keys[:n_probe], eps, 10, FRAC_BITS)
     t0 = time.perf_counter()
     oracle.decode(blob)
     per_key = (time.perf_counter() - t0) / n_probe
@@ -82,7 +88,7 @@ def cpu_baseline(host_keys, eps: int, budget_s: float = 12.0):
     n_s -= n_s % 1024 if n_s > 1024 else 0
     sample = np.ascontiguousarray(host_keys[:n_s])
     t0 = time.perf_counter()
-    blob = oracle.compress(sample, eps, 10)
+    blob = oracle.compress(sample, eps, 10, FRAC_BITS)
     t_enc = time.perf_counter() - t0
     t0 = time.perf_counter()
     out = oracle.decode(blob)
@@ -90,7 +96,7 @@ def cpu_baseline(host_keys, eps: int, budget_s: float = 12.0):
     assert np.array_equal(out, sample)
     return {
         "value": round(n_s * 8 / t_dec / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-        "sample": f"first {n_s} keys of the workload, eps={eps}, B=1024; oracle decode "
+        "sample": f"first {n_s} keys of the workload, eps={eps}, B=1024, F={FRAC_BITS}; oracle decode "
                   f"{t_dec:.2f} s, oracle compress {t_enc:.2f} s ({n_s * 8 / t_enc / 1e9:.4f} GB/s)",
         "compress_GBps": round(n_s * 8 / t_enc / 1e9, 4),
     }
@@ -115,7 +121,7 @@ def bench_batch(dev, steps: int, warmup: int, nlists: int = 4096, cands=(7, 31, 
     n = keys.numel()
     log(f"batch: generated {nlists} lists, {n} keys in {time.perf_counter() - t0:.1f} s")
     offs = np.concatenate([[0], np.cumsum(lengths)[:-1]]).astype(np.int64)
-    p, table = lc.batch_plan(lengths, cands[0], 4, max(cands))
+    p, table = lc.batch_plan(lengths, cands[0], 4, max(cands), frac_bits=FRAC_BITS)
     d_lists = torch.from_numpy(table.view(np.uint8).copy()).to(dev)
     ws = torch.empty(p.ws_bytes, dtype=torch.uint8, device=dev)
     blob = torch.empty(p.blob_bytes, dtype=torch.uint8, device=dev)
@@ -156,7 +162,7 @@ def bench_batch(dev, steps: int, warmup: int, nlists: int = 4096, cands=(7, 31, 
 
     # per-list launches into the same slot layout of a second buffer
     blob2 = torch.empty(p.blob_bytes, dtype=torch.uint8, device=dev)
-    ws2 = torch.empty(max(16, max(lc.compress_bound(int(m), 4, int(e))[1] for m, e in zip(lengths, chosen))),
+    ws2 = torch.empty(max(16, max(lc.compress_bound(int(m), 4, int(e), frac_bits=FRAC_BITS)[1] for m, e in zip(lengths, chosen))),
                       dtype=torch.uint8, device=dev)
     nb2 = torch.zeros(nlists, dtype=torch.int64, device=dev)
     fl2 = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -165,7 +171,7 @@ def bench_batch(dev, steps: int, warmup: int, nlists: int = 4096, cands=(7, 31, 
     oviews = [out2[o:o + m] for o, m in zip(offs, lengths)]
     bviews = [blob2[int(table["blob_off"][l]):int(table["blob_off"][l] + table["blob_cap"][l])] for l in range(nlists)]
     for l in range(nlists):
-        lc.compress_async(kviews[l], int(chosen[l]), bviews[l], ws2, nb2[l:l + 1], fl2)
+        lc.compress_async(kviews[l], int(chosen[l]), bviews[l], ws2, nb2[l:l + 1], fl2, frac_bits=FRAC_BITS)
     torch.cuda.synchronize()
     assert int(fl2.item()) == 0
     infos = [lc.Blob.from_device(bviews[l]) for l in range(nlists)]
@@ -174,7 +180,7 @@ def bench_batch(dev, steps: int, warmup: int, nlists: int = 4096, cands=(7, 31, 
     def per_list(marks):
         mark(marks, 0)
         for l in range(nlists):
-            lc.compress_async(kviews[l], int(chosen[l]), bviews[l], ws2, nb2[l:l + 1], fl2)
+            lc.compress_async(kviews[l], int(chosen[l]), bviews[l], ws2, nb2[l:l + 1], fl2, frac_bits=FRAC_BITS)
         mark(marks, 1)
         for l in range(nlists):
             lc.decompress(infos[l], out=oviews[l])
@@ -229,7 +235,8 @@ def bench_batch(dev, steps: int, warmup: int, nlists: int = 4096, cands=(7, 31, 
     key_bytes = n * 4
     # block size picked by the autotuner: exact bytes and decode time per size
     log("batch: block-size autotune")
-    _, tune = lc.autotune_batch(keys, lengths, cands, block_candidates=(8, 9, 10, 11, 12), objective="size")
+    _, tune = lc.autotune_batch(keys, lengths, cands, block_candidates=(8, 9, 10, 11, 12), objective="size",
+                              frac_bits=FRAC_BITS)
     block_tune = [{"log2_block": r["log2_block"], "bits_per_key": round(8.0 * r["bytes"] / n, 4),
                    "decode_GBps": round(key_bytes / r["decode_ms"] / 1e6, 2), "chosen": r["chosen"]} for r in tune]
     picked = next(r for r in tune if r["chosen"])
@@ -237,7 +244,8 @@ def bench_batch(dev, steps: int, warmup: int, nlists: int = 4096, cands=(7, 31, 
                    "compress_ms": {k: round(v, 3) for k, v in picked.get("compress_ms_by_tiling", {}).items()}}
     return {
         "workload": f"{nlists} sorted uint32 lists, lengths ~ L^-1.1 on [100, 1e6] ({n} keys), geometric gaps "
-                    f"with per-list mean log-uniform in [2, 2000]; eps per list argmin-size over {list(cands)}",
+                    f"with per-list mean log-uniform in [2, 2000]; eps per list argmin-size over {list(cands)}; "
+                    f"F = {FRAC_BITS}",
         "n": n, "nlists": nlists,
         "ratio": round(float(bsizes.sum()) / key_bytes, 5),
         "bits_per_key": round(8.0 * float(bsizes.sum()) / n, 4),
@@ -269,7 +277,7 @@ def bench_lookups(dev, n: int = 200_000_000, eps: int = 63, n_access: int = 10_0
     from paper_2412_10770_amd import lc, workloads
 
     keys = workloads.heterogeneous_runs(n, device=dev)
-    blob = lc.compress(keys, eps)
+    blob = lc.compress(keys, eps, frac_bits=FRAC_BITS)
     idx = workloads.uniform_indices(n_access, n, seed=workloads.SEED_BASE + 104, device=dev)
     q = workloads.uniform_keys(n_lb, int(keys[0]), int(keys[-1]), seed=workloads.SEED_BASE + 105, device=dev)
     acc = lc.access(blob, idx)
@@ -308,7 +316,8 @@ def bench_lookups(dev, n: int = 200_000_000, eps: int = 63, n_access: int = 10_0
             "bytes": n * 8,
         },
         "workload": f"{n} uint64 keys, alternating dense (gaps U[1,4]) and Zipf(1.2) runs of 1e4..1e6 keys; "
-                    f"eps {eps}; {n_access} access(i), i uniform; {n_lb} lower_bound(q), q uniform over the key range",
+                    f"eps {eps}, F = {FRAC_BITS}; {n_access} access(i), i uniform; {n_lb} lower_bound(q), q uniform "
+                    f"over the key range",
         "bits_per_key": round(blob.bits_per_key, 4),
         "access_lookups_per_s": round(n_access / float(np.mean(ta)) * 1e3, 1),
         "lower_bound_lookups_per_s": round(n_lb / float(np.mean(tl)) * 1e3, 1),
@@ -347,7 +356,7 @@ def bench_queries(dev, n: int = 100_000_000, eps: int = 63, n_quantile: int = 10
         return float(np.mean(ts))
 
     keys = workloads.lognormal_distinct(n, device=dev)
-    blob = lc.compress(keys, eps)
+    blob = lc.compress(keys, eps, frac_bits=FRAC_BITS)
     out = torch.empty(n, dtype=torch.int64, device=dev)
     lc.decompress(blob, out=out)
     assert torch.equal(out, keys)
@@ -371,7 +380,7 @@ def bench_queries(dev, n: int = 100_000_000, eps: int = 63, n_quantile: int = 10
     for s_, l_ in zip(shorts, longs):
         a = pl[offs[s_]:offs[s_] + lengths[s_]]
         b = pl[offs[l_]:offs[l_] + lengths[l_]]
-        pairs.append((a, b, lc.compress(a, 31), lc.compress(b, 31)))
+        pairs.append((a, b, lc.compress(a, 31, frac_bits=FRAC_BITS), lc.compress(b, 31, frac_bits=FRAC_BITS)))
     del pl
     # buffers sized for the largest pair, allocated once
     mx_and = max(lc.setop_bound(A, B, lc.SETOP_INTERSECT)[1] for _, _, A, B in pairs)
@@ -415,7 +424,7 @@ def bench_queries(dev, n: int = 100_000_000, eps: int = 63, n_quantile: int = 10
 
     # many pairs at once: AND of random pairs of lists of the whole batch
     pl2, _ = workloads.posting_lists(4096, device=dev)
-    batch = lc.batch_compress(pl2, lengths, candidates=(7, 31, 127))
+    batch = lc.batch_compress(pl2, lengths, candidates=(7, 31, 127), frac_bits=FRAC_BITS)
     del pl2
     npq = 4096
     qpairs = rng.integers(0, len(lengths), (npq, 2))
@@ -444,7 +453,7 @@ def bench_queries(dev, n: int = 100_000_000, eps: int = 63, n_quantile: int = 10
     short_keys = int(sum(A.n for _, _, A, _ in pairs))
     long_keys = int(sum(B.n for _, _, _, B in pairs))
     return {
-        "workload": f"approximate decode and quantiles on {n} lognormal uint64 keys (eps {eps}); list AND / OR "
+        "workload": f"approximate decode and quantiles on {n} lognormal uint64 keys (eps {eps}, F = {FRAC_BITS}); list AND / OR "
                     f"of {npairs} pairs of posting lists (a list of 1e3..1e4 keys with one of the {npairs} longest, "
                     f"eps 31), one call per pair",
         "decode_exact_GBps": round(n * 8 / t_exact / 1e6, 2),
@@ -485,7 +494,7 @@ def bench_serve(dev, n: int = 1_000_000_000, qps_points=(1e3, 1e4, 1e5, 1e6, Non
     best = None
     sizes = {}
     for e in eps_cands:
-        b = lc.compress(keys, e)
+        b = lc.compress(keys, e, frac_bits=FRAC_BITS)
         sizes[e] = b.nbytes
         if best is None or b.nbytes < best.nbytes:
             best = b
@@ -533,7 +542,7 @@ def bench_serve(dev, n: int = 1_000_000_000, qps_points=(1e3, 1e4, 1e5, 1e6, Non
     sat = points[-1]
     return {
         "workload": f"{n} sorted uint64 keys, gaps max(1, ceil(lognormal(3, 1.5))); store eps argmin-size over "
-                    f"{list(eps_cands)}; Poisson arrivals, 70% decode_range (length floor(exp(U[0, ln 1e6]))), "
+                    f"{list(eps_cands)}, F = {FRAC_BITS}; Poisson arrivals, 70% decode_range (length floor(exp(U[0, ln 1e6]))), "
                     f"20% access, 10% lower_bound; output arena {arena_bytes >> 20} MiB, "
                     f"{max_batch} requests per launch, {max_inflight} launches in flight",
         "store": {"eps": blob.info.eps, "bytes": blob.nbytes, "bits_per_key": round(blob.bits_per_key, 4),
@@ -545,9 +554,12 @@ def bench_serve(dev, n: int = 1_000_000_000, qps_points=(1e3, 1e4, 1e5, 1e6, Non
 
 
 def bench_fits(dev, keys_lognormal=None, reps: int = 3):
-    """Greedy against fewest-segment fit: compress time (HIP events, mean of
-    `reps` after one warm-up), blob size and segment count, per workload and
-    eps.  Every fewest-segment blob is decoded and compared with its keys."""
+    """The fits side by side: greedy, fewest anchored segments ("min") and
+    the optimal free-intercept fit ("opt") at F = 20, and greedy and opt at
+    F = 0 (integer slopes and intercepts: no fraction array).  Compress and
+    decompress time (HIP events, mean of `reps` after one warm-up), blob size
+    and segment count, per workload and eps.  Every blob is decoded and
+    compared with its keys."""
     import numpy as np
     import torch
 
@@ -563,44 +575,62 @@ def bench_fits(dev, keys_lognormal=None, reps: int = 3):
         ("lognormal_gaps_100M_u64", lambda: workloads.lognormal_gaps(100_000_000, device=dev), (63, 255, 1023)),
         ("heterogeneous_runs_200M_u64", lambda: workloads.heterogeneous_runs(200_000_000, device=dev), (63,)),
     ]
+    variants = (("greedy", "greedy", 20), ("min", "min", 20), ("opt", "opt", 20),
+                ("greedy_F0", "greedy", 0), ("opt_F0", "opt", 0))
     res = {}
     for name, make, eps_list in cases:
         keys = make()
         torch.cuda.synchronize()
         n, kb = keys.numel(), keys.element_size()
+        out = torch.empty_like(keys)
         rows = {}
         for eps in eps_list:
-            bmax, ws_bytes = lc.compress_bound(n, kb, eps)
+            bmax, ws_bytes = lc.compress_bound(n, kb, eps, fit="opt")  # the largest of the variants
             blob = torch.empty(bmax, dtype=torch.uint8, device=dev)
             ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
             nb = torch.zeros(1, dtype=torch.int64, device=dev)
             fl = torch.zeros(1, dtype=torch.int32, device=dev)
             row = {}
-            for fit in ("greedy", "min"):
-                lc.compress_async(keys, eps, blob, ws, nb, fl, fit=fit)
+            for label, fit, F in variants:
+                lc.compress_async(keys, eps, blob, ws, nb, fl, frac_bits=F, fit=fit)
                 torch.cuda.synchronize()
                 marks = []
                 for _ in range(reps):
                     e0, e1 = ev(), ev()
                     e0.record()
-                    lc.compress_async(keys, eps, blob, ws, nb, fl, fit=fit)
+                    lc.compress_async(keys, eps, blob, ws, nb, fl, frac_bits=F, fit=fit)
                     e1.record()
                     marks.append((e0, e1))
                 torch.cuda.synchronize()
-                assert int(fl.item()) == 0, (name, eps, fit, int(fl.item()))
+                assert int(fl.item()) == 0, (name, eps, label, int(fl.item()))
                 ms = float(np.mean([a.elapsed_time(b) for a, b in marks]))
                 b = lc.Blob.from_device(blob)
-                if fit == "min":
-                    assert torch.equal(lc.decompress(b), keys), (name, eps, "min-fit round trip")
-                row[fit] = {"compress_ms": round(ms, 3), "keys_per_s": round(n / ms * 1e3, 1),
-                            "bits_per_key": round(b.bits_per_key, 4), "nseg_total": b.info.nseg_total}
-            row["bytes_saved_pct"] = round(100 * (1 - row["min"]["bits_per_key"] / row["greedy"]["bits_per_key"]), 3)
-            row["segments_saved_pct"] = round(100 * (1 - row["min"]["nseg_total"] / row["greedy"]["nseg_total"]), 3)
+                lc.decompress(b, out=out)
+                torch.cuda.synchronize()
+                assert torch.equal(out, keys), (name, eps, label, "round trip")
+                dmarks = []
+                for _ in range(reps):
+                    e0, e1 = ev(), ev()
+                    e0.record()
+                    lc.decompress(b, out=out)
+                    e1.record()
+                    dmarks.append((e0, e1))
+                torch.cuda.synchronize()
+                dms = float(np.mean([a.elapsed_time(c) for a, c in dmarks]))
+                row[label] = {"compress_ms": round(ms, 3), "keys_per_s": round(n / ms * 1e3, 1),
+                              "decompress_ms": round(dms, 3), "decoded_GBps": round(n * kb / dms / 1e6, 1),
+                              "bits_per_key": round(b.bits_per_key, 4), "nseg_total": b.info.nseg_total}
+            g = row["greedy"]
+            for label in ("min", "opt", "greedy_F0", "opt_F0"):
+                row[label]["bytes_saved_pct_vs_greedy"] = round(100 * (1 - row[label]["bits_per_key"] / g["bits_per_key"]), 3)
+                row[label]["segments_saved_pct_vs_greedy"] = round(100 * (1 - row[label]["nseg_total"] / g["nseg_total"]), 3)
+            row["opt_F0"]["bytes_saved_pct_vs_greedy_F0"] = round(
+                100 * (1 - row["opt_F0"]["bits_per_key"] / row["greedy_F0"]["bits_per_key"]), 3)
             rows[str(eps)] = row
             log(f"fits {name} eps={eps}: {row}")
             del blob, ws
         res[name] = {"n": n, "key_bytes": kb, "per_eps": rows}
-        del keys
+        del keys, out
         torch.cuda.empty_cache()
     return res
 
@@ -623,9 +653,13 @@ def main():
     ap.add_argument("--no-lookups", action="store_true", help="skip the heterogeneous-runs lookup measurement")
     ap.add_argument("--no-queries", action="store_true", help="skip the quantile / approximate / AND / OR measurement")
     ap.add_argument("--queries-only", action="store_true", help="only the quantile / approximate / AND / OR measurement")
-    ap.add_argument("--no-fits", action="store_true", help="skip the greedy / fewest-segment fit comparison")
-    ap.add_argument("--fits-only", action="store_true", help="only the greedy / fewest-segment fit comparison")
+    ap.add_argument("--frac-bits", type=int, default=FRAC_BITS,
+                    help="fractional bits F of the slopes in every measured blob (the fit comparison sweeps its own)")
+    ap.add_argument("--no-fits", action="store_true", help="skip the fit comparison (greedy, fewest anchored segments, optimal)")
+    ap.add_argument("--fits-only", action="store_true", help="only the fit comparison (greedy, fewest anchored segments, optimal)")
     args = ap.parse_args()
+    global FRAC_BITS
+    FRAC_BITS = args.frac_bits
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path is "
               "single-GPU here. Run with --gpus 1.", file=sys.stderr)
@@ -661,7 +695,7 @@ def main():
     blobs, wss = {}, None
     max_ws = 0
     for e in eps_list:
-        bmax, ws_bytes = lc.compress_bound(n, 8, e)
+        bmax, ws_bytes = lc.compress_bound(n, 8, e, frac_bits=FRAC_BITS)
         blobs[e] = torch.empty(bmax, dtype=torch.uint8, device=dev)
         max_ws = max(max_ws, ws_bytes)
     wss = torch.empty(max_ws, dtype=torch.uint8, device=dev)
@@ -686,7 +720,7 @@ def main():
     # one untimed compress per eps to learn the blob layout (headers)
     infos = {}
     for k, e in enumerate(eps_list):
-        lc.compress_async(keys, e, blobs[e], wss, nbytes[k:k + 1], flags)
+        lc.compress_async(keys, e, blobs[e], wss, nbytes[k:k + 1], flags, frac_bits=FRAC_BITS)
     torch.cuda.synchronize()
     assert int(flags.item()) == 0, "keys not sorted"
     for e in eps_list:
@@ -703,7 +737,7 @@ def main():
             b = infos[e]
             e0, e1, e2 = ev(), ev(), ev()
             e0.record()
-            lc.compress_async(keys, e, blobs[e], wss, nbytes[k:k + 1], flags)
+            lc.compress_async(keys, e, blobs[e], wss, nbytes[k:k + 1], flags, frac_bits=FRAC_BITS)
             e1.record()
             lc.decompress(lc.Blob(blobs[e], b.info), out=out)
             e2.record()
@@ -761,7 +795,7 @@ def main():
     achieved = float(np.mean(dec_alg_bytes)) / (dec_avg_ms / 1e3) / 1e9
     rec = recorded_traffic()
     traffic = None
-    if rec is not None and rec.get("n") == n and rec.get("eps") == eps_list:
+    if rec is not None and rec.get("n") == n and rec.get("eps") == eps_list and rec.get("frac_bits") == FRAC_BITS:
         traffic = rec["bytes_per_decompress"]
     # encode against both rooflines: HBM (keys read + blob written) and VALU
     # (issued lane-operations of the compress kernels, from the counter record)
@@ -769,7 +803,7 @@ def main():
     enc_hbm = float(np.mean([(n * 8 + infos[e].nbytes) / (enc_ms[e] / 1e3) / 1e9 for e in eps_list]))
     vrec = recorded_valu()
     enc_alu = None
-    if vrec is not None and vrec.get("n") == n and vrec.get("eps") == eps_list:
+    if vrec is not None and vrec.get("n") == n and vrec.get("eps") == eps_list and vrec.get("frac_bits") == FRAC_BITS:
         enc_alu = float(np.mean([vrec["valu_insts_per_call"][str(e)] * 64 / (enc_ms[e] / 1e3) / 1e12
                                  for e in eps_list]))
     roofline_encode = {
@@ -802,10 +836,11 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{n} sorted distinct uint64 keys, floor(2^40 x / M), x ~ lognormal(0, 2); "
-                        f"blocks of 1024; eps swept over {eps_list}; per step: compress + decompress "
+                        f"blocks of 1024, F = {FRAC_BITS} (integer slopes when 0); eps swept over {eps_list}; "
+                        f"per step: compress + decompress "
                         f"per eps, decompress_range of {r_end - r_begin} keys, {args.access} access, "
                         f"{args.lower_bound} lower_bound on the eps={ref_eps} blob",
-            "n": n, "key_bytes": 8, "log2_block": 10, "eps": eps_list,
+            "n": n, "key_bytes": 8, "log2_block": 10, "eps": eps_list, "frac_bits": FRAC_BITS,
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",

@@ -37,7 +37,7 @@ def check_fullsize(lc, keys: torch.Tensor, eps: int, n_access: int, n_lb: int, s
     n = keys.numel()
     kb = keys.element_size()
     _say(f"full-size case n={n} kb={kb} eps={eps} fit={fit} F={frac_bits}")
-    blob = lc.compress(keys, eps, 10, frac_bits, fit=fit)  # log2_block 10 (F 20): the benchmark's configuration
+    blob = lc.compress(keys, eps, 10, frac_bits, fit=fit)  # log2_block 10 as the benchmark
     h = blob.info
     B = 1 << h.log2_block
     assert h.n == n and h.nblocks == (n + B - 1) // B
@@ -104,11 +104,13 @@ def wl():
     return workloads
 
 
-def test_lognormal_100m(lc, wl):
+# F = 0 is the benchmark's configuration, F = 20 the library default
+@pytest.mark.parametrize("frac_bits", [0, 20])
+def test_lognormal_100m(lc, wl, frac_bits):
     """100M distinct uint64 keys, lognormal(0, 2) scaled to 2^40; eps 15 / 63 / 255."""
     keys = wl.lognormal_distinct(100_000_000, device=DEV)
     for eps in (15, 63, 255):
-        check_fullsize(lc, keys, eps, n_access=1_000_000, n_lb=1_000_000, seed=eps)
+        check_fullsize(lc, keys, eps, n_access=1_000_000, n_lb=1_000_000, seed=eps, frac_bits=frac_bits)
 
 
 def test_lognormal_100m_min_fit(lc, wl):
@@ -146,21 +148,23 @@ def test_heterogeneous_runs_200m_min_fit(lc, wl):
     check_fullsize(lc, keys, 63, n_access=1_000_000, n_lb=1_000_000, seed=4, fit="min")
 
 
-def test_heterogeneous_runs_200m(lc, wl):
+@pytest.mark.parametrize("frac_bits", [0, 20])
+def test_heterogeneous_runs_200m(lc, wl, frac_bits):
     """200M uint64 keys, alternating dense / Zipf(1.2) runs; eps 63; 10M access, 1M lower_bound."""
     keys = wl.heterogeneous_runs(200_000_000, device=DEV)
-    check_fullsize(lc, keys, 63, n_access=10_000_000, n_lb=1_000_000, seed=3)
+    check_fullsize(lc, keys, 63, n_access=10_000_000, n_lb=1_000_000, seed=3, frac_bits=frac_bits)
 
 
-def test_posting_lists_4096(lc, wl):
+@pytest.mark.parametrize("frac_bits", [0, 20])
+def test_posting_lists_4096(lc, wl, frac_bits):
     """The batch workload at full size: 4096 uint32 lists (~2.9e8 keys), eps
     autotuned over {7, 31, 127}.  Whole-batch round trip; on sampled lists
     (the longest, the shortest and random ones) the chosen eps equals the
     argmin of the oracle's exact sizes and the blob equals the oracle's."""
     cands = (7, 31, 127)
     keys, lengths = wl.posting_lists(4096, device=DEV)
-    _say(f"posting lists full size: {keys.numel()} keys")
-    batch = lc.batch_compress(keys, lengths, candidates=cands)
+    _say(f"posting lists full size: {keys.numel()} keys, F={frac_bits}")
+    batch = lc.batch_compress(keys, lengths, candidates=cands, frac_bits=frac_bits)
     assert torch.equal(lc.batch_decompress(batch), keys)
     host = keys.cpu().numpy().view(np.uint32)
     offs = np.concatenate([[0], np.cumsum(lengths)[:-1]])
@@ -169,7 +173,7 @@ def test_posting_lists_4096(lc, wl):
     picks |= {int(np.argmax(lengths)), int(np.argmin(lengths))}
     for l in sorted(picks):
         x = host[offs[l]:offs[l] + lengths[l]]
-        blobs = [oracle.compress(x, e, 10) for e in cands]
+        blobs = [oracle.compress(x, e, 10, frac_bits) for e in cands]
         best = int(np.argmin([len(b) for b in blobs]))
         assert batch.eps[l] == cands[best], l
         assert np.array_equal(batch.blob(l).data.cpu().numpy(), blobs[best]), l
@@ -180,18 +184,19 @@ def test_serving_store_1e9(lc, wl):
     gaps, stored at the eps with the smallest blob among {15, 63, 255, 1023}
     (checked against all four sizes); 3000 mixed Poisson requests served with
     results copied out and compared with the definitions computed by torch
-    from the raw keys on the device (K[a:b], K[i], searchsorted)."""
+    from the raw keys on the device (K[a:b], K[i], searchsorted).  F = 0,
+    as the benchmark."""
     n = 1_000_000_000
     keys = wl.lognormal_gaps(n, seed=wl.SEED_BASE + 5, device=DEV)
     _say("serving store 1e9")
     sizes = {}
     for e in (15, 63, 255, 1023):
-        b = lc.compress(keys, e)
+        b = lc.compress(keys, e, frac_bits=0)
         sizes[e] = b.nbytes
         del b
         torch.cuda.empty_cache()
     eps = min(sizes, key=lambda e: (sizes[e], e))
-    blob = lc.compress(keys, eps)
+    blob = lc.compress(keys, eps, frac_bits=0)
     assert blob.nbytes == sizes[eps]
     lo, hi = int(keys[0]), int(keys[-1])
     op, a, b, arr = wl.request_stream(3000, n, lo, hi, 1e6, seed=77)
