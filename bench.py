@@ -636,6 +636,7 @@ def bench_fits(dev, keys_lognormal=None, reps: int = 3):
 
 
 def main():
+    global FRAC_BITS
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -658,7 +659,6 @@ def main():
     ap.add_argument("--no-fits", action="store_true", help="skip the fit comparison (greedy, fewest anchored segments, optimal)")
     ap.add_argument("--fits-only", action="store_true", help="only the fit comparison (greedy, fewest anchored segments, optimal)")
     args = ap.parse_args()
-    global FRAC_BITS
     FRAC_BITS = args.frac_bits
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path is "
