@@ -467,6 +467,25 @@ def test_opt_fit_lines_caps_and_top_of_range(lc):
     check_all(lc, low_high, 7, 6, rng, nq=100, fit="opt")
 
 
+def test_opt_fit_large_hulls(lc):
+    """Strictly convex keys (i^2) keep every key of a segment on the lower
+    hull and pop the upper one back to two vertices at every key; concave
+    keys (sqrt) the other way round.  With eps large enough for one segment
+    per block, hulls reach 1024 vertices, so each step's scan takes 16 passes
+    of the wave and the pops run long."""
+    rng = np.random.default_rng(8)
+    n = 6 * 1024 + 77
+    i = np.arange(n, dtype=np.uint64)
+    convex = i * i
+    concave = np.floor(1e9 * np.sqrt(np.arange(n, dtype=np.float64))).astype(np.uint64)
+    for keys in (convex, concave, convex.astype(np.uint32)):
+        for eps, F in ((1 << 20, 0), (1 << 20, 20), (1 << 30, 0)):
+            check_all(lc, keys, eps, 10, rng, nq=200, frac_bits=F, fit="opt")
+    # segments of a few hundred keys inside blocks: hulls grow, the segment closes, they reset
+    check_all(lc, convex, 1 << 12, 10, rng, nq=200, frac_bits=0, fit="opt")
+    check_all(lc, concave, 1 << 16, 12, rng, nq=200, frac_bits=20, fit="opt")
+
+
 @pytest.mark.parametrize("frac_bits", [0, 20, 32])
 def test_opt_fit_short_and_long_segments_alternate(lc, frac_bits):
     rng = np.random.default_rng(95 + frac_bits)
