@@ -1038,6 +1038,9 @@ __global__ __launch_bounds__(64) void fit_opt_kernel(const void* __restrict__ ke
     const uint64_t span = (uint64_t)sk[nb - 1] - first;
     // every numerator below is at most (span + 2 eps + 1) 2^F
     const bool fast = span < (1ull << 50) && fast_division_ok(span, 2 * eps, F);
+    // hull cross products y (h - h') with y < 2^50 and index differences
+    // < 2^13: each product below 2^63 and the sums below 2^64 in u64
+    const bool narrow = span < (1ull << 50);
 
     uint32_t nseg = 0;
     uint64_t maxA = 0, maxd = 0;
@@ -1089,19 +1092,26 @@ __global__ __launch_bounds__(64) void fit_opt_kernel(const void* __restrict__ ke
             // strictly below (lower hull) / above (upper hull) the line h2 -> e:
             //   (y1 - y2)(e - h2) vs (ye - y2)(h1 - h2), rearranged so every
             //   term is non-negative: y1 (e - h2) + y2 (h1 - h2) vs ye (h1 - h2) + y2 (e - h2)
-            const uint64_t ye_u = Ke - Ks, ye_l = Ke - Ks;
+            const uint64_t ye = Ke - Ks;
+            // sign of y1 (e - h2) + y2 (h1 - h2) - ye (h1 - h2) - y2 (e - h2):
+            // -1, 0 or 1, in u64 when the block is narrow, else in u128
+            auto turn = [&](uint64_t y1, uint64_t y2, uint32_t h1, uint32_t h2) -> int {
+                if (narrow) {
+                    const uint64_t l = y1 * (e - h2) + y2 * (h1 - h2), r_ = ye * (h1 - h2) + y2 * (e - h2);
+                    return l < r_ ? -1 : l > r_ ? 1 : 0;
+                }
+                const u128 l = (u128)y1 * (e - h2) + (u128)y2 * (h1 - h2);
+                const u128 r_ = (u128)ye * (h1 - h2) + (u128)y2 * (e - h2);
+                return l < r_ ? -1 : l > r_ ? 1 : 0;
+            };
             while (nU >= 2) {
                 const uint32_t h1 = hU[nU - 1], h2 = hU[nU - 2];
-                const u128 lhs = (u128)yU(h1) * (e - h2) + (u128)yU(h2) * (h1 - h2);
-                const u128 rhs = (u128)ye_u * (h1 - h2) + (u128)yU(h2) * (e - h2);
-                if (lhs < rhs) break;
+                if (turn(yU(h1), yU(h2), h1, h2) < 0) break;
                 nU--;
             }
             while (nL >= 2) {
                 const uint32_t h1 = hL[nL - 1], h2 = hL[nL - 2];
-                const u128 lhs = (u128)yL(h1) * (e - h2) + (u128)yL(h2) * (h1 - h2);
-                const u128 rhs = (u128)ye_l * (h1 - h2) + (u128)yL(h2) * (e - h2);
-                if (lhs > rhs) break;
+                if (turn(yL(h1), yL(h2), h1, h2) > 0) break;
                 nL--;
             }
             __syncthreads();  // every lane has read the hulls before lane 0 writes
