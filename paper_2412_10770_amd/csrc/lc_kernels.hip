@@ -2269,15 +2269,53 @@ __device__ __forceinline__ uint64_t lower_bound_one(const uint8_t* __restrict__ 
     // key distributions the anchors of sparse blocks are too uneven for a
     // proportional guess to pay off)
     uint32_t t = 0;
-    for (uint32_t step = pow2_floor(v.nseg); step; step >>= 1)
-        if (t + step < v.nseg && seg_first(t + step) < x) t += step;
+    uint64_t Kt = first;  // first key of segment t (segment 0 starts the block)
+    for (uint32_t step = pow2_floor(v.nseg); step; step >>= 1) {
+        if (t + step < v.nseg) {
+            const uint64_t k = seg_first(t + step);
+            if (k < x) {
+                t += step;
+                Kt = k;
+            }
+        }
+    }
     const uint32_t s = st[t];
     const uint32_t e = t + 1 < v.nseg ? st[t + 1] : v.nkeys;
     const uint64_t anchor = first + load_w(an, t, v.ab);
     const uint64_t A = load_w(sl, t, v.sb);
     const uint64_t frac = L.fb ? load_w(sl + a16((uint64_t)v.sb * v.nseg), t, L.fb) : 0;
-    // keys s+1 .. e-1 of the segment: first one >= x, else e
-    uint32_t lo = s + 1, hi = e;
+    // The eps window, from the model alone (no memory reads): with
+    // G(d) = floor((A d + frac) / 2^F) and dl = intercept - K[s] (0 when
+    // anchored; |dl| <= eps, exact as a signed difference modulo 2^64), key
+    // s + d is certainly below x when G(d) + dl + eps < x - K[s], and
+    // certainly not when G(d) + dl - eps >= x - K[s]; G is non-decreasing in
+    // d.  Sums that would pass 2^64 certify nothing.
+    const uint64_t X = x - Kt;                              // >= 1
+    const int64_t dl = (int64_t)(anchor - Kt);
+    const uint64_t up = (uint64_t)(dl + (int64_t)L.eps);    // in [0, 2 eps]
+    const uint64_t down = (uint64_t)((int64_t)L.eps - dl);  // in [0, 2 eps]
+    const bool down_ok = X <= ~0ull - down;
+    auto G = [&](uint32_t d) -> uint64_t { return (A * (uint64_t)d + frac) >> L.F; };
+    auto below = [&](uint32_t d) -> bool {
+        const uint64_t g = G(d);
+        return g <= ~0ull - up && g + up < X;
+    };
+    auto above = [&](uint32_t d) -> bool { return down_ok && G(d) >= X + down; };
+    const uint32_t len = e - s;
+    uint32_t da = 1, db = len;  // first d in [1, len) not certainly below x, else len
+    while (da < db) {
+        const uint32_t m = (da + db) >> 1;
+        if (below(m)) da = m + 1;
+        else db = m;
+    }
+    uint32_t dc = da, dd = len;  // first d in [da, len) certainly not below x, else len
+    while (dc < dd) {
+        const uint32_t m = (dc + dd) >> 1;
+        if (above(m)) dd = m;
+        else dc = m + 1;
+    }
+    // keys in the window: first one >= x, else s + dc (which is e or a key >= x)
+    uint32_t lo = s + da, hi = s + dc;
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
         uint64_t k = anchor + ((A * (uint64_t)(mid - s) + frac) >> L.F) + code_at(blob, L, b, mid) - L.eps;
