@@ -136,3 +136,29 @@ def test_u32_store_unaligned_ranges(lc, wl):
     buf, off, size, res, st = _serve(lc, blob, op, a, b, np.zeros(m, np.uint64), max_batch=128, max_inflight=2)
     assert np.all(res["status"] == 0)
     _check_results(lc, host, buf, off, size, op, a, b, 4)
+
+
+@pytest.mark.parametrize("F", [0, 20])
+def test_optimal_fit_store(lc, wl, F):
+    """A store compressed with the optimal fit (free intercepts; fraction
+    array at F = 20, none at F = 0): mixed requests served in batches equal
+    the definitions and the same requests served one by one."""
+    keys = wl.lognormal_gaps(400_000, seed=wl.SEED_BASE + 51, device=DEV)
+    host = wl.as_numpy(keys)
+    blob = lc.compress(keys, 63, frac_bits=F, fit="opt")
+    assert blob.info.flags == 1
+    rng = np.random.default_rng(15 + F)
+    m = 600
+    op = rng.choice([1, 1, 2, 3], m).astype(np.uint32)
+    a = rng.integers(0, len(host) - 1, m).astype(np.uint64)
+    b = np.minimum(a + rng.integers(1, 20_000, m).astype(np.uint64), len(host)).astype(np.uint64)
+    lbq = op == 3
+    a[lbq] = rng.integers(0, int(host[-1]) + 3, int(lbq.sum())).astype(np.uint64)
+    _say(f"serve optimal-fit store F={F}")
+    arrival = np.zeros(m, np.uint64)
+    buf, off, size, res, st = _serve(lc, blob, op, a, b, arrival, max_batch=256, max_inflight=3)
+    assert np.all(res["status"] == 0)
+    _check_results(lc, host, buf, off, size, op, a, b, 8)
+    alone, _, _, res1, _ = _serve(lc, blob, op, a, b, arrival, max_batch=1, max_inflight=1)
+    assert np.all(res1["status"] == 0)
+    assert torch.equal(alone, buf)
