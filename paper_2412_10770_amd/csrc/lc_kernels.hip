@@ -2157,6 +2157,60 @@ __global__ __launch_bounds__(64) void decode_kernel(const uint8_t* __restrict__ 
     decode_block<KB, RANGE, APPROX>(blob, a, a.b_first + rel, a.raw_cap, out);
 }
 
+// Full decode with the cache staging in the same launch: the first T
+// workgroups stream chunks of kStreamChunk blocks (directory entries,
+// slabs, then the segment areas found from the chunk's first and last
+// directory entries, checked against the layout) through the caches in
+// block order, eight 16-byte loads in flight per lane; the remaining
+// workgroups decode one block each, XCD-major, as decode_kernel.  A block
+// may decode before its chunk is streamed (it then reads from HBM).
+constexpr uint32_t kStreamChunk = 16;
+constexpr uint32_t kStreamGroups = 8192;
+
+template <int KB>
+__global__ __launch_bounds__(64) void decode_full_kernel(const uint8_t* __restrict__ blob, DecodeArgs a, uint32_t T,
+                                                         void* __restrict__ out)
+{
+    const Layout& L = a.L;
+    if (blockIdx.x < T) {
+        const uint64_t nch = (L.nblocks + kStreamChunk - 1) / kStreamChunk;
+        const uint4* dir = reinterpret_cast<const uint4*>(blob + L.off_dir);
+        const uint4* p = reinterpret_cast<const uint4*>(blob);
+        uint32_t acc = 0;
+        for (uint64_t c = blockIdx.x; c < nch; c += T) {
+            const uint64_t b0 = c * kStreamChunk;
+            const uint64_t b1 = (b0 + kStreamChunk < L.nblocks ? b0 + kStreamChunk : L.nblocks) - 1;
+            const uint64_t d_lo = (L.off_dir + 16 * b0) / 16, dn = b1 + 1 - b0;
+            const uint64_t r_lo = (L.off_res + b0 * L.res_stride) / 16, rn = (b1 + 1 - b0) * L.res_stride / 16;
+            const uint4 e0 = dir[b0], e1 = dir[b1];
+            uint64_t lo = e0.x | ((uint64_t)e0.y << 32);
+            uint64_t hi = (e1.x | ((uint64_t)e1.y << 32)) + a16(2ull * e1.z) +
+                          a16((uint64_t)((e1.w >> 16) & 0xFF) * e1.z) + a16((uint64_t)(e1.w >> 24) * e1.z) +
+                          a16((uint64_t)L.fb * e1.z);
+            if (!(lo >= L.off_seg && lo <= hi && hi <= a.bytes)) lo = hi = L.off_seg;  // corrupt: skip
+            const uint64_t s_lo = lo / 16, sn = (hi - lo) / 16;
+            const uint64_t tot = dn + rn + sn;  // >= 1
+            auto at = [&](uint64_t i) {
+                i = i < tot ? i : tot - 1;
+                return i < dn ? d_lo + i : i < dn + rn ? r_lo + (i - dn) : s_lo + (i - dn - rn);
+            };
+            for (uint64_t i0 = threadIdx.x; i0 < tot; i0 += 64 * 8) {
+                uint4 v[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) v[u] = p[at(i0 + 64ull * u)];
+#pragma unroll
+                for (int u = 0; u < 8; u++) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+            }
+        }
+        asm volatile("" ::"v"(acc));  // keeps the loads; no instruction is emitted
+        return;
+    }
+    const uint32_t w = blockIdx.x - T;
+    const uint64_t rel = (uint64_t)(w % 8) * a.per_xcd + w / 8;
+    if (rel >= a.nblk) return;
+    decode_block<KB, false>(blob, a, a.b_first + rel, a.raw_cap, out);
+}
+
 // Streams the directory entries and segment areas of blocks [b_lo, b_hi]
 // through the caches (the approximate decode reads no slab); the segment
 // byte range comes from the first and last directory entries, checked
@@ -3306,11 +3360,32 @@ hipError_t launch_decode(const uint8_t* d_blob, const Layout& L, uint64_t begin,
                        : (approx ? decode_kernel<8, true, true> : range ? decode_kernel<8, true> : decode_kernel<8, false>);
     hipError_t e = allow_lds((const void*)k, lds);
     if (e != hipSuccess) return e;
-    // Stage the compressed bytes the decode will read in the on-die cache:
-    // the whole tail of the blob for a full decode; the directory entries and
-    // slabs of the blocks touched for a range (its segment areas are found
-    // only through the directory); the directory entries and segment areas
-    // for the approximate decode, which reads no slab.
+    // A full decode stages the blob in the on-die cache from inside its own
+    // launch (decode_full_kernel; T a multiple of 8 keeps the XCD-major block
+    // order).  Otherwise a separate pass stages the bytes the decode will
+    // read: the whole tail of the blob for a full decode past the grid limit;
+    // the directory entries and slabs of the blocks touched for a range (its
+    // segment areas are found only through the directory); the directory
+    // entries and segment areas for the approximate decode, which reads no slab.
+    if (!range && L.nblocks <= kMaxGrid - kStreamGroups) {
+        auto kf = L.kb == 4 ? decode_full_kernel<4> : decode_full_kernel<8>;
+        e = allow_lds((const void*)kf, lds);
+        if (e != hipSuccess) return e;
+        const uint64_t nch = (L.nblocks + kStreamChunk - 1) / kStreamChunk;
+        const uint32_t T = (uint32_t)((nch < kStreamGroups ? nch : kStreamGroups) + 7) / 8 * 8;
+        DecodeArgs a;
+        a.L = L;
+        a.begin = begin;
+        a.end = end;
+        a.b_first = 0;
+        a.nblk = L.nblocks;
+        a.per_xcd = (a.nblk + 7) / 8;
+        a.raw_cap = raw_cap;
+        a.bytes = L.blob_bytes;
+        a.flags = nullptr;
+        hipLaunchKernelGGL(kf, dim3((uint32_t)(T + a.per_xcd * 8)), dim3(64), lds, stream, d_blob, a, T, d_out);
+        return hipGetLastError();
+    }
     if (approx) {
         if (b_hi + 1 - b_lo >= kTouchMinBytes / 1024)
             hipLaunchKernelGGL(touch_blocks_kernel, dim3(kTouchGrid), dim3(256), 0, stream, d_blob, L, b_lo, b_hi);
