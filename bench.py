@@ -845,7 +845,7 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-            "kernel": "lc_decompress (decode_full_kernel<8>: cache-staging workgroups + decode workgroups)",
+            "kernel": "lc_decompress (decode_full_kernel<8, false>: cache-staging workgroups + decode workgroups)",
             "bytes_per_launch": int(np.mean(dec_alg_bytes)), "avg_launch_ms": round(dec_avg_ms, 4),
         },
         "roofline_encode": roofline_encode,

@@ -2157,29 +2157,31 @@ __global__ __launch_bounds__(64) void decode_kernel(const uint8_t* __restrict__ 
     decode_block<KB, RANGE, APPROX>(blob, a, a.b_first + rel, a.raw_cap, out);
 }
 
-// Full decode with the cache staging in the same launch: the first T
-// workgroups stream chunks of kStreamChunk blocks (directory entries,
-// slabs, then the segment areas found from the chunk's first and last
-// directory entries, checked against the layout) through the caches in
-// block order, eight 16-byte loads in flight per lane; the remaining
-// workgroups decode one block each, XCD-major, as decode_kernel.  A block
-// may decode before its chunk is streamed (it then reads from HBM).
+// Decode with the cache staging in the same launch: the first T
+// workgroups stream chunks of kStreamChunk blocks of the launch's blocks
+// [b_first, b_first + nblk) (directory entries, slabs, then the segment
+// areas found from the chunk's first and last directory entries, checked
+// against the layout) through the caches in block order, eight 16-byte
+// loads in flight per lane; the remaining workgroups decode one block
+// each, XCD-major, as decode_kernel (RANGE: the keys of [begin, end)).  A
+// block may decode before its chunk is streamed (it then reads from HBM).
 constexpr uint32_t kStreamChunk = 16;
 constexpr uint32_t kStreamGroups = 8192;
 
-template <int KB>
+template <int KB, bool RANGE>
 __global__ __launch_bounds__(64) void decode_full_kernel(const uint8_t* __restrict__ blob, DecodeArgs a, uint32_t T,
                                                          void* __restrict__ out)
 {
     const Layout& L = a.L;
     if (blockIdx.x < T) {
-        const uint64_t nch = (L.nblocks + kStreamChunk - 1) / kStreamChunk;
+        const uint64_t nch = (a.nblk + kStreamChunk - 1) / kStreamChunk;
+        const uint64_t b_end = a.b_first + a.nblk;  // <= L.nblocks
         const uint4* dir = reinterpret_cast<const uint4*>(blob + L.off_dir);
         const uint4* p = reinterpret_cast<const uint4*>(blob);
         uint32_t acc = 0;
         for (uint64_t c = blockIdx.x; c < nch; c += T) {
-            const uint64_t b0 = c * kStreamChunk;
-            const uint64_t b1 = (b0 + kStreamChunk < L.nblocks ? b0 + kStreamChunk : L.nblocks) - 1;
+            const uint64_t b0 = a.b_first + c * kStreamChunk;
+            const uint64_t b1 = (b0 + kStreamChunk < b_end ? b0 + kStreamChunk : b_end) - 1;
             const uint64_t d_lo = (L.off_dir + 16 * b0) / 16, dn = b1 + 1 - b0;
             const uint64_t r_lo = (L.off_res + b0 * L.res_stride) / 16, rn = (b1 + 1 - b0) * L.res_stride / 16;
             const uint4 e0 = dir[b0], e1 = dir[b1];
@@ -2208,7 +2210,7 @@ __global__ __launch_bounds__(64) void decode_full_kernel(const uint8_t* __restri
     const uint32_t w = blockIdx.x - T;
     const uint64_t rel = (uint64_t)(w % 8) * a.per_xcd + w / 8;
     if (rel >= a.nblk) return;
-    decode_block<KB, false>(blob, a, a.b_first + rel, a.raw_cap, out);
+    decode_block<KB, RANGE>(blob, a, a.b_first + rel, a.raw_cap, out);
 }
 
 // Streams the directory entries and segment areas of blocks [b_lo, b_hi]
@@ -3360,25 +3362,28 @@ hipError_t launch_decode(const uint8_t* d_blob, const Layout& L, uint64_t begin,
                        : (approx ? decode_kernel<8, true, true> : range ? decode_kernel<8, true> : decode_kernel<8, false>);
     hipError_t e = allow_lds((const void*)k, lds);
     if (e != hipSuccess) return e;
-    // A full decode stages the blob in the on-die cache from inside its own
-    // launch (decode_full_kernel; T a multiple of 8 keeps the XCD-major block
-    // order).  Otherwise a separate pass stages the bytes the decode will
-    // read: the whole tail of the blob for a full decode past the grid limit;
-    // the directory entries and slabs of the blocks touched for a range (its
-    // segment areas are found only through the directory); the directory
-    // entries and segment areas for the approximate decode, which reads no slab.
-    if (!range && L.nblocks <= kMaxGrid - kStreamGroups) {
-        auto kf = L.kb == 4 ? decode_full_kernel<4> : decode_full_kernel<8>;
+    // A decode (full or range) stages the compressed bytes of its blocks in
+    // the on-die cache from inside its own launch (decode_full_kernel; T a
+    // multiple of 8 keeps the XCD-major block order).  Otherwise a separate
+    // pass stages the bytes the decode will read: the whole tail of the blob
+    // for a full decode past the grid limit; the directory entries and slabs
+    // of the blocks touched for such a range (its segment areas are found
+    // only through the directory); the directory entries and segment areas
+    // for the approximate decode, which reads no slab.
+    const uint64_t nblk = b_hi + 1 - b_lo;
+    if (!approx && nblk <= kMaxGrid - kStreamGroups) {
+        auto kf = L.kb == 4 ? (range ? decode_full_kernel<4, true> : decode_full_kernel<4, false>)
+                            : (range ? decode_full_kernel<8, true> : decode_full_kernel<8, false>);
         e = allow_lds((const void*)kf, lds);
         if (e != hipSuccess) return e;
-        const uint64_t nch = (L.nblocks + kStreamChunk - 1) / kStreamChunk;
+        const uint64_t nch = (nblk + kStreamChunk - 1) / kStreamChunk;
         const uint32_t T = (uint32_t)((nch < kStreamGroups ? nch : kStreamGroups) + 7) / 8 * 8;
         DecodeArgs a;
         a.L = L;
         a.begin = begin;
         a.end = end;
-        a.b_first = 0;
-        a.nblk = L.nblocks;
+        a.b_first = b_lo;
+        a.nblk = nblk;
         a.per_xcd = (a.nblk + 7) / 8;
         a.raw_cap = raw_cap;
         a.bytes = L.blob_bytes;
