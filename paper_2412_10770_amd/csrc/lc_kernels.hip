@@ -253,6 +253,29 @@ __device__ __forceinline__ void bounds_f64(double Df, double epsf, double scf, d
     h = r < 0.0 ? q - 1.0 : q;
 }
 
+// bounds_f64 that also gives, for D < eps, m = floor((eps - D) 2^F / d) (the
+// term of a segment whose lower ends are all negative; mbig otherwise): one
+// quotient of |D - eps| 2^F serves both sides, since the lanes of a wave
+// that take either side share its instructions anyway.
+__device__ __forceinline__ void bounds_m_f64(double Df, double epsf, double scf, double df, double inv,
+                                             double mbig, double& pp, double& h, double& m)
+{
+    constexpr double kTwo52 = 4503599627370496.0;
+    const bool up = Df >= epsf;
+    const double x = (up ? Df - epsf : epsf - Df) * scf;
+    double q = __builtin_fma(x, inv, kTwo52) - kTwo52;
+    double r = __builtin_fma(-q, df, x);
+    const bool neg = r < 0.0;
+    q = neg ? q - 1.0 : q;
+    r = neg ? r + df : r;
+    pp = up ? q + (r != 0.0 ? 2.0 : 1.0) : 0.0;
+    m = up ? mbig : q;
+    const double y = (Df + epsf + 1.0) * scf - 1.0;
+    const double q2 = __builtin_fma(y, inv, kTwo52) - kTwo52;
+    const double r2 = __builtin_fma(-q2, df, y);
+    h = r2 < 0.0 ? q2 - 1.0 : q2;
+}
+
 // div_fast where the caller has established the 2^49 bound (a uniform flag), else div_small.
 __device__ __forceinline__ uint64_t div_pick(bool fast, uint64_t x, uint32_t d, double inv, uint32_t* rem = nullptr)
 {
@@ -1555,28 +1578,24 @@ __device__ __forceinline__ void lanes_fit(const LaneBlock& in, const void* __res
     uint64_t Ka = first, P = 0, H = ~0ull, maxA = 0, maxd = 0;
     double inv = 1.0;  // recip(d) for the next key, d = its distance from the anchor
     constexpr double kBig = 1.8e19;  // no upper end yet: above every real bound (< 2^49)
-    double Pf = 0.0, Hf = kBig;  // the fast path's P and H
+    double Pf = 0.0, Hf = kBig, Mf = kBig;  // the fast path's P, H and M
+    uint64_t M = ~0ull;                      // the other path's M
     const double epsf = (double)eps, scf = (double)(1ull << F);
     uint64_t prev = (nb && in.has_prev) ? (uint64_t)Kb[-1] : 0;
     bool unsorted = false;
 
     // closes segment [s, e) with slope interval (Pc, Hc) (P encoding: 1 + the
-    // largest non-negative lower end, 0 while there is none); the keys are
-    // re-read from global memory only when every lower end is negative
-    auto close = [&](uint32_t e, uint64_t Pc, uint64_t Hc) {
+    // largest non-negative lower end, 0 while there is none); when every
+    // lower end is negative, lo = -Mc with Mc the running minimum of
+    // floor((eps - D) 2^F / d) over the segment's keys, kept by the walk
+    auto close = [&](uint32_t e, uint64_t Pc, uint64_t Hc, uint64_t Mc) {
         uint64_t A = 0;
         if (e > s + 1) {
             if (Pc != 0) {
                 const uint64_t lo = Pc - 1;
                 A = lo + (Hc - lo) / 2;
             } else {
-                uint64_t M = ~0ull;
-                for (uint32_t j = s + 1; j < e; j++) {
-                    const uint32_t d = j - s;
-                    const uint64_t m = div_pick(fast, (eps - ((uint64_t)Kb[j] - Ka)) << F, d, recip(d));
-                    M = m < M ? m : M;
-                }
-                A = Hc >= M ? (Hc - M) / 2 : 0;
+                A = Hc >= Mc ? (Hc - Mc) / 2 : 0;
             }
         }
         if (RECORDS) {
@@ -1615,19 +1634,21 @@ __device__ __forceinline__ void lanes_fit(const LaneBlock& in, const void* __res
                     if (e > 0) {
                         const uint32_t d = e - s;
                         const double inv_next = recip(d + 1);  // the next step's, off the critical path
-                        double pp, h;
-                        bounds_f64(exact_f64(key - Ka), epsf, scf, (double)d, inv, pp, h);
+                        double pp, h, mm;
+                        bounds_m_f64(exact_f64(key - Ka), epsf, scf, (double)d, inv, kBig, pp, h, mm);
                         const double Pn = pp > Pf ? pp : Pf, Hn = h < Hf ? h : Hf;
                         if (Pn != 0.0 && Pn - 1.0 > Hn) {
-                            close(e, (uint64_t)Pf, (uint64_t)Hf);
+                            close(e, (uint64_t)Pf, (uint64_t)Hf, (uint64_t)Mf);
                             s = e;
                             Ka = key;
                             Pf = 0.0;
                             Hf = kBig;
+                            Mf = kBig;
                             inv = 1.0;  // d = 1 at the next key
                         } else {
                             Pf = Pn;
                             Hf = Hn;
+                            Mf = mm < Mf ? mm : Mf;
                             inv = inv_next;
                         }
                     }
@@ -1646,28 +1667,34 @@ __device__ __forceinline__ void lanes_fit(const LaneBlock& in, const void* __res
                         const double inv_next = recip(d + 1);
                         const uint64_t D = key - Ka;
                         bool fail = D >= lim;
-                        uint64_t Pn = P, Hn = H;
+                        uint64_t Pn = P, Hn = H, Mn = M;
                         if (!fail) {
-                            if (D >= eps) {
-                                uint32_t rem;
-                                const uint64_t q = div_small((D - eps) << F, d, inv, &rem);
+                            // one quotient of |D - eps| 2^F: the lower end, or the M term
+                            const bool up = D >= eps;
+                            uint32_t rem;
+                            const uint64_t q = div_small((up ? D - eps : eps - D) << F, d, inv, &rem);
+                            if (up) {
                                 const uint64_t pp = q + (rem != 0) + 1;  // 1 + ceil((D - eps) 2^F / d)
                                 Pn = pp > P ? pp : P;
+                            } else {
+                                Mn = q < M ? q : M;  // floor((eps - D) 2^F / d)
                             }
                             const uint64_t h = div_small(((D + eps + 1) << F) - 1, d, inv);
                             Hn = h < H ? h : H;
                             fail = Pn != 0 && Pn - 1 > Hn;
                         }
                         if (fail) {
-                            close(e, P, H);
+                            close(e, P, H, M);
                             s = e;
                             Ka = key;
                             P = 0;
                             H = ~0ull;
+                            M = ~0ull;
                             inv = 1.0;
                         } else {
                             P = Pn;
                             H = Hn;
+                            M = Mn;
                             inv = inv_next;
                         }
                     }
@@ -1680,9 +1707,9 @@ __device__ __forceinline__ void lanes_fit(const LaneBlock& in, const void* __res
     }
     if (nb) {
         if (fast)
-            close(nb, (uint64_t)Pf, Hf >= kBig ? ~0ull : (uint64_t)Hf);
+            close(nb, (uint64_t)Pf, Hf >= kBig ? ~0ull : (uint64_t)Hf, (uint64_t)Mf);
         else
-            close(nb, P, H);
+            close(nb, P, H, M);
     }
     if (__ballot(unsorted) != 0 && lane == 0) atomicOr(flags, kFlagUnsorted);
     if (nb) {
