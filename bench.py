@@ -265,6 +265,70 @@ def bench_batch(dev, steps: int, warmup: int, nlists: int = 4096, cands=(7, 31, 
     }
 
 
+def bench_small(dev, n: int = 1_000_000, eps: int = 63, n_access: int = 100_000, reps: int = 20):
+    """The plain-method configuration: n sorted uint32 keys, gaps uniform in
+    [1, 64], eps 63, 1024-key blocks: compress + decompress + n_access
+    access(i) with i uniform, each timed with HIP events (mean of reps after
+    one warm-up), beside the CPU oracle on the same keys (compress, decode).
+    Small enough that launches and the per-block walk, not bandwidth, set
+    the time."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2412_10770_amd import lc, workloads
+
+    keys = workloads.uniform_gaps(n, device=dev)
+    host = workloads.as_numpy(keys)
+    idx = workloads.uniform_indices(n_access, n, seed=workloads.SEED_BASE + 106, device=dev)
+    bmax, wsb = lc.compress_bound(n, 4, eps, frac_bits=FRAC_BITS)
+    blob = torch.empty(bmax, dtype=torch.uint8, device=dev)
+    ws = torch.empty(max(wsb, 16), dtype=torch.uint8, device=dev)
+    nb = torch.zeros(1, dtype=torch.int64, device=dev)
+    fl = torch.zeros(1, dtype=torch.int32, device=dev)
+    lc.compress_async(keys, eps, blob, ws, nb, fl, frac_bits=FRAC_BITS)
+    torch.cuda.synchronize()
+    b = lc.Blob.from_device(blob)
+    out = lc.decompress(b)
+    acc = lc.access(b, idx)
+    assert torch.equal(out, keys) and torch.equal(acc, keys[idx])
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    tc, td, ta = [], [], []
+    for _ in range(reps + 1):
+        e0, e1, e2, e3 = ev(), ev(), ev(), ev()
+        e0.record()
+        lc.compress_async(keys, eps, blob, ws, nb, fl, frac_bits=FRAC_BITS)
+        e1.record()
+        lc.decompress(b, out=out)
+        e2.record()
+        lc.access(b, idx, out=acc, flags=fl, check=False)
+        e3.record()
+        torch.cuda.synchronize()
+        tc.append(e0.elapsed_time(e1))
+        td.append(e1.elapsed_time(e2))
+        ta.append(e2.elapsed_time(e3))
+    assert int(fl.item()) == 0
+    import time
+    t0 = time.perf_counter()
+    ob = oracle.compress(host, eps, 10, FRAC_BITS)
+    t_oc = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.decode(ob)
+    t_od = time.perf_counter() - t0
+    assert np.array_equal(ob, b.data.cpu().numpy())
+    c, d_, a_ = float(np.mean(tc[1:])), float(np.mean(td[1:])), float(np.mean(ta[1:]))
+    return {
+        "workload": f"{n} sorted uint32 keys, K[0] = 0, gaps uniform in [1, 64]; eps {eps}, blocks of 1024, "
+                    f"F = {FRAC_BITS}; compress + decompress + {n_access} access(i), i uniform",
+        "bits_per_key": round(b.bits_per_key, 4), "ratio": round(b.ratio, 5),
+        "compress_ms": round(c, 4), "decompress_ms": round(d_, 4),
+        "decoded_GBps": round(n * 4 / d_ / 1e6, 2), "access_lookups_per_s": round(n_access / a_ * 1e3, 1),
+        "step_ms": round(c + d_ + a_, 4),
+        "oracle_cpu_one_core": {"compress_ms": round(t_oc * 1e3, 2), "decode_ms": round(t_od * 1e3, 2)},
+        "note": "the GPU blob equals the oracle's byte for byte",
+    }
+
+
 def bench_lookups(dev, n: int = 200_000_000, eps: int = 63, n_access: int = 10_000_000, n_lb: int = 1_000_000,
                   reps: int = 10):
     """Point lookups on the heterogeneous-runs workload: n uint64 keys in
@@ -857,6 +921,7 @@ def main():
     }
     if not args.no_lookups:
         result["lookups"] = bench_lookups(dev)
+        result["plain_method_1M"] = bench_small(dev)
         torch.cuda.empty_cache()
     if not args.no_queries:
         result["queries"] = bench_queries(dev)
