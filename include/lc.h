@@ -172,6 +172,10 @@ lc_status lc_decompress_range(const void* d_blob, const lc_blob_info* info, uint
 /* Random access on the compressed form: d_out[q] = K[d_idx[q]] for
  * q < m (d_idx: device u64[m]; d_out: device, key_bytes each).  An index
  * >= n writes 0 and ORs LC_FLAG_RANGE into *d_flags (device u32, required).
+ * The blob's directory and segment areas are trusted as lc_compress wrote
+ * them (unlike the block decoders, point queries do not re-check directory
+ * entries; the same holds for lc_lower_bound, lc_quantile and the server's
+ * point requests).
  * Errors: LC_EINVAL, LC_EDEVICE. */
 lc_status lc_access(const void* d_blob, const lc_blob_info* info, const uint64_t* d_idx,
                     uint64_t m, void* d_out, uint32_t* d_flags, void* stream);

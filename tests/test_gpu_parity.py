@@ -633,3 +633,52 @@ def test_lanes_fit_unsorted_and_determinism(lc):
         bad[pos] = bad[pos - 1] - np.uint64(1)
         with pytest.raises(lc.LcError):
             lc.compress(_to_dev(bad), 15, 6)
+
+
+def test_corrupt_directory_entries_skip_their_blocks(lc):
+    """Directory entries inconsistent with the layout (a segment area past the
+    blob or before its region, no segments, an invalid byte width, a wrong
+    key count) make the block decoders -- the full decode and ranges, with
+    their staging workgroups -- skip those blocks and write nothing there;
+    every other block decodes.  (Point queries trust the blob.)"""
+    rng = np.random.default_rng(21)
+    keys = np.cumsum(rng.integers(1, 100, 40 * 1024 + 77)).astype(np.uint64)
+    blob = lc.compress(_to_dev(keys), 63)
+    h = blob.info
+    data = blob.data.cpu().numpy().copy()
+    dirs = data[h.off_dir:h.off_dir + 16 * h.nblocks].reshape(-1, 16)
+    bad = {
+        0: lambda d: d[0:8].view(np.uint64).__setitem__(0, h.blob_bytes + 4096),
+        3: lambda d: d[0:8].view(np.uint64).__setitem__(0, h.off_seg - 16),
+        11: lambda d: d[8:12].view(np.uint32).__setitem__(0, 0),
+        20: lambda d: d.__setitem__(14, 3),
+        33: lambda d: d[12:14].view(np.uint16).__setitem__(0, 5),
+        40: lambda d: d[8:12].view(np.uint32).__setitem__(0, 0xFFFFFFFF),
+    }
+    for b, f in bad.items():
+        row = dirs[b].copy()
+        f(row)
+        dirs[b] = row
+    data[h.off_dir:h.off_dir + 16 * h.nblocks] = dirs.ravel()
+    cb = lc.Blob.from_device(torch.from_numpy(data).to(DEV))
+    n = len(keys)
+    B = 1 << h.log2_block
+    out = torch.full((n,), -1, dtype=torch.int64, device=DEV)
+    lc.decompress(cb, out=out)
+    got = out.cpu().numpy()
+    for b in range(h.nblocks):
+        lo, hi = b * B, min(n, (b + 1) * B)
+        if b in bad:
+            assert np.all(got[lo:hi] == -1), b
+        else:
+            assert np.array_equal(got[lo:hi].view(np.uint64), keys[lo:hi]), b
+    for a, e in ((0, n), (5 * B + 7, 25 * B + 3), (10 * B, 12 * B), (39 * B + 1, n)):
+        o = torch.full((e - a,), -1, dtype=torch.int64, device=DEV)
+        lc.decompress_range(cb, a, e, out=o)
+        g = o.cpu().numpy()
+        for b in range(a // B, (e - 1) // B + 1):
+            lo, hi = max(a, b * B), min(e, (b + 1) * B)
+            if b in bad:
+                assert np.all(g[lo - a:hi - a] == -1), (a, e, b)
+            else:
+                assert np.array_equal(g[lo - a:hi - a].view(np.uint64), keys[lo:hi]), (a, e, b)
