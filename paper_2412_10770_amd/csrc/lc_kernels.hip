@@ -1076,11 +1076,9 @@ __global__ __launch_bounds__(64) void fit_opt_kernel(const void* __restrict__ ke
         auto yU = [&](uint32_t i) -> uint64_t { return (uint64_t)sk[i] - Ks; };
         auto yL = [&](uint32_t i) -> uint64_t { return i == s ? r : (uint64_t)sk[i] - Ks; };
         uint32_t nU = 1, nL = 1;
-        if (lane == 0) {
-            hU[0] = (uint16_t)s;
-            hL[0] = (uint16_t)s;
-        }
-        __syncthreads();
+        hU[0] = (uint16_t)s;  // every lane, as below
+        hL[0] = (uint16_t)s;
+        __builtin_amdgcn_wave_barrier();
         uint64_t lo = 0, hi = ~0ull;
         uint32_t e = s + 1;
         for (; e < nb; e++) {
@@ -1137,14 +1135,15 @@ __global__ __launch_bounds__(64) void fit_opt_kernel(const void* __restrict__ ke
                 if (turn(yL(h1), yL(h2), h1, h2) > 0) break;
                 nL--;
             }
-            __syncthreads();  // every lane has read the hulls before lane 0 writes
-            if (lane == 0) {
-                hU[nU] = (uint16_t)e;
-                hL[nL] = (uint16_t)e;
-            }
+            // every lane writes the same entries, so each lane's later reads
+            // follow its own write in program order (one wave per workgroup:
+            // no barrier needed, only the compiler must keep the order)
+            __builtin_amdgcn_wave_barrier();
+            hU[nU] = (uint16_t)e;
+            hL[nL] = (uint16_t)e;
             nU++;
             nL++;
-            __syncthreads();
+            __builtin_amdgcn_wave_barrier();
         }
         // slope, then the intercept interval [g, h] of that slope, relative to
         // Lo_s = (K[s] - eps + r) 2^F: g' = max(0, max_j (y_j - r) 2^F - A d_j),
@@ -1189,7 +1188,7 @@ __global__ __launch_bounds__(64) void fit_opt_kernel(const void* __restrict__ ke
         maxd = delta > maxd ? delta : maxd;
         nseg++;
         s = e;
-        __syncthreads();  // the hull stacks are reset for the next segment
+        __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
 
