@@ -8,15 +8,26 @@
 //   tile_reduce  per 256 blocks: segment-area bytes, segment counts
 //   tile_scan    one workgroup: exclusive scan over tiles, header, blob size
 //   dir_emit     per 256 blocks: in-tile scan -> directory entries
-//   seg_emit     one wave per block: segment SoA in 16-byte chunks
+//   fit_lanes    one block per lane, 64 per wave, the same greedy fit walked
+//                key by key in lockstep (lists of >= 16384 blocks), then
+//   code_pack    one wave per block: residual codes from the segment records
+//   fit_min      one wave per block: the fewest segments of the anchored class
+//   fit_opt      one wave per block: the optimal fit over free fixed-point
+//                intercepts, scanning the two convex hulls per key
+//   seg_emit     16 lanes per block: segment SoA in 16-byte chunks
 // Decode (Def. 1 Dec, K[i] = floor(f(i)) + Delta[i]):
-//   touch        streams the compressed bytes through the on-die cache
+//   decode_full  staging workgroups stream the blocks' compressed bytes
+//                through the on-die cache while the others decode (a full
+//                decode or a range, one launch)
 //   decode       one wave per block: segment table and residual slab staged
 //                in LDS (model arrays read from the blob for large areas),
-//                16-byte coalesced stores; also serves ranges
+//                16-byte coalesced stores (the decode part of decode_full;
+//                alone for the approximate decode and past the grid limit)
+//   touch        the separate staging pass of those cases
 //   access       one lane per query, K[i] from the compressed block
-//   lower_bound  one lane per query: first_keys -> segment anchors -> search
-//                inside one segment (the segment pruning of Sec. III-A)
+//   lower_bound  one lane per query: first_keys -> segment anchors -> the
+//                eps window of the model -> search inside it (the segment
+//                pruning of Sec. III-A)
 // Batches of lists: batch_fit / batch_scan / batch_emit / batch_pick /
 //   batch_decode run the same per-block work over all lists of a batch.
 // Request server: serve decodes the range blocks and answers the point
