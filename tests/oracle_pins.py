@@ -64,6 +64,8 @@ def load_golden(name: str) -> dict:
                 in_blob = True
             elif key == "keys":
                 out["keys"] = [int(t) for t in val.split()]
+            elif key == "fit":
+                out["fit"] = val
             else:
                 out[key] = int(val)
     out["blob"] = np.array(out["blob"], np.uint8)
@@ -289,10 +291,10 @@ def check_byte_widths(ref):
 
 
 def check_golden(ref):
-    for name in ("ap4_eps1.txt", "break4_eps1.txt"):
+    for name in ("ap4_eps1.txt", "break4_eps1.txt", "opt4_frac_eps0.txt"):
         g = load_golden(name)
         keys = np.array(g["keys"], np.uint32 if g["key_bytes"] == 4 else np.uint64)
-        blob = ref.compress(keys, g["eps"], g["log2_block"], g["frac_bits"])
+        blob = ref.compress(keys, g["eps"], g["log2_block"], g["frac_bits"], fit=g.get("fit", "greedy"))
         assert np.array_equal(blob, g["blob"]), name
         assert np.array_equal(ref.decode(g["blob"]), keys), name
 

@@ -113,11 +113,12 @@ def test_edge_lists(lc, wl):
 
 
 def test_golden_blobs_on_gpu(lc):
-    for name in ("ap4_eps1.txt", "break4_eps1.txt"):
+    for name in ("ap4_eps1.txt", "break4_eps1.txt", "opt4_frac_eps0.txt"):
         g = P.load_golden(name)
         keys = np.array(g["keys"], np.uint32 if g["key_bytes"] == 4 else np.uint64)
-        blob = lc.compress(_to_dev(keys), g["eps"], g["log2_block"], g["frac_bits"])
+        blob = lc.compress(_to_dev(keys), g["eps"], g["log2_block"], g["frac_bits"], fit=g.get("fit", "greedy"))
         assert np.array_equal(blob.data.cpu().numpy(), g["blob"]), name
+        assert np.array_equal(_host(lc.decompress(blob), g["key_bytes"]), keys), name
 
 
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 1023, 1024, 1025, 4096 * 3 + 5])
