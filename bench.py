@@ -623,7 +623,8 @@ def bench_fits(dev, keys_lognormal=None, reps: int = 3):
     F = 0 (integer slopes and intercepts: no fraction array).  Compress and
     decompress time (HIP events, mean of `reps` after one warm-up), blob size
     and segment count, per workload and eps.  Every blob is decoded and
-    compared with its keys."""
+    compared with its keys; 1e6 access(i) and 1e6 lower_bound(q) (uniform)
+    are timed on it and compared with the definitions."""
     import numpy as np
     import torch
 
@@ -647,6 +648,19 @@ def bench_fits(dev, keys_lognormal=None, reps: int = 3):
         torch.cuda.synchronize()
         n, kb = keys.numel(), keys.element_size()
         out = torch.empty_like(keys)
+        # point queries on every variant's blob: 1e6 access(i), 1e6 lower_bound(q)
+        nq = 1_000_000
+        idx = workloads.uniform_indices(nq, n, seed=workloads.SEED_BASE + 107, device=dev)
+        lo_k, hi_k = int(keys[0]) & ((1 << (8 * kb)) - 1), int(keys[-1]) & ((1 << (8 * kb)) - 1)
+        qs = workloads.uniform_keys(nq, lo_k, hi_k, seed=workloads.SEED_BASE + 108, device=dev, key_bytes=kb)
+        want_acc = keys[idx]
+        if kb == 4:  # u32 bit patterns in int32: compare as unsigned
+            want_pos = torch.searchsorted(keys.to(torch.int64) & 0xFFFFFFFF, qs.to(torch.int64) & 0xFFFFFFFF,
+                                          side="left")
+        else:
+            want_pos = torch.searchsorted(keys, qs, side="left")
+        acc = torch.empty_like(want_acc)
+        pos = torch.empty(nq, dtype=torch.int64, device=dev)
         rows = {}
         for eps in eps_list:
             bmax, ws_bytes = lc.compress_bound(n, kb, eps, fit="opt")  # the largest of the variants
@@ -681,8 +695,27 @@ def bench_fits(dev, keys_lognormal=None, reps: int = 3):
                     dmarks.append((e0, e1))
                 torch.cuda.synchronize()
                 dms = float(np.mean([a.elapsed_time(c) for a, c in dmarks]))
+                lc.access(b, idx, out=acc, flags=fl, check=False)
+                lc.lower_bound(b, qs, out=pos)
+                torch.cuda.synchronize()
+                assert int(fl.item()) == 0 and torch.equal(acc, want_acc) and torch.equal(pos, want_pos), \
+                    (name, eps, label, "lookups")
+                qmarks = []
+                for _ in range(reps):
+                    e0, e1, e2 = ev(), ev(), ev()
+                    e0.record()
+                    lc.access(b, idx, out=acc, flags=fl, check=False)
+                    e1.record()
+                    lc.lower_bound(b, qs, out=pos)
+                    e2.record()
+                    qmarks.append((e0, e1, e2))
+                torch.cuda.synchronize()
+                ams = float(np.mean([a.elapsed_time(c) for a, c, _ in qmarks]))
+                lms = float(np.mean([c.elapsed_time(d) for _, c, d in qmarks]))
                 row[label] = {"compress_ms": round(ms, 3), "keys_per_s": round(n / ms * 1e3, 1),
                               "decompress_ms": round(dms, 3), "decoded_GBps": round(n * kb / dms / 1e6, 1),
+                              "access_lookups_per_s": round(nq / ams * 1e3, 1),
+                              "lower_bound_lookups_per_s": round(nq / lms * 1e3, 1),
                               "bits_per_key": round(b.bits_per_key, 4), "nseg_total": b.info.nseg_total}
             g = row["greedy"]
             for label in ("min", "opt", "greedy_F0", "opt_F0"):
@@ -694,7 +727,7 @@ def bench_fits(dev, keys_lognormal=None, reps: int = 3):
             log(f"fits {name} eps={eps}: {row}")
             del blob, ws
         res[name] = {"n": n, "key_bytes": kb, "per_eps": rows}
-        del keys, out
+        del keys, out, idx, qs, want_acc, want_pos, acc, pos
         torch.cuda.empty_cache()
     return res
 
