@@ -2332,7 +2332,8 @@ __device__ __forceinline__ uint64_t access_one(const uint8_t* __restrict__ blob,
 // over the block's segment anchors (segment pruning), then over the decoded
 // keys of one segment.  An anchor is its segment's first key, except in
 // blobs of the optimal fit (kFlagFrac), whose anchors are intercepts within
-// eps of it: there the segment search decodes each probed first key.
+// eps of it: there a probe decodes its segment's first key only when x is
+// within eps of the intercept.
 template <int KB>
 __device__ __forceinline__ uint64_t lower_bound_one(const uint8_t* __restrict__ blob, const Layout& L, uint64_t x)
 {
@@ -2363,12 +2364,31 @@ __device__ __forceinline__ uint64_t lower_bound_one(const uint8_t* __restrict__ 
     // proportional guess to pay off)
     uint32_t t = 0;
     uint64_t Kt = first;  // first key of segment t (segment 0 starts the block)
-    for (uint32_t step = pow2_floor(v.nseg); step; step >>= 1) {
-        if (t + step < v.nseg) {
-            const uint64_t k = seg_first(t + step);
-            if (k < x) {
-                t += step;
-                Kt = k;
+    // With free intercepts, the stored delta = intercept - first is within eps
+    // of K[start] - first, and exact (no wrap modulo 2^64) for 4-byte keys or
+    // when first >= eps; then a probe decides from the delta alone unless it
+    // lies within eps of x - first, and only the segment found is decoded.
+    const bool by_delta = free_icpt && (KB == 4 || first >= L.eps);
+    if (by_delta) {
+        const uint64_t X = x - first;  // >= 1; X + eps does not overflow (first >= eps)
+        for (uint32_t step = pow2_floor(v.nseg); step; step >>= 1) {
+            if (t + step < v.nseg) {
+                const uint64_t dlt = load_w(an, t + step, v.ab);
+                const bool below = (X > L.eps && dlt < X - L.eps) ? true
+                                   : dlt >= X + L.eps            ? false
+                                                                 : seg_first(t + step) < x;
+                if (below) t += step;
+            }
+        }
+        if (t != 0) Kt = seg_first(t);
+    } else {
+        for (uint32_t step = pow2_floor(v.nseg); step; step >>= 1) {
+            if (t + step < v.nseg) {
+                const uint64_t k = seg_first(t + step);
+                if (k < x) {
+                    t += step;
+                    Kt = k;
+                }
             }
         }
     }

@@ -83,6 +83,11 @@ def check_all(lc, keys: np.ndarray, eps: int, log2b: int, rng, nq: int = 2000, f
     cand += [int(x) for x in keys[rng.integers(0, n, nq // 4)]]
     cand += [min(top, int(x) + 1) for x in keys[rng.integers(0, n, nq // 4)]]
     cand += [max(0, int(x) - 1) for x in keys[rng.integers(0, n, nq // 4)]]
+    # eps and 2 eps away: the edges of the window in which a free intercept
+    # leaves the segment search undecided
+    for off in (eps, eps + 1, 2 * eps, 2 * eps + 1):
+        cand += [min(top, int(x) + off) for x in keys[rng.integers(0, n, nq // 8)]]
+        cand += [max(0, int(x) - off) for x in keys[rng.integers(0, n, nq // 8)]]
     lo, hi = int(keys[0]), int(keys[-1])
     cand += [lo + int(v) for v in rng.integers(0, max(1, min(hi - lo + 1, 2 ** 62)), nq // 4)]
     q = np.array(cand, dtype=keys.dtype)
