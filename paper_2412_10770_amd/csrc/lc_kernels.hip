@@ -1929,9 +1929,10 @@ __device__ __forceinline__ uint64_t slope_term(uint64_t A, uint32_t d, uint32_t 
 // Decodes keys [jlo, jhi) of one block whose model arrays (u16 start[],
 // anchor-first_key[] of AB bytes, A[] of SB bytes, and with FRAC the
 // intercept fractions of c.fb bytes) are read through `start`, `an`, `sl`,
-// `fr` -- LDS copies for staged blocks, the blob otherwise.  AB / SB are the
-// block's byte widths (0: read at the runtime widths).
-template <int KB, bool RANGE, bool CLAMP, uint32_t AB, uint32_t SB, bool FRAC, typename P16, typename P8>
+// `fr` -- LDS copies for staged blocks, the blob otherwise.  AB / SB / FB
+// are the block's byte widths (0: read at the runtime widths).
+template <int KB, bool RANGE, bool CLAMP, uint32_t AB, uint32_t SB, bool FRAC, uint32_t FB = 0, typename P16,
+          typename P8>
 __device__ __forceinline__ void decode_keys(const BlockCtx& c, P16 start, P8 an, P8 sl, P8 fr,
                                             void* __restrict__ out)
 {
@@ -1953,9 +1954,12 @@ __device__ __forceinline__ void decode_keys(const BlockCtx& c, P16 start, P8 an,
         if constexpr (CLAMP) t = t < c.tmax ? t : c.tmax;
         const uint32_t d = j - start[t];
         uint64_t pred;
-        if constexpr (FRAC)  // A d + frac < 2^64 (the optimal fit's cap)
-            pred = c.first + anchor_of(t) + ((slope_of(t) * d + load_w(fr, t, c.fb)) >> c.F);
-        else
+        if constexpr (FRAC) {  // A d + frac < 2^64 (the optimal fit's cap)
+            uint64_t f;
+            if constexpr (FB != 0) f = load_fixed<FB>(fr, t);
+            else f = load_w(fr, t, c.fb);
+            pred = c.first + anchor_of(t) + ((slope_of(t) * d + f) >> c.F);
+        } else
             pred = c.first + anchor_of(t) + slope_term<SB == 0 ? 8 : SB>(slope_of(t), d, c.F);
         const uint32_t bitpos = j * c.w;
         const uint32_t wd = bitpos >> 5, sh = bitpos & 31;
@@ -2011,12 +2015,23 @@ __device__ __forceinline__ void decode_staged(const BlockCtx& c, const uint8_t* 
     const uint16_t* st = reinterpret_cast<const uint16_t*>(s_raw);
     const uint8_t* an = s_raw + off_an;
     const uint8_t* sl = s_raw + off_sl;
-    if (c.fb) {  // blobs of the optimal fit: runtime widths
+#define LC_DECODE_CASE(A_, S_) \
+    case (A_) * 16 + (S_): decode_keys<KB, RANGE, CLAMP, A_, S_, false>(c, st, an, sl, sl, out); return;
+#define LC_DECODE_FRAC4_CASE(A_, S_) \
+    case (A_) * 16 + (S_): decode_keys<KB, RANGE, CLAMP, A_, S_, true, 4>(c, st, an, sl, s_raw + off_fr, out); return;
+    if (c.fb) {  // blobs of the optimal fit: fixed widths for 4-byte fractions (F > 16)
+        if (c.fb == 4) {
+            switch (c.ab * 16 + c.sb) {
+                LC_DECODE_FRAC4_CASE(1, 1) LC_DECODE_FRAC4_CASE(1, 2) LC_DECODE_FRAC4_CASE(1, 4) LC_DECODE_FRAC4_CASE(1, 8)
+                LC_DECODE_FRAC4_CASE(2, 1) LC_DECODE_FRAC4_CASE(2, 2) LC_DECODE_FRAC4_CASE(2, 4) LC_DECODE_FRAC4_CASE(2, 8)
+                LC_DECODE_FRAC4_CASE(4, 1) LC_DECODE_FRAC4_CASE(4, 2) LC_DECODE_FRAC4_CASE(4, 4) LC_DECODE_FRAC4_CASE(4, 8)
+                LC_DECODE_FRAC4_CASE(8, 1) LC_DECODE_FRAC4_CASE(8, 2) LC_DECODE_FRAC4_CASE(8, 4) LC_DECODE_FRAC4_CASE(8, 8)
+                default: break;
+            }
+        }
         decode_keys<KB, RANGE, CLAMP, 0, 0, true>(c, st, an, sl, s_raw + off_fr, out);
         return;
     }
-#define LC_DECODE_CASE(A_, S_) \
-    case (A_) * 16 + (S_): decode_keys<KB, RANGE, CLAMP, A_, S_, false>(c, st, an, sl, sl, out); return;
     switch (c.ab * 16 + c.sb) {
         LC_DECODE_CASE(1, 1) LC_DECODE_CASE(1, 2) LC_DECODE_CASE(1, 4) LC_DECODE_CASE(1, 8)
         LC_DECODE_CASE(2, 1) LC_DECODE_CASE(2, 2) LC_DECODE_CASE(2, 4) LC_DECODE_CASE(2, 8)
@@ -2025,6 +2040,7 @@ __device__ __forceinline__ void decode_staged(const BlockCtx& c, const uint8_t* 
         default: decode_keys<KB, RANGE, CLAMP, 0, 0, false>(c, st, an, sl, sl, out); return;
     }
 #undef LC_DECODE_CASE
+#undef LC_DECODE_FRAC4_CASE
 }
 
 // Streams bytes [lo, hi) of the blob through the caches (wide coalesced
