@@ -523,6 +523,39 @@ def test_opt_fit_width_combinations(lc):
         check_all(lc, keys, eps, 6, rng, nq=32, frac_bits=F, fit="opt")
 
 
+def _opt_frac4_lists():
+    """Lists at F = 20 (4-byte fractions) for the optimal fit: the width
+    lists, plus 64-key blocks of one or two flat runs and 1-key tail blocks,
+    whose slopes take 1 or 2 bytes."""
+    out = [(k, e, 20) for k, e, _ in _width_combo_lists()]
+    rng = np.random.default_rng(5)
+    for eps in (0, 1, 7, 255, 70000, (1 << 31) - 1):
+        for jump in (1, 300, 1 << 20, 1 << 40):
+            vals = np.cumsum(rng.integers(1, 3, 6)).astype(np.uint64) * np.uint64(jump)
+            out.append((np.concatenate([np.repeat(vals, 64), vals[-1:] + np.uint64(jump)]), eps, 20))
+            out.append((np.repeat(np.arange(12, dtype=np.uint64) * np.uint64(jump), 32), eps, 20))
+    return out
+
+
+def test_opt_fit_frac4_width_combinations(lc):
+    """The block decoder has a loop per (anchor, slope) byte width for 4-byte
+    fractions; every pair an optimal-fit blob reaches at F = 20 is decoded
+    (lists chosen on the CPU by the pairs their oracle blobs use)."""
+    rng = np.random.default_rng(21)
+    seen = set()
+    for keys, eps, F in _opt_frac4_lists():
+        blob = oracle.compress(keys, eps, 6, F, fit="opt")
+        h = oracle.header(blob)
+        d = blob[h["off_dir"]:h["off_dir"] + 16 * h["nblocks"]].reshape(-1, 16)
+        pairs = set(zip(d[:, 14].tolist(), d[:, 15].tolist()))
+        if pairs <= seen:
+            continue
+        seen |= pairs
+        check_all(lc, keys, eps, 6, rng, nq=64, frac_bits=F, fit="opt")
+    want = {(a, s) for a in (1, 2, 4, 8) for s in (1, 2, 4, 8)} - {(8, 1)}
+    assert want <= seen, sorted(want - seen)
+
+
 def test_opt_fit_configs_reduced(lc, wl):
     """The benchmark recipes at sizes the oracle's optimal fit finishes in
     seconds, at F = 20 and F = 0."""
