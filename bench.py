@@ -27,6 +27,8 @@ sys.path.insert(0, ROOT)
 METRIC = "decoded GB/s + lookups/s vs plain per-list kernel; comp. ratio; p99 latency"
 HBM_PEAK_GBPS = 8000.0
 CALIB_COPY_BYTES = 256 << 20  # plain device copy of known size, read by counter runs to scale them
+FLUSH_BYTES = 512 << 20  # each cold decode follows a copy of this many bytes (2x the on-die cache)
+HEADLINE_MAX_BYTES = 2048  # the last stdout line (the headline) stays this short
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "decode_traffic.json")
 VALU_FILE = os.path.join(ROOT, "profiles", "compress_valu.json")
 # VALU peak in lane-operations: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a wave64
@@ -74,38 +76,85 @@ def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(host_keys, eps_list, budget_s: float = 24.0):
-    """Oracle decode (plain C, one thread) over the same eps sweep as the
-    timed step, on a prefix of the workload sized to about budget_s seconds
-    of oracle compress + decode in total: sum(8 n) / sum(decode time)."""
+def host_cpu():
+    """The host's CPU model (from /proc/cpuinfo) and the cores this process may use."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, avail
+
+
+def cpu_baseline(host_keys, eps_list, budget_s: float = 24.0, max_threads: int = 16, reps: int = 5):
+    """The oracle's plain C decoder timed on the host over the same eps sweep
+    as the step, on a prefix of the workload sized to about budget_s seconds
+    of oracle work.  Single core: the whole prefix as one blob per eps.  All
+    cores: the prefix split at block boundaries into one piece per thread,
+    each piece compressed by the oracle into its own blob and the blobs
+    decoded concurrently (the oracle is called through ctypes, which releases
+    the interpreter lock, so the threads run in parallel).  Each figure is the
+    median of `reps` runs after one warm-up; value = sum(8 n) / sum over eps
+    of the all-core median."""
+    import statistics
+    from concurrent.futures import ThreadPoolExecutor
+
     import numpy as np
     import oracle
 
+    model, avail = host_cpu()
+    threads = max(1, min(max_threads, avail))
     n_probe = min(len(host_keys), 1 << 20)
     blob = oracle.compress(host_keys[:n_probe], eps_list[0], 10, FRAC_BITS)
     t0 = time.perf_counter()
     oracle.decode(blob)
     per_key = (time.perf_counter() - t0) / n_probe
-    # compress takes about as long as decode per key
-    n_s = int(min(len(host_keys), max(n_probe, budget_s / (2 * len(eps_list)) / max(per_key, 1e-9))))
+    # per eps: one compress (about a decode's time) + (1 + reps) single-core decodes, then the
+    # same on all cores (a fraction of that)
+    units = len(eps_list) * (2 + reps) * (1.0 + 2.0 / threads)
+    n_s = int(min(len(host_keys), max(n_probe, budget_s / units / max(per_key, 1e-9))))
     n_s -= n_s % 1024 if n_s > 1024 else 0
     sample = np.ascontiguousarray(host_keys[:n_s])
-    t_enc = t_dec = 0.0
-    for eps in eps_list:
-        t0 = time.perf_counter()
-        blob = oracle.compress(sample, eps, 10, FRAC_BITS)
-        t_enc += time.perf_counter() - t0
-        t0 = time.perf_counter()
-        out = oracle.decode(blob)
-        t_dec += time.perf_counter() - t0
-        assert np.array_equal(out, sample)
+    cuts = [0] + [((n_s * t // threads) >> 10) << 10 for t in range(1, threads)] + [n_s]
+    pieces = [sample[a:b] for a, b in zip(cuts, cuts[1:]) if b > a]
+
+    def median_time(fn):
+        fn()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return statistics.median(ts)
+
+    one_dec = one_enc = all_dec = all_enc = 0.0
+    with ThreadPoolExecutor(max_workers=len(pieces)) as pool:
+        for eps in eps_list:
+            t0 = time.perf_counter()
+            blob = oracle.compress(sample, eps, 10, FRAC_BITS)
+            one_enc += time.perf_counter() - t0
+            assert np.array_equal(oracle.decode(blob), sample)
+            one_dec += median_time(lambda: oracle.decode(blob))
+            t0 = time.perf_counter()
+            pblobs = list(pool.map(lambda k: oracle.compress(k, eps, 10, FRAC_BITS), pieces))
+            all_enc += time.perf_counter() - t0
+            all_dec += median_time(lambda: list(pool.map(oracle.decode, pblobs)))
     nb = n_s * 8 * len(eps_list)
     eps_s = "/".join(str(e) for e in eps_list)
     return {
-        "value": round(nb / t_dec / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-        "sample": f"first {n_s} keys of the workload, each eps of {eps_s}, B=1024, F={FRAC_BITS}; oracle decode "
-                  f"{t_dec:.2f} s, oracle compress {t_enc:.2f} s ({nb / t_enc / 1e9:.4f} GB/s) in total",
-        "compress_GBps": round(nb / t_enc / 1e9, 4),
+        "value": round(nb / all_dec / 1e9, 4), "unit": "GB/s", "cores": len(pieces), "kind": "oracle",
+        "sample": f"first {n_s} keys, eps {eps_s}: oracle decode, {len(pieces)} threads on block-aligned pieces, "
+                  f"median of {reps} after 1 warm-up",
+        "single_core_GBps": round(nb / one_dec / 1e9, 4),
+        "compress_GBps": {"single_core": round(nb / one_enc / 1e9, 4), "all_cores": round(nb / all_enc / 1e9, 4)},
+        "host": {"cpu": model, "cores_available": avail, "nproc": os.cpu_count()},
     }
 
 
@@ -739,6 +788,61 @@ def bench_fits(dev, keys_lognormal=None, reps: int = 3):
     return res
 
 
+def _pick(d, keys):
+    return {k: d[k] for k in keys if isinstance(d, dict) and k in d}
+
+
+def headline(result: dict) -> dict:
+    """The compact headline record printed last on stdout: the metric, the
+    roofline of the dominant kernel (cold and warm), the CPU baseline and a
+    few figures of each sub-measurement.  Everything else stays in the full
+    record (stderr and the --full-json file)."""
+    h = _pick(result, ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+                       "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "roofline_warm"))
+    enc = result.get("roofline_encode")
+    if enc:
+        h["roofline_encode"] = dict(_pick(enc, ("bound", "achieved", "peak", "unit", "frac", "avg_call_ms")),
+                                    hbm_frac=enc.get("hbm", {}).get("frac"))
+    cpu = result.get("cpu_baseline")
+    if cpu:
+        h["cpu_baseline"] = dict(_pick(cpu, ("value", "unit", "cores", "kind", "sample", "single_core_GBps")),
+                                 host_cpu=cpu.get("host", {}).get("cpu"))
+    pe = result.get("per_eps", {})
+    h["ratio"] = {e: v.get("ratio") for e, v in pe.items()}
+    h["compress_ms"] = {e: v.get("compress_ms") for e, v in pe.items()}
+    h.update(_pick(result, ("decompress_range_GBps", "access_lookups_per_s", "lower_bound_lookups_per_s")))
+    bt = result.get("batching")
+    if bt:
+        st = bt.get("step_ms", {})
+        h["batching"] = {"decoded_GBps": bt.get("decoded_GBps"), "bits_per_key": bt.get("bits_per_key"),
+                         "step_ms": _pick(st, ("batched_graph", "per_list_eager"))}
+    sv = result.get("serving")
+    if sv and sv.get("points"):
+        h["serving"] = {"sat": _pick(sv["points"][-1], ("qps_achieved", "p50_us", "p99_us")),
+                        "speedup_vs_unbatched": sv.get("saturation_speedup_vs_unbatched")}
+    # drop the optional parts, least important first, until the line fits
+    for k in ("compress_ms", "ratio", "serving", "batching"):
+        if len(json.dumps(h)) <= HEADLINE_MAX_BYTES:
+            break
+        h.pop(k, None)
+    if len(json.dumps(h)) > HEADLINE_MAX_BYTES and "cpu_baseline" in h:
+        h["cpu_baseline"].pop("sample", None)
+    return h
+
+
+def emit(result: dict, full_json: str | None):
+    """Full record to stderr (and to full_json when given), then the
+    headline as the last line on stdout."""
+    full = json.dumps(result)
+    print(f"[bench] full record: {full}", file=sys.stderr, flush=True)
+    if full_json:
+        d = os.path.dirname(os.path.abspath(full_json))
+        os.makedirs(d, exist_ok=True)
+        with open(full_json, "w") as f:
+            f.write(full + "\n")
+    print(json.dumps(headline(result)), flush=True)
+
+
 def main():
     global FRAC_BITS
     ap = argparse.ArgumentParser()
@@ -750,6 +854,8 @@ def main():
     ap.add_argument("--access", type=int, default=10_000_000)
     ap.add_argument("--lower-bound", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--full-json", type=str, default=os.path.join("gpurun_out", "bench_full.json"),
+                    help="file receiving the full result record ('' for none); stdout's last line is the headline")
     ap.add_argument("--no-batch", action="store_true", help="skip the posting-list batch measurement")
     ap.add_argument("--batch-only", action="store_true", help="only the posting-list batch measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the request-server measurement")
@@ -820,6 +926,10 @@ def main():
     calib_dst.copy_(calib_src)
     torch.cuda.synchronize()
     del calib_src, calib_dst
+    # cache flush before every cold decode: a copy of FLUSH_BYTES (read and write) evicts the
+    # blob from the 256 MB on-die cache and the L2s
+    flush_src = torch.ones(FLUSH_BYTES // 8, dtype=torch.int64, device=dev)
+    flush_dst = torch.empty_like(flush_src)
 
     # one untimed compress per eps to learn the blob layout (headers)
     infos = {}
@@ -836,16 +946,23 @@ def main():
         return torch.cuda.Event(enable_timing=True)
 
     def step(timed: bool):
+        """Per eps: compress, decompress at once (warm: the blob was just
+        written), flush the caches, decompress again (cold); then the
+        range, access and lower_bound batches on the eps = 63 blob."""
         rec = {}
         for k, e in enumerate(eps_list):
-            b = infos[e]
-            e0, e1, e2 = ev(), ev(), ev()
+            b = lc.Blob(blobs[e], infos[e].info)
+            e0, e1, e2, e3, e4 = ev(), ev(), ev(), ev(), ev()
             e0.record()
             lc.compress_async(keys, e, blobs[e], wss, nbytes[k:k + 1], flags, frac_bits=FRAC_BITS)
             e1.record()
-            lc.decompress(lc.Blob(blobs[e], b.info), out=out)
+            lc.decompress(b, out=out)
             e2.record()
-            rec[e] = (e0, e1, e2)
+            flush_dst.copy_(flush_src)
+            e3.record()
+            lc.decompress(b, out=out)
+            e4.record()
+            rec[e] = (e0, e1, e2, e3, e4)
         q0, q1, q2, q3 = ev(), ev(), ev(), ev()
         q0.record()
         lc.decompress_range(bref, r_begin, r_end, out=r_out)
@@ -875,32 +992,41 @@ def main():
     wall = time.perf_counter() - t_start
     log(f"timed region {wall:.3f} s")
     assert int(flags.item()) == 0
+    del flush_src, flush_dst
 
     per_eps = {}
-    dec_ms_total, dec_bytes_total, dec_alg_bytes = 0.0, 0.0, []
+    alg_bytes = []
+    cold_ms, warm_ms = [], []
     for e in eps_list:
         enc = [r[e][0].elapsed_time(r[e][1]) for r in recs]
-        dec = [r[e][1].elapsed_time(r[e][2]) for r in recs]
+        warm = [r[e][1].elapsed_time(r[e][2]) for r in recs]
+        cold = [r[e][3].elapsed_time(r[e][4]) for r in recs]
         b = infos[e]
-        dms = float(np.mean(dec))
+        cms, wms = float(np.mean(cold)), float(np.mean(warm))
         per_eps[str(e)] = {
             "ratio": round(b.ratio, 5), "bits_per_key": round(b.bits_per_key, 4),
             "blob_bytes": b.nbytes, "nseg_total": b.info.nseg_total,
             "paper_size_formula_bits_per_key": round((96 * b.info.nseg_total + n * b.info.width) / n, 4),
-            "decode_ms": round(dms, 4), "decode_GBps": round(n * 8 / dms / 1e6, 2),
+            "decode_ms_cold": round(cms, 4), "decode_GBps_cold": round(n * 8 / cms / 1e6, 2),
+            "decode_ms_warm": round(wms, 4), "decode_GBps_warm": round(n * 8 / wms / 1e6, 2),
             "compress_ms": round(float(np.mean(enc)), 4),
             "compress_GBps": round(n * 8 / float(np.mean(enc)) / 1e6, 2),
         }
-        dec_ms_total += sum(dec)
-        dec_bytes_total += n * 8 * len(dec)
-        dec_alg_bytes.append(b.nbytes + n * 8)
-    value = dec_bytes_total / (dec_ms_total / 1e3) / 1e9
-    dec_avg_ms = dec_ms_total / (len(eps_list) * len(recs))
-    achieved = float(np.mean(dec_alg_bytes)) / (dec_avg_ms / 1e3) / 1e9
+        cold_ms += cold
+        warm_ms += warm
+        alg_bytes.append(b.nbytes + n * 8)
+    nd = len(cold_ms)
+    value = n * 8 * nd / (sum(cold_ms) / 1e3) / 1e9
+    value_warm = n * 8 * nd / (sum(warm_ms) / 1e3) / 1e9
+    cold_avg, warm_avg = sum(cold_ms) / nd, sum(warm_ms) / nd
+    bytes_per_launch = float(np.mean(alg_bytes))
+    achieved = bytes_per_launch / (cold_avg / 1e3) / 1e9
+    achieved_warm = bytes_per_launch / (warm_avg / 1e3) / 1e9
     rec = recorded_traffic()
-    traffic = None
+    traffic = traffic_warm = None
     if rec is not None and rec.get("n") == n and rec.get("eps") == eps_list and rec.get("frac_bits") == FRAC_BITS:
-        traffic = rec["bytes_per_decompress"]
+        traffic = rec.get("bytes_per_decompress_cold")
+        traffic_warm = rec.get("bytes_per_decompress_warm")
     # encode against both rooflines: HBM (keys read + blob written) and VALU
     # (issued lane-operations of the compress kernels, from the counter record)
     enc_ms = {e: float(np.mean([r[e][0].elapsed_time(r[e][1]) for r in recs])) for e in eps_list}
@@ -911,7 +1037,7 @@ def main():
         enc_alu = float(np.mean([vrec["valu_insts_per_call"][str(e)] * 64 / (enc_ms[e] / 1e3) / 1e12
                                  for e in eps_list]))
     roofline_encode = {
-        "bound": "alu", "kernel": "lc_compress (fit_lanes_kernel<8> + code_pack_kernel<8> + tile_reduce + tile_scan + dir_emit + seg_emit)",
+        "bound": "alu", "kernel": "lc_compress (all its kernels)",
         "achieved": None if enc_alu is None else round(enc_alu, 2), "peak": round(VALU_PEAK_TOPS, 2),
         "unit": "T VALU lane-ops/s", "frac": None if enc_alu is None else round(enc_alu / VALU_PEAK_TOPS, 4),
         "traffic": None,
@@ -939,18 +1065,22 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {
-            "workload": f"{n} sorted distinct uint64 keys, floor(2^40 x / M), x ~ lognormal(0, 2); "
-                        f"blocks of 1024, F = {FRAC_BITS} (integer slopes when 0); eps swept over {eps_list}; "
-                        f"per step: compress + decompress "
-                        f"per eps, decompress_range of {r_end - r_begin} keys, {args.access} access, "
-                        f"{args.lower_bound} lower_bound on the eps={ref_eps} blob",
+            "workload": f"{n} sorted distinct u64 keys, floor(2^40 x/M), x~lognormal(0,2); B=1024, F={FRAC_BITS}, "
+                        f"eps {'/'.join(map(str, eps_list))}; per step and eps: compress, decode (warm), "
+                        f"{FLUSH_BYTES >> 20} MiB flush copy, decode (cold: the value); then range of "
+                        f"{r_end - r_begin} keys, {args.access} access, {args.lower_bound} lower_bound (eps {ref_eps})",
             "n": n, "key_bytes": 8, "log2_block": 10, "eps": eps_list, "frac_bits": FRAC_BITS,
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-            "kernel": "lc_decompress (decode_full_kernel<8, false>: cache-staging workgroups + decode workgroups)",
-            "bytes_per_launch": int(np.mean(dec_alg_bytes)), "avg_launch_ms": round(dec_avg_ms, 4),
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic, "cache": "cold",
+            "kernel": "decode_full_kernel<8, false> (lc_decompress)",
+            "bytes_per_launch": int(bytes_per_launch), "avg_launch_ms": round(cold_avg, 4),
+        },
+        "roofline_warm": {
+            "bound": "hbm", "achieved": round(achieved_warm, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved_warm / HBM_PEAK_GBPS, 4), "traffic": traffic_warm, "cache": "warm",
+            "avg_launch_ms": round(warm_avg, 4), "decoded_GBps": round(value_warm, 2),
         },
         "roofline_encode": roofline_encode,
         "per_eps": per_eps,
@@ -981,7 +1111,7 @@ def main():
         log("timing the CPU oracle on a prefix of the keys")
         host = workloads.as_numpy(keys)
         result["cpu_baseline"] = cpu_baseline(host, eps_list)
-    print(json.dumps(result), flush=True)
+    emit(result, args.full_json)
 
 
 if __name__ == "__main__":

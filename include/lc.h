@@ -128,8 +128,11 @@ typedef struct lc_blob_info {
 } lc_blob_info;
 
 /* Worst-case sizes for compressing n keys with parameters p (host only,
- * pure).  *blob_max: bytes the blob buffer must hold; *ws_bytes: bytes of the
- * device workspace lc_compress needs.  Either output pointer may be NULL.
+ * pure).  Sec. II-A: the compressed form K^c = (f, Delta) is the model f
+ * (its segments) plus n residuals of w = ceil(log2(2 eps + 1)) bits, so
+ * size(K^c) is largest when every block needs the most segments; *blob_max
+ * is that size in blob v1.  *ws_bytes: bytes of the device workspace
+ * lc_compress needs.  Either output pointer may be NULL.
  * Errors: LC_EINVAL (bad p, p NULL, n > 2^40). */
 lc_status lc_compress_bound(uint64_t n, const lc_params* p, uint64_t* blob_max,
                             uint64_t* ws_bytes);
@@ -151,7 +154,10 @@ lc_status lc_compress(const void* d_keys, uint64_t n, const lc_params* p, void* 
                       uint32_t* d_flags, void* stream);
 
 /* Parse and check a blob header from host memory (at least 128 bytes, the
- * first bytes of the blob).  Pure host code.
+ * first bytes of the blob).  The header describes K^c = (f, Delta) of
+ * Sec. II-A: the model's segment count and layout, eps and the residual
+ * width w, and size(K^c) in bytes (blob_bytes, the numerator of the
+ * compression ratio of Def. 1).  Pure host code.
  * Errors: LC_EINVAL (NULL), LC_EFORMAT (magic, version or fields). */
 lc_status lc_info(const void* h_header, uint64_t header_bytes, lc_blob_info* out);
 
@@ -163,19 +169,21 @@ lc_status lc_info(const void* h_header, uint64_t header_bytes, lc_blob_info* out
 lc_status lc_decompress(const void* d_blob, const lc_blob_info* info, void* d_out,
                         void* stream);
 
-/* Dec restricted to [begin, end): d_out[i - begin] = K[i] (key_bytes each,
- * d_out aligned to key_bytes).  0 <= begin <= end <= n, else LC_EINVAL.
+/* Dec of Def. 1 restricted to [begin, end): d_out[i - begin] = Dec(K^c)[i]
+ * = K[i] (key_bytes each, d_out aligned to key_bytes).  Only the blocks
+ * holding the range are read.  0 <= begin <= end <= n, else LC_EINVAL.
  * An empty range enqueues nothing. */
 lc_status lc_decompress_range(const void* d_blob, const lc_blob_info* info, uint64_t begin,
                               uint64_t end, void* d_out, void* stream);
 
-/* Random access on the compressed form: d_out[q] = K[d_idx[q]] for
- * q < m (d_idx: device u64[m]; d_out: device, key_bytes each).  An index
- * >= n writes 0 and ORs LC_FLAG_RANGE into *d_flags (device u32, required).
- * The blob's directory and segment areas are trusted as lc_compress wrote
- * them (unlike the block decoders, point queries do not re-check directory
- * entries; the same holds for lc_lower_bound, lc_quantile and the server's
- * point requests).
+/* Random access on the compressed form, the lookup of Sec. II-B: d_out[q]
+ * = Dec(K^c)[d_idx[q]] = K[d_idx[q]] (Def. 1) for q < m, each from one
+ * block without decoding the others (d_idx: device u64[m]; d_out: device,
+ * key_bytes each).  An index >= n writes 0 and ORs LC_FLAG_RANGE into
+ * *d_flags (device u32, required).  A directory entry inconsistent with the
+ * layout (a corrupt blob) writes 0 and ORs LC_FLAG_BADLIST; no read leaves
+ * the blob.  lc_lower_bound, lc_quantile and the server's point requests
+ * check the entry the same way (they answer n, 0 and 0 / n for such a block).
  * Errors: LC_EINVAL, LC_EDEVICE. */
 lc_status lc_access(const void* d_blob, const lc_blob_info* info, const uint64_t* d_idx,
                     uint64_t m, void* d_out, uint32_t* d_flags, void* stream);
@@ -210,8 +218,9 @@ lc_status lc_decompress_approx(const void* d_blob, const lc_blob_info* info, uin
 #define LC_SETOP_INTERSECT 1u /* AND: the sorted set of keys in both lists */
 #define LC_SETOP_UNION 2u     /* OR: the sorted set of keys in either list */
 
-/* Host, pure: output capacity (keys) and workspace bytes of lc_setop for two
- * blobs of the same key width (AND: min(n_a, n_b); OR: n_a + n_b).
+/* Host, pure: output capacity (keys) and workspace bytes of lc_setop (the
+ * list AND / OR of Sec. III-A) for two blobs of the same key width (AND:
+ * min(n_a, n_b); OR: n_a + n_b).
  * Errors: LC_EINVAL (bad op, infos inconsistent, key widths differ). */
 lc_status lc_setop_bound(const lc_blob_info* a, const lc_blob_info* b, uint32_t op, uint64_t* out_max,
                          uint64_t* ws_bytes);
@@ -287,11 +296,14 @@ typedef struct lc_batch_params {
 
 /* Host, pure: fill blob_off, blob_cap, block_off and group_off of
  * h_lists[0 .. p->nlists) (slots packed in list order, each its list's
- * worst-case size at p->max_eps) and p's totals.  key_off, n and eps are
+ * worst-case size at p->max_eps, the size(K^c) bound of Sec. II-A) and p's
+ * totals, for a batch of lists such as the posting lists of Sec. III-A.  key_off, n and eps are
  * left as given.  Errors: LC_EINVAL (bad parameters, NULL). */
 lc_status lc_batch_plan(lc_batch_params* p, lc_batch_list* h_lists);
 
-/* Compress every list.  d_keys: nkeys concatenated keys; d_lists: device
+/* Enc of Def. 1 (the fit of Sec. II-A) for every list of a batch, e.g. the
+ * posting lists of an inverted index (Sec. III-A).  d_keys: nkeys
+ * concatenated keys; d_lists: device
  * copy of the planned table; d_blob: blob_cap bytes (>= p->blob_bytes);
  * d_ws: p->ws_bytes of workspace; d_sizes: device u64[nlists] receiving each
  * list's blob size; d_stats: device u32[2] the caller zeroes: [0] flags
@@ -303,8 +315,9 @@ lc_status lc_batch_compress(const void* d_keys, uint64_t nkeys, const lc_batch_l
                             const lc_batch_params* p, void* d_blob, uint64_t blob_cap, void* d_ws,
                             uint64_t ws_bytes, uint64_t* d_sizes, uint32_t* d_stats, void* stream);
 
-/* Size pass of the eps autotuner: the exact blob size every list would have
- * at each candidate eps, without writing any blob: d_sizes[c * nlists + l]
+/* Size pass of the eps autotuner (the per-partition eps choice of
+ * Sec. IV-A, with each list a partition): the exact size(K^c) every list
+ * would have at each candidate eps, without writing any blob: d_sizes[c * nlists + l]
  * for candidate h_cands[c] (~0 for a list that does not fit the buffers).
  * h_cands: ncand (1 .. LC_BATCH_MAX_CANDIDATES) strictly increasing values
  * <= p->max_eps.  One fit launch over all (candidate, work item) pairs and
@@ -314,7 +327,8 @@ lc_status lc_batch_sizes(const void* d_keys, uint64_t nkeys, const lc_batch_list
                          const lc_batch_params* p, const uint32_t* h_cands, uint32_t ncand, void* d_ws,
                          uint64_t ws_bytes, uint64_t* d_sizes, uint32_t* d_stats, void* stream);
 
-/* Autotuner step: for every list l set d_lists[l].eps to the candidate
+/* Autotuner step (Sec. IV-A: eps set per partition by its space cost): for
+ * every list l set d_lists[l].eps to the candidate
  * h_cands[c] with the smallest d_sizes[c * nlists + l] (the sizes of
  * lc_batch_sizes run once per candidate); ties go to the smaller eps.
  * h_cands: ncand (1 .. LC_BATCH_MAX_CANDIDATES) strictly increasing values
@@ -322,7 +336,8 @@ lc_status lc_batch_sizes(const void* d_keys, uint64_t nkeys, const lc_batch_list
 lc_status lc_batch_pick_eps(lc_batch_list* d_lists, const lc_batch_params* p, const uint64_t* d_sizes,
                             const uint32_t* h_cands, uint32_t ncand, void* stream);
 
-/* Decompress every list of a batch buffer written by lc_batch_compress with
+/* Dec of Def. 1 for every list of a batch buffer written by
+ * lc_batch_compress with
  * the same table (a list's eps must be the one its blob was written with):
  * list l's keys go to d_out + key_off * key_bytes (nout keys in all; d_out
  * aligned to the key width).  max_seg_bytes: d_stats[1] of that compress; it
@@ -386,24 +401,27 @@ typedef struct lc_serve_stats {
 
 typedef struct lc_server lc_server; /* opaque */
 
-/* Creates a server for the blob at d_blob (parsed header `info`) on the
- * current device.  d_arena: arena_bytes (>= 16) of device memory, 16-byte
- * aligned, for request outputs -- the HBM budget.  The blob and the arena
+/* Creates a server (the read path of a compressed key store, Sec. III-B)
+ * for the blob at d_blob (parsed header `info`) on the current device.
+ * d_arena: arena_bytes (>= 16) of device memory, 16-byte aligned, for
+ * request outputs -- the HBM budget.  The blob and the arena
  * stay owned by the caller and must outlive the server.  The server
  * allocates its streams, events, pinned staging and small device request
  * tables here (none later).  Errors: LC_EINVAL, LC_EDEVICE. */
 lc_status lc_server_create(const void* d_blob, const lc_blob_info* info, void* d_arena, uint64_t arena_bytes,
                            const lc_serve_config* cfg, lc_server** out);
 
-/* Serves h_reqs[0 .. n) as they arrive (by arrival_ns, measured from the
- * call) and returns when all are complete; h_res[i] describes h_reqs[i].
+/* Serves h_reqs[0 .. n) -- range decodes (Def. 1), accesses and
+ * lower_bounds (Sec. II-B) on the store of Sec. III-B -- as they arrive (by
+ * arrival_ns, measured from the call) and returns when all are complete; h_res[i] describes h_reqs[i].
  * Busy-polls on the calling thread.  stats may be NULL.  Errors: LC_EINVAL
  * (NULL arguments), LC_EDEVICE (a launch failed: in-flight work is drained,
  * unserved requests get status LC_EDEVICE). */
 lc_status lc_server_run(lc_server* s, const lc_request* h_reqs, uint64_t n, lc_request_result* h_res,
                         lc_serve_stats* stats);
 
-/* Waits for the server's streams and frees what lc_server_create allocated. */
+/* Waits for the server's streams and frees what lc_server_create allocated
+ * (the end of the Sec. III-B store's read path). */
 lc_status lc_server_destroy(lc_server* s);
 
 /* ---- AND over many pairs of lists of one batch (Sec. III-A) -------------
@@ -422,14 +440,16 @@ typedef struct lc_list_pair {
     uint64_t n;             /* set by the plan: keys of the probe list (capacity of the pair's output) */
 } lc_list_pair;
 
-/* Host, pure: fills probe, target, key_off, block_off and n of h_pairs[0 ..
- * npairs) from the host copy of the batch table (as lc_batch_plan left it)
+/* Host, pure: plans the many-pair list AND of Sec. III-A.  Fills probe,
+ * target, key_off, block_off and n of h_pairs[0 .. npairs) from the host
+ * copy of the batch table (as lc_batch_plan left it)
  * and returns the totals and the workspace size of lc_batch_and.  Errors:
  * LC_EINVAL (a list index >= nlists, NULL, bad parameters). */
 lc_status lc_batch_and_plan(const lc_batch_params* p, const lc_batch_list* h_lists, lc_list_pair* h_pairs,
                             uint32_t npairs, uint64_t* total_keys, uint64_t* total_blocks, uint64_t* ws_bytes);
 
-/* Runs the plan: d_pairs is the device copy of the planned table; pair i's
+/* Runs the plan (list AND of Sec. III-A for every pair): d_pairs is the
+ * device copy of the planned table; pair i's
  * result keys go to d_out + key_off (d_out: total_keys keys, aligned to the
  * key width) and their number to d_counts[i] (device u64[npairs]).
  * max_seg_bytes: as lc_batch_decompress.  A pair whose lists do not fit the

@@ -2299,9 +2299,8 @@ struct BlockView {
     uint32_t nseg, nkeys, ab, sb;
 };
 
-__device__ __forceinline__ BlockView block_view(const uint8_t* blob, const Layout& L, uint64_t b)
+__device__ __forceinline__ BlockView block_view(const uint4& dv)
 {
-    const uint4 dv = reinterpret_cast<const uint4*>(blob + L.off_dir)[b];
     BlockView v;
     v.seg_off = dv.x | ((uint64_t)dv.y << 32);
     v.nseg = dv.z;
@@ -2324,13 +2323,21 @@ __device__ __forceinline__ uint64_t code_at(const uint8_t* blob, const Layout& L
 }
 
 // K[i] for i < L.n: directory entry, the segment of position j among the
-// block's u16 starts, anchor, slope, one or two slab words.
+// block's u16 starts, anchor, slope, one or two slab words.  A directory
+// entry inconsistent with the layout (a corrupt blob) gives 0 and sets bad,
+// so no read leaves the blob.
 template <int KB, bool APPROX = false>
-__device__ __forceinline__ uint64_t access_one(const uint8_t* __restrict__ blob, const Layout& L, uint64_t i)
+__device__ __forceinline__ uint64_t access_one(const uint8_t* __restrict__ blob, const Layout& L, uint64_t i,
+                                               bool& bad)
 {
     const uint64_t b = i >> L.log2b;
     const uint32_t j = (uint32_t)(i & ((1ull << L.log2b) - 1));
-    const BlockView v = block_view(blob, L, b);
+    const uint4 dv = reinterpret_cast<const uint4*>(blob + L.off_dir)[b];
+    if (!dir_ok(dv, L, b, L.blob_bytes)) {
+        bad = true;
+        return 0;
+    }
+    const BlockView v = block_view(dv);
     const uint16_t* st = reinterpret_cast<const uint16_t*>(blob + v.seg_off);
     const uint32_t t = find_segment(st, v.nseg, v.nkeys, j);
     const uint8_t* an = blob + v.seg_off + a16(2ull * v.nseg);
@@ -2349,9 +2356,11 @@ __device__ __forceinline__ uint64_t access_one(const uint8_t* __restrict__ blob,
 // keys of one segment.  An anchor is its segment's first key, except in
 // blobs of the optimal fit (kFlagFrac), whose anchors are intercepts within
 // eps of it: there a probe decodes its segment's first key only when x is
-// within eps of the intercept.
+// within eps of the intercept.  A directory entry inconsistent with the
+// layout, or segment starts out of order, give n and set bad.
 template <int KB>
-__device__ __forceinline__ uint64_t lower_bound_one(const uint8_t* __restrict__ blob, const Layout& L, uint64_t x)
+__device__ __forceinline__ uint64_t lower_bound_one(const uint8_t* __restrict__ blob, const Layout& L, uint64_t x,
+                                                    bool& bad)
 {
     const uint8_t* fk = blob + L.off_first;
     if (L.n == 0 || load_key<KB>(fk, 0) >= x) return 0;
@@ -2359,7 +2368,12 @@ __device__ __forceinline__ uint64_t lower_bound_one(const uint8_t* __restrict__ 
     uint64_t b = 0;
     for (uint64_t step = 1ull << (63 - __clzll((long long)L.nblocks)); step; step >>= 1)
         if (b + step < L.nblocks && load_key<KB>(fk, b + step) < x) b += step;
-    const BlockView v = block_view(blob, L, b);
+    const uint4 dv = reinterpret_cast<const uint4*>(blob + L.off_dir)[b];
+    if (!dir_ok(dv, L, b, L.blob_bytes)) {
+        bad = true;
+        return L.n;
+    }
+    const BlockView v = block_view(dv);
     const uint16_t* st = reinterpret_cast<const uint16_t*>(blob + v.seg_off);
     const uint8_t* an = blob + v.seg_off + a16(2ull * v.nseg);
     const uint8_t* sl = an + a16((uint64_t)v.ab * v.nseg);
@@ -2410,6 +2424,10 @@ __device__ __forceinline__ uint64_t lower_bound_one(const uint8_t* __restrict__ 
     }
     const uint32_t s = st[t];
     const uint32_t e = t + 1 < v.nseg ? st[t + 1] : v.nkeys;
+    if (!(s < e && e <= v.nkeys)) {  // corrupt starts: the window below would leave the slab
+        bad = true;
+        return L.n;
+    }
     const uint64_t anchor = first + load_w(an, t, v.ab);
     const uint64_t A = load_w(sl, t, v.sb);
     const uint64_t frac = L.fb ? load_w(sl + a16((uint64_t)v.sb * v.nseg), t, L.fb) : 0;
@@ -2460,7 +2478,7 @@ __global__ __launch_bounds__(256) void access_kernel(const uint8_t* __restrict__
                                                      const uint64_t* __restrict__ idx, uint64_t m,
                                                      void* __restrict__ out, uint32_t* __restrict__ flags)
 {
-    bool bad = false;
+    bool bad = false, corrupt = false;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < m; q += stride) {
         const uint64_t i = idx[q];
@@ -2469,9 +2487,10 @@ __global__ __launch_bounds__(256) void access_kernel(const uint8_t* __restrict__
             bad = true;
             continue;
         }
-        store_key<KB>(out, q, access_one<KB>(blob, L, i));
+        store_key<KB>(out, q, access_one<KB>(blob, L, i, corrupt));
     }
     if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(flags, kFlagRange);
+    if (__ballot(corrupt) != 0 && lane_id() == 0) atomicOr(flags, kFlagBadList);
 }
 
 template <int KB>
@@ -2480,8 +2499,9 @@ __global__ __launch_bounds__(256) void lower_bound_kernel(const uint8_t* __restr
                                                           uint64_t* __restrict__ pos)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    bool corrupt = false;  // n answers for queries in an inconsistent block; there is no flag word
     for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < m; q += stride)
-        pos[q] = lower_bound_one<KB>(blob, L, load_key<KB>(qs, q));
+        pos[q] = lower_bound_one<KB>(blob, L, load_key<KB>(qs, q), corrupt);
 }
 
 // ---------------------------------------------------------------------------
@@ -2499,7 +2519,8 @@ __global__ __launch_bounds__(256) void quantile_kernel(const uint8_t* __restrict
         const unsigned __int128 prod = (unsigned __int128)L.n * ks[t];
         const unsigned __int128 i = prod / q;
         const uint64_t idx = i < (unsigned __int128)(L.n - 1) ? (uint64_t)i : L.n - 1;
-        store_key<KB>(out, t, access_one<KB, APPROX>(blob, L, idx));
+        bool corrupt = false;  // 0 for an index in an inconsistent block; there is no flag word
+        store_key<KB>(out, t, access_one<KB, APPROX>(blob, L, idx, corrupt));
     }
 }
 
@@ -2510,11 +2531,12 @@ static_assert(kSetTile == kSetTileKeys, "host workspace plan uses the same tile"
 template <int KB>
 __device__ __forceinline__ bool contains_one(const uint8_t* __restrict__ blob, const Layout& L, uint64_t x)
 {
-    const uint64_t p = lower_bound_one<KB>(blob, L, x);
-    if (p >= L.n) return false;
-    uint64_t v = access_one<KB>(blob, L, p);
+    bool corrupt = false;
+    const uint64_t p = lower_bound_one<KB>(blob, L, x, corrupt);
+    if (p >= L.n || corrupt) return false;
+    uint64_t v = access_one<KB>(blob, L, p, corrupt);
     if constexpr (KB == 4) v &= 0xFFFFFFFFull;
-    return v == x;
+    return v == x && !corrupt;
 }
 
 // first index i of the decoded sorted array with a[i] >= x
@@ -2709,8 +2731,9 @@ __global__ __launch_bounds__(64) void serve_kernel(const uint8_t* __restrict__ b
     const uint64_t q = (w - s.range_items) * 64 + threadIdx.x;
     if (q >= s.npoint) return;
     const ServePoint P = points[q];
-    if (P.op == kServeAccess) store_key<KB>(arena + P.out_off, 0, access_one<KB>(blob, s.L, P.key));
-    else *reinterpret_cast<uint64_t*>(arena + P.out_off) = lower_bound_one<KB>(blob, s.L, P.key);
+    bool corrupt = false;  // the server's blob passed lc_info; an inconsistent block answers 0 / n
+    if (P.op == kServeAccess) store_key<KB>(arena + P.out_off, 0, access_one<KB>(blob, s.L, P.key, corrupt));
+    else *reinterpret_cast<uint64_t*>(arena + P.out_off) = lower_bound_one<KB>(blob, s.L, P.key, corrupt);
 }
 
 // ---------------------------------------------------------------------------
@@ -3061,6 +3084,8 @@ __device__ __forceinline__ bool pair_fits(const lc_list_pair& pr, const lc_batch
     *lt = lists[pr.target];
     *Lp = list_layout(a, lp->n, lp->eps);
     *Lt = list_layout(a, lt->n, lt->eps);
+    Lp->blob_bytes = lp->blob_cap;  // point queries check directory entries against the slot
+    Lt->blob_bytes = lt->blob_cap;
     return list_fits(*lp, a, *Lp, lp->eps, true) && list_fits(*lt, a, *Lt, lt->eps, true) && pr.n == lp->n &&
            pr.key_off <= total_keys && pr.n <= total_keys - pr.key_off && pr.block_off <= total_blocks &&
            Lp->nblocks <= total_blocks - pr.block_off;

@@ -239,3 +239,29 @@ def test_batch_and_plan(lc):
     assert tk == sum(n) and tb == sum(nb) and ws >= tk * 13
     with pytest.raises(lc.LcError):
         lc.batch_and_plan(B, [(0, 6)])
+
+
+def _declaration_comments():
+    """{name: the comment block right above its declaration} for every
+    lc_status entry point of include/lc.h."""
+    text = open(os.path.join(ROOT, "include", "lc.h")).read()
+    out = {}
+    for m in re.finditer(r"/\*((?:(?!\*/).)*)\*/\s*\n\s*lc_status\s+(lc_\w+)\s*\(", text, re.S):
+        out[m.group(2)] = m.group(1)
+    return out
+
+
+def test_every_entry_point_cites_the_passage_or_the_callers_it_serves():
+    """Each lc_status declaration's comment names the passage of the paper
+    that defines its operation (a Def. or a Sec.), or -- for an entry point
+    that exists for callers rather than for an operation of the paper --
+    the callers it is for."""
+    comments = _declaration_comments()
+    declared = [n for n in _declared() if n != "lc_strerror"]
+    assert sorted(comments) == sorted(declared)
+    for name, c in comments.items():
+        assert re.search(r"\b(Def\.|Sec\.)\s*[0-9IV]", c) or "callers" in c, name
+    # the passages the boundary's core calls follow
+    assert "Def. 1" in comments["lc_access"] and "Sec. II-B" in comments["lc_access"]
+    assert "Def. 1" in comments["lc_decompress_range"]
+    assert "Sec. II-A" in comments["lc_compress_bound"] and "Sec. II-A" in comments["lc_info"]

@@ -153,13 +153,15 @@ def test_determinism(lc):
 
 
 def test_unsorted_flag(lc):
-    keys = np.arange(5000, dtype=np.uint64) * np.uint64(7)
+    keys = np.arange(5000, dtype=np.uint64) * np.uint64(7) + np.uint64(10)
     for pos in (0, 1, 1023, 1024, 2500, 4999):
         bad = keys.copy()
         if pos == 0:
-            bad[0] = bad[1] + 1
+            bad[0] = bad[1] + np.uint64(1)
         else:
-            bad[pos] = bad[pos - 1] - 1
+            bad[pos] = bad[pos - 1] - np.uint64(1)  # one key below its predecessor (keys start at 10: no wrap)
+        assert bad[pos] != keys[pos] and not np.all(np.diff(bad.astype(np.int64)) >= 0)
+        assert np.flatnonzero(np.diff(bad.astype(np.int64)) < 0)[0] in (pos - 1, pos)
         with pytest.raises(lc.LcError):
             lc.compress(_to_dev(bad), 15)
 
@@ -679,7 +681,7 @@ def test_corrupt_directory_entries_skip_their_blocks(lc):
     blob or before its region, no segments, an invalid byte width, a wrong
     key count) make the block decoders -- the full decode and ranges, with
     their staging workgroups -- skip those blocks and write nothing there;
-    every other block decodes.  (Point queries trust the blob.)"""
+    every other block decodes.  (Point queries: the next test.)"""
     rng = np.random.default_rng(21)
     keys = np.cumsum(rng.integers(1, 100, 40 * 1024 + 77)).astype(np.uint64)
     blob = lc.compress(_to_dev(keys), 63)
@@ -721,3 +723,57 @@ def test_corrupt_directory_entries_skip_their_blocks(lc):
                 assert np.all(g[lo - a:hi - a] == -1), (a, e, b)
             else:
                 assert np.array_equal(g[lo - a:hi - a].view(np.uint64), keys[lo:hi]), (a, e, b)
+
+
+def test_corrupt_directory_entries_in_point_queries(lc):
+    """access and lower_bound check the directory entry they read: an
+    index in a block with an inconsistent entry answers 0 and raises
+    LC_FLAG_BADLIST (access), a query whose block is inconsistent answers n
+    (lower_bound); every other query gives the definitions' answers."""
+    rng = np.random.default_rng(22)
+    keys = np.cumsum(rng.integers(1, 100, 40 * 1024 + 77)).astype(np.uint64)
+    blob = lc.compress(_to_dev(keys), 63)
+    h = blob.info
+    data = blob.data.cpu().numpy().copy()
+    dirs = data[h.off_dir:h.off_dir + 16 * h.nblocks].reshape(-1, 16)
+    bad = {
+        0: lambda d: d[0:8].view(np.uint64).__setitem__(0, h.blob_bytes + 4096),
+        3: lambda d: d[0:8].view(np.uint64).__setitem__(0, h.off_seg - 16),
+        11: lambda d: d[8:12].view(np.uint32).__setitem__(0, 0),
+        20: lambda d: d.__setitem__(14, 3),
+        33: lambda d: d[12:14].view(np.uint16).__setitem__(0, 5),
+        40: lambda d: d[8:12].view(np.uint32).__setitem__(0, 0xFFFFFFFF),
+    }
+    for b, f in bad.items():
+        row = dirs[b].copy()
+        f(row)
+        dirs[b] = row
+    data[h.off_dir:h.off_dir + 16 * h.nblocks] = dirs.ravel()
+    cb = lc.Blob.from_device(torch.from_numpy(data).to(DEV))
+    n = len(keys)
+    B = 1 << h.log2_block
+    # access: every block's first, middle and last index
+    idx = np.unique(np.concatenate([[b * B, b * B + B // 2, min(n, (b + 1) * B) - 1] for b in range(h.nblocks)]))
+    idx = idx[idx < n]
+    flags = torch.zeros(1, dtype=torch.int32, device=DEV)
+    got = lc.access(cb, torch.from_numpy(idx.astype(np.int64)).to(DEV), flags=flags, check=False).cpu().numpy()
+    got = got.view(np.uint64)
+    blk = idx // B
+    in_bad = np.isin(blk, list(bad))
+    assert np.all(got[in_bad] == 0)
+    assert np.array_equal(got[~in_bad], keys[idx[~in_bad]])
+    assert int(flags.item()) == lc.LC_FLAG_BADLIST
+    # an intact blob raises no flag for the same indices
+    flags.zero_()
+    lc.access(blob, torch.from_numpy(idx.astype(np.int64)).to(DEV), flags=flags, check=False)
+    assert int(flags.item()) == 0
+    # lower_bound: keys, keys + 1 and keys - 1 in every block
+    q = np.unique(np.concatenate([keys[idx], keys[idx] + np.uint64(1), keys[idx] - np.uint64(1)]))
+    pos = lc.lower_bound(cb, torch.from_numpy(q.view(np.int64)).to(DEV)).cpu().numpy().astype(np.uint64)
+    want = np.searchsorted(keys, q, side="left").astype(np.uint64)
+    # the block a query searches: the last whose first key is < q
+    first = keys[::B]
+    qb = np.searchsorted(first, q, side="left").astype(np.int64) - 1
+    hit = (qb >= 0) & np.isin(qb, list(bad))
+    assert np.all(pos[hit] == n)
+    assert np.array_equal(pos[~hit], want[~hit])
