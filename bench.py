@@ -95,9 +95,10 @@ def host_cpu():
 
 def cpu_baseline(host_keys, eps_list, budget_s: float = 24.0, max_threads: int = 16, reps: int = 5):
     """The oracle's plain C decoder timed on the host over the same eps sweep
-    as the step, on a prefix of the workload sized to about budget_s seconds
-    of oracle work.  Single core: the whole prefix as one blob per eps.  All
-    cores: the prefix split at block boundaries into one piece per thread,
+    as the step, on a sample of the workload (whole blocks spread over the
+    list) sized to about budget_s seconds of oracle work.  Single core: the
+    sample as one blob per eps.  All cores: the sample split at block
+    boundaries into one piece per thread (runs dealt round-robin),
     each piece compressed by the oracle into its own blob and the blobs
     decoded concurrently (the oracle is called through ctypes, which releases
     the interpreter lock, so the threads run in parallel).  Each figure is the
@@ -111,19 +112,33 @@ def cpu_baseline(host_keys, eps_list, budget_s: float = 24.0, max_threads: int =
 
     model, avail = host_cpu()
     threads = max(1, min(max_threads, avail))
-    n_probe = min(len(host_keys), 1 << 20)
-    blob = oracle.compress(host_keys[:n_probe], eps_list[0], 10, FRAC_BITS)
+
+    def spread(m: int, chunks: int = 64):
+        """About m keys as `chunks` block-aligned runs of whole 1024-key blocks spread evenly over
+        the keys (so the sample has the whole range's mix of dense and sparse blocks, and its
+        blocks are blocks of the full list); all keys (cut into runs) when m reaches their number."""
+        n = len(host_keys)
+        run = max(1024, (m // chunks) & ~1023)
+        if run * chunks >= n:
+            cuts = [(n * c // chunks) & ~1023 for c in range(chunks)] + [n]
+            return [host_keys[a:b] for a, b in zip(cuts, cuts[1:]) if b > a]
+        starts = [(int(s) & ~1023) for s in np.linspace(0, n - run, chunks)]
+        return [host_keys[s:s + run] for s in starts]
+
+    probe = np.ascontiguousarray(np.concatenate(spread(64 * 1024)))
+    blob = oracle.compress(probe, eps_list[0], 10, FRAC_BITS)
     t0 = time.perf_counter()
     oracle.decode(blob)
-    per_key = (time.perf_counter() - t0) / n_probe
+    per_key = (time.perf_counter() - t0) / len(probe)
     # per eps: one compress (about a decode's time) + (1 + reps) single-core decodes, then the
     # same on all cores (a fraction of that)
     units = len(eps_list) * (2 + reps) * (1.0 + 2.0 / threads)
-    n_s = int(min(len(host_keys), max(n_probe, budget_s / units / max(per_key, 1e-9))))
-    n_s -= n_s % 1024 if n_s > 1024 else 0
-    sample = np.ascontiguousarray(host_keys[:n_s])
-    cuts = [0] + [((n_s * t // threads) >> 10) << 10 for t in range(1, threads)] + [n_s]
-    pieces = [sample[a:b] for a, b in zip(cuts, cuts[1:]) if b > a]
+    runs = spread(int(budget_s / units / max(per_key, 1e-9)))
+    sample = np.ascontiguousarray(np.concatenate(runs))
+    n_s = len(sample)
+    # thread t takes runs t, t + threads, ... (in order, so each piece is a sorted list of whole
+    # blocks): every piece gets a share of the dense and of the sparse stretches
+    pieces = [np.ascontiguousarray(np.concatenate(runs[t::threads])) for t in range(min(threads, len(runs)))]
 
     def median_time(fn):
         fn()
@@ -150,8 +165,8 @@ def cpu_baseline(host_keys, eps_list, budget_s: float = 24.0, max_threads: int =
     eps_s = "/".join(str(e) for e in eps_list)
     return {
         "value": round(nb / all_dec / 1e9, 4), "unit": "GB/s", "cores": len(pieces), "kind": "oracle",
-        "sample": f"first {n_s} keys, eps {eps_s}: oracle decode, {len(pieces)} threads on block-aligned pieces, "
-                  f"median of {reps} after 1 warm-up",
+        "sample": f"{n_s} keys (64 block-aligned runs spread over the list), eps {eps_s}: oracle decode, "
+                  f"{len(pieces)} threads on block-aligned pieces, median of {reps} after 1 warm-up",
         "single_core_GBps": round(nb / one_dec / 1e9, 4),
         "compress_GBps": {"single_core": round(nb / one_enc / 1e9, 4), "all_cores": round(nb / all_enc / 1e9, 4)},
         "host": {"cpu": model, "cores_available": avail, "nproc": os.cpu_count()},
@@ -780,7 +795,8 @@ def bench_fits(dev, keys_lognormal=None, reps: int = 3):
             row["opt_F0"]["bytes_saved_pct_vs_greedy_F0"] = round(
                 100 * (1 - row["opt_F0"]["bits_per_key"] / row["greedy_F0"]["bits_per_key"]), 3)
             rows[str(eps)] = row
-            log(f"fits {name} eps={eps}: {row}")
+            log(f"fits {name} eps={eps}: " + ", ".join(f"{k} {v['bits_per_key']} b/key {v['compress_ms']} ms"
+                                                       for k, v in row.items()))
             del blob, ws
         res[name] = {"n": n, "key_bytes": kb, "per_eps": rows}
         del keys, out, idx, qs, want_acc, want_pos, acc, pos
