@@ -60,6 +60,7 @@ typedef int32_t lc_status;
 #define LC_ENOSPC (-2)   /* blob_cap or ws_bytes below what lc_compress_bound gives */
 #define LC_EFORMAT (-3)  /* header: bad magic/version or inconsistent fields */
 #define LC_EDEVICE (-4)  /* a kernel launch failed (hipGetLastError after launch) */
+#define LC_ETOOBIG (-5)  /* lc_compress_noalloc: the workspace would exceed LC_NOALLOC_SCRATCH_BYTES */
 
 #define LC_FLAG_UNSORTED 1u /* compress: keys not non-decreasing; blob is invalid */
 #define LC_FLAG_RANGE 2u    /* access: an index >= n; its output slot is 0 */
@@ -152,6 +153,25 @@ lc_status lc_compress_bound(uint64_t n, const lc_params* p, uint64_t* blob_max,
 lc_status lc_compress(const void* d_keys, uint64_t n, const lc_params* p, void* d_blob,
                       uint64_t blob_cap, void* d_ws, uint64_t ws_bytes, uint64_t* d_blob_bytes,
                       uint32_t* d_flags, void* stream);
+
+/* Bytes of the static device scratch of lc_compress_noalloc (per GPU). */
+#define LC_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* lc_compress for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops and harnesses that forbid
+ * hipMalloc.  Same arguments, results and errors as lc_compress minus the
+ * workspace: the library's own static device array of
+ * LC_NOALLOC_SCRATCH_BYTES per GPU (held until the process ends) serves as
+ * the workspace, and the call allocates nothing.  Limit: the workspace that
+ * lc_compress_bound reports for (n, p) must fit in that array, else
+ * LC_ETOOBIG and nothing is enqueued (about 3.7e6 keys at 1024-key blocks,
+ * 3.0e6 with the optimal fit).  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (other streams, other host threads)
+ * race and must be serialised by the caller; calls in order on one stream
+ * are safe.  The first call on a device looks up the array's device
+ * address (with that device current); LC_EDEVICE if that fails. */
+lc_status lc_compress_noalloc(const void* d_keys, uint64_t n, const lc_params* p, void* d_blob,
+                              uint64_t blob_cap, uint64_t* d_blob_bytes, uint32_t* d_flags, void* stream);
 
 /* Parse and check a blob header from host memory (at least 128 bytes, the
  * first bytes of the blob).  The header describes K^c = (f, Delta) of

@@ -8,7 +8,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblc.so")
-SOURCES = [os.path.join(CSRC, "lc_kernels.hip"), os.path.join(CSRC, "lc_api.cpp"), os.path.join(CSRC, "lc_serve.cpp")]
+SOURCES = [os.path.join(CSRC, "lc_kernels.hip"), os.path.join(CSRC, "lc_api.cpp"), os.path.join(CSRC, "lc_serve.cpp"),
+           os.path.join(CSRC, "lc_noalloc.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -620,6 +620,7 @@ LC_API const char* lc_strerror(lc_status s)
     case LC_ENOSPC: return "buffer too small";
     case LC_EFORMAT: return "not a valid blob header";
     case LC_EDEVICE: return "kernel launch failed";
+    case LC_ETOOBIG: return "input too large for the static scratch of lc_compress_noalloc";
     default: return "unknown status";
     }
 }

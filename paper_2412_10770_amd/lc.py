@@ -26,6 +26,8 @@ LC_EINVAL = -1
 LC_ENOSPC = -2
 LC_EFORMAT = -3
 LC_EDEVICE = -4
+LC_ETOOBIG = -5
+NOALLOC_SCRATCH_BYTES = 64 << 20  # LC_NOALLOC_SCRATCH_BYTES: workspace limit of lc_compress_noalloc
 LC_FLAG_UNSORTED = 1
 LC_FLAG_RANGE = 2
 LC_FLAG_INTERNAL = 4
@@ -37,7 +39,7 @@ HEADER_BYTES = 128
 DEFAULT_LOG2_BLOCK = 10
 DEFAULT_FRAC_BITS = 20
 
-EXPORTED = ("lc_compress_bound", "lc_compress", "lc_info", "lc_decompress", "lc_decompress_range",
+EXPORTED = ("lc_compress_bound", "lc_compress", "lc_compress_noalloc", "lc_info", "lc_decompress", "lc_decompress_range",
             "lc_access", "lc_lower_bound", "lc_quantile", "lc_decompress_approx", "lc_setop_bound", "lc_setop",
             "lc_batch_plan", "lc_batch_compress", "lc_batch_sizes",
             "lc_batch_pick_eps", "lc_batch_decompress", "lc_batch_and_plan", "lc_batch_and", "lc_server_create", "lc_server_run",
@@ -102,6 +104,7 @@ def _load():
     sig = {
         "lc_compress_bound": [u64, P, ctypes.POINTER(u64), ctypes.POINTER(u64)],
         "lc_compress": [vp, u64, P, vp, u64, vp, u64, vp, vp, vp],
+        "lc_compress_noalloc": [vp, u64, P, vp, u64, vp, vp, vp],
         "lc_info": [vp, u64, I],
         "lc_decompress": [vp, I, vp, vp],
         "lc_decompress_range": [vp, I, u64, u64, vp, vp],
@@ -259,6 +262,21 @@ def compress_async(keys: torch.Tensor, eps: int, blob: torch.Tensor, workspace: 
                            ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
                            ctypes.c_void_p(blob_bytes.data_ptr()), ctypes.c_void_p(flags.data_ptr()),
                            _stream(stream)), "lc_compress")
+
+
+def compress_noalloc_async(keys: torch.Tensor, eps: int, blob: torch.Tensor, blob_bytes: torch.Tensor,
+                           flags: torch.Tensor, log2_block: int = DEFAULT_LOG2_BLOCK,
+                           frac_bits: int = DEFAULT_FRAC_BITS, stream=None, fit="greedy"):
+    """Enqueue lc_compress_noalloc (the library's static scratch as the
+    workspace; nothing allocated); no synchronisation.  Raises LcError with
+    LC_ETOOBIG when the workspace would exceed NOALLOC_SCRATCH_BYTES."""
+    _dev(keys, "keys")
+    kb = _key_bytes(keys)
+    p = params(kb, eps, log2_block, frac_bits, fit)
+    _check(lib.lc_compress_noalloc(ctypes.c_void_p(keys.data_ptr()), keys.numel(), ctypes.byref(p),
+                                   ctypes.c_void_p(blob.data_ptr()), blob.numel(),
+                                   ctypes.c_void_p(blob_bytes.data_ptr()), ctypes.c_void_p(flags.data_ptr()),
+                                   _stream(stream)), "lc_compress_noalloc")
 
 
 def compress(keys: torch.Tensor, eps: int, log2_block: int = DEFAULT_LOG2_BLOCK,

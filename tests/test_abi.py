@@ -38,8 +38,19 @@ def test_library_exports_every_declared_symbol(lc):
 
 def test_strerror(lc):
     assert lc.strerror(0) == "ok"
-    for code in (-1, -2, -3, -4):
+    for code in (-1, -2, -3, -4, -5):
         assert lc.strerror(code) not in ("", "unknown status")
+
+
+def test_noalloc_checks_on_the_host(lc):
+    """lc_compress_noalloc refuses, before any device call, inputs whose
+    workspace exceeds its static scratch (LC_ETOOBIG) and bad parameters."""
+    p = lc.params(8, 63, 10, 0)
+    assert lc.lib.lc_compress_noalloc(None, 10 ** 8, ctypes.byref(p), None, 0, None, None, None) == lc.LC_ETOOBIG
+    assert lc.compress_bound(10 ** 8, 8, 63, 10, 0)[1] > lc.NOALLOC_SCRATCH_BYTES
+    bad = lc.lc_params(3, 10, 0, 0, 63)
+    assert lc.lib.lc_compress_noalloc(None, 10, ctypes.byref(bad), None, 0, None, None, None) == lc.LC_EINVAL
+    assert lc.lib.lc_compress_noalloc(None, 2 ** 41, ctypes.byref(p), None, 0, None, None, None) == lc.LC_EINVAL
 
 
 def test_compress_bound(lc):
