@@ -199,12 +199,13 @@ __device__ __forceinline__ uint64_t wave_scan64(uint64_t v)
 // remainder.
 // 1 / d to nearly full FP64 precision: the hardware reciprocal is an
 // approximation, refined by one Newton-Raphson step (squares its error).
-__device__ __forceinline__ double recip(uint32_t d)
+__device__ __forceinline__ double recip_f(double dd)
 {
-    const double dd = (double)d;
     const double r0 = __builtin_amdgcn_rcp(dd);
     return __builtin_fma(r0, __builtin_fma(-dd, r0, 1.0), r0);
 }
+
+__device__ __forceinline__ double recip(uint32_t d) { return recip_f((double)d); }
 
 __device__ __forceinline__ uint64_t div_small(uint64_t x, uint32_t d, double inv, uint32_t* rem = nullptr)
 {
@@ -1536,6 +1537,7 @@ __device__ __forceinline__ void lanes_fit(const LaneBlock& in, const void* __res
     // one-round divisions when every block of the wave allows them (a wrapped span does not)
     const bool fast = __ballot(!fast_division_ok(nb ? (uint64_t)Kb[nb - 1] - first : 0, eps, F)) == 0;
     const bool careful = __ballot(nb == 0 || in.koff + B > kend) != 0;  // wave-uniform
+    const bool full = __ballot(nb != B) == 0;  // every lane walks a whole block (wave-uniform)
 
     // the blocks this lane loads parts of, and their key counts (fixed for the walk)
     uint64_t qoff[kLoads];
@@ -1587,9 +1589,7 @@ __device__ __forceinline__ void lanes_fit(const LaneBlock& in, const void* __res
     uint32_t s = 0, nseg = 0;
     uint64_t Ka = first, P = 0, H = ~0ull, maxA = 0, maxd = 0;
     double inv = 1.0;  // recip(d) for the next key, d = its distance from the anchor
-    constexpr double kBig = 1.8e19;  // no upper end yet: above every real bound (< 2^49)
-    double Pf = 0.0, Hf = kBig, Mf = kBig;  // the fast path's P, H and M
-    uint64_t M = ~0ull;                      // the other path's M
+    uint64_t M = ~0ull;                      // the slow path's M
     const double epsf = (double)eps, scf = (double)(1ull << F);
     uint64_t prev = (nb && in.has_prev) ? (uint64_t)Kb[-1] : 0;
     bool unsorted = false;
@@ -1618,6 +1618,56 @@ __device__ __forceinline__ void lanes_fit(const LaneBlock& in, const void* __res
         maxd = Ka - first;  // anchors grow with the segment index
     };
 
+    // Fast-path state, all exact integers in FP64 (every numerator is below
+    // 2^49): Lf = the largest lower end ceil((D - eps) 2^F / d) over the open
+    // segment's keys, signed (negative while every key lies below eps of the
+    // anchor), Hf = the smallest upper end floor(((D + eps + 1) 2^F - 1) / d);
+    // a key that makes Lf > Hf closes the segment.  The closed segment's slope
+    // is max(0, Lf + floor((Hf - Lf) / 2)): the midpoint of [Lf, Hf], which is
+    // also the midpoint of [0, Hf] shifted by the negative part of Lf, exactly
+    // the rule of the slow path's (P, H, M) encoding.  Keys enter as their
+    // distance from the block's first key (exact below 2^49), the anchor as
+    // Kad, and d and its reciprocal advance with the walk.
+    constexpr double kBig = 1.8e19;                        // no bound yet: beyond every real bound
+    constexpr double kRound = 6755399441055744.0;          // 1.5 * 2^52: FMA into it rounds to an integer
+    double Lf = -kBig, Hf = kBig, Kad = 0.0, df = 1.0, maxAf = 0.0;
+    const double epsLo = epsf * scf, epsHi = (epsf + 1.0) * scf - 1.0;
+    auto close_f = [&](uint32_t e) {
+        const double A = __builtin_fmax(0.0, Lf + __builtin_floor((Hf - Lf) * 0.5));
+        if (RECORDS) {
+            in.st[nseg] = (uint16_t)s;
+            in.dl[nseg] = (uint64_t)__double_as_longlong(Kad + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
+            in.sa[nseg] = (uint64_t)__double_as_longlong(A + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
+        }
+        nseg++;
+        maxAf = __builtin_fmax(maxAf, A);
+        (void)e;
+    };
+    // one key of the fast walk: e = its index (> 0), kd = its distance from
+    // the block's first key
+    auto step_f = [&](uint32_t e, double kd) {
+        const double D = kd - Kad;
+        const double xl = __builtin_fma(D, scf, -epsLo);
+        const double ql = __builtin_fma(xl, inv, kRound) - kRound;  // floor or ceil of xl / d
+        const double rl = __builtin_fma(-ql, df, xl);
+        const double lo = rl > 0.0 ? ql + 1.0 : ql;                 // ceil(xl / d)
+        const double xh = __builtin_fma(D, scf, epsHi);
+        const double qh = __builtin_fma(xh, inv, kRound) - kRound;
+        const double rh = __builtin_fma(-qh, df, xh);
+        const double hi = rh < 0.0 ? qh - 1.0 : qh;                 // floor(xh / d)
+        const double Ln = __builtin_fmax(Lf, lo), Hn = __builtin_fmin(Hf, hi);
+        const double dn = df + 1.0;
+        const double inv_next = recip_f(dn);  // the next key's, off the critical path
+        const bool fail = Ln > Hn;
+        if (fail) close_f(e);
+        Lf = fail ? -kBig : Ln;
+        Hf = fail ? kBig : Hn;
+        Kad = fail ? kd : Kad;
+        s = fail ? e : s;
+        df = fail ? 1.0 : dn;
+        inv = fail ? 1.0 : inv_next;
+    };
+
     const uint32_t nchunks = B / kLaneChunk;
     load_chunk(0);
     store_chunk(0);
@@ -1631,37 +1681,27 @@ __device__ __forceinline__ void lanes_fit(const LaneBlock& in, const void* __res
 #pragma unroll
         for (uint32_t t = 0; t < kLaneChunk; t++) kc[t] = row[t];
         if (fast) {
-            // Every quantity of a step is an integer below 2^49 here (block span
-            // + eps + 1 < 2^(49 - F)), exact in FP64 (bounds_f64), and the cap
-            // cannot be reached.
+            // order check and key distances first: independent of the walk
+            double kd[kLaneChunk];
 #pragma unroll
             for (uint32_t t = 0; t < kLaneChunk; t++) {
                 const uint32_t e = c * kLaneChunk + t;
-                const uint64_t key = kc[t];
-                if (e < nb) {
-                    unsorted |= key < prev;
-                    prev = key;
-                    if (e > 0) {
-                        const uint32_t d = e - s;
-                        const double inv_next = recip(d + 1);  // the next step's, off the critical path
-                        double pp, h, mm;
-                        bounds_m_f64(exact_f64(key - Ka), epsf, scf, (double)d, inv, kBig, pp, h, mm);
-                        const double Pn = pp > Pf ? pp : Pf, Hn = h < Hf ? h : Hf;
-                        if (Pn != 0.0 && Pn - 1.0 > Hn) {
-                            close(e, (uint64_t)Pf, (uint64_t)Hf, (uint64_t)Mf);
-                            s = e;
-                            Ka = key;
-                            Pf = 0.0;
-                            Hf = kBig;
-                            Mf = kBig;
-                            inv = 1.0;  // d = 1 at the next key
-                        } else {
-                            Pf = Pn;
-                            Hf = Hn;
-                            Mf = mm < Mf ? mm : Mf;
-                            inv = inv_next;
-                        }
-                    }
+                const bool valid = full ? true : e < nb;
+                unsorted |= valid && kc[t] < prev;
+                prev = valid ? kc[t] : prev;
+                kd[t] = exact_f64(kc[t] - first);
+            }
+            if (full) {
+#pragma unroll
+                for (uint32_t t = 0; t < kLaneChunk; t++) {
+                    const uint32_t e = c * kLaneChunk + t;
+                    if (e > 0) step_f(e, kd[t]);
+                }
+            } else {
+#pragma unroll
+                for (uint32_t t = 0; t < kLaneChunk; t++) {
+                    const uint32_t e = c * kLaneChunk + t;
+                    if (e > 0 && e < nb) step_f(e, kd[t]);
                 }
             }
         } else {
@@ -1716,10 +1756,13 @@ __device__ __forceinline__ void lanes_fit(const LaneBlock& in, const void* __res
         __syncthreads();
     }
     if (nb) {
-        if (fast)
-            close(nb, (uint64_t)Pf, Hf >= kBig ? ~0ull : (uint64_t)Hf, (uint64_t)Mf);
-        else
+        if (fast) {
+            close_f(nb);
+            maxA = (uint64_t)__double_as_longlong(maxAf + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
+            maxd = (uint64_t)__double_as_longlong(Kad + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
+        } else {
             close(nb, P, H, M);
+        }
     }
     if (__ballot(unsorted) != 0 && lane == 0) atomicOr(flags, kFlagUnsorted);
     if (nb) {
