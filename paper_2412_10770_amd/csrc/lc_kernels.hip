@@ -1386,6 +1386,25 @@ __device__ __forceinline__ bool dir_ok(const uint4& dv, const Layout& L, uint64_
 
 constexpr uint32_t kEmitLanes = 16;
 
+// The start, anchor-delta and slope arrays of one segment area (n records
+// read from st / dl / sa, LDS or global) packed at byte widths 2, ab and sb
+// into 16-byte chunks at out, lanes `lane`, `lane + G`, ... writing; returns
+// the first chunk after the slopes.
+template <uint32_t G, typename P16, typename P64>
+__device__ __forceinline__ uint4* emit_records(P16 st, P64 dl, P64 sa, uint32_t n, uint32_t ab, uint32_t sb,
+                                               uint4* __restrict__ out, uint32_t lane)
+{
+    const uint32_t c_start = (uint32_t)(a16(2ull * n) / 16);
+    const uint32_t c_anchor = (uint32_t)(a16((uint64_t)ab * n) / 16);
+    const uint32_t c_slope = (uint32_t)(a16((uint64_t)sb * n) / 16);
+    for (uint32_t c = lane; c < c_start; c += G) out[c] = pack_chunk(st, n, c, 2);
+    out += c_start;
+    for (uint32_t c = lane; c < c_anchor; c += G) out[c] = pack_chunk(dl, n, c, ab);
+    out += c_anchor;
+    for (uint32_t c = lane; c < c_slope; c += G) out[c] = pack_chunk(sa, n, c, sb);
+    return out + c_slope;
+}
+
 // Segment area of block b (G lanes): the records in the workspace packed at
 // the block's widths into 16-byte chunks at the directory's offset.
 template <uint32_t G>
@@ -1397,17 +1416,9 @@ __device__ __forceinline__ void emit_block(const Workspace& ws, const Layout& L,
     const uint32_t n = dv.z;
     const uint32_t ab = (dv.w >> 16) & 0xFF, sb = dv.w >> 24;
     const uint64_t rec = b << L.log2b;
-    uint4* out = reinterpret_cast<uint4*>(blob + seg_off);
-    const uint32_t c_start = (uint32_t)(a16(2ull * n) / 16);
-    const uint32_t c_anchor = (uint32_t)(a16((uint64_t)ab * n) / 16);
-    const uint32_t c_slope = (uint32_t)(a16((uint64_t)sb * n) / 16);
-    for (uint32_t c = lane; c < c_start; c += G) out[c] = pack_chunk(ws.seg_start + rec, n, c, 2);
-    out += c_start;
-    for (uint32_t c = lane; c < c_anchor; c += G) out[c] = pack_chunk(ws.seg_delta + rec, n, c, ab);
-    out += c_anchor;
-    for (uint32_t c = lane; c < c_slope; c += G) out[c] = pack_chunk(ws.seg_A + rec, n, c, sb);
+    uint4* out = emit_records<G>(ws.seg_start + rec, ws.seg_delta + rec, ws.seg_A + rec, n, ab, sb,
+                                 reinterpret_cast<uint4*>(blob + seg_off), lane);
     if (L.fb) {  // intercept fractions of the optimal fit
-        out += c_slope;
         const uint32_t c_frac = (uint32_t)(a16((uint64_t)L.fb * n) / 16);
         for (uint32_t c = lane; c < c_frac; c += G) out[c] = pack_chunk(ws.seg_frac + rec, n, c, L.fb);
     }
@@ -1834,7 +1845,8 @@ __device__ __forceinline__ void code_pack_block(const void* __restrict__ keys, c
                                                 const uint16_t* __restrict__ rst, const uint64_t* __restrict__ rdl,
                                                 const uint64_t* __restrict__ rsa, uint32_t log2b,
                                                 uint64_t res_stride, uint32_t w, uint64_t eps, uint32_t F,
-                                                uint8_t* __restrict__ slab_dst)
+                                                uint8_t* __restrict__ slab_dst, uint4* __restrict__ seg_dst = nullptr,
+                                                uint32_t ab = 0, uint32_t sb = 0)
 {
     using KT = typename std::conditional<KB == 4, uint32_t, uint64_t>::type;
     extern __shared__ __align__(16) uint8_t smem[];
@@ -1866,6 +1878,14 @@ __device__ __forceinline__ void code_pack_block(const void* __restrict__ keys, c
         }
     }
     __syncthreads();
+    // the block's segment area, when the directory is already written (from
+    // the staged copy of the records when there is one)
+    if (seg_dst != nullptr) {
+        if (staged)
+            emit_records<64>(s_st, s_delta, s_A, nseg, ab, sb, seg_dst, lane);
+        else
+            emit_records<64>(rst, rdl, rsa, nseg, ab, sb, seg_dst, lane);
+    }
     uint32_t carry = 0;
     for (uint32_t w0 = 0; w0 < nwords; w0 += 64) {
         const uint32_t x = w0 + lane;
@@ -1928,15 +1948,20 @@ __device__ __forceinline__ void code_pack_block(const void* __restrict__ keys, c
     for (uint32_t c = lane; c < slab_words / 4; c += 64) dst[c] = src4[c];
 }
 
+// Residual slab and segment area of block b, after the directory is written
+// (the area goes to the directory entry's offset, at its byte widths).
 template <int KB>
 __global__ __launch_bounds__(64) void code_pack_kernel(const void* __restrict__ keys, Layout L,
                                                         uint8_t* __restrict__ blob, Workspace ws, uint64_t blk0)
 {
     const uint64_t b = blk0 + blockIdx.x;  // the launcher keeps b < nblocks
     const uint64_t rec = b << L.log2b;
+    const uint4 dv = reinterpret_cast<const uint4*>(blob + L.off_dir)[b];
+    const uint64_t seg_off = dv.x | ((uint64_t)dv.y << 32);
     code_pack_block<KB>(reinterpret_cast<const uint8_t*>(keys) + rec * KB, ws.blk[b], ws.seg_start + rec,
                         ws.seg_delta + rec, ws.seg_A + rec, L.log2b, L.res_stride, L.w, L.eps, L.F,
-                        blob + L.off_res + b * L.res_stride);
+                        blob + L.off_res + b * L.res_stride, reinterpret_cast<uint4*>(blob + seg_off),
+                        (dv.w >> 16) & 0xFF, dv.w >> 24);
 }
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -3424,6 +3449,7 @@ hipError_t launch_batch_and(const uint8_t* d_blob, const lc_batch_list* d_lists,
 hipError_t launch_compress(const void* d_keys, const Layout& L, uint32_t fit, uint8_t* d_blob, const Workspace& ws,
                            uint64_t* d_blob_bytes, uint32_t* d_flags, hipStream_t stream)
 {
+    bool lanes = false;
     if (L.nblocks && fit == LC_FIT_OPT) {
         const uint64_t B = 1ull << L.log2b;
         const size_t lds = L.kb * B + L.res_stride + 16 + 4 * B;
@@ -3452,12 +3478,8 @@ hipError_t launch_compress(const void* d_keys, const Layout& L, uint32_t fit, ui
             const uint64_t ng = waves - g0 < kMaxGrid ? waves - g0 : kMaxGrid;
             hipLaunchKernelGGL(kf, dim3((uint32_t)ng), dim3(64), 0, stream, d_keys, L, d_blob, ws, d_flags, g0 * 64);
         }
-        const size_t lds = code_pack_lds(L.log2b, L.res_stride);
-        auto kc = L.kb == 4 ? code_pack_kernel<4> : code_pack_kernel<8>;
-        for (uint64_t b0 = 0; b0 < L.nblocks; b0 += kMaxGrid) {
-            const uint64_t nw = L.nblocks - b0 < kMaxGrid ? L.nblocks - b0 : kMaxGrid;
-            hipLaunchKernelGGL(kc, dim3((uint32_t)nw), dim3(64), lds, stream, d_keys, L, d_blob, ws, b0);
-        }
+        // the codes and the segment areas come after the directory (code_pack_kernel)
+        lanes = true;
     } else if (L.nblocks) {
         const size_t lds = 4 * (L.res_stride + 16);
         auto k = L.kb == 4 ? fit_pack_kernel<4> : fit_pack_kernel<8>;
@@ -3481,11 +3503,21 @@ hipError_t launch_compress(const void* d_keys, const Layout& L, uint32_t fit, ui
             const uint64_t g = nt - t0 < kMaxGrid ? nt - t0 : kMaxGrid;
             hipLaunchKernelGGL(dir_emit_kernel, dim3((uint32_t)g), dim3(256), 0, stream, ws, L, d_blob, t0);
         }
-        constexpr uint64_t per = 256 / kEmitLanes;
-        const uint64_t egroups = (L.nblocks + per - 1) / per;
-        for (uint64_t g0 = 0; g0 < egroups; g0 += kMaxGrid) {
-            const uint64_t g = egroups - g0 < kMaxGrid ? egroups - g0 : kMaxGrid;
-            hipLaunchKernelGGL(seg_emit_kernel, dim3((uint32_t)g), dim3(256), 0, stream, ws, L, d_blob, g0 * per);
+        if (lanes) {
+            const size_t lds = code_pack_lds(L.log2b, L.res_stride);
+            auto kc = L.kb == 4 ? code_pack_kernel<4> : code_pack_kernel<8>;
+            for (uint64_t b0 = 0; b0 < L.nblocks; b0 += kMaxGrid) {
+                const uint64_t nw = L.nblocks - b0 < kMaxGrid ? L.nblocks - b0 : kMaxGrid;
+                hipLaunchKernelGGL(kc, dim3((uint32_t)nw), dim3(64), lds, stream, d_keys, L, d_blob, ws, b0);
+            }
+        } else {
+            constexpr uint64_t per = 256 / kEmitLanes;
+            const uint64_t egroups = (L.nblocks + per - 1) / per;
+            for (uint64_t g0 = 0; g0 < egroups; g0 += kMaxGrid) {
+                const uint64_t g = egroups - g0 < kMaxGrid ? egroups - g0 : kMaxGrid;
+                hipLaunchKernelGGL(seg_emit_kernel, dim3((uint32_t)g), dim3(256), 0, stream, ws, L, d_blob,
+                                   g0 * per);
+            }
         }
     }
     return hipGetLastError();
