@@ -233,6 +233,22 @@ __device__ __forceinline__ bool fast_division_ok(uint64_t span, uint64_t eps, ui
     return eps + 1 < lim && span < lim - eps - 1;
 }
 
+// max / min of two doubles that are never NaN, without the quieting that
+// fmax / fmin add to operands the compiler cannot prove canonical
+__device__ __forceinline__ double vmax_f64(double a, double b)
+{
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+__device__ __forceinline__ double vmin_f64(double a, double b)
+{
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 // v as a double, exactly, for v < 2^52: the mantissa of 2^52 + v holds v.
 __device__ __forceinline__ double exact_f64(uint64_t v)
 {
@@ -1498,6 +1514,9 @@ __device__ __forceinline__ uint32_t wave_incl_sum32(uint32_t v)
 constexpr uint32_t kLaneChunk = 16;
 constexpr uint64_t kLanesMinBlocks = 16384;
 
+// Dynamic LDS of a lane-fit launch: the reciprocal table of lanes_fit.
+inline size_t lane_fit_lds(uint32_t log2b) { return 8 * ((1ull << log2b) + 2); }
+
 // One lane's block for lanes_fit.
 struct LaneBlock {
     uint64_t koff;          // index of the block's first key in the key array
@@ -1535,10 +1554,15 @@ __device__ __forceinline__ void lanes_fit(const LaneBlock& in, const void* __res
     constexpr uint32_t kLoads = kParts;                // loads per lane and chunk (64 blocks per wave)
     constexpr uint32_t kPer = 16 / KB;                 // keys per load
     __shared__ KT s_keys[2][64 * kPitch];
+    // 1 / d for d = 0 .. B + 1 (entry 0 unused), from the launch's dynamic LDS
+    // (lane_fit_lds bytes): the fast walk reads the next key's reciprocal
+    // instead of computing it
+    extern __shared__ __align__(16) double s_inv[];
 
     const uint32_t lane = threadIdx.x;
     const uint32_t B = 1u << log2b;
     const uint32_t nb = in.nb;
+    for (uint32_t i = lane; i <= B + 1; i += 64) s_inv[i] = recip(i > 0 ? i : 1u);
     const KT* K0 = reinterpret_cast<const KT*>(keys);
     const KT* Kb = K0 + in.koff;
     const uint64_t kend = nkeys;  // key index bound of every load
@@ -1604,6 +1628,7 @@ __device__ __forceinline__ void lanes_fit(const LaneBlock& in, const void* __res
     const double epsf = (double)eps, scf = (double)(1ull << F);
     uint64_t prev = (nb && in.has_prev) ? (uint64_t)Kb[-1] : 0;
     bool unsorted = false;
+    uint64_t uns_b = 0;  // ballots of order violations seen by the fast path
 
     // closes segment [s, e) with slope interval (Pc, Hc) (P encoding: 1 + the
     // largest non-negative lower end, 0 while there is none); when every
@@ -1644,37 +1669,43 @@ __device__ __forceinline__ void lanes_fit(const LaneBlock& in, const void* __res
     double Lf = -kBig, Hf = kBig, Kad = 0.0, df = 1.0, maxAf = 0.0;
     const double epsLo = epsf * scf, epsHi = (epsf + 1.0) * scf - 1.0;
     auto close_f = [&](uint32_t e) {
-        const double A = __builtin_fmax(0.0, Lf + __builtin_floor((Hf - Lf) * 0.5));
+        const double A = vmax_f64(0.0, Lf + __builtin_floor((Hf - Lf) * 0.5));
         if (RECORDS) {
             in.st[nseg] = (uint16_t)s;
             in.dl[nseg] = (uint64_t)__double_as_longlong(Kad + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
             in.sa[nseg] = (uint64_t)__double_as_longlong(A + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
         }
         nseg++;
-        maxAf = __builtin_fmax(maxAf, A);
+        maxAf = vmax_f64(maxAf, A);
         (void)e;
     };
     // one key of the fast walk: e = its index (> 0), kd = its distance from
-    // the block's first key
+    // the block's first key; d_i = e - s as an integer (df as a double), inv
+    // = 1 / df.  Each quotient is rounded to an integer by one FMA (the floor
+    // or the ceiling of the exact one) and corrected by the sign of its exact
+    // FMA remainder.
+    uint32_t d_i = 1;
     auto step_f = [&](uint32_t e, double kd) {
         const double D = kd - Kad;
+        const uint32_t dn_i = d_i + 1;
+        const double inv_next = s_inv[dn_i];  // the next key's, off the critical path
         const double xl = __builtin_fma(D, scf, -epsLo);
-        const double ql = __builtin_fma(xl, inv, kRound) - kRound;  // floor or ceil of xl / d
+        const double ql = __builtin_fma(xl, inv, kRound) - kRound;
         const double rl = __builtin_fma(-ql, df, xl);
-        const double lo = rl > 0.0 ? ql + 1.0 : ql;                 // ceil(xl / d)
+        const double lo = ql + (rl > 0.0 ? 1.0 : 0.0);  // ceil(xl / d)
         const double xh = __builtin_fma(D, scf, epsHi);
         const double qh = __builtin_fma(xh, inv, kRound) - kRound;
         const double rh = __builtin_fma(-qh, df, xh);
-        const double hi = rh < 0.0 ? qh - 1.0 : qh;                 // floor(xh / d)
-        const double Ln = __builtin_fmax(Lf, lo), Hn = __builtin_fmin(Hf, hi);
+        const double hi = qh - (rh < 0.0 ? 1.0 : 0.0);  // floor(xh / d)
+        const double Ln = vmax_f64(Lf, lo), Hn = vmin_f64(Hf, hi);
         const double dn = df + 1.0;
-        const double inv_next = recip_f(dn);  // the next key's, off the critical path
         const bool fail = Ln > Hn;
         if (fail) close_f(e);
         Lf = fail ? -kBig : Ln;
         Hf = fail ? kBig : Hn;
         Kad = fail ? kd : Kad;
         s = fail ? e : s;
+        d_i = fail ? 1u : dn_i;
         df = fail ? 1.0 : dn;
         inv = fail ? 1.0 : inv_next;
     };
@@ -1698,7 +1729,7 @@ __device__ __forceinline__ void lanes_fit(const LaneBlock& in, const void* __res
             for (uint32_t t = 0; t < kLaneChunk; t++) {
                 const uint32_t e = c * kLaneChunk + t;
                 const bool valid = full ? true : e < nb;
-                unsorted |= valid && kc[t] < prev;
+                uns_b |= __ballot(valid && kc[t] < prev);
                 prev = valid ? kc[t] : prev;
                 kd[t] = exact_f64(kc[t] - first);
             }
@@ -1775,7 +1806,7 @@ __device__ __forceinline__ void lanes_fit(const LaneBlock& in, const void* __res
             close(nb, P, H, M);
         }
     }
-    if (__ballot(unsorted) != 0 && lane == 0) atomicOr(flags, kFlagUnsorted);
+    if ((__ballot(unsorted) | uns_b) != 0 && lane == 0) atomicOr(flags, kFlagUnsorted);
     if (nb) {
         if (RECORDS) {
             if (KB == 4)
@@ -3318,8 +3349,8 @@ hipError_t launch_batch_fit(const void* d_keys, const lc_batch_list* d_lists, co
                            : (sizes_only ? batch_lanes_kernel<8, true> : batch_lanes_kernel<8, false>);
         for (uint64_t i0 = 0; i0 < items; i0 += kMaxGrid) {
             const uint64_t g = items - i0 < kMaxGrid ? items - i0 : kMaxGrid;
-            hipLaunchKernelGGL(k, dim3((uint32_t)g), dim3(64), 0, stream, d_keys, d_lists, a, c, d_blob, ws, d_stats,
-                               i0);
+            hipLaunchKernelGGL(k, dim3((uint32_t)g), dim3(64), lane_fit_lds(a.log2b), stream, d_keys, d_lists, a, c,
+                               d_blob, ws, d_stats, i0);
         }
         if (!sizes_only) {
             auto kc = a.kb == 4 ? batch_code_pack_kernel<4> : batch_code_pack_kernel<8>;
@@ -3476,7 +3507,8 @@ hipError_t launch_compress(const void* d_keys, const Layout& L, uint32_t fit, ui
         const uint64_t waves = (L.nblocks + 63) / 64;
         for (uint64_t g0 = 0; g0 < waves; g0 += kMaxGrid) {
             const uint64_t ng = waves - g0 < kMaxGrid ? waves - g0 : kMaxGrid;
-            hipLaunchKernelGGL(kf, dim3((uint32_t)ng), dim3(64), 0, stream, d_keys, L, d_blob, ws, d_flags, g0 * 64);
+            hipLaunchKernelGGL(kf, dim3((uint32_t)ng), dim3(64), lane_fit_lds(L.log2b), stream, d_keys, L, d_blob, ws,
+                               d_flags, g0 * 64);
         }
         // the codes and the segment areas come after the directory (code_pack_kernel)
         lanes = true;
