@@ -2320,6 +2320,39 @@ __global__ __launch_bounds__(64) void decode_kernel(const uint8_t* __restrict__ 
 constexpr uint32_t kStreamChunk = 16;
 constexpr uint32_t kStreamGroups = 8192;
 
+// Streams the directory entries, slabs and segment areas of blocks [b0, b1]
+// of a blob of `bytes` bytes through the caches, eight 16-byte loads in
+// flight per lane; the segment byte range comes from the first and last
+// directory entries, checked against the layout (a corrupt range is
+// skipped).  The loaded words are folded into acc, which the caller keeps
+// alive so the loads are not removed.
+__device__ __forceinline__ void stream_blocks(const uint8_t* __restrict__ blob, const Layout& L, uint64_t bytes,
+                                              uint64_t b0, uint64_t b1, uint32_t& acc)
+{
+    const uint4* dir = reinterpret_cast<const uint4*>(blob + L.off_dir);
+    const uint4* p = reinterpret_cast<const uint4*>(blob);
+    const uint64_t d_lo = (L.off_dir + 16 * b0) / 16, dn = b1 + 1 - b0;
+    const uint64_t r_lo = (L.off_res + b0 * L.res_stride) / 16, rn = (b1 + 1 - b0) * L.res_stride / 16;
+    const uint4 e0 = dir[b0], e1 = dir[b1];
+    uint64_t lo = e0.x | ((uint64_t)e0.y << 32);
+    uint64_t hi = (e1.x | ((uint64_t)e1.y << 32)) + a16(2ull * e1.z) + a16((uint64_t)((e1.w >> 16) & 0xFF) * e1.z) +
+                  a16((uint64_t)(e1.w >> 24) * e1.z) + a16((uint64_t)L.fb * e1.z);
+    if (!(lo >= L.off_seg && lo <= hi && hi <= bytes)) lo = hi = L.off_seg;  // corrupt: skip
+    const uint64_t s_lo = lo / 16, sn = (hi - lo) / 16;
+    const uint64_t tot = dn + rn + sn;  // >= 1
+    auto at = [&](uint64_t i) {
+        i = i < tot ? i : tot - 1;
+        return i < dn ? d_lo + i : i < dn + rn ? r_lo + (i - dn) : s_lo + (i - dn - rn);
+    };
+    for (uint64_t i0 = threadIdx.x; i0 < tot; i0 += 64 * 8) {
+        uint4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) v[u] = p[at(i0 + 64ull * u)];
+#pragma unroll
+        for (int u = 0; u < 8; u++) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+    }
+}
+
 template <int KB, bool RANGE>
 __global__ __launch_bounds__(64) void decode_full_kernel(const uint8_t* __restrict__ blob, DecodeArgs a, uint32_t T,
                                                          void* __restrict__ out)
@@ -2328,33 +2361,11 @@ __global__ __launch_bounds__(64) void decode_full_kernel(const uint8_t* __restri
     if (blockIdx.x < T) {
         const uint64_t nch = (a.nblk + kStreamChunk - 1) / kStreamChunk;
         const uint64_t b_end = a.b_first + a.nblk;  // <= L.nblocks
-        const uint4* dir = reinterpret_cast<const uint4*>(blob + L.off_dir);
-        const uint4* p = reinterpret_cast<const uint4*>(blob);
         uint32_t acc = 0;
         for (uint64_t c = blockIdx.x; c < nch; c += T) {
             const uint64_t b0 = a.b_first + c * kStreamChunk;
             const uint64_t b1 = (b0 + kStreamChunk < b_end ? b0 + kStreamChunk : b_end) - 1;
-            const uint64_t d_lo = (L.off_dir + 16 * b0) / 16, dn = b1 + 1 - b0;
-            const uint64_t r_lo = (L.off_res + b0 * L.res_stride) / 16, rn = (b1 + 1 - b0) * L.res_stride / 16;
-            const uint4 e0 = dir[b0], e1 = dir[b1];
-            uint64_t lo = e0.x | ((uint64_t)e0.y << 32);
-            uint64_t hi = (e1.x | ((uint64_t)e1.y << 32)) + a16(2ull * e1.z) +
-                          a16((uint64_t)((e1.w >> 16) & 0xFF) * e1.z) + a16((uint64_t)(e1.w >> 24) * e1.z) +
-                          a16((uint64_t)L.fb * e1.z);
-            if (!(lo >= L.off_seg && lo <= hi && hi <= a.bytes)) lo = hi = L.off_seg;  // corrupt: skip
-            const uint64_t s_lo = lo / 16, sn = (hi - lo) / 16;
-            const uint64_t tot = dn + rn + sn;  // >= 1
-            auto at = [&](uint64_t i) {
-                i = i < tot ? i : tot - 1;
-                return i < dn ? d_lo + i : i < dn + rn ? r_lo + (i - dn) : s_lo + (i - dn - rn);
-            };
-            for (uint64_t i0 = threadIdx.x; i0 < tot; i0 += 64 * 8) {
-                uint4 v[8];
-#pragma unroll
-                for (int u = 0; u < 8; u++) v[u] = p[at(i0 + 64ull * u)];
-#pragma unroll
-                for (int u = 0; u < 8; u++) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
-            }
+            stream_blocks(blob, L, a.bytes, b0, b1, acc);
         }
         asm volatile("" ::"v"(acc));  // keeps the loads; no instruction is emitted
         return;
@@ -2906,6 +2917,28 @@ __device__ __forceinline__ uint32_t find_list(const lc_batch_list* __restrict__ 
     return lo;
 }
 
+// find_list for a whole wave with x uniform: each round the 64 lanes probe
+// 64 evenly spaced lists of the remaining range at once and the ballot of
+// "offset <= x" narrows it to one stride, so 4096 lists take two rounds of
+// loads instead of twelve dependent ones.
+template <bool BY_GROUP>
+__device__ __forceinline__ uint32_t find_list_wave(const lc_batch_list* __restrict__ lists, uint32_t nlists,
+                                                   uint64_t x)
+{
+    const uint32_t lane = lane_id();
+    uint32_t lo = 0, n = nlists;
+    while (n > 1) {
+        const uint32_t step = (n + 63) / 64;
+        const uint32_t idx = lo + lane * step;
+        const bool ok = lane == 0 || (idx < lo + n && (BY_GROUP ? lists[idx].group_off : lists[idx].block_off) <= x);
+        const uint64_t mask = __ballot(ok);
+        const uint32_t k = 63 - __clzll(mask);
+        lo += k * step;
+        n = n - k * step < step ? n - k * step : step;
+    }
+    return lo;
+}
+
 // Workspace of one list: block infos and segment records at its block offset.
 __device__ __forceinline__ Workspace list_ws(const Workspace& ws, uint64_t block_off, uint32_t log2b, uint64_t blk_off)
 {
@@ -2931,7 +2964,7 @@ __global__ __launch_bounds__(64) void batch_fit_kernel(const void* __restrict__ 
     const uint64_t item = item0 + blockIdx.x;
     const uint64_t cand = SIZES ? item / a.total_groups : 0;
     const uint64_t g = SIZES ? item % a.total_groups : item;
-    const uint32_t l = find_list<true>(lists, a.nlists, g);
+    const uint32_t l = find_list_wave<true>(lists, a.nlists, g);
     const lc_batch_list li = lists[l];
     const uint32_t eps = SIZES ? cands.eps[cand] : li.eps;
     const Layout L = list_layout(a, li.n, eps);
@@ -3007,7 +3040,7 @@ __global__ __launch_bounds__(64) void batch_code_pack_kernel(const void* __restr
                                                              uint8_t* __restrict__ blob, Workspace ws, uint64_t b0)
 {
     const uint64_t gb = b0 + blockIdx.x;  // the launcher keeps gb < total_blocks
-    const uint32_t l = find_list<false>(lists, a.nlists, gb);
+    const uint32_t l = find_list_wave<false>(lists, a.nlists, gb);
     const lc_batch_list li = lists[l];
     const Layout L = list_layout(a, li.n, li.eps);
     const uint64_t lb = gb - li.block_off;
@@ -3126,7 +3159,7 @@ template <int KB>
 __device__ __forceinline__ bool batch_block(const lc_batch_list* __restrict__ lists, const BatchArgs& a, uint64_t gb,
                                             lc_batch_list* li, Layout* L, uint64_t* b)
 {
-    const uint32_t l = find_list<false>(lists, a.nlists, gb);
+    const uint32_t l = find_list_wave<false>(lists, a.nlists, gb);
     *li = lists[l];
     *L = list_layout(a, li->n, li->eps);
     *b = gb - li->block_off;
