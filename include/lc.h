@@ -303,11 +303,11 @@ typedef struct lc_batch_list {
 
 /* Parameters shared by the lists of a batch. */
 typedef struct lc_batch_params {
-    uint8_t key_bytes, log2_block, frac_bits; /* as lc_params (the greedy fit) */
-    uint8_t tiling;        /* LC_TILING_* */
+    uint8_t key_bytes, log2_block, frac_bits; /* as lc_params */
+    uint8_t tiling;        /* LC_TILING_* (the greedy fit's wave tiling; ignored by the other fits) */
     uint32_t nlists;       /* >= 1 */
     uint32_t max_eps;      /* the largest eps any list may take; sizes the slots */
-    uint32_t reserved2;
+    uint32_t fit;          /* LC_FIT_* of every list of the batch, as lc_params.fit (0: greedy) */
     uint64_t total_blocks; /* set by lc_batch_plan */
     uint64_t total_groups; /* set by lc_batch_plan */
     uint64_t blob_bytes;   /* set by lc_batch_plan: bytes of the batch buffer */

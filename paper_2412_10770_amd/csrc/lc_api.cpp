@@ -127,22 +127,24 @@ constexpr uint64_t kBlockInfoBytes = sizeof(lc::BlockInfo);
 
 lc_status check_batch(const lc_batch_params* p)
 {
-    if (!p || p->nlists == 0 || p->tiling > LC_TILING_LANES || p->reserved2 != 0) return LC_EINVAL;
+    if (!p || p->nlists == 0 || p->tiling > LC_TILING_LANES || p->fit > LC_FIT_OPT) return LC_EINVAL;
     lc_params q{};
     q.key_bytes = p->key_bytes;
     q.log2_block = p->log2_block;
     q.frac_bits = p->frac_bits;
+    q.fit = (uint8_t)p->fit;
     q.eps = p->max_eps;
     return check_params(&q);
 }
 
 // Batch workspace: block infos for up to LC_BATCH_MAX_CANDIDATES size passes,
-// then the segment records of every block (start, anchor delta, slope).
+// then the segment records of every block (start, anchor delta, slope, and
+// the intercept fraction with the optimal fit).
 struct BatchWs {
-    uint64_t blk, start, delta, slope, total;
+    uint64_t blk, start, delta, slope, frac, total;
 };
 
-BatchWs plan_batch_ws(uint64_t total_blocks, uint32_t log2b)
+BatchWs plan_batch_ws(uint64_t total_blocks, uint32_t log2b, uint32_t fit)
 {
     const uint64_t recs = total_blocks << log2b;
     BatchWs w;
@@ -150,7 +152,8 @@ BatchWs plan_batch_ws(uint64_t total_blocks, uint32_t log2b)
     w.start = lc::align16(LC_BATCH_MAX_CANDIDATES * total_blocks * kBlockInfoBytes);
     w.delta = w.start + lc::align16(recs * 2);
     w.slope = w.delta + recs * 8;
-    w.total = w.slope + recs * 8;
+    w.frac = w.slope + recs * 8;
+    w.total = w.frac + (fit == LC_FIT_OPT ? recs * 4 : 0);
     if (w.total == 0) w.total = 16;
     return w;
 }
@@ -164,6 +167,7 @@ lc::BatchArgs batch_args(const lc_batch_params* p, uint64_t nkeys, uint64_t blob
     a.nlists = p->nlists;
     a.max_eps = p->max_eps;
     a.tiling = p->tiling;
+    a.fit = p->fit;
     a.total_blocks = p->total_blocks;
     a.total_groups = p->total_groups;
     a.nkeys = nkeys;
@@ -186,7 +190,7 @@ lc_status check_batch_fit(const void* d_keys, const lc_batch_list* d_lists, cons
         return LC_EINVAL;
     if (p->total_blocks && (!d_keys || !d_ws || misaligned(d_keys, p->key_bytes) || misaligned(d_ws, 16)))
         return LC_EINVAL;
-    const BatchWs w = plan_batch_ws(p->total_blocks, p->log2_block);
+    const BatchWs w = plan_batch_ws(p->total_blocks, p->log2_block, p->fit);
     if (p->total_blocks && ws_bytes < w.total) return LC_ENOSPC;
     uint8_t* ws = static_cast<uint8_t*>(d_ws);
     *W = lc::Workspace{};
@@ -195,6 +199,7 @@ lc_status check_batch_fit(const void* d_keys, const lc_batch_list* d_lists, cons
         W->seg_start = reinterpret_cast<uint16_t*>(ws + w.start);
         W->seg_delta = reinterpret_cast<uint64_t*>(ws + w.delta);
         W->seg_A = reinterpret_cast<uint64_t*>(ws + w.slope);
+        W->seg_frac = p->fit == LC_FIT_OPT ? reinterpret_cast<uint32_t*>(ws + w.frac) : nullptr;
     }
     return LC_OK;
 }
@@ -443,6 +448,7 @@ LC_API lc_status lc_batch_plan(lc_batch_params* p, lc_batch_list* h_lists)
     q.key_bytes = p->key_bytes;
     q.log2_block = p->log2_block;
     q.frac_bits = p->frac_bits;
+    q.fit = (uint8_t)p->fit;
     q.eps = p->max_eps;
     uint64_t blob = 0, blocks = 0, groups = 0;
     for (uint32_t l = 0; l < p->nlists; l++) {
@@ -462,7 +468,7 @@ LC_API lc_status lc_batch_plan(lc_batch_params* p, lc_batch_list* h_lists)
     p->total_blocks = blocks;
     p->total_groups = groups;
     p->blob_bytes = blob;
-    p->ws_bytes = plan_batch_ws(blocks, p->log2_block).total;
+    p->ws_bytes = plan_batch_ws(blocks, p->log2_block, p->fit).total;
     return LC_OK;
 }
 

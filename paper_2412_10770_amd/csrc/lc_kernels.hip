@@ -737,16 +737,17 @@ __device__ __forceinline__ uint64_t mid_slope(uint64_t P, uint64_t H, uint64_t M
     return H >= M ? (H - M) / 2 : 0;  // floor((H - M) / 2), clamped at 0
 }
 
-template <int KB>
-__global__ __launch_bounds__(kMinLanes) void fit_min_kernel(const void* __restrict__ keys, Layout L,
-                                                             uint8_t* __restrict__ blob, Workspace ws,
-                                                             uint32_t* __restrict__ flags, uint64_t blk0)
+// Block b of a list (keys, L, blob slot, workspace of the list); SIZES: the
+// size pass, block info only (no records, slab or first key written).
+template <int KB, bool SIZES>
+__device__ __forceinline__ void fit_min_block(const void* __restrict__ keys, const Layout L,
+                                              uint8_t* __restrict__ blob, const Workspace& ws,
+                                              uint32_t* __restrict__ flags, uint64_t b)
 {
     using KT = typename std::conditional<KB == 4, uint32_t, uint64_t>::type;
     extern __shared__ __align__(16) uint8_t smem[];
     const uint32_t B = 1u << L.log2b;
     const uint32_t lane = threadIdx.x;
-    const uint64_t b = blk0 + blockIdx.x;  // the launcher keeps b < nblocks
     const uint64_t base = b << L.log2b;
     const uint32_t nb = (L.n - base) < B ? (uint32_t)(L.n - base) : B;  // >= 1
     const KT* Kg = reinterpret_cast<const KT*>(keys) + base;
@@ -925,11 +926,13 @@ __global__ __launch_bounds__(kMinLanes) void fit_min_kernel(const void* __restri
     const uint64_t rec = b << L.log2b;
     uint64_t maxA = 0;
     auto emit = [&](uint32_t t, uint32_t s, uint64_t anchor, uint64_t A) {
+        if (SIZES) return;
         ws.seg_start[rec + t] = (uint16_t)s;
         ws.seg_delta[rec + t] = anchor - first;
         ws.seg_A[rec + t] = A;
     };
     auto put_code = [&](uint32_t j, uint32_t s, uint64_t anchor, uint64_t A) {
+        if (SIZES) return;
         const uint64_t pred = anchor + ((A * (uint64_t)(j - s)) >> F);
         const uint64_t code = ((uint64_t)sk[j] - pred + eps) & wmask;
         const uint32_t bitpos = j * w;
@@ -1003,11 +1006,13 @@ __global__ __launch_bounds__(kMinLanes) void fit_min_kernel(const void* __restri
     maxA = wave_max64(maxA);
     __syncthreads();
 
-    uint4* dst = reinterpret_cast<uint4*>(blob + L.off_res + b * L.res_stride);
-    const uint4* src4 = reinterpret_cast<const uint4*>(s_slab);
-    for (uint32_t c = lane; c < slab_words / 4; c += kMinLanes) dst[c] = src4[c];
+    if (!SIZES) {
+        uint4* dst = reinterpret_cast<uint4*>(blob + L.off_res + b * L.res_stride);
+        const uint4* src4 = reinterpret_cast<const uint4*>(s_slab);
+        for (uint32_t c = lane; c < slab_words / 4; c += kMinLanes) dst[c] = src4[c];
+        if (lane == 0) store_key<KB>(blob + L.off_first, b, first);
+    }
     if (lane == 0) {
-        store_key<KB>(blob + L.off_first, b, first);
         const uint64_t maxd = m ? (uint64_t)sk[bnd[1]] - first : 0;  // the last anchor is the largest
         const uint32_t ab = byte_width(maxd), sb = byte_width(maxA);
         BlockInfo bi;
@@ -1019,6 +1024,14 @@ __global__ __launch_bounds__(kMinLanes) void fit_min_kernel(const void* __restri
         bi.pad = 0;
         ws.blk[b] = bi;
     }
+}
+
+template <int KB>
+__global__ __launch_bounds__(kMinLanes) void fit_min_kernel(const void* __restrict__ keys, Layout L,
+                                                             uint8_t* __restrict__ blob, Workspace ws,
+                                                             uint32_t* __restrict__ flags, uint64_t blk0)
+{
+    fit_min_block<KB, false>(keys, L, blob, ws, flags, blk0 + blockIdx.x);  // the launcher keeps b < nblocks
 }
 
 // ---------------------------------------------------------------------------
@@ -1046,10 +1059,12 @@ __global__ __launch_bounds__(kMinLanes) void fit_min_kernel(const void* __restri
 // first (mod 2^64), fraction = C mod 2^F.  One wave per block, sequential
 // over the block's keys.
 // LDS: keys KT[B] | slab u32[res_stride / 4 + 4] | lower hull u16[B] | upper hull u16[B].
-template <int KB>
-__global__ __launch_bounds__(64) void fit_opt_kernel(const void* __restrict__ keys, Layout L,
-                                                     uint8_t* __restrict__ blob, Workspace ws,
-                                                     uint32_t* __restrict__ flags, uint64_t blk0)
+// Block b of a list (keys, L, blob slot, workspace of the list); SIZES: the
+// size pass, block info only (no records, slab or first key written).
+template <int KB, bool SIZES>
+__device__ __forceinline__ void fit_opt_block(const void* __restrict__ keys, const Layout L,
+                                              uint8_t* __restrict__ blob, const Workspace& ws,
+                                              uint32_t* __restrict__ flags, uint64_t b)
 {
     using KT = typename std::conditional<KB == 4, uint32_t, uint64_t>::type;
     using u128 = unsigned __int128;
@@ -1057,7 +1072,6 @@ __global__ __launch_bounds__(64) void fit_opt_kernel(const void* __restrict__ ke
     extern __shared__ __align__(16) uint8_t smem[];
     const uint32_t B = 1u << L.log2b;
     const uint32_t lane = threadIdx.x;
-    const uint64_t b = blk0 + blockIdx.x;  // the launcher keeps b < nblocks
     const uint64_t base = b << L.log2b;
     const uint32_t nb = (L.n - base) < B ? (uint32_t)(L.n - base) : B;  // >= 1
     const KT* Kg = reinterpret_cast<const KT*>(keys) + base;
@@ -1195,13 +1209,13 @@ __global__ __launch_bounds__(64) void fit_opt_kernel(const void* __restrict__ ke
         const uint64_t c_hi = (Ks - eps + r) + (Cp >> F);  // floor(C / 2^F), modulo 2^64
         const uint64_t frac = Cp & fmask;
         const uint64_t delta = c_hi - first;
-        if (lane == 0) {
+        if (lane == 0 && !SIZES) {
             ws.seg_start[base + nseg] = (uint16_t)s;
             ws.seg_delta[base + nseg] = delta;
             ws.seg_A[base + nseg] = A;
             ws.seg_frac[base + nseg] = (uint32_t)frac;
         }
-        if (w != 0) {
+        if (w != 0 && !SIZES) {
             for (uint32_t j = s + lane; j < e; j += 64) {
                 const uint64_t pred = c_hi + ((A * (uint64_t)(j - s) + frac) >> F);
                 const uint64_t code = ((uint64_t)sk[j] - pred + eps) & wmask;
@@ -1220,11 +1234,13 @@ __global__ __launch_bounds__(64) void fit_opt_kernel(const void* __restrict__ ke
     }
     __syncthreads();
 
-    uint4* dst = reinterpret_cast<uint4*>(blob + L.off_res + b * L.res_stride);
-    const uint4* src4 = reinterpret_cast<const uint4*>(s_slab);
-    for (uint32_t c = lane; c < slab_words / 4; c += 64) dst[c] = src4[c];
+    if (!SIZES) {
+        uint4* dst = reinterpret_cast<uint4*>(blob + L.off_res + b * L.res_stride);
+        const uint4* src4 = reinterpret_cast<const uint4*>(s_slab);
+        for (uint32_t c = lane; c < slab_words / 4; c += 64) dst[c] = src4[c];
+        if (lane == 0) store_key<KB>(blob + L.off_first, b, first);
+    }
     if (lane == 0) {
-        store_key<KB>(blob + L.off_first, b, first);
         const uint32_t ab = byte_width(maxd), sb = byte_width(maxA);
         BlockInfo bi;
         bi.nseg = nseg;
@@ -1236,6 +1252,14 @@ __global__ __launch_bounds__(64) void fit_opt_kernel(const void* __restrict__ ke
         bi.pad = 0;
         ws.blk[b] = bi;
     }
+}
+
+template <int KB>
+__global__ __launch_bounds__(64) void fit_opt_kernel(const void* __restrict__ keys, Layout L,
+                                                     uint8_t* __restrict__ blob, Workspace ws,
+                                                     uint32_t* __restrict__ flags, uint64_t blk0)
+{
+    fit_opt_block<KB, false>(keys, L, blob, ws, flags, blk0 + blockIdx.x);  // the launcher keeps b < nblocks
 }
 
 // Sums over tiles of kTileBlocks blocks.
@@ -2878,8 +2902,8 @@ __device__ __forceinline__ Layout list_layout(const BatchArgs& a, uint64_t n, ui
     L.max_nseg = 0;
     L.max_seg_bytes = 0;
     L.blob_bytes = 0;
-    L.flags = 0;  // batches use the greedy fit: no intercept fractions
-    L.fb = 0;
+    L.flags = a.fit == LC_FIT_OPT ? kFlagFrac : 0u;  // the optimal fit stores intercept fractions
+    L.fb = L.flags ? frac_bytes(a.F) : 0u;
     return L;
 }
 
@@ -2895,7 +2919,7 @@ __device__ __forceinline__ bool list_fits(const lc_batch_list& li, const BatchAr
     ok = ok && li.block_off <= a.total_blocks && L.nblocks <= a.total_blocks - li.block_off;
     ok = ok && li.group_off <= a.total_groups && (L.nblocks + 3) / 4 <= a.total_groups - li.group_off;
     if (use_blob) {
-        const uint64_t worst = L.off_seg + L.nblocks * (a16(2 * B) + 2 * a16(8 * B));
+        const uint64_t worst = L.off_seg + L.nblocks * (a16(2 * B) + 2 * a16(8 * B) + a16(L.fb * B));
         ok = ok && (li.blob_off & 15) == 0 && li.blob_off <= a.blob_cap && li.blob_cap <= a.blob_cap - li.blob_off &&
              worst <= li.blob_cap;
     }
@@ -2949,6 +2973,7 @@ __device__ __forceinline__ Workspace list_ws(const Workspace& ws, uint64_t block
     w.seg_start = ws.seg_start ? ws.seg_start + rec : nullptr;
     w.seg_delta = ws.seg_delta ? ws.seg_delta + rec : nullptr;
     w.seg_A = ws.seg_A ? ws.seg_A + rec : nullptr;
+    w.seg_frac = ws.seg_frac ? ws.seg_frac + rec : nullptr;
     return w;
 }
 
@@ -2976,6 +3001,37 @@ __global__ __launch_bounds__(64) void batch_fit_kernel(const void* __restrict__ 
     const Workspace w = list_ws(ws, li.block_off, a.log2b, cand * a.total_blocks + li.block_off);
     const uint8_t* k = reinterpret_cast<const uint8_t*>(keys) + li.key_off * KB;
     fit_rows<KB, SIZES>(k, L, SIZES ? nullptr : blob + li.blob_off, w, stats, local * 4);
+}
+
+// The fewest-segment (FIT = LC_FIT_MIN) or optimal (LC_FIT_OPT) fit over the
+// blocks of a batch, one workgroup per block as the single-list kernels:
+// item = a batch block, or (candidate, block) for the size pass (SIZES:
+// block infos only).  The block's list is found and checked like
+// batch_fit_kernel's.
+template <int KB, bool SIZES, uint32_t FIT>
+__global__ __launch_bounds__(64) void batch_block_fit_kernel(const void* __restrict__ keys,
+                                                             const lc_batch_list* __restrict__ lists, BatchArgs a,
+                                                             Cands cands, uint8_t* __restrict__ blob, Workspace ws,
+                                                             uint32_t* __restrict__ stats, uint64_t item0)
+{
+    const uint64_t item = item0 + blockIdx.x;
+    const uint64_t cand = SIZES ? item / a.total_blocks : 0;
+    const uint64_t gb = SIZES ? item % a.total_blocks : item;
+    const lc_batch_list li = lists[find_list_wave<false>(lists, a.nlists, gb)];
+    const uint32_t eps = SIZES ? cands.eps[cand] : li.eps;
+    const Layout L = list_layout(a, li.n, eps);
+    const uint64_t b = gb - li.block_off;
+    if (!list_fits(li, a, L, eps, !SIZES) || gb < li.block_off || b >= L.nblocks) {
+        if (threadIdx.x == 0) atomicOr(stats, kFlagBadList);
+        return;
+    }
+    const Workspace w = list_ws(ws, li.block_off, a.log2b, cand * a.total_blocks + li.block_off);
+    const uint8_t* k = reinterpret_cast<const uint8_t*>(keys) + li.key_off * KB;
+    uint8_t* bl = SIZES ? nullptr : blob + li.blob_off;
+    if (FIT == LC_FIT_MIN)
+        fit_min_block<KB, SIZES>(k, L, bl, w, stats, b);
+    else
+        fit_opt_block<KB, SIZES>(k, L, bl, w, stats, b);
 }
 
 // Lane-per-block fit over the blocks of a batch (lanes_fit): item = a
@@ -3103,7 +3159,8 @@ __global__ __launch_bounds__(256) void batch_scan_kernel(const lc_batch_list* __
             const uint32_t ab = bi.ab, sb = bi.sb;
             bad = bi.nkeys != want || bi.nseg < 1 || bi.nseg > want || !ab || !sb || ab > 8 || sb > 8 ||
                   (ab & (ab - 1)) || (sb & (sb - 1)) ||
-                  bi.seg_bytes != a16(2ull * bi.nseg) + a16((uint64_t)ab * bi.nseg) + a16((uint64_t)sb * bi.nseg);
+                  bi.seg_bytes != a16(2ull * bi.nseg) + a16((uint64_t)ab * bi.nseg) + a16((uint64_t)sb * bi.nseg) +
+                                      a16((uint64_t)L.fb * bi.nseg);
             if (bad) bi = BlockInfo{};
         }
         if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(stats, kFlagBadList);
@@ -3376,7 +3433,29 @@ hipError_t launch_batch_fit(const void* d_keys, const lc_batch_list* d_lists, co
     while ((1ull << w) < 2ull * eps_max + 1) w++;
     const uint64_t res_stride = align16(((1ull << a.log2b) * w + 7) / 8);
     const bool lanes = a.tiling == LC_TILING_LANES || (a.tiling == LC_TILING_AUTO && a.total_blocks >= kLanesMinBlocks);
-    if (lanes) {
+    if (a.fit == LC_FIT_MIN || a.fit == LC_FIT_OPT) {
+        const uint64_t B = 1ull << a.log2b;
+        const size_t lds = a.fit == LC_FIT_OPT
+                               ? a.kb * B + res_stride + 16 + 4 * B
+                               : 16 + a.kb * B + res_stride + 16 + align16(2 * B) + align16(2 * (B + 1));
+        auto k = a.kb == 4 ? (sizes_only ? batch_block_fit_kernel<4, true, LC_FIT_MIN>
+                                         : batch_block_fit_kernel<4, false, LC_FIT_MIN>)
+                           : (sizes_only ? batch_block_fit_kernel<8, true, LC_FIT_MIN>
+                                         : batch_block_fit_kernel<8, false, LC_FIT_MIN>);
+        if (a.fit == LC_FIT_OPT)
+            k = a.kb == 4 ? (sizes_only ? batch_block_fit_kernel<4, true, LC_FIT_OPT>
+                                        : batch_block_fit_kernel<4, false, LC_FIT_OPT>)
+                          : (sizes_only ? batch_block_fit_kernel<8, true, LC_FIT_OPT>
+                                        : batch_block_fit_kernel<8, false, LC_FIT_OPT>);
+        const hipError_t e = allow_lds((const void*)k, lds);
+        if (e != hipSuccess) return e;
+        const uint64_t items = a.total_blocks * ncand;
+        for (uint64_t i0 = 0; i0 < items; i0 += kMaxGrid) {
+            const uint64_t g = items - i0 < kMaxGrid ? items - i0 : kMaxGrid;
+            hipLaunchKernelGGL(k, dim3((uint32_t)g), dim3(64), lds, stream, d_keys, d_lists, a, c, d_blob, ws, d_stats,
+                               i0);
+        }
+    } else if (lanes) {
         const uint64_t items = (a.total_blocks + 63) / 64 * ncand;
         auto k = a.kb == 4 ? (sizes_only ? batch_lanes_kernel<4, true> : batch_lanes_kernel<4, false>)
                            : (sizes_only ? batch_lanes_kernel<8, true> : batch_lanes_kernel<8, false>);

@@ -60,7 +60,8 @@ inline uint64_t ntiles_of(uint64_t nblocks) { return (nblocks + kTileBlocks - 1)
 // Parameters of a batch of lists, as kernel arguments.
 struct BatchArgs {
     uint32_t kb, log2b, F, nlists, max_eps;
-    uint32_t tiling;        // LC_TILING_* of the fit
+    uint32_t tiling;        // LC_TILING_* of the greedy fit
+    uint32_t fit;           // LC_FIT_* of every list
     uint64_t total_blocks, total_groups;
     uint64_t nkeys;         // keys in the concatenated key (compress) / output (decompress) array
     uint64_t blob_cap;      // bytes of the batch buffer

@@ -63,7 +63,7 @@ class lc_blob_info(ctypes.Structure):
 class lc_batch_params(ctypes.Structure):
     _fields_ = [("key_bytes", ctypes.c_uint8), ("log2_block", ctypes.c_uint8), ("frac_bits", ctypes.c_uint8),
                 ("tiling", ctypes.c_uint8), ("nlists", ctypes.c_uint32), ("max_eps", ctypes.c_uint32),
-                ("reserved2", ctypes.c_uint32)] + \
+                ("fit", ctypes.c_uint32)] + \
                [(f, ctypes.c_uint64) for f in ("total_blocks", "total_groups", "blob_bytes", "ws_bytes")]
 
 
@@ -440,11 +440,12 @@ def _tiling(tiling) -> int:
 
 
 def batch_plan(lengths, eps, key_bytes: int, max_eps: int | None = None, log2_block: int = DEFAULT_LOG2_BLOCK,
-               frac_bits: int = DEFAULT_FRAC_BITS, key_offsets=None, tiling="auto"):
+               frac_bits: int = DEFAULT_FRAC_BITS, key_offsets=None, tiling="auto", fit="greedy"):
     """lc_batch_plan: (lc_batch_params, host table) for lists of the given
     lengths, stored one after another in the key array unless key_offsets is
     given.  eps: one value or one per list; max_eps sizes the blob slots;
-    tiling: the fit's wave tiling ("auto", "rows" or "lanes"; same blobs)."""
+    tiling: the greedy fit's wave tiling ("auto", "rows" or "lanes"; same
+    blobs); fit: "greedy", "min" or "opt" for every list (as compress)."""
     lengths = np.asarray(lengths, dtype=np.uint64).ravel()
     nl = lengths.size
     table = np.zeros(nl, dtype=BATCH_LIST_DTYPE)
@@ -455,7 +456,7 @@ def batch_plan(lengths, eps, key_bytes: int, max_eps: int | None = None, log2_bl
     table["eps"] = np.broadcast_to(np.asarray(eps, dtype=np.uint32), (nl,))
     if max_eps is None:
         max_eps = int(table["eps"].max()) if nl else 0
-    p = lc_batch_params(key_bytes, log2_block, frac_bits, _tiling(tiling), nl, max_eps, 0, 0, 0, 0, 0)
+    p = lc_batch_params(key_bytes, log2_block, frac_bits, _tiling(tiling), nl, max_eps, _fit(fit), 0, 0, 0, 0)
     _check(lib.lc_batch_plan(ctypes.byref(p), table.ctypes.data_as(ctypes.c_void_p)), "lc_batch_plan")
     return p, table
 
@@ -527,18 +528,20 @@ def _raise_flags(fl: int, what: str):
 
 
 def batch_compress(keys: torch.Tensor, lengths, eps=None, candidates=None, log2_block: int = DEFAULT_LOG2_BLOCK,
-                   frac_bits: int = DEFAULT_FRAC_BITS, stream=None, check: bool = True, tiling="auto") -> Batch:
+                   frac_bits: int = DEFAULT_FRAC_BITS, stream=None, check: bool = True, tiling="auto",
+                   fit="greedy") -> Batch:
     """Compress the lists stored one after another in keys.  Either eps (one
     value or one per list) or candidates (the autotuner picks each list's eps
-    among them by exact blob size, ties to the smaller).  tiling: the fit's
-    wave tiling (same blobs either way)."""
+    among them by exact blob size, ties to the smaller).  tiling: the greedy
+    fit's wave tiling (same blobs either way); fit: "greedy", "min" or "opt"
+    for every list of the batch."""
     _dev(keys, "keys")
     kb = _key_bytes(keys)
     if (eps is None) == (candidates is None):
         raise ValueError("give exactly one of eps and candidates")
     cands = sorted(set(int(c) for c in candidates)) if candidates is not None else None
     p, table = batch_plan(lengths, cands[0] if cands else eps, kb, max(cands) if cands else None, log2_block,
-                          frac_bits, tiling=tiling)
+                          frac_bits, tiling=tiling, fit=fit)
     dev = keys.device
     nl = p.nlists
     lists = torch.from_numpy(table.view(np.uint8).copy()).to(dev)

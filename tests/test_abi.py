@@ -156,6 +156,16 @@ def test_batch_plan(lc):
         assert p.total_blocks == nb.sum() and p.total_groups == ng.sum() and p.blob_bytes == sum(caps)
         assert p.ws_bytes >= 18 * p.total_blocks * B + 8 * 16 * p.total_blocks
         assert list(t["eps"]) == [7] * len(lengths)
+    # the optimal fit's slots hold the intercept fractions, its workspace one
+    # u32 fraction per key slot more
+    for F in (0, 20):
+        g, _ = lc.batch_plan(lengths, 7, 8, max_eps=127, frac_bits=F)
+        o, t = lc.batch_plan(lengths, 7, 8, max_eps=127, frac_bits=F, fit="opt")
+        assert o.fit == 2 and g.fit == 0
+        assert list(t["blob_cap"]) == [lc.compress_bound(n, 8, 127, 10, F, fit="opt")[0] for n in lengths]
+        assert o.ws_bytes == g.ws_bytes + 4 * o.total_blocks * 1024
+        m, t = lc.batch_plan(lengths, 7, 8, max_eps=127, frac_bits=F, fit="min")
+        assert m.blob_bytes == g.blob_bytes and m.ws_bytes == g.ws_bytes
 
 
 def test_batch_bad_args(lc):
@@ -170,7 +180,8 @@ def test_batch_bad_args(lc):
                 lc.lc_batch_params(4, 10, 33, 0, 2, 31, 0, 0, 0, 0, 0),
                 lc.lc_batch_params(4, 10, 20, 0, 0, 31, 0, 0, 0, 0, 0),
                 lc.lc_batch_params(4, 10, 20, 0, 2, 2 ** 31, 0, 0, 0, 0, 0),
-                lc.lc_batch_params(4, 10, 20, 3, 2, 31, 0, 0, 0, 0, 0)):  # no such tiling
+                lc.lc_batch_params(4, 10, 20, 3, 2, 31, 0, 0, 0, 0, 0),  # no such tiling
+                lc.lc_batch_params(4, 10, 20, 0, 2, 31, 3, 0, 0, 0, 0)):  # no such fit
         assert lc.lib.lc_batch_plan(P(bad), tp) == lc.LC_EINVAL
     assert lc.lib.lc_batch_plan(P(good), None) == lc.LC_EINVAL
     assert lc.lib.lc_batch_plan(P(good), tp) == lc.LC_OK

@@ -71,9 +71,9 @@ def _mixed_lists(rng, kb, count):
     return out
 
 
-def _check_batch(lc, batch, lists, eps, log2b, frac_bits, kb):
+def _check_batch(lc, batch, lists, eps, log2b, frac_bits, kb, fit="greedy"):
     for l, keys in enumerate(lists):
-        want = oracle.compress(keys, int(eps[l]), log2b, frac_bits)
+        want = oracle.compress(keys, int(eps[l]), log2b, frac_bits, fit=fit)
         got = batch.blob(l).data.cpu().numpy()
         assert int(batch.sizes[l]) == len(want), (l, len(keys), int(eps[l]))
         assert np.array_equal(got, want), (l, len(keys), int(eps[l]))
@@ -102,6 +102,41 @@ def test_fixed_eps_per_list(lc, kb, log2b, frac_bits, tiling):
     b = batch.blob(l)
     idx = torch.from_numpy(rng.integers(0, len(lists[l]), 500).astype(np.int64)).to(DEV)
     assert np.array_equal(_host(lc.access(b, idx), kb), lists[l][idx.cpu().numpy()])
+
+
+# the better-ratio fits for every list of a batch (Sec. II-A's optimal-L
+# goal): per-list blobs equal the oracle's fit of that list
+@pytest.mark.parametrize("fit", ["min", "opt"])
+@pytest.mark.parametrize("kb,log2b,frac_bits", [(4, 10, 20), (8, 10, 0), (8, 6, 20), (4, 8, 0)])
+def test_batch_fits_fixed_eps(lc, fit, kb, log2b, frac_bits):
+    rng = np.random.default_rng(300 + kb + log2b + frac_bits)
+    lists = _mixed_lists(rng, kb, 24)
+    eps = rng.choice([0, 1, 7, 31, 127, 1000], len(lists)).astype(np.uint32)
+    _say(f"batch fit={fit} kb={kb} log2b={log2b} F={frac_bits} lists={len(lists)}")
+    keys, _ = _concat(lists, kb)
+    batch = lc.batch_compress(keys, [len(x) for x in lists], eps=eps, log2_block=log2b, frac_bits=frac_bits, fit=fit)
+    assert batch.params.fit == lc.FITS[fit]
+    _check_batch(lc, batch, lists, eps, log2b, frac_bits, kb, fit=fit)
+    l = max(range(len(lists)), key=lambda i: len(lists[i]))
+    b = batch.blob(l)
+    assert b.info.flags == (1 if fit == "opt" else 0)
+    idx = torch.from_numpy(rng.integers(0, len(lists[l]), 500).astype(np.int64)).to(DEV)
+    assert np.array_equal(_host(lc.access(b, idx), kb), lists[l][idx.cpu().numpy()])
+
+
+@pytest.mark.parametrize("fit", ["min", "opt"])
+@pytest.mark.parametrize("frac_bits", [0, 20])
+def test_batch_fits_autotune_picks_the_oracle_argmin(lc, fit, frac_bits):
+    rng = np.random.default_rng(400 + frac_bits)
+    lists = _mixed_lists(rng, 4, 20)
+    keys, _ = _concat(lists, 4)
+    lengths = [len(x) for x in lists]
+    _say(f"batch autotune fit={fit} F={frac_bits} lists={len(lists)}")
+    want = np.array([[len(oracle.compress(x, e, 10, frac_bits, fit=fit)) for x in lists] for e in CANDS])
+    best = np.array([CANDS[int(np.argmin(want[:, l]))] for l in range(len(lists))], dtype=np.uint32)
+    batch = lc.batch_compress(keys, lengths, candidates=CANDS, frac_bits=frac_bits, fit=fit)
+    assert np.array_equal(batch.eps, best)
+    _check_batch(lc, batch, lists, best, 10, frac_bits, 4, fit=fit)
 
 
 @pytest.mark.parametrize("tiling", TILINGS)
