@@ -305,12 +305,19 @@ def bench_batch(dev, steps: int, warmup: int, nlists: int = 4096, cands=(7, 31, 
     b, pl = res["batched_eager"], res["per_list_eager"]
     key_bytes = n * 4
     # block size picked by the autotuner: exact bytes and decode time per size
-    log("batch: block-size autotune")
+    log("batch: block-size and fit autotune")
+    fits = (("greedy", 0), ("greedy", 20), ("opt", 0), ("opt", 20))
     _, tune = lc.autotune_batch(keys, lengths, cands, block_candidates=(8, 9, 10, 11, 12), objective="size",
-                              frac_bits=FRAC_BITS)
-    block_tune = [{"log2_block": r["log2_block"], "bits_per_key": round(8.0 * r["bytes"] / n, 4),
-                   "decode_GBps": round(key_bytes / r["decode_ms"] / 1e6, 2), "chosen": r["chosen"]} for r in tune]
+                                frac_bits=FRAC_BITS, fit_candidates=fits)
+    row = lambda r: {"log2_block": r["log2_block"], "fit": r["fit"], "frac_bits": r["frac_bits"],  # noqa: E731
+                     "bits_per_key": round(8.0 * r["bytes"] / n, 4),
+                     "decode_GBps": round(key_bytes / r["decode_ms"] / 1e6, 2), "chosen": r["chosen"]}
+    block_tune = [row(r) for r in tune if r["fit"] == "greedy" and r["frac_bits"] == FRAC_BITS]
     picked = next(r for r in tune if r["chosen"])
+    lb_best = picked["log2_block"]
+    ref = next(r for r in tune if r["log2_block"] == lb_best and r["fit"] == "greedy" and r["frac_bits"] == FRAC_BITS)
+    fit_tune = [dict(row(r), bytes_saved_pct_vs_greedy=round(100.0 * (ref["bytes"] - r["bytes"]) / ref["bytes"], 3))
+                for r in tune if r["log2_block"] == lb_best]
     tiling_tune = {"log2_block": picked["log2_block"], "tiling": picked.get("tiling"),
                    "compress_ms": {k: round(v, 3) for k, v in picked.get("compress_ms_by_tiling", {}).items()}}
     return {
@@ -329,6 +336,7 @@ def bench_batch(dev, steps: int, warmup: int, nlists: int = 4096, cands=(7, 31, 
         "step_ms": {k: v["ms"] for k, v in res.items()},
         "phases_ms": {k: {kk: vv for kk, vv in v.items() if kk != "ms"} for k, v in res.items() if "eager" in k},
         "block_size_autotune": block_tune,
+        "fit_autotune": fit_tune,
         "tiling_autotune": tiling_tune,
         "note": "batched step = autotune (size pass over the candidates + pick) + compress + decompress; "
                 "per-list step = compress + decompress only (eps given), identical blobs; the step runs at "

@@ -71,7 +71,7 @@ typedef int32_t lc_status;
                                block was skipped) */
 
 #define LC_DEFAULT_LOG2_BLOCK 10
-#define LC_DEFAULT_FRAC_BITS 20
+#define LC_DEFAULT_FRAC_BITS 0
 #define LC_MAX_EPS 0x7FFFFFFFu
 #define LC_HEADER_BYTES 128
 
@@ -106,7 +106,8 @@ typedef int32_t lc_status;
  *   log2_block 6..12 (block size B = 2^log2_block keys; segments never cross
  *              a block)
  *   frac_bits  0..32, fractional bits F of the fixed-point slope A / 2^F
- *              (LC_DEFAULT_FRAC_BITS = 20)
+ *              (LC_DEFAULT_FRAC_BITS = 0: integer slopes, the smallest and
+ *              fastest blobs measured on every workload here)
  *   fit        LC_FIT_GREEDY (0), LC_FIT_MIN or LC_FIT_OPT
  *   eps        0..LC_MAX_EPS, the error bound of Def. 2; residuals take
  *              w = ceil(log2(2 eps + 1)) bits each (Sec. II-A) */

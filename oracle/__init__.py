@@ -113,7 +113,7 @@ class Ref:
         """Residual width ceil(log2(2 eps + 1)) as the oracle computes it."""
         return int(self.L.lcref_width(eps))
 
-    def fit_block(self, keys, eps: int, frac_bits: int = 20, fit: str = "greedy"):
+    def fit_block(self, keys, eps: int, frac_bits: int = 0, fit: str = "greedy"):
         """Fit of one block.  fit: "greedy" (each anchored segment as long as
         it goes) or "min" (fewest segments of the same anchored class) return
         (start, anchor, A) arrays; "opt" (free fixed-point intercept C,
@@ -134,7 +134,7 @@ class Ref:
         m = fn(k.ctypes.data, nb, eps, frac_bits, st.ctypes.data, an.ctypes.data, sl.ctypes.data)
         return st[:m].copy(), an[:m].copy(), sl[:m].copy()
 
-    def compress(self, keys, eps: int, log2_block: int = 10, frac_bits: int = 20,
+    def compress(self, keys, eps: int, log2_block: int = 10, frac_bits: int = 0,
                  fit: str = "greedy") -> np.ndarray:
         """Encode sorted keys into a blob v1 (uint8 array)."""
         k = _keys_array(keys)
@@ -188,11 +188,11 @@ def width(eps: int) -> int:
     return default().width(eps)
 
 
-def fit_block(keys, eps: int, frac_bits: int = 20, fit: str = "greedy"):
+def fit_block(keys, eps: int, frac_bits: int = 0, fit: str = "greedy"):
     return default().fit_block(keys, eps, frac_bits, fit)
 
 
-def compress(keys, eps: int, log2_block: int = 10, frac_bits: int = 20,
+def compress(keys, eps: int, log2_block: int = 10, frac_bits: int = 0,
              fit: str = "greedy") -> np.ndarray:
     return default().compress(keys, eps, log2_block, frac_bits, fit)
 
@@ -245,7 +245,7 @@ def quantile(keys, k, q: int) -> np.ndarray:
     return kk[np.asarray(idx, dtype=np.int64)]
 
 
-def predict(keys, eps: int, log2_block: int = 10, frac_bits: int = 20,
+def predict(keys, eps: int, log2_block: int = 10, frac_bits: int = 0,
             fit: str = "greedy") -> np.ndarray:
     """The fitted eps-PLA without residuals (Def. 2; the AQP reading of
     Sec. III-C): per block, segment t starting at s_t with anchor a_t, slope

@@ -37,7 +37,7 @@ SETOP_UNION = 2
 BATCH_MAX_CANDIDATES = 8
 HEADER_BYTES = 128
 DEFAULT_LOG2_BLOCK = 10
-DEFAULT_FRAC_BITS = 20
+DEFAULT_FRAC_BITS = 0
 
 EXPORTED = ("lc_compress_bound", "lc_compress", "lc_compress_noalloc", "lc_info", "lc_decompress", "lc_decompress_range",
             "lc_access", "lc_lower_bound", "lc_quantile", "lc_decompress_approx", "lc_setop_bound", "lc_setop",
@@ -718,26 +718,41 @@ def time_batch_fit(keys: torch.Tensor, lengths, eps_candidates=(7, 31, 127), log
     return out
 
 
+def _pick(report, objective):
+    fastest = min(r["decode_ms"] for r in report)
+    if objective == "speed":
+        return min(report, key=lambda r: (r["decode_ms"], r["bytes"]))
+    if objective == "balanced":
+        return min((r for r in report if r["decode_ms"] <= 1.1 * fastest), key=lambda r: (r["bytes"], r["decode_ms"]))
+    return min(report, key=lambda r: (r["bytes"], r["decode_ms"]))
+
+
 def autotune_batch(keys: torch.Tensor, lengths, eps_candidates=(7, 31, 127), block_candidates=(8, 9, 10, 11, 12),
                    objective: str = "size", time_reps: int = 3, frac_bits: int = DEFAULT_FRAC_BITS, stream=None,
-                   tilings=("rows", "lanes")):
+                   tilings=("rows", "lanes"), fit_candidates=None):
     """Pick the batch's block size (and, per list, eps among eps_candidates)
     by measurement.  For every log2 block size the whole batch is compressed
-    with the on-device eps autotune; its exact total bytes and its batch
-    decode time (HIP events, mean of time_reps runs) are recorded.
-    objective "size": fewest bytes (ties: faster decode); "speed": fastest
-    decode; "balanced": fewest bytes among the candidates whose decode is
-    within 10% of the fastest.  Then, for the chosen block size, the fit's
-    wave tiling is picked by timing the whole compress under each of tilings
-    (same bytes, so only speed decides).  Returns (chosen Batch, report
-    list); the chosen entry records the tiling times and the tiling picked."""
+    with the on-device eps autotune (greedy fit, frac_bits); its exact total
+    bytes and its batch decode time (HIP events, mean of time_reps runs) are
+    recorded.  objective "size": fewest bytes (ties: faster decode); "speed":
+    fastest decode; "balanced": fewest bytes among the candidates whose
+    decode is within 10% of the fastest.  Then, at the chosen block size,
+    every (fit, F) of fit_candidates (e.g. (("greedy", 0), ("opt", 0)),
+    greedy at frac_bits always included) is measured the same way and the
+    objective picks among them too; last, the greedy fit's wave tiling is
+    picked by timing the whole compress under each of tilings (same bytes,
+    so only speed decides).  Returns (chosen Batch, report list): one entry
+    per block size (greedy, frac_bits) and one per further (fit, F) at the
+    chosen block size; the chosen entry has "chosen" set and, for the greedy
+    fit, the tiling times and the tiling picked."""
     if objective not in ("size", "speed", "balanced"):
         raise ValueError("objective is 'size', 'speed' or 'balanced'")
     report, batches = [], {}
     out = torch.empty(keys.numel(), dtype=key_dtype(_key_bytes(keys)), device=keys.device)
-    for lb in block_candidates:
-        b = batch_compress(keys, lengths, candidates=eps_candidates, log2_block=lb, frac_bits=frac_bits,
-                           stream=stream)
+
+    def measure(lb, fit, F):
+        b = batch_compress(keys, lengths, candidates=eps_candidates, log2_block=lb, frac_bits=F, stream=stream,
+                           fit=fit)
         batch_decompress(b, out=out, stream=stream)  # warm, and checks the flags
         t = []
         for _ in range(max(1, time_reps)):
@@ -747,19 +762,24 @@ def autotune_batch(keys: torch.Tensor, lengths, eps_candidates=(7, 31, 127), blo
             e1.record()
             torch.cuda.synchronize()
             t.append(e0.elapsed_time(e1))
-        report.append({"log2_block": lb, "bytes": b.nbytes, "decode_ms": float(sum(t) / len(t))})
-        batches[lb] = b
-    fastest = min(r["decode_ms"] for r in report)
-    if objective == "speed":
-        best = min(report, key=lambda r: (r["decode_ms"], r["bytes"]))
-    elif objective == "balanced":
-        best = min((r for r in report if r["decode_ms"] <= 1.1 * fastest), key=lambda r: (r["bytes"], r["decode_ms"]))
-    else:
-        best = min(report, key=lambda r: (r["bytes"], r["decode_ms"]))
+        r = {"log2_block": lb, "fit": fit, "frac_bits": F, "bytes": b.nbytes, "decode_ms": float(sum(t) / len(t))}
+        report.append(r)
+        batches[id(r)] = b
+        return r
+
+    for lb in block_candidates:
+        measure(lb, "greedy", frac_bits)
+    best = _pick(report, objective)
+    for fit, F in (fit_candidates or ()):
+        if (fit, F) != ("greedy", frac_bits):
+            measure(best["log2_block"], fit, F)
+    best = _pick([r for r in report if r["log2_block"] == best["log2_block"]], objective)
     for r in report:
         r["chosen"] = r is best
-    if tilings:
-        t = time_batch_fit(keys, lengths, eps_candidates, best["log2_block"], tilings, time_reps, frac_bits)
+    if tilings and best["fit"] == "greedy":
+        t = time_batch_fit(keys, lengths, eps_candidates, best["log2_block"], tilings, time_reps, best["frac_bits"])
         best["compress_ms_by_tiling"] = t
         best["tiling"] = min(t, key=t.get)
-    return batches[best["log2_block"]], report
+    chosen = batches[id(best)]
+    batches.clear()
+    return chosen, report

@@ -148,7 +148,7 @@ def test_autotune_picks_the_oracle_argmin(lc, kb, tiling):
     keys, _ = _concat(lists, kb)
     lengths = [len(x) for x in lists]
     # the size pass itself
-    p, table = lc.batch_plan(lengths, CANDS[0], kb, max(CANDS), tiling=tiling)
+    p, table = lc.batch_plan(lengths, CANDS[0], kb, max(CANDS), frac_bits=20, tiling=tiling)
     d_lists = torch.from_numpy(table.view(np.uint8).copy()).to(DEV)
     ws = torch.empty(p.ws_bytes, dtype=torch.uint8, device=DEV)
     sizes = torch.empty(len(CANDS) * len(lists), dtype=torch.int64, device=DEV)
@@ -159,7 +159,7 @@ def test_autotune_picks_the_oracle_argmin(lc, kb, tiling):
     want_sizes = np.array([[len(oracle.compress(x, e, 10, 20)) for x in lists] for e in CANDS])
     assert np.array_equal(got_sizes, want_sizes)
     best = np.array([CANDS[int(np.argmin(want_sizes[:, l]))] for l in range(len(lists))], dtype=np.uint32)
-    batch = lc.batch_compress(keys, lengths, candidates=CANDS, tiling=tiling)
+    batch = lc.batch_compress(keys, lengths, candidates=CANDS, frac_bits=20, tiling=tiling)
     assert np.array_equal(batch.eps, best)
     _check_batch(lc, batch, lists, best, 10, 20, kb)
 
@@ -174,7 +174,7 @@ def test_bad_list_is_flagged_and_skipped(lc, tiling):
     bad = 9
     offs_bad = offs.copy()
     offs_bad[bad] = keys.numel() - lengths[bad] + 1  # one key past the end
-    p, table = lc.batch_plan(lengths, 31, 4, key_offsets=offs_bad, tiling=tiling)
+    p, table = lc.batch_plan(lengths, 31, 4, frac_bits=20, key_offsets=offs_bad, tiling=tiling)
     d_lists = torch.from_numpy(table.view(np.uint8).copy()).to(DEV)
     ws = torch.empty(p.ws_bytes, dtype=torch.uint8, device=DEV)
     blob = torch.zeros(p.blob_bytes, dtype=torch.uint8, device=DEV)
@@ -219,7 +219,7 @@ def test_posting_lists_reduced(lc, wl, tiling):
     """The batch workload's recipe at 256 lists of 100 .. 10^5 keys, autotuned."""
     keys, lengths = wl.posting_lists(256, device=DEV, hi=1e5)
     _say(f"posting lists reduced: {len(lengths)} lists, {keys.numel()} keys, tiling={tiling}")
-    batch = lc.batch_compress(keys, lengths, candidates=CANDS, tiling=tiling)
+    batch = lc.batch_compress(keys, lengths, candidates=CANDS, frac_bits=20, tiling=tiling)
     out = lc.batch_decompress(batch)
     assert torch.equal(out, keys)
     host = _host(keys, 4)
@@ -291,6 +291,29 @@ def test_autotune_block_size(lc, wl):
     fast, rep2 = lc.autotune_batch(keys, lengths, block_candidates=(8, 12), objective="speed", time_reps=2)
     c2 = next(r for r in rep2 if r["chosen"])
     assert c2["decode_ms"] == min(r["decode_ms"] for r in rep2)
+
+
+def test_autotune_fit_and_frac_bits(lc, wl):
+    """The autotuner's (fit, F) candidates at the chosen block size: the
+    choice has the fewest bytes among them, and its lists equal the oracle's
+    blobs for that fit and F."""
+    keys, lengths = wl.posting_lists(48, device=DEV, hi=2e4)
+    _say(f"autotune fit / F: {keys.numel()} keys")
+    fits = (("greedy", 0), ("greedy", 20), ("opt", 0), ("opt", 20), ("min", 0))
+    best, report = lc.autotune_batch(keys, lengths, block_candidates=(9, 10), objective="size", frac_bits=0,
+                                     fit_candidates=fits, tilings=())
+    chosen = next(r for r in report if r["chosen"])
+    at = [r for r in report if r["log2_block"] == chosen["log2_block"]]
+    assert {(r["fit"], r["frac_bits"]) for r in at} == set(fits)
+    assert chosen["bytes"] == min(r["bytes"] for r in at)
+    assert best.params.fit == lc.FITS[chosen["fit"]] and best.params.frac_bits == chosen["frac_bits"]
+    assert torch.equal(lc.batch_decompress(best), keys)
+    host = keys.cpu().numpy().view(np.uint32)
+    offs = np.concatenate([[0], np.cumsum(lengths)[:-1]])
+    for l in (0, int(np.argmax(lengths))):
+        x = host[offs[l]:offs[l] + lengths[l]]
+        want = oracle.compress(x, int(best.eps[l]), chosen["log2_block"], chosen["frac_bits"], fit=chosen["fit"])
+        assert np.array_equal(best.blob(l).data.cpu().numpy(), want)
 
 
 @pytest.mark.parametrize("kb", [4, 8])

@@ -118,7 +118,7 @@ def test_lognormal_100m_min_fit(lc, wl):
     the greedy fit, same checks."""
     keys = wl.lognormal_distinct(100_000_000, device=DEV)
     for eps in (63, 255):
-        g = lc.compress(keys, eps).info.nseg_total
+        g = lc.compress(keys, eps, frac_bits=20).info.nseg_total
         m = check_fullsize(lc, keys, eps, n_access=1_000_000, n_lb=1_000_000, seed=100 + eps, fit="min")
         assert m.info.nseg_total <= g
 
@@ -128,7 +128,7 @@ def test_lognormal_100m_opt_fit(lc, wl):
     F = 20 (4-byte fractions) and F = 0 (none): never more segments than the
     fewest-segment anchored fit at F = 20, same checks."""
     keys = wl.lognormal_distinct(100_000_000, device=DEV)
-    m = lc.compress(keys, 63, fit="min").info.nseg_total
+    m = lc.compress(keys, 63, frac_bits=20, fit="min").info.nseg_total
     for F in (20, 0):
         o = check_fullsize(lc, keys, 63, n_access=1_000_000, n_lb=1_000_000, seed=300 + F, fit="opt", frac_bits=F)
         assert o.info.flags == 1

@@ -75,7 +75,7 @@ def test_min_fit_equals_greedy_when_greedy_is_one_segment():
     for g in (0, 1, 3, 1000):
         k = (np.uint64(7) + np.uint64(g) * np.arange(1024, dtype=np.uint64))
         for eps in (0, 7):
-            gs = oracle.fit_block(k, eps)
+            gs = oracle.fit_block(k, eps, 20)
             ms = oracle.fit_block(k, eps, 20, "min")
             assert len(gs[0]) == 1
             assert all(np.array_equal(x, y) for x, y in zip(gs, ms))
