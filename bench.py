@@ -867,8 +867,107 @@ def emit(result: dict, full_json: str | None):
     print(json.dumps(headline(result)), flush=True)
 
 
+def _counter_rows(d: str):
+    """(dispatch id, kernel name, counter name, value) of a rocprofv3 --pmc
+    csv output folder, in dispatch order."""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])))
+    rows.sort()
+    return rows
+
+
+def summarize_traffic(fetch_dir: str, write_dir: str, n: int, eps_list, out: str = TRAFFIC_FILE):
+    """profiles/decode_traffic.json from two counter runs (FETCH_SIZE, then
+    WRITE_SIZE, KiB per dispatch) of the core benchmark: both scaled by what
+    they read for the untimed CALIB_COPY_BYTES copy; a decompress is cold
+    when the dispatch before it is the FLUSH_BYTES flush copy, warm
+    otherwise; decompress calls after the first (the untimed round-trip
+    check) come in (warm, cold) pairs, one pair per eps in order."""
+    import numpy as np
+    def per_dispatch(d, counter):  # bytes per dispatch (rows of one dispatch summed)
+        acc = {}
+        for i, k, c, v in _counter_rows(d):
+            if c == counter:
+                acc[i] = (k, acc.get(i, (k, 0.0))[1] + v * 1024.0)
+        return acc
+    f, w = per_dispatch(fetch_dir, "FETCH_SIZE"), per_dispatch(write_dir, "WRITE_SIZE")
+    if not f or not w:
+        raise SystemExit(f"no FETCH_SIZE / WRITE_SIZE rows under {fetch_dir} / {write_dir}")
+    copies = [i for i in sorted(w) if "decode" not in w[i][0]]
+    calib = next(i for i in copies if abs(w[i][1] - CALIB_COPY_BYTES) < 0.05 * CALIB_COPY_BYTES)
+    fs, ws = CALIB_COPY_BYTES / f[calib][1], CALIB_COPY_BYTES / w[calib][1]
+    flush = {i for i in copies if abs(w[i][1] * ws - FLUSH_BYTES) < 0.05 * FLUSH_BYTES}
+    dec = [i for i in sorted(w) if "decode_full_kernel<8, false>" in w[i][0]]
+    by = {"cold": {str(e): [] for e in eps_list}, "warm": {str(e): [] for e in eps_list}}
+    order = sorted(w)
+    for k, i in enumerate(dec[1:]):
+        prev = order[order.index(i) - 1]
+        kind = "cold" if prev in flush else "warm"
+        e = str(eps_list[(k // 2) % len(eps_list)])
+        by[kind][e].append(f[i][1] * fs + w[i][1] * ws)
+    rec = {"n": n, "eps": list(eps_list), "frac_bits": FRAC_BITS, "fetch_scale": round(fs, 4),
+           "write_scale": round(ws, 4), "kernel_src_sha256_16": kernel_src_hash(),
+           "kernels": ["decode_full_kernel<8, false>"]}
+    for kind in ("cold", "warm"):
+        vals = [v for e in by[kind] for v in by[kind][e]]
+        rec[f"bytes_per_decompress_{kind}"] = int(np.mean(vals))
+        rec[f"bytes_per_decompress_{kind}_by_eps"] = {e: int(np.mean(v)) for e, v in by[kind].items() if v}
+        rec[f"calls_{kind}"] = len(vals)
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return rec
+
+
+def summarize_valu(valu_dir: str, n: int, eps_list, out: str = VALU_FILE):
+    """profiles/compress_valu.json from a counter run (SQ_INSTS_VALU) of the
+    core benchmark restricted to the compress kernels: every lc_compress call
+    starts with its fit kernel; calls come one per eps in order."""
+    import numpy as np
+    acc = {}
+    for i, k, c, v in _counter_rows(valu_dir):
+        if c == "SQ_INSTS_VALU":
+            acc[i] = (k, acc.get(i, (k, 0.0))[1] + v)
+    rows = [(i, k, v) for i, (k, v) in sorted(acc.items())]
+    if not rows:
+        raise SystemExit(f"no SQ_INSTS_VALU rows under {valu_dir}")
+    calls, names = [], set()
+    for i, k, v in rows:
+        name = k.replace("void ", "").replace("lc::(anonymous namespace)::", "").split("(")[0]
+        names.add(name)
+        if "fit_" in name or not calls:
+            calls.append(0.0)
+        calls[-1] += v
+    per = {str(e): [] for e in eps_list}
+    for k, v in enumerate(calls):
+        per[str(eps_list[k % len(eps_list)])].append(v)
+    rec = {"n": n, "eps": list(eps_list), "frac_bits": FRAC_BITS,
+           "valu_insts_per_call": {e: int(np.mean(v)) for e, v in per.items() if v},
+           "calls_counted": {e: len(v) for e, v in per.items()},
+           "kernel_src_sha256_16": kernel_src_hash(), "kernels": sorted(names)}
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return rec
+
+
 def main():
     global FRAC_BITS
+    if len(sys.argv) > 1 and sys.argv[1] in ("--summarize-traffic", "--summarize-valu"):
+        # host only: turn counter runs (rocprofv3 csv folders) into the profiles/*.json bench reads
+        sp = argparse.ArgumentParser()
+        sp.add_argument("dirs", nargs="+")
+        sp.add_argument("--n", type=int, default=100_000_000)
+        sp.add_argument("--eps", type=str, default="15,63,255")
+        a = sp.parse_args(sys.argv[2:])
+        eps_list = [int(e) for e in a.eps.split(",")]
+        if sys.argv[1] == "--summarize-traffic":
+            print(json.dumps(summarize_traffic(a.dirs[0], a.dirs[1], a.n, eps_list)))
+        else:
+            print(json.dumps(summarize_valu(a.dirs[0], a.n, eps_list)))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
