@@ -742,7 +742,7 @@ def bench_fits(dev, keys_lognormal=None, reps: int = 3):
         pos = torch.empty(nq, dtype=torch.int64, device=dev)
         rows = {}
         for eps in eps_list:
-            bmax, ws_bytes = lc.compress_bound(n, kb, eps, fit="opt")  # the largest of the variants
+            bmax, ws_bytes = lc.compress_bound(n, kb, eps, frac_bits=20, fit="opt")  # the largest of the variants
             blob = torch.empty(bmax, dtype=torch.uint8, device=dev)
             ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
             nb = torch.zeros(1, dtype=torch.int64, device=dev)
