@@ -249,6 +249,25 @@ __device__ __forceinline__ double vmin_f64(double a, double b)
     return r;
 }
 
+// c ? a : b per lane as one v_cndmask on the active lanes' mask.  Written
+// as asm so that the compiler keeps it a select after the branch that c also
+// guards, rather than a move inside that branch (which, for a register a
+// pending LDS read writes, would wait for the read).
+__device__ __forceinline__ uint32_t sel_u32(uint64_t mask, uint32_t a, uint32_t b)
+{
+    uint32_t r;
+    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(b), "v"(a), "s"(mask));
+    return r;
+}
+
+__device__ __forceinline__ double sel_f64(uint64_t mask, double a, double b)
+{
+    const uint32_t lo = sel_u32(mask, (uint32_t)__double_as_longlong(a), (uint32_t)__double_as_longlong(b));
+    const uint32_t hi = sel_u32(mask, (uint32_t)(__double_as_longlong(a) >> 32),
+                                (uint32_t)(__double_as_longlong(b) >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // v as a double, exactly, for v < 2^52: the mantissa of 2^52 + v holds v.
 __device__ __forceinline__ double exact_f64(uint64_t v)
 {
@@ -1586,7 +1605,7 @@ __device__ __forceinline__ void lanes_fit(const LaneBlock& in, const void* __res
     const uint32_t lane = threadIdx.x;
     const uint32_t B = 1u << log2b;
     const uint32_t nb = in.nb;
-    for (uint32_t i = lane; i <= B + 1; i += 64) s_inv[i] = recip(i > 0 ? i : 1u);
+    for (uint32_t i = lane; i <= B + 1; i += 64) s_inv[i] = 1.0 / (double)(i > 0 ? i : 1u);  // correctly rounded
     const KT* K0 = reinterpret_cast<const KT*>(keys);
     const KT* Kb = K0 + in.koff;
     const uint64_t kend = nkeys;  // key index bound of every load
@@ -1678,60 +1697,79 @@ __device__ __forceinline__ void lanes_fit(const LaneBlock& in, const void* __res
         maxd = Ka - first;  // anchors grow with the segment index
     };
 
-    // Fast-path state, all exact integers in FP64 (every numerator is below
-    // 2^49): Lf = the largest lower end ceil((D - eps) 2^F / d) over the open
-    // segment's keys, signed (negative while every key lies below eps of the
-    // anchor), Hf = the smallest upper end floor(((D + eps + 1) 2^F - 1) / d);
-    // a key that makes Lf > Hf closes the segment.  The closed segment's slope
-    // is max(0, Lf + floor((Hf - Lf) / 2)): the midpoint of [Lf, Hf], which is
-    // also the midpoint of [0, Hf] shifted by the negative part of Lf, exactly
-    // the rule of the slow path's (P, H, M) encoding.  Keys enter as their
-    // distance from the block's first key (exact below 2^49), the anchor as
-    // Kad, and d and its reciprocal advance with the walk.
-    constexpr double kBig = 1.8e19;                        // no bound yet: beyond every real bound
-    constexpr double kRound = 6755399441055744.0;          // 1.5 * 2^52: FMA into it rounds to an integer
-    double Lf = -kBig, Hf = kBig, Kad = 0.0, df = 1.0, maxAf = 0.0;
+    // Fast path, exact FP64 arithmetic (every numerator is below 2^49).  For
+    // key e at distance d = e - s from the anchor s, with D = K[e] - K[s]:
+    //   lower end ceil((D - eps) 2^F / d)            = floor(xl / d), xl = D 2^F - eps 2^F + (d - 1) / 2
+    //   upper end floor(((D + eps + 1) 2^F - 1) / d) = floor(xh / d), xh = D 2^F + (eps + 1) 2^F - 1 - (d - 1) / 2
+    // using floor(y / d) = round((y + 1/2 - d/2) / d) for integers y (and the
+    // ceiling as the floor of y + d - 1): that quotient lies at least 1/(2d)
+    // inside its rounding interval, and with |y| < 2^49 and 1/d correctly
+    // rounded the product errs by at most 1/(16d), so one FMA into the
+    // mantissa of 1.5 * 2^52 yields the exact integer, with no remainder
+    // correction.  The bounds stay in that offset domain (Lf = kRound +
+    // largest lower end, Hf = kRound + smallest upper end); only max, min and
+    // compares touch them.  xl and xh split into a per-key term Pk = K' 2^F +
+    // e/2 (resp. Qk = K' 2^F - e/2, K' = K[e] - K[0]) and a per-segment term
+    // Ca = -eps 2^F - 1/2 - Pk(s) (resp. Cb = (eps + 1) 2^F - 1/2 - Qk(s)),
+    // so a step is two adds, two FMAs, a max, a min and a compare.  A closed
+    // segment's slope is max(0, Lf + floor((Hf - Lf) / 2)) in real terms: the
+    // midpoint of [Lf, Hf], which is also the slow path's (P, H, M) rule.
+    // No bound yet: only the high word of a reset bound is set, which puts it
+    // beyond every real bound whatever its low word holds.
+    constexpr uint32_t kLoResetHi = 0xC3F00000u, kHiResetHi = 0x43F00000u;  // -2^64 .. -2^65, 2^64 .. 2^65
+    constexpr double kRound = 6755399441055744.0;  // 1.5 * 2^52: FMA into it rounds to an integer
+    constexpr double kTwo52 = 4503599627370496.0;
     const double epsLo = epsf * scf, epsHi = (epsf + 1.0) * scf - 1.0;
-    auto close_f = [&](uint32_t e) {
-        const double A = vmax_f64(0.0, Lf + __builtin_floor((Hf - Lf) * 0.5));
+    const double cLo = -epsLo - 0.5, cHi = epsHi + 0.5;
+    const double m52 = -kTwo52 * scf;  // K' 2^F = fma(2^52 + K', 2^F, -2^52 2^F), exactly
+    auto with_hi = [](double v, uint32_t hi) {
+        return __longlong_as_double((long long)(((uint64_t)hi << 32) | (uint32_t)__double_as_longlong(v)));
+    };
+    double Lf = with_hi(0.0, kLoResetHi), Hf = with_hi(0.0, kHiResetHi), Ca = cLo, Cb = cHi;
+    double maxAf = 0.0;
+    uint64_t Kadu = 0;  // K' of the open segment's anchor
+    // LDS byte address of s_inv[d + 1], d = the distance of the current key
+    // from its anchor: the reciprocal the next key needs if this one joins
+    uint32_t inv_two = (uint32_t)(uintptr_t)(s_inv + 2);
+    asm("" : "+v"(inv_two));  // kept in a register, not rebuilt at every step
+    uint32_t ib = inv_two;
+    auto to_u64 = [](double v) {  // an exact integer below 2^52
+        return (uint64_t)__double_as_longlong(v + kTwo52) & 0x000FFFFFFFFFFFFFull;
+    };
+    // offset-domain bounds -> slope; a block's last segment may hold its
+    // anchor only (bounds still reset: slope 0), every other closed segment
+    // holds two keys or more (a key one step from its anchor never closes one)
+    auto close_f = [&](bool last) {
+        double A = vmax_f64(0.0, (Lf - kRound) + __builtin_floor((Hf - Lf) * 0.5));
+        if (last) A = Lf < 2251799813685248.0 ? 0.0 : A;
         if (RECORDS) {
             in.st[nseg] = (uint16_t)s;
-            in.dl[nseg] = (uint64_t)__double_as_longlong(Kad + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
-            in.sa[nseg] = (uint64_t)__double_as_longlong(A + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
+            in.dl[nseg] = Kadu;
+            in.sa[nseg] = to_u64(A);
         }
         nseg++;
         maxAf = vmax_f64(maxAf, A);
-        (void)e;
     };
-    // one key of the fast walk: e = its index (> 0), kd = its distance from
-    // the block's first key; d_i = e - s as an integer (df as a double), inv
-    // = 1 / df.  Each quotient is rounded to an integer by one FMA (the floor
-    // or the ceiling of the exact one) and corrected by the sign of its exact
-    // FMA remainder.
-    uint32_t d_i = 1;
-    auto step_f = [&](uint32_t e, double kd) {
-        const double D = kd - Kad;
-        const uint32_t dn_i = d_i + 1;
-        const double inv_next = s_inv[dn_i];  // the next key's, off the critical path
-        const double xl = __builtin_fma(D, scf, -epsLo);
-        const double ql = __builtin_fma(xl, inv, kRound) - kRound;
-        const double rl = __builtin_fma(-ql, df, xl);
-        const double lo = ql + (rl > 0.0 ? 1.0 : 0.0);  // ceil(xl / d)
-        const double xh = __builtin_fma(D, scf, epsHi);
-        const double qh = __builtin_fma(xh, inv, kRound) - kRound;
-        const double rh = __builtin_fma(-qh, df, xh);
-        const double hi = qh - (rh < 0.0 ? 1.0 : 0.0);  // floor(xh / d)
-        const double Ln = vmax_f64(Lf, lo), Hn = vmin_f64(Hf, hi);
-        const double dn = df + 1.0;
-        const bool fail = Ln > Hn;
-        if (fail) close_f(e);
-        Lf = fail ? -kBig : Ln;
-        Hf = fail ? kBig : Hn;
-        Kad = fail ? kd : Kad;
-        s = fail ? e : s;
-        d_i = fail ? 1u : dn_i;
-        df = fail ? 1.0 : dn;
-        inv = fail ? 1.0 : inv_next;
+    // one key of the fast walk: e = its index (> 0), Pk / Qk its terms,
+    // kdu = K' as an integer
+    auto step_f = [&](uint32_t e, double Pk, double Qk, uint64_t kdu) {
+        const double inv_next = *reinterpret_cast<const __attribute__((address_space(3))) double*>(ib);
+        const double ql = __builtin_fma(Pk + Ca, inv, kRound);
+        const double qh = __builtin_fma(Qk + Cb, inv, kRound);
+        const double Ln = vmax_f64(Lf, ql), Hn = vmin_f64(Hf, qh);
+        const bool fail = Ln > Hn;  // the key closes the segment
+        const uint64_t m = __builtin_amdgcn_ballot_w64(fail);
+        if (fail) {
+            close_f(false);
+            Ca = cLo - Pk;
+            Cb = cHi - Qk;
+            s = e;
+            Kadu = kdu;
+        }
+        Lf = with_hi(Ln, sel_u32(m, kLoResetHi, (uint32_t)(__double_as_longlong(Ln) >> 32)));
+        Hf = with_hi(Hn, sel_u32(m, kHiResetHi, (uint32_t)(__double_as_longlong(Hn) >> 32)));
+        inv = sel_f64(m, 1.0, inv_next);
+        ib = sel_u32(m, inv_two, ib + 8);
     };
 
     const uint32_t nchunks = B / kLaneChunk;
@@ -1747,27 +1785,31 @@ __device__ __forceinline__ void lanes_fit(const LaneBlock& in, const void* __res
 #pragma unroll
         for (uint32_t t = 0; t < kLaneChunk; t++) kc[t] = row[t];
         if (fast) {
-            // order check and key distances first: independent of the walk
-            double kd[kLaneChunk];
+            // order check and the per-key terms first: independent of the walk
+            const double hc = (double)(c * (kLaneChunk / 2));  // e / 2 at t = 0
+            double X[kLaneChunk];  // K' 2^F
 #pragma unroll
             for (uint32_t t = 0; t < kLaneChunk; t++) {
                 const uint32_t e = c * kLaneChunk + t;
                 const bool valid = full ? true : e < nb;
                 uns_b |= __ballot(valid && kc[t] < prev);
                 prev = valid ? kc[t] : prev;
-                kd[t] = exact_f64(kc[t] - first);
+                X[t] = __builtin_fma(__longlong_as_double((long long)(0x4330000000000000ull | (kc[t] - first))), scf,
+                                     m52);
             }
             if (full) {
 #pragma unroll
                 for (uint32_t t = 0; t < kLaneChunk; t++) {
                     const uint32_t e = c * kLaneChunk + t;
-                    if (e > 0) step_f(e, kd[t]);
+                    const double h = hc + 0.5 * t;
+                    if (e > 0) step_f(e, X[t] + h, X[t] - h, kc[t] - first);
                 }
             } else {
 #pragma unroll
                 for (uint32_t t = 0; t < kLaneChunk; t++) {
                     const uint32_t e = c * kLaneChunk + t;
-                    if (e > 0 && e < nb) step_f(e, kd[t]);
+                    const double h = hc + 0.5 * t;
+                    if (e > 0 && e < nb) step_f(e, X[t] + h, X[t] - h, kc[t] - first);
                 }
             }
         } else {
@@ -1823,9 +1865,9 @@ __device__ __forceinline__ void lanes_fit(const LaneBlock& in, const void* __res
     }
     if (nb) {
         if (fast) {
-            close_f(nb);
-            maxA = (uint64_t)__double_as_longlong(maxAf + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
-            maxd = (uint64_t)__double_as_longlong(Kad + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
+            close_f(true);
+            maxA = to_u64(maxAf);
+            maxd = Kadu;
         } else {
             close(nb, P, H, M);
         }
