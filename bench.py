@@ -103,12 +103,17 @@ def cpu_baseline(host_keys, eps_list, budget_s: float = 24.0, max_threads: int =
     decoded concurrently (the oracle is called through ctypes, which releases
     the interpreter lock, so the threads run in parallel).  Each figure is the
     median of `reps` runs after one warm-up; value = sum(8 n) / sum over eps
-    of the all-core median."""
+    of the all-core median.  Point queries at the middle eps of the sweep:
+    the oracle answers a batch of access(i) (i uniform) or lower_bound(q)
+    (q uniform over the keys' range) by decoding the blob and applying the
+    plain definition; all cores: each thread answers its own piece's share of
+    the batch from that piece's blob."""
     import statistics
     from concurrent.futures import ThreadPoolExecutor
 
     import numpy as np
     import oracle
+    from paper_2412_10770_amd import workloads
 
     model, avail = host_cpu()
     threads = max(1, min(max_threads, avail))
@@ -132,7 +137,8 @@ def cpu_baseline(host_keys, eps_list, budget_s: float = 24.0, max_threads: int =
     per_key = (time.perf_counter() - t0) / len(probe)
     # per eps: one compress (about a decode's time) + (1 + reps) single-core decodes, then the
     # same on all cores (a fraction of that)
-    units = len(eps_list) * (2 + reps) * (1.0 + 2.0 / threads)
+    # + two query batches, each (1 + reps) decodes of the sample on one core and on all cores
+    units = (len(eps_list) * (2 + reps) + 2 * (1 + reps)) * (1.0 + 2.0 / threads)
     runs = spread(int(budget_s / units / max(per_key, 1e-9)))
     sample = np.ascontiguousarray(np.concatenate(runs))
     n_s = len(sample)
@@ -149,6 +155,7 @@ def cpu_baseline(host_keys, eps_list, budget_s: float = 24.0, max_threads: int =
             ts.append(time.perf_counter() - t0)
         return statistics.median(ts)
 
+    q_eps = eps_list[len(eps_list) // 2]
     one_dec = one_enc = all_dec = all_enc = 0.0
     with ThreadPoolExecutor(max_workers=len(pieces)) as pool:
         for eps in eps_list:
@@ -161,7 +168,30 @@ def cpu_baseline(host_keys, eps_list, budget_s: float = 24.0, max_threads: int =
             pblobs = list(pool.map(lambda k: oracle.compress(k, eps, 10, FRAC_BITS), pieces))
             all_enc += time.perf_counter() - t0
             all_dec += median_time(lambda: list(pool.map(oracle.decode, pblobs)))
+            if eps == q_eps:
+                q_blob, q_pblobs = blob, pblobs
+
+        # point queries: one batch of n_q over the sample; on all cores piece t takes n_q / pieces of
+        # them, drawn over its own indices and key range
+        n_q = 1 << 20
+        share = n_q // len(pieces)
+        idx = workloads.uniform_indices(n_q, n_s, seed=workloads.SEED_BASE + 202).numpy()
+        qk = workloads.uniform_keys(n_q, int(sample[0]), int(sample[-1]), seed=workloads.SEED_BASE + 203).numpy()
+        p_idx = [workloads.uniform_indices(share, len(k), seed=workloads.SEED_BASE + 204 + t).numpy()
+                 for t, k in enumerate(pieces)]
+        p_q = [workloads.uniform_keys(share, int(k[0]), int(k[-1]), seed=workloads.SEED_BASE + 204 + t).numpy()
+               for t, k in enumerate(pieces)]
+        assert np.array_equal(oracle.access(oracle.decode(q_blob), idx), sample[idx])
+        assert np.array_equal(oracle.lower_bound(oracle.decode(q_blob), qk).astype(np.int64),
+                              np.searchsorted(sample, qk.astype(sample.dtype)))
+        one_acc = median_time(lambda: oracle.access(oracle.decode(q_blob), idx))
+        one_lb = median_time(lambda: oracle.lower_bound(oracle.decode(q_blob), qk))
+        pt = range(len(pieces))
+        all_acc = median_time(lambda: list(pool.map(lambda t: oracle.access(oracle.decode(q_pblobs[t]), p_idx[t]), pt)))
+        all_lb = median_time(lambda: list(pool.map(lambda t: oracle.lower_bound(oracle.decode(q_pblobs[t]), p_q[t]),
+                                                   pt)))
     nb = n_s * 8 * len(eps_list)
+    n_all = share * len(pieces)
     eps_s = "/".join(str(e) for e in eps_list)
     return {
         "value": round(nb / all_dec / 1e9, 4), "unit": "GB/s", "cores": len(pieces), "kind": "oracle",
@@ -169,6 +199,11 @@ def cpu_baseline(host_keys, eps_list, budget_s: float = 24.0, max_threads: int =
                   f"{len(pieces)} threads on block-aligned pieces, median of {reps} after 1 warm-up",
         "single_core_GBps": round(nb / one_dec / 1e9, 4),
         "compress_GBps": {"single_core": round(nb / one_enc / 1e9, 4), "all_cores": round(nb / all_enc / 1e9, 4)},
+        "access_lookups_per_s": {"single_core": round(n_q / one_acc, 1), "all_cores": round(n_all / all_acc, 1)},
+        "lower_bound_lookups_per_s": {"single_core": round(n_q / one_lb, 1), "all_cores": round(n_all / all_lb, 1)},
+        "queries": f"eps {q_eps}: {n_q} access(i), i uniform, and {n_q} lower_bound(q), q uniform over the "
+                   f"sample's key range, each batch answered by an oracle decode of the blob and the plain "
+                   f"definition; all cores: {share} of each per piece from its own blob",
         "host": {"cpu": model, "cores_available": avail, "nproc": os.cpu_count()},
     }
 
