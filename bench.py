@@ -1012,8 +1012,9 @@ def main():
     ap.add_argument("--access", type=int, default=10_000_000)
     ap.add_argument("--lower-bound", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--full-json", type=str, default=os.path.join("gpurun_out", "bench_full.json"),
-                    help="file receiving the full result record ('' for none); stdout's last line is the headline")
+    ap.add_argument("--full-json", type=str, default="",
+                    help="file that also receives the full result record (it always goes to stderr); "
+                         "stdout's last line is the headline")
     ap.add_argument("--no-batch", action="store_true", help="skip the posting-list batch measurement")
     ap.add_argument("--batch-only", action="store_true", help="only the posting-list batch measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the request-server measurement")
