@@ -178,6 +178,34 @@ def test_access_out_of_range_flag(lc):
         lc.access(blob, idx)
 
 
+def test_point_queries_beyond_one_per_thread(lc, wl):
+    """More queries than threads in one launch (2^24 + 4099): threads past
+    the first pass loop to a second query.  access (with one index out of
+    range, last), lower_bound and quantiles against the plain definitions;
+    quantiles on the threads' second queries plus a random sample."""
+    rng = np.random.default_rng(7)
+    keys = wl.as_numpy(wl.lognormal_distinct(1_000_000, device="cpu"))
+    n = len(keys)
+    m = (1 << 24) + 4099
+    _say(f"point queries m={m} n={n}")
+    blob = lc.compress(_to_dev(keys), 63, 10, 0)
+    idx = rng.integers(0, n, m).astype(np.int64)
+    idx[-1] = n  # out of range: flagged, answered 0
+    flags = torch.zeros(1, dtype=torch.int32, device=DEV)
+    acc = _host(lc.access(blob, torch.from_numpy(idx).to(DEV), flags=flags, check=False), 8)
+    assert int(flags.item()) == lc.LC_FLAG_RANGE
+    assert acc[-1] == 0 and np.array_equal(acc[:-1], oracle.access(keys, idx[:-1]))
+    lo, hi = int(keys[0]), int(keys[-1])
+    q = (lo + rng.integers(0, hi - lo + 2, m)).astype(np.uint64)
+    pos = lc.lower_bound(blob, _to_dev(q)).cpu().numpy().astype(np.uint64)
+    assert np.array_equal(pos, oracle.lower_bound(keys, q))
+    qq = 1_000_003
+    ks = rng.integers(0, qq + 1, m).astype(np.int64)
+    got = _host(lc.quantile(blob, torch.from_numpy(ks).to(DEV), qq), 8)
+    sel = np.concatenate([np.arange((1 << 24) - 64, m), rng.integers(0, m, 20_000)])
+    assert np.array_equal(got[sel], oracle.quantile(keys, ks[sel], qq))
+
+
 def test_configs_reduced(lc, wl):
     """The benchmark recipes at sizes the oracle finishes in seconds."""
     rng = np.random.default_rng(2)
