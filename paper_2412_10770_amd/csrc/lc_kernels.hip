@@ -2164,6 +2164,49 @@ __device__ __forceinline__ void decode_keys(const BlockCtx& c, P16 start, P8 an,
     // window of the bitmap.
     const uint32_t j0 = (uint32_t)(0 - (reinterpret_cast<uintptr_t>(out) / KB + c.obase)) & (V - 1);
     if (lane < j0 && lane >= c.jlo && lane < c.jhi) store_key<KB>(out, c.obase + lane, key_at(lane, seg_of(lane)));
+    if constexpr (F0 && KB == 4) {
+        // A lane's groups are 64 V keys apart, a multiple of 32, so the slab
+        // word offset and shift of its key g + k, its bit in the bitmap word
+        // pair and the prefix mask are the same in every group: computed
+        // once, then a group advances by 2 V w slab words and 2 V bitmap
+        // words.
+        const uint32_t g0 = j0 + lane * V;
+        uint32_t wo[V], sh[V];
+#pragma unroll
+        for (uint32_t k = 0; k < V; k++) {
+            const uint32_t bp = (g0 + k) * c.w;
+            wo[k] = bp >> 5;
+            sh[k] = bp & 31;
+        }
+        const uint32_t bsh = g0 & 31;
+        const uint32_t m0 = 0xFFFFFFFFu >> (31 - bsh);
+        const uint32_t fe = (uint32_t)first_e;
+        uint32_t sw = 0, wb = g0 >> 5;
+        for (uint32_t g = g0; g < c.jhi; g += 64 * V, sw += 2 * V * c.w, wb += 2 * V) {
+            if (RANGE && g + V <= c.jlo) continue;
+            const uint64_t bits = (uint64_t)c.s_bm[wb] | ((uint64_t)c.s_bm[wb + 1] << 32);
+            uint32_t t = c.s_pre[wb] + __popc((uint32_t)bits & m0) - 1;
+            uint32_t v[V];
+#pragma unroll
+            for (uint32_t k = 0; k < V; k++) {
+                if (k) t += (uint32_t)(bits >> (bsh + k)) & 1u;
+                uint32_t tc = t;
+                if constexpr (CLAMP) tc = tc < c.tmax ? tc : c.tmax;
+                const uint32_t* sp = c.s_slab + sw + wo[k];
+                const uint32_t code = __builtin_amdgcn_alignbit(sp[1], sp[0], sh[k]) & wmask32;
+                v[k] = fe + (uint32_t)anchor_of(tc) + (uint32_t)slope_of(tc) * (g + k - start[tc]) + code;
+            }
+            if (g >= c.jlo && g + V <= c.jhi) {
+                __builtin_nontemporal_store(u32x4{v[0], v[1], v[2], v[3]},
+                                            reinterpret_cast<u32x4*>(reinterpret_cast<uint8_t*>(out) + (c.obase + g) * KB));
+            } else {
+#pragma unroll
+                for (uint32_t k = 0; k < V; k++)
+                    if (g + k >= c.jlo && g + k < c.jhi) store_key<KB>(out, c.obase + g + k, v[k]);
+            }
+        }
+        return;
+    }
     for (uint32_t g = j0 + lane * V; g < c.jhi; g += 64 * V) {
         if (RANGE && g + V <= c.jlo) continue;
         const uint32_t wb = g >> 5;
