@@ -106,3 +106,6 @@ def test_cpu_baseline_reports_host_cores_and_medians():
     assert 1 <= r["cores"] <= 4 and r["value"] > 0 and r["single_core_GBps"] > 0
     assert r["host"]["cpu"] and r["host"]["cores_available"] >= 1
     assert "median of 3" in r["sample"]
+    for op in ("access_lookups_per_s", "lower_bound_lookups_per_s"):
+        assert r[op]["single_core"] > 0 and r[op]["all_cores"] > 0
+    assert "eps 63" in r["queries"]
